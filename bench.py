@@ -1,0 +1,201 @@
+"""Benchmark: pair interactions/s of the acceleration + force-gradient sweep on one MI355X.
+
+Workload: King W0 = 6 cluster, N = 2^20, Kroupa masses with 1% binaries carried as centre-of-mass
+particles, Henon units, eps = 0, all particles active; one step = the acceleration pass followed by
+the force-gradient pass on the fresh accelerations (the middle of an FSI cycle), in mixed precision
+(FP32 pair arithmetic, FP64 merge, FP64 re-evaluation of tiles holding pairs closer than
+r_fb = 1e-3).  The all-FP64 path is timed on the same input for the speedup.  Inputs are resident
+in HBM before timing starts.
+
+Prints one JSON line.  Rate = N (N - 1) / (t_acc + t_grad): each pair credited once per sweep.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOPS_ACC = 20     # flops per pair, acceleration (FMA = 2, rsqrt = 1)
+FLOPS_GRAD = 35    # flops per pair, force gradient
+# Non-packed vector peak of MI355X: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz.  The library is
+# built without packed FP32 instructions, so FP32 and FP64 share this issue-rate ceiling.
+PEAK_VALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # 78.64
+
+
+def synthetic_acc_field(d):
+    """Smooth input accelerations for the gradient parity sample (any field is a valid input)."""
+    x, y, z = d["x"], d["y"], d["z"]
+    s = (x * x + y * y + z * z + 0.1) ** -1.5
+    return np.stack([-x * s, -y * s, -z * s], axis=1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--r-fb", type=float, default=1e-3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sample", type=int, default=256, help="targets sampled for the error check")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2210_02472_amd as bf
+    from paper_2210_02472_amd import ics
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    d = ics.king_cluster(ics.rng_for(2), args.n, 6.0, 0.01) if args.n != (1 << 20) else ics.config3_king1m()
+    n = args.n
+    log(f"generated King W0=6 N={n} in {time.time() - t0:.1f}s")
+    P = bf.Particles.from_numpy(d, "cuda:0")
+    ctx = bf.Context(0)
+    out_a = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    out_g = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+
+    def sweep(prec):
+        ctx.forces(P, None, None, G=1.0, eps2=0.0, prec=prec, r_fb=args.r_fb, out=out_a)
+        ctx.force_gradient(P, out_a, None, None, G=1.0, eps2=0.0, prec=prec, r_fb=args.r_fb, out=out_g)
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            sweep(prec)
+        torch.cuda.synchronize()
+        ctx.enable_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            sweep(prec)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        ka = ctx.kernel_times(bf.BF_OP_FORCES)
+        kg = ctx.kernel_times(bf.BF_OP_GRADIENT)
+        ctx.enable_timing(False)
+        return wall, ka, kg
+
+    pairs = float(n) * float(n - 1)
+    log("mixed sweep ...")
+    wall_m, ka_m, kg_m = timed("mixed", args.steps, args.warmup)
+    ms_step = wall_m / args.steps * 1e3
+    value = pairs / (wall_m / args.steps)
+    acc_m = [t.clone() for t in out_a]
+    grad_m = [t.clone() for t in out_g]
+    log(f"mixed: {ms_step:.1f} ms/step, {value:.4e} pairs/s")
+    log("fp64 sweep ...")
+    wall_d, ka_d, kg_d = timed("fp64", args.fp64_steps, 0)
+    ms_fp64 = wall_d / args.fp64_steps * 1e3
+    log(f"fp64: {ms_fp64:.1f} ms/step")
+
+    # mixed sweep vs FP64 GPU sweep, all targets (relative per-target error)
+    def rel(a, b):
+        da = torch.sqrt(sum((x - y) ** 2 for x, y in zip(a, b)))
+        nb = torch.sqrt(sum(y ** 2 for y in b))
+        e = (da / nb).cpu().numpy()
+        return float(np.sqrt(np.mean(e * e))), float(e.max())
+    acc_vs64 = rel(acc_m, out_a)
+    grad_vs64 = rel(grad_m, out_g)
+
+    # mixed vs the FP64 CPU oracle on sampled targets (same inputs on both sides)
+    import oracle
+    Po = oracle.Particles.from_dict(d)
+    rng = np.random.default_rng(2210)
+    T = np.sort(rng.choice(n, args.sample, replace=False))
+    ref_a = oracle.forces(Po, T, None)
+    got_a = np.stack([t.cpu().numpy()[T] for t in acc_m], axis=1)
+    e_a = np.linalg.norm(got_a - ref_a, axis=1) / np.linalg.norm(ref_a, axis=1)
+    af = synthetic_acc_field(d)
+    acc_in = [torch.as_tensor(np.ascontiguousarray(af[:, k]), device="cuda") for k in range(3)]
+    g = ctx.force_gradient(P, acc_in, None, None, prec="mixed", r_fb=args.r_fb)
+    ref_g = oracle.gradient(Po, af, T, None)
+    got_g = np.stack([t.cpu().numpy()[T] for t in g], axis=1)
+    e_g = np.linalg.norm(got_g - ref_g, axis=1) / np.linalg.norm(ref_g, axis=1)
+    flags = ctx.read_flags()
+
+    cfg_a = ctx.query_config(bf.BF_OP_FORCES, "mixed", n, n)
+    cfg_g = ctx.query_config(bf.BF_OP_GRADIENT, "mixed", n, n)
+    avg = lambda v: float(np.mean(v)) if v else float("nan")  # noqa: E731
+    ka, kg = avg(ka_m), avg(kg_m)
+    grad_tflops = pairs * FLOPS_GRAD / (kg * 1e-3) / 1e12
+    acc_tflops = pairs * FLOPS_ACC / (ka * 1e-3) / 1e12
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nthreads = oracle.num_threads()
+        probe = np.sort(rng.choice(n, 16, replace=False))
+        t1 = time.perf_counter()
+        oracle.forces(Po, probe, None)
+        oracle.gradient(Po, af, probe, None)
+        tp = time.perf_counter() - t1
+        k = int(min(8192, max(16, 16 * args.cpu_seconds / max(tp, 1e-3))))
+        Ts = np.sort(rng.choice(n, k, replace=False))
+        log(f"cpu oracle sample: {k} targets x {n} sources on {nthreads} threads ...")
+        t1 = time.perf_counter()
+        oracle.forces(Po, Ts, None)
+        oracle.gradient(Po, af, Ts, None)
+        tc = time.perf_counter() - t1
+        cpu = {"value": k * (n - 1) / tc, "unit": "pair interactions/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"{k} random targets x all {n} sources, acceleration + force-gradient passes, FP64, "
+                         f"{tc:.1f} s"}
+
+    rec = {
+        "metric": "pair interactions/s (acc+force-gradient) at N=2^20, mixed vs FP64; rel. err",
+        "value": value,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 accumulate",
+        "data": "synthetic",
+        "config": {"workload": f"King W0=6 cluster N={n}, Kroupa IMF + 1% binaries as COM particles, Henon units, "
+                               f"eps=0, all active; acceleration + force-gradient sweep, mixed precision with FP64 "
+                               f"re-evaluation of tiles holding pairs closer than r_fb={args.r_fb}",
+                   "n": n, "eps": 0.0, "r_fb": args.r_fb,
+                   "acc_kernel": {"k_per_lane": cfg_a[0], "waves": cfg_a[1], "split": cfg_a[2]},
+                   "grad_kernel": {"k_per_lane": cfg_g[0], "waves": cfg_g[1], "split": cfg_g[2]}},
+        "roofline": {"bound": "alu", "kernel": "k_pairs<GradMixed> (force-gradient pass)",
+                     "achieved": grad_tflops, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": grad_tflops / PEAK_VALU_TFLOPS, "traffic": None,
+                     "flops_per_pair": FLOPS_GRAD, "pairs_per_launch": pairs, "avg_kernel_ms": kg},
+        "acc_pass": {"avg_kernel_ms": ka, "tflops": acc_tflops, "frac": acc_tflops / PEAK_VALU_TFLOPS,
+                     "pairs_per_s": pairs / (ka * 1e-3)},
+        "fp64": {"ms_per_step": ms_fp64, "value": pairs / (wall_d / args.fp64_steps),
+                 "acc_kernel_ms": avg(ka_d), "grad_kernel_ms": avg(kg_d),
+                 "frac": pairs * (FLOPS_ACC + FLOPS_GRAD) / ((avg(ka_d) + avg(kg_d)) * 1e-3) / 1e12 / PEAK_VALU_TFLOPS},
+        "speedup_vs_fp64": ms_fp64 / ms_step,
+        "rel_err": {"acc_vs_oracle_rms": float(np.sqrt(np.mean(e_a ** 2))), "acc_vs_oracle_max": float(e_a.max()),
+                    "grad_vs_oracle_rms": float(np.sqrt(np.mean(e_g ** 2))), "grad_vs_oracle_max": float(e_g.max()),
+                    "oracle_sample_targets": int(args.sample),
+                    "acc_vs_fp64_gpu_rms": acc_vs64[0], "acc_vs_fp64_gpu_max": acc_vs64[1],
+                    "grad_vs_fp64_gpu_rms": grad_vs64[0], "grad_vs_fp64_gpu_max": grad_vs64[1]},
+        "device_flags": flags,
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

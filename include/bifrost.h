@@ -1,0 +1,286 @@
+/*
+ * bifrost.h -- C ABI of the MI355X (gfx950) direct-summation pass of the
+ * hierarchical fourth-order forward symplectic integrator HHS-FSI
+ * (Rantala et al. 2022, BIFROST, arXiv 2210.02472).
+ *
+ * Library: libbifrost_hip.so (hand-written HIP kernels for gfx950).
+ *
+ * General conventions (apply to every entry point unless stated otherwise):
+ *  - Every array argument is a DEVICE pointer owned by the caller; the library
+ *    only owns context-internal scratch (grown on demand, reused afterwards).
+ *  - Calls are stream-ordered and asynchronous on the context's stream unless
+ *    marked "synchronising".  Inputs must stay valid until the work completes.
+ *  - Particle data is structure-of-arrays FP64, particle-indexed, length n.
+ *  - Per-particle outputs are particle-indexed (length n); only entries whose
+ *    particle is listed in `targets` are written, all others are left untouched.
+ *  - Outputs must not alias inputs (bf_fsi_step's in/out state excepted).
+ *  - A source equal to the target (same particle index) is skipped.
+ *  - Index lists hold int32 particle indices (n < 2^31).  Kernels clamp an
+ *    out-of-range list entry to particle 0 (so they never read out of bounds)
+ *    and raise BF_FLAG_BADINDEX; bf_validate_set checks a list synchronously.
+ *  - Errors are return codes (bf_status); nothing is thrown across the ABI.
+ *    Argument checks happen before any launch.  Conditions found on the device
+ *    raise bits in a per-context flag word read by bf_read_flags.
+ *  - One context per host thread.
+ *  - Separations: r_ji = x_j - x_i, s^2 = |r_ji|^2 + eps2 (Plummer softening;
+ *    eps2 = 0 is the paper's unsoftened form).
+ */
+#ifndef BIFROST_H
+#define BIFROST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BF_API __attribute__((visibility("default")))
+
+typedef enum {
+    BF_OK = 0,
+    BF_ERR_ARG = -1,         /* invalid argument (NULL pointer, bad size, bad range, bad enum) */
+    BF_ERR_HIP = -2,         /* a HIP runtime call failed (message in bf_last_error) */
+    BF_ERR_NONFINITE = -3,   /* reserved for callers that turn BF_FLAG_NONFINITE into an error */
+    BF_ERR_UNSUPPORTED = -4, /* no kernel variant for this request */
+    BF_ERR_NOMEM = -5        /* scratch allocation failed */
+} bf_status;
+
+typedef enum {
+    BF_PREC_FP64 = 0,  /* all pair arithmetic in FP64 */
+    BF_PREC_MIXED = 1  /* FP32 pair arithmetic, per-tile FP32 partial sums merged into FP64
+                          accumulators, FP64 re-evaluation of every tile that holds a pair
+                          closer than r_fb (see bf_forces) */
+} bf_prec;
+
+/* device flag bits (bf_read_flags) */
+#define BF_FLAG_NONFINITE  0x1u  /* an output was NaN or infinite */
+#define BF_FLAG_COINCIDENT 0x2u  /* two distinct particles at zero separation with eps2 == 0 */
+#define BF_FLAG_BADINDEX   0x4u  /* an index list held an entry outside [0, n) */
+
+/* Read-only FP64 particle arrays (x, y, z, vx, vy, vz, m), each of length n.
+ * Entry points that do not need velocities accept vx = vy = vz = NULL. */
+typedef struct bf_particles {
+    const double *x, *y, *z, *vx, *vy, *vz, *m;
+    int64_t n;
+} bf_particles;
+
+/* Mutable FP64 state for bf_fsi_step (positions and velocities updated in place). */
+typedef struct bf_state {
+    double *x, *y, *z, *vx, *vy, *vz;
+    const double *m;
+    int64_t n;
+} bf_state;
+
+/* A particle set: if idx != NULL it is the device list idx[0..count) of particle
+ * indices; otherwise it is the contiguous range [begin, begin + count).  Sets used
+ * as sources of a sum must not repeat a particle. */
+typedef struct bf_set {
+    const int32_t *idx;
+    int32_t count;
+    int32_t begin;
+} bf_set;
+
+typedef struct bf_ctx bf_ctx;
+
+/* ---- context ------------------------------------------------------------------------ */
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  Ownership of *ctx passes to the
+ * caller (free with bf_destroy).  BF_ERR_ARG if ctx is NULL or device is invalid. */
+BF_API int bf_create(bf_ctx **ctx, int device, void *hip_stream);
+/* Destroy a context (synchronising) and free its scratch.  NULL is accepted. */
+BF_API int bf_destroy(bf_ctx *ctx);
+/* Rebind the context to another stream of the same device. */
+BF_API int bf_set_stream(bf_ctx *ctx, void *hip_stream);
+/* Static string for a bf_status value. */
+BF_API const char *bf_status_string(int status);
+/* Thread-local text of the last error raised by a bf_* call on this thread ("" if none). */
+BF_API const char *bf_last_error(void);
+/* Synchronising: wait for the context's stream, return the device flag word in *flags,
+ * and clear it if `clear` != 0. */
+BF_API int bf_read_flags(bf_ctx *ctx, uint32_t *flags, int clear);
+/* Synchronising: check that every entry of a list set lies in [0, n).  Returns BF_OK or
+ * BF_ERR_ARG.  Range sets are checked on the host. */
+BF_API int bf_validate_set(bf_ctx *ctx, const bf_set *set, int64_t n);
+/* Library version string. */
+BF_API const char *bf_version(void);
+
+/* ---- the direct-summation pass ------------------------------------------------------ */
+
+/* Newtonian accelerations (Sec. 2.1, Eq. new-newton-acc; inter-level sums of Sec. 2.2):
+ *     a_i = sum_{j in sources, j != i} G m_j r_ji / s^3        for i in targets.
+ * Writes ax/ay/az[i] (FP64, particle-indexed) for every target i.
+ * prec = BF_PREC_MIXED: every LDS tile of sources is first summed in FP32; a tile in which
+ * some pair has s^2 < r_fb^2 (FP32 estimate) is re-evaluated for that wavefront entirely in
+ * FP64 from the FP64 masters (this also removes the self pair).  r_fb >= 0 is a length
+ * (ignored for BF_PREC_FP64).  Distinct particles at zero separation with eps2 == 0
+ * contribute nothing (mixed: BF_FLAG_COINCIDENT is raised).
+ * Errors: BF_ERR_ARG for NULL pointers, n <= 0, negative eps2 or r_fb, bad prec, a range
+ * outside [0, n), count < 0.  count == 0 for targets or sources is a no-op (targets: nothing
+ * written; sources: zeros written). */
+BF_API int bf_forces(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, const bf_set *sources,
+                     double G, double eps2, int prec, double r_fb,
+                     double *ax, double *ay, double *az);
+
+/* Force-gradient sum (Sec. 2.1, Eq. new-grad-acc; inter-level form Sec. 2.2):
+ *     Gsum_i = sum_{j in sources, j != i} G m_j / s^5 (s^2 a_ji - 3 (a_ji . r_ji) r_ji),
+ *     a_ji = a_j - a_i,
+ * with a given by ax/ay/az (FP64, particle-indexed, the accelerations of the same
+ * potential term that is being kicked).  The gradient acceleration of a kick of length
+ * eps is a + eps^2/24 Gsum, and g' of the gradient time-step criteria is Gsum/24.
+ * Writes gx/gy/gz[i] for every target i.  prec and r_fb as in bf_forces. */
+BF_API int bf_force_gradient(bf_ctx *ctx, const bf_particles *P, const bf_set *targets,
+                             const bf_set *sources, const double *ax, const double *ay,
+                             const double *az, double G, double eps2, int prec, double r_fb,
+                             double *gx, double *gy, double *gz);
+
+/* Pairwise time-steps (Sec. 3, Eqs. dt-freefall and dt-flyby), unsoftened:
+ *     dt_ff,i = eta_ff min_j (|r_ij|^3 / (G (m_i + m_j)))^(1/2)
+ *     dt_fb,i = eta_fb min_j |r_ij| / |v_ij|
+ * over sources j != i.  A pair with v_ij = 0 gives no fly-by bound; a target without a
+ * valid source gets +inf.  Needs velocities.  prec as in bf_forces (the mixed path takes
+ * the maxima of G(m_i+m_j)/r^3 and |v_ij|^2/r^2 in FP32 and finishes in FP64; tiles with a
+ * pair closer than max(r_fb, tiny) are re-evaluated in FP64).
+ * Writes dt_ff[i], dt_fb[i] for every target i. */
+BF_API int bf_dt_min(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, const bf_set *sources,
+                     double G, double eta_ff, double eta_fb, int prec, double r_fb,
+                     double *dt_ff, double *dt_fb);
+
+/* Global PN1.0 acceleration (Sec. 3, Eqs. subsyspn and subsyspn-mass), FP64: the pairwise
+ * first post-Newtonian acceleration summed over sources j != i for which i or j is in
+ * bh_idx[0..n_bh) (device list of distinct particle indices).  The two-body term (not
+ * printed in the paper) is the harmonic-gauge form; with n = (x_i - x_j)/r, v_ij = v_i - v_j:
+ *   a_i += G m_j/(c^2 r^2) {[G(5 m_i + 4 m_j)/r + 3/2 (n.v_j)^2 - v_i^2 + 4 v_i.v_j - 2 v_j^2] n
+ *                           + [4 n.v_i - 3 n.v_j] v_ij}.
+ * Writes apx/apy/apz[i] for every target i (zero for targets with no such pair).
+ * BF_ERR_ARG for c <= 0, n_bh < 0, n_bh > 0 with bh_idx NULL. */
+BF_API int bf_pn1_bh(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, const bf_set *sources,
+                     const int32_t *bh_idx, int32_t n_bh, double G, double c,
+                     double *apx, double *apy, double *apz);
+
+/* Synchronising.  Kinetic and potential energy of a set (Sec. 2.1, the N-body
+ * Hamiltonian) in FP64: T = sum 1/2 m v^2, U = -sum_{i<j} G m_i m_j / s_ij, written to the
+ * host scalars *kinetic and *potential.  Deterministic for a given set and device. */
+BF_API int bf_energy(bf_ctx *ctx, const bf_particles *P, const bf_set *set, double G, double eps2,
+                     double *kinetic, double *potential);
+
+/* ---- integrator step ---------------------------------------------------------------- */
+
+typedef struct bf_fsi_params {
+    double G, eps2;
+    int prec;          /* bf_prec for the force and gradient passes */
+    double r_fb;       /* close-pair radius of the mixed path */
+    const int32_t *bh_idx; int32_t n_bh; double c;  /* n_bh == 0: no PN1.0 half-kicks */
+} bf_fsi_params;
+
+#define BF_A_VALID 0x1  /* ax/ay/az already hold the accelerations of the current state */
+
+/* One FSI cycle of length dt (Sec. 2.1, Eq. fsi-cycle) over the particles of `set`, which
+ * act as both targets and sources (the sub-Hamiltonian of that set):
+ *   v += dt/6 a; x += dt/2 v; v += 2dt/3 (a + dt^2/24 Gsum); x += dt/2 v; v += dt/6 a,
+ * each a evaluated at the current positions.  With n_bh > 0 the cycle is wrapped in two PN1.0
+ * half-kicks v += dt/2 a_PN (Sec. 3, composition e^{eps/2 U_PN} e^{eps H_FSI} e^{eps/2 U_PN}).
+ * ax/ay/az (particle-indexed, caller-owned) hold the accelerations of the final state on
+ * return; with flags & BF_A_VALID their input values are reused for the first kick.
+ * All updates are FP64.  Errors as in bf_forces. */
+BF_API int bf_fsi_step(bf_ctx *ctx, const bf_state *S, const bf_set *set, double dt,
+                       const bf_fsi_params *prm, double *ax, double *ay, double *az, int flags);
+
+/* Elementwise kicks and drifts used by integrator drivers (FP64, over the set):
+ *   bf_kick:  v_i += h (a_i + h2 g_i)   (g may be NULL, then h2 is ignored)
+ *   bf_drift: x_i += h v_i                                              (Sec. 2.1) */
+BF_API int bf_kick(bf_ctx *ctx, const bf_state *S, const bf_set *set, double h, const double *ax,
+                   const double *ay, const double *az, double h2, const double *gx, const double *gy,
+                   const double *gz);
+BF_API int bf_drift(bf_ctx *ctx, const bf_state *S, const bf_set *set, double h);
+
+/* ---- batched ensembles -------------------------------------------------------------- */
+
+/* Accelerations for an ensemble of independent clusters stored back to back in P
+ * (cluster c owns particles [cluster_off[c], cluster_off[c+1])), each summing only over its
+ * own cluster, for the active particles active_idx[active_off[c] .. active_off[c+1]) of each
+ * cluster (global particle indices inside the cluster's range).  cluster_off and active_off
+ * are DEVICE arrays of n_clusters + 1 int64 entries; their contents may change between calls
+ * (and between replays of a captured graph) as long as max_active_total and max_cluster_n
+ * bound them.  One persistent launch covers all clusters (Sec. 2.2's uneven level sizes).
+ * Results as bf_forces for each cluster. */
+BF_API int bf_forces_batched(bf_ctx *ctx, const bf_particles *P, int32_t n_clusters,
+                             const int64_t *cluster_off, const int32_t *active_idx,
+                             const int64_t *active_off, int64_t max_active_total, int64_t max_cluster_n,
+                             double G, double eps2, int prec, double r_fb,
+                             double *ax, double *ay, double *az);
+
+/* Force-gradient sums for the same ensemble layout (Gsum of the active particles of every
+ * cluster from all particles of that cluster; ax/ay/az particle-indexed as in
+ * bf_force_gradient). */
+BF_API int bf_force_gradient_batched(bf_ctx *ctx, const bf_particles *P, int32_t n_clusters,
+                                     const int64_t *cluster_off, const int32_t *active_idx,
+                                     const int64_t *active_off, int64_t max_active_total,
+                                     int64_t max_cluster_n, const double *ax, const double *ay,
+                                     const double *az, double G, double eps2, int prec, double r_fb,
+                                     double *gx, double *gy, double *gz);
+
+/* One FSI cycle of length dt (Sec. 2.1, Eq. fsi-cycle) of the active particles of every cluster,
+ * with every particle of the cluster as a source (inactive particles stay frozen): kick dt/6,
+ * drift dt/2, batched forces, batched gradient, kick 2dt/3 with a + dt^2/24 Gsum, drift dt/2,
+ * batched forces, kick dt/6.  ax/ay/az must hold the accelerations of the current state of the
+ * active particles on entry and hold those of the new state on return.  Stream-ordered. */
+BF_API int bf_fsi_step_batched(bf_ctx *ctx, const bf_state *S, int32_t n_clusters,
+                               const int64_t *cluster_off, const int32_t *active_idx,
+                               const int64_t *active_off, int64_t max_active_total,
+                               int64_t max_cluster_n, double G, double eps2, int prec, double r_fb,
+                               double dt, double *ax, double *ay, double *az);
+
+/* Capture into a HIP graph the same FSI cycle as bf_fsi_step_batched.  ax/ay/az must hold the
+ * accelerations of the current state when the graph is launched and hold those of the new state
+ * afterwards.  Scratch is sized here for the given bounds; replays read the device arrays'
+ * current contents (offsets, lists) and allocate nothing.  *graph_exec receives an opaque handle
+ * (free with bf_graph_destroy). */
+BF_API int bf_graph_capture_batched_fsi(bf_ctx *ctx, const bf_state *S, int32_t n_clusters,
+                                        const int64_t *cluster_off, const int32_t *active_idx,
+                                        const int64_t *active_off, int64_t max_active_total,
+                                        int64_t max_cluster_n, double G, double eps2, int prec,
+                                        double r_fb, double dt, double *ax, double *ay, double *az,
+                                        void **graph_exec);
+/* Launch a captured graph on the context's stream. */
+BF_API int bf_graph_launch(bf_ctx *ctx, void *graph_exec);
+/* Free a captured graph (NULL accepted). */
+BF_API int bf_graph_destroy(void *graph_exec);
+
+/* ---- tuning ------------------------------------------------------------------------- */
+
+typedef enum { BF_OP_FORCES = 0, BF_OP_GRADIENT = 1, BF_OP_DTMIN = 2 } bf_op;
+
+/* Synchronising.  Time every kernel variant (targets per lane, waves per workgroup,
+ * source split) for operation `op` at precision `prec` on n_targets x n_sources synthetic
+ * pairs and store the fastest in the context for that size bucket.  If cache_path is not
+ * NULL the table is merged into that JSON file (read first if it exists). */
+BF_API int bf_autotune(bf_ctx *ctx, int op, int prec, int64_t n_targets, int64_t n_sources,
+                       const char *cache_path);
+/* Load a tuning table written by bf_autotune. */
+BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
+
+/* Kernel configuration the context would use for a pass (for reporting):
+ * targets per lane, waves per workgroup, source split. */
+BF_API int bf_query_config(bf_ctx *ctx, int op, int prec, int64_t n_targets, int64_t n_sources,
+                           int *k_per_lane, int *waves, int *split);
+/* Force the kernel configuration for subsequent calls of op/prec (0 restores the default
+ * choice; split 0 means automatic). */
+BF_API int bf_set_config(bf_ctx *ctx, int op, int prec, int k_per_lane, int waves, int split);
+
+/* ---- kernel timing ------------------------------------------------------------------ */
+
+/* When on != 0 the context records a pair of HIP events on its stream around every launch
+ * of the main pair kernel of bf_forces / bf_force_gradient / bf_dt_min (pack and reduction
+ * kernels excluded).  Turning timing on or off discards earlier records. */
+BF_API int bf_enable_timing(bf_ctx *ctx, int on);
+/* Synchronising.  Copy the durations (milliseconds) of the recorded launches of op
+ * (bf_op) into ms[0 .. min(count, cap)), set *count to the number recorded, and discard
+ * them. */
+BF_API int bf_kernel_times(bf_ctx *ctx, int op, float *ms, int cap, int *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIFROST_H */

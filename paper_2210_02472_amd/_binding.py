@@ -1,0 +1,403 @@
+"""ctypes binding of libbifrost_hip.so (the C ABI declared in include/bifrost.h).
+
+Argument marshalling only: tensors are passed as device pointers, torch supplies device
+memory and the current stream, and every numerical step runs in the library's kernels.
+There is no fallback: if the library or a GPU is missing the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbifrost_hip.so")
+
+BF_OK = 0
+BF_PREC_FP64 = 0
+BF_PREC_MIXED = 1
+BF_FLAG_NONFINITE = 0x1
+BF_FLAG_COINCIDENT = 0x2
+BF_FLAG_BADINDEX = 0x4
+BF_A_VALID = 0x1
+BF_OP_FORCES, BF_OP_GRADIENT, BF_OP_DTMIN = 0, 1, 2
+
+PRECISIONS = {"fp64": BF_PREC_FP64, "mixed": BF_PREC_MIXED}
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+_int = ctypes.c_int
+
+
+class _Particles(ctypes.Structure):
+    _fields_ = [("x", _vp), ("y", _vp), ("z", _vp), ("vx", _vp), ("vy", _vp), ("vz", _vp), ("m", _vp), ("n", _i64)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("x", _vp), ("y", _vp), ("z", _vp), ("vx", _vp), ("vy", _vp), ("vz", _vp), ("m", _vp), ("n", _i64)]
+
+
+class _Set(ctypes.Structure):
+    _fields_ = [("idx", _vp), ("count", _i32), ("begin", _i32)]
+
+
+class _FsiParams(ctypes.Structure):
+    _fields_ = [("G", _d), ("eps2", _d), ("prec", _int), ("r_fb", _d), ("bh_idx", _vp), ("n_bh", _i32), ("c", _d)]
+
+
+class BifrostError(RuntimeError):
+    def __init__(self, func: str, code: int, msg: str):
+        super().__init__(f"{func} failed with status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbifrost_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python paper_2210_02472_amd/build.py`")
+    lib = ctypes.CDLL(path)
+    P, S, ST, FP = ctypes.POINTER(_Particles), ctypes.POINTER(_Set), ctypes.POINTER(_State), ctypes.POINTER(_FsiParams)
+    sig = {
+        "bf_create": [ctypes.POINTER(_vp), _int, _vp],
+        "bf_destroy": [_vp],
+        "bf_set_stream": [_vp, _vp],
+        "bf_read_flags": [_vp, ctypes.POINTER(ctypes.c_uint32), _int],
+        "bf_validate_set": [_vp, S, _i64],
+        "bf_forces": [_vp, P, S, S, _d, _d, _int, _d, _vp, _vp, _vp],
+        "bf_force_gradient": [_vp, P, S, S, _vp, _vp, _vp, _d, _d, _int, _d, _vp, _vp, _vp],
+        "bf_dt_min": [_vp, P, S, S, _d, _d, _d, _int, _d, _vp, _vp],
+        "bf_pn1_bh": [_vp, P, S, S, _vp, _i32, _d, _d, _vp, _vp, _vp],
+        "bf_energy": [_vp, P, S, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)],
+        "bf_fsi_step": [_vp, ST, S, _d, FP, _vp, _vp, _vp, _int],
+        "bf_kick": [_vp, ST, S, _d, _vp, _vp, _vp, _d, _vp, _vp, _vp],
+        "bf_drift": [_vp, ST, S, _d],
+        "bf_forces_batched": [_vp, P, _i32, _vp, _vp, _vp, _i64, _i64, _d, _d, _int, _d, _vp, _vp, _vp],
+        "bf_force_gradient_batched": [_vp, P, _i32, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _d, _d, _int, _d,
+                                      _vp, _vp, _vp],
+        "bf_fsi_step_batched": [_vp, ST, _i32, _vp, _vp, _vp, _i64, _i64, _d, _d, _int, _d, _d, _vp, _vp, _vp],
+        "bf_graph_capture_batched_fsi": [_vp, ST, _i32, _vp, _vp, _vp, _i64, _i64, _d, _d, _int, _d, _d, _vp, _vp,
+                                         _vp, ctypes.POINTER(_vp)],
+        "bf_graph_launch": [_vp, _vp],
+        "bf_graph_destroy": [_vp],
+        "bf_autotune": [_vp, _int, _int, _i64, _i64, ctypes.c_char_p],
+        "bf_autotune_load": [_vp, ctypes.c_char_p],
+        "bf_query_config": [_vp, _int, _int, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                            ctypes.POINTER(_int)],
+        "bf_set_config": [_vp, _int, _int, _int, _int, _int],
+        "bf_enable_timing": [_vp, _int],
+        "bf_kernel_times": [_vp, _int, ctypes.POINTER(ctypes.c_float), _int, ctypes.POINTER(_int)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = _int
+    lib.bf_status_string.argtypes = [_int]
+    lib.bf_status_string.restype = ctypes.c_char_p
+    lib.bf_last_error.argtypes = []
+    lib.bf_last_error.restype = ctypes.c_char_p
+    lib.bf_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(name: str, rc: int):
+    if rc != BF_OK:
+        msg = _lib.bf_last_error().decode() or _lib.bf_status_string(rc).decode()
+        raise BifrostError(name, rc, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, n: Optional[int] = None, name: str = "tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements")
+    return t
+
+
+@dataclass
+class ParticleSet:
+    """A set of particles: an int32 device index list, or the range [begin, begin + count)."""
+    idx: Optional[torch.Tensor] = None
+    begin: int = 0
+    count: int = 0
+
+    @staticmethod
+    def range(begin: int, count: int) -> "ParticleSet":
+        return ParticleSet(None, int(begin), int(count))
+
+    @staticmethod
+    def of(sel, n: int, device=None) -> "ParticleSet":
+        """None -> all n particles; a ParticleSet as is; a tensor/array/list -> index list."""
+        if sel is None:
+            return ParticleSet(None, 0, n)
+        if isinstance(sel, ParticleSet):
+            return sel
+        t = sel if isinstance(sel, torch.Tensor) else torch.as_tensor(sel)
+        t = t.to(device=device or "cuda", dtype=torch.int32).contiguous()
+        return ParticleSet(t, 0, int(t.numel()))
+
+    def _c(self) -> _Set:
+        return _Set(_ptr(self.idx), int(self.count), int(self.begin))
+
+
+class Particles:
+    """FP64 structure-of-arrays particle state on the device (x, y, z, vx, vy, vz, m)."""
+    KEYS = ("x", "y", "z", "vx", "vy", "vz", "m")
+
+    def __init__(self, **arrays: torch.Tensor):
+        n = int(arrays["m"].numel())
+        for k in self.KEYS:
+            setattr(self, k, _need(arrays[k], torch.float64, n, k))
+        self.n = n
+
+    @staticmethod
+    def from_numpy(d: dict, device="cuda") -> "Particles":
+        return Particles(**{k: torch.as_tensor(d[k], dtype=torch.float64, device=device).contiguous()
+                            for k in Particles.KEYS})
+
+    def to_numpy(self) -> dict:
+        return {k: getattr(self, k).cpu().numpy() for k in self.KEYS}
+
+    def _c(self) -> _Particles:
+        return _Particles(*(_ptr(getattr(self, k)) for k in self.KEYS), self.n)
+
+    def _state(self) -> _State:
+        return _State(*(_ptr(getattr(self, k)) for k in self.KEYS), self.n)
+
+
+class Context:
+    """A bf_ctx bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU available for libbifrost_hip")
+        self.device = device
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = st
+        h = _vp()
+        _check("bf_create", lib.bf_create(ctypes.byref(h), device, _vp(st.cuda_stream)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.bf_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._stream = stream
+        _check("bf_set_stream", _lib.bf_set_stream(self._h, _vp(stream.cuda_stream)))
+
+    def read_flags(self, clear: bool = True) -> int:
+        f = ctypes.c_uint32(0)
+        _check("bf_read_flags", _lib.bf_read_flags(self._h, ctypes.byref(f), int(clear)))
+        return int(f.value)
+
+    def validate_set(self, s: ParticleSet, n: int):
+        _check("bf_validate_set", _lib.bf_validate_set(self._h, ctypes.byref(s._c()), int(n)))
+
+    # ---- the pass ----------------------------------------------------------------------------
+
+    def _outs(self, P: Particles, out, k: int):
+        if out is None:
+            return [torch.zeros(P.n, dtype=torch.float64, device=P.m.device) for _ in range(k)]
+        for t in out:
+            _need(t, torch.float64, P.n, "output")
+        return list(out)
+
+    def forces(self, P: Particles, targets=None, sources=None, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3,
+               out: Optional[Sequence[torch.Tensor]] = None):
+        """Accelerations (particle-indexed ax, ay, az; only target entries written)."""
+        t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
+        o = self._outs(P, out, 3)
+        _check("bf_forces", _lib.bf_forces(self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()),
+                                           float(G), float(eps2), PRECISIONS[prec], float(r_fb), *map(_ptr, o)))
+        return o
+
+    def force_gradient(self, P: Particles, acc: Sequence[torch.Tensor], targets=None, sources=None, G=1.0, eps2=0.0,
+                       prec="mixed", r_fb=1e-3, out: Optional[Sequence[torch.Tensor]] = None):
+        """Force-gradient sums Gsum (particle-indexed gx, gy, gz)."""
+        t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
+        for a in acc:
+            _need(a, torch.float64, P.n, "acceleration")
+        o = self._outs(P, out, 3)
+        _check("bf_force_gradient", _lib.bf_force_gradient(
+            self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()), *map(_ptr, acc), float(G),
+            float(eps2), PRECISIONS[prec], float(r_fb), *map(_ptr, o)))
+        return o
+
+    def dt_min(self, P: Particles, targets=None, sources=None, G=1.0, eta_ff=0.2, eta_fb=0.2, prec="mixed", r_fb=1e-3,
+               out: Optional[Sequence[torch.Tensor]] = None):
+        """Free-fall and fly-by time-steps (particle-indexed dt_ff, dt_fb)."""
+        t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
+        o = self._outs(P, out, 2)
+        _check("bf_dt_min", _lib.bf_dt_min(self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()),
+                                           float(G), float(eta_ff), float(eta_fb), PRECISIONS[prec], float(r_fb),
+                                           *map(_ptr, o)))
+        return o
+
+    def pn1_bh(self, P: Particles, bh, targets=None, sources=None, G=1.0, c=1e4,
+               out: Optional[Sequence[torch.Tensor]] = None):
+        """PN1.0 accelerations over pairs that involve a listed black hole."""
+        t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
+        b = ParticleSet.of(bh, P.n)
+        o = self._outs(P, out, 3)
+        _check("bf_pn1_bh", _lib.bf_pn1_bh(self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()),
+                                           _ptr(b.idx), int(b.count), float(G), float(c), *map(_ptr, o)))
+        return o
+
+    def energy(self, P: Particles, subset=None, G=1.0, eps2=0.0):
+        s = ParticleSet.of(subset, P.n)
+        k, u = _d(0.0), _d(0.0)
+        _check("bf_energy", _lib.bf_energy(self._h, ctypes.byref(P._c()), ctypes.byref(s._c()), float(G), float(eps2),
+                                           ctypes.byref(k), ctypes.byref(u)))
+        return k.value, u.value
+
+    def fsi_step(self, P: Particles, dt: float, subset=None, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3, bh=None,
+                 c=1e4, acc: Optional[Sequence[torch.Tensor]] = None, acc_valid: bool = False):
+        """One FSI cycle in place over `subset`; returns the accelerations of the final state."""
+        s = ParticleSet.of(subset, P.n)
+        b = ParticleSet.of(bh, P.n) if bh is not None else ParticleSet(None, 0, 0)
+        a = self._outs(P, acc, 3)
+        prm = _FsiParams(float(G), float(eps2), PRECISIONS[prec], float(r_fb), _ptr(b.idx), int(b.count), float(c))
+        _check("bf_fsi_step", _lib.bf_fsi_step(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()), float(dt),
+                                               ctypes.byref(prm), *map(_ptr, a), BF_A_VALID if acc_valid else 0))
+        return a
+
+    def kick(self, P: Particles, subset, h, acc, h2=0.0, grad=None):
+        s = ParticleSet.of(subset, P.n)
+        g = grad if grad is not None else (None, None, None)
+        _check("bf_kick", _lib.bf_kick(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()), float(h),
+                                       *map(_ptr, acc), float(h2), *map(_ptr, g)))
+
+    def drift(self, P: Particles, subset, h):
+        s = ParticleSet.of(subset, P.n)
+        _check("bf_drift", _lib.bf_drift(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()), float(h)))
+
+    # ---- batched ensembles -------------------------------------------------------------------
+
+    def forces_batched(self, P: Particles, cluster_off: torch.Tensor, active_idx: torch.Tensor,
+                       active_off: torch.Tensor, max_active_total: int, max_cluster_n: int, G=1.0, eps2=0.0,
+                       prec="mixed", r_fb=1e-3, out=None):
+        _need(cluster_off, torch.int64, None, "cluster_off")
+        _need(active_off, torch.int64, None, "active_off")
+        _need(active_idx, torch.int32, None, "active_idx")
+        o = self._outs(P, out, 3)
+        nc = int(cluster_off.numel()) - 1
+        _check("bf_forces_batched", _lib.bf_forces_batched(
+            self._h, ctypes.byref(P._c()), nc, _ptr(cluster_off), _ptr(active_idx), _ptr(active_off),
+            int(max_active_total), int(max_cluster_n), float(G), float(eps2), PRECISIONS[prec], float(r_fb),
+            *map(_ptr, o)))
+        return o
+
+    def force_gradient_batched(self, P: Particles, cluster_off, active_idx, active_off, max_active_total: int,
+                               max_cluster_n: int, acc, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3, out=None):
+        o = self._outs(P, out, 3)
+        nc = int(cluster_off.numel()) - 1
+        _check("bf_force_gradient_batched", _lib.bf_force_gradient_batched(
+            self._h, ctypes.byref(P._c()), nc, _ptr(cluster_off), _ptr(active_idx), _ptr(active_off),
+            int(max_active_total), int(max_cluster_n), *map(_ptr, acc), float(G), float(eps2), PRECISIONS[prec],
+            float(r_fb), *map(_ptr, o)))
+        return o
+
+    def fsi_step_batched(self, P: Particles, cluster_off, active_idx, active_off, max_active_total, max_cluster_n,
+                         dt, acc, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3):
+        """One FSI cycle of every cluster's active particles (see bf_fsi_step_batched)."""
+        nc = int(cluster_off.numel()) - 1
+        _check("bf_fsi_step_batched", _lib.bf_fsi_step_batched(
+            self._h, ctypes.byref(P._state()), nc, _ptr(cluster_off), _ptr(active_idx), _ptr(active_off),
+            int(max_active_total), int(max_cluster_n), float(G), float(eps2), PRECISIONS[prec], float(r_fb),
+            float(dt), *map(_ptr, acc)))
+
+    def capture_batched_fsi(self, P: Particles, cluster_off, active_idx, active_off, max_active_total,
+                            max_cluster_n, dt, acc, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3):
+        """Capture one batched FSI cycle into a HIP graph (see bf_graph_capture_batched_fsi)."""
+        g = _vp()
+        nc = int(cluster_off.numel()) - 1
+        _check("bf_graph_capture_batched_fsi", _lib.bf_graph_capture_batched_fsi(
+            self._h, ctypes.byref(P._state()), nc, _ptr(cluster_off), _ptr(active_idx), _ptr(active_off),
+            int(max_active_total), int(max_cluster_n), float(G), float(eps2), PRECISIONS[prec], float(r_fb),
+            float(dt), *map(_ptr, acc), ctypes.byref(g)))
+        return Graph(self, g)
+
+    # ---- configuration -----------------------------------------------------------------------
+
+    def autotune(self, op: int, prec: str, n_targets: int, n_sources: int, cache_path: Optional[str] = None):
+        _check("bf_autotune", _lib.bf_autotune(self._h, op, PRECISIONS[prec], int(n_targets), int(n_sources),
+                                               cache_path.encode() if cache_path else None))
+
+    def autotune_load(self, cache_path: str):
+        _check("bf_autotune_load", _lib.bf_autotune_load(self._h, cache_path.encode()))
+
+    def query_config(self, op: int, prec: str, n_targets: int, n_sources: int):
+        k, w, s = _int(0), _int(0), _int(0)
+        _check("bf_query_config", _lib.bf_query_config(self._h, op, PRECISIONS[prec], int(n_targets), int(n_sources),
+                                                       ctypes.byref(k), ctypes.byref(w), ctypes.byref(s)))
+        return k.value, w.value, s.value
+
+    def enable_timing(self, on: bool = True):
+        _check("bf_enable_timing", _lib.bf_enable_timing(self._h, int(on)))
+
+    def kernel_times(self, op: int, cap: int = 4096):
+        """Durations (ms) of the pair-kernel launches of op recorded since the last call."""
+        buf = (ctypes.c_float * cap)()
+        cnt = _int(0)
+        _check("bf_kernel_times", _lib.bf_kernel_times(self._h, op, buf, cap, ctypes.byref(cnt)))
+        return [float(buf[i]) for i in range(min(cnt.value, cap))]
+
+    def set_config(self, op: int, prec: str, k: int = 0, waves: int = 0, split: int = 0):
+        _check("bf_set_config", _lib.bf_set_config(self._h, op, PRECISIONS[prec], int(k), int(waves), int(split)))
+
+
+class Graph:
+    """A captured HIP graph (opaque handle) replayed on the context's stream."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx, self._g = ctx, handle
+
+    def launch(self):
+        _check("bf_graph_launch", _lib.bf_graph_launch(self.ctx.handle, self._g))
+
+    def close(self):
+        if self._g and self._g.value:
+            _lib.bf_graph_destroy(self._g)
+            self._g = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,469 @@
+// Batched ensembles of independent clusters in one persistent launch.
+//
+// Cluster c owns particles [coff[c], coff[c+1]) and active particles aidx[aoff[c] .. aoff[c+1]).
+// A work item is (cluster, slab of 64*K*W active targets, chunk of kBatchChunk sources of that
+// cluster).  k_batch_plan counts items per cluster and scans them (one workgroup); the persistent
+// workgroups of k_batch_pairs pull items from an atomic counter until the queue is empty and
+// write per-chunk partials; k_batch_reduce adds each target's chunks in chunk order.  Every
+// item's result and output location are fixed, so the outcome does not depend on which
+// workgroup ran it.  All sizes of the launches depend only on host-side bounds, so the whole
+// sequence can be captured in a HIP graph and replayed while the offsets and lists change.
+#include <algorithm>
+#include <string>
+
+#include "pair_ops.h"
+
+namespace bf {
+
+constexpr int kBatchChunk = 4096;  // sources per work item (16 tiles of 256)
+constexpr int kBK = 2, kBW = 4;    // targets per lane, waves per workgroup
+constexpr int kSlab = 64 * kBK * kBW;
+
+struct Batch {
+    PairArgs base;        // masters, constants, flags; tgt/src/pack are set per item
+    int32_t nclusters;
+    const int64_t* coff;  // [nclusters + 1]
+    const int32_t* aidx;  // active particle indices
+    const int64_t* aoff;  // [nclusters + 1]
+    int64_t max_active;
+    int64_t max_cluster_n;
+    int32_t max_chunks;
+    int32_t pack_bytes;   // bytes per packed source
+    int32_t* item_off;    // [nclusters + 1]
+    int32_t* counter;
+    int32_t* bad;         // [nclusters] 1 if the cluster's offsets are invalid
+    double* part;         // [max_chunks][NC][max_active]
+    double *o0, *o1, *o2;
+};
+
+// cluster bounds with validation (invalid clusters are skipped and flagged)
+__device__ __forceinline__ bool cluster_bounds(const Batch& b, int c, int64_t& cb, int64_t& ce, int64_t& a0,
+                                               int64_t& a1) {
+    cb = b.coff[c]; ce = b.coff[c + 1];
+    a0 = b.aoff[c]; a1 = b.aoff[c + 1];
+    return cb >= 0 && ce >= cb && ce <= b.base.P.n && ce - cb <= b.max_cluster_n && a0 >= 0 && a1 >= a0 &&
+           a1 <= b.max_active;
+}
+
+// One workgroup of 1024 threads: per-cluster item counts, exclusive scan, reset of the queue.
+__global__ __launch_bounds__(1024) void k_batch_plan(const Batch b) {
+    __shared__ int32_t sums[1024];
+    const int nc = b.nclusters;
+    const int per = (nc + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(nc, lo + per);
+    int32_t s = 0;
+    for (int c = lo; c < hi; ++c) {
+        int64_t cb, ce, a0, a1;
+        int32_t items = 0;
+        const bool ok = cluster_bounds(b, c, cb, ce, a0, a1);
+        if (!ok) atomicOr(b.base.flags, BF_FLAG_BADINDEX);
+        b.bad[c] = ok ? 0 : 1;
+        if (ok && a1 > a0 && ce > cb) {
+            const int64_t nslab = (a1 - a0 + kSlab - 1) / kSlab;
+            const int64_t nch = (ce - cb + kBatchChunk - 1) / kBatchChunk;
+            items = (int32_t)(nslab * nch);
+        }
+        b.item_off[c] = items;  // counts for now
+        s += items;
+    }
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int32_t v = sums[t];
+            sums[t] = run;
+            run += v;
+        }
+        b.item_off[nc] = run;
+        *b.counter = 0;
+    }
+    __syncthreads();
+    int32_t run = sums[threadIdx.x];
+    for (int c = lo; c < hi; ++c) {
+        const int32_t v = b.item_off[c];
+        b.item_off[c] = run;
+        run += v;
+    }
+}
+
+template <class Op, int K, int W>
+__global__ __launch_bounds__(64 * W) void k_batch_pairs(const Batch b) {
+    __shared__ typename Op::Src tile[64 * W];
+    __shared__ int32_t s_item;
+    const int wave = threadIdx.x >> 6;
+    const int32_t total = b.item_off[b.nclusters];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(b.counter, 1);
+        __syncthreads();
+        const int32_t item = s_item;
+        if (item >= total) break;
+        // cluster of the item: largest c with item_off[c] <= item (empty clusters share offsets)
+        int lo = 0, hi = b.nclusters - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.item_off[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const int c = lo;
+        int64_t cb, ce, a0, a1;
+        cluster_bounds(b, c, cb, ce, a0, a1);  // validated by k_batch_plan (bad clusters have no items)
+        const int32_t na = (int32_t)(a1 - a0), ns = (int32_t)(ce - cb);
+        const int32_t nch = (ns + kBatchChunk - 1) / kBatchChunk;
+        const int32_t local = item - b.item_off[c];
+        const int32_t slab = local / nch, q = local % nch;
+        PairArgs a = b.base;
+        a.tgt = DevSet{b.aidx + a0, na, 0};
+        a.src = DevSet{nullptr, ns, (int32_t)cb};
+        a.pack = static_cast<const char*>(b.base.pack) + cb * b.pack_bytes;
+        const int j0 = q * kBatchChunk;
+        const int j1 = min(ns, j0 + kBatchChunk);
+        typename Op::A64 acc[K];
+        int slot[K], pidx[K];
+        sweep<Op, K, W>(a, tile, slab * (64 * K * W) + wave * (64 * K), j0, j1, acc, slot, pidx);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (slot[k] < na) {
+                double v[Op::NC];
+                Op::comps(acc[k], v);
+#pragma unroll
+                for (int comp = 0; comp < Op::NC; ++comp)
+                    b.part[((size_t)q * Op::NC + comp) * b.max_active + a0 + slot[k]] = v[comp];
+            }
+        }
+    }
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_batch_reduce(const Batch b) {
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= b.max_active) return;
+    const int64_t atot = b.aoff[b.nclusters];
+    if (a >= atot) return;
+    int lo = 0, hi = b.nclusters - 1;  // cluster with aoff[c] <= a < aoff[c+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.aoff[mid] <= a) lo = mid;
+        else hi = mid - 1;
+    }
+    const int c = lo;
+    if (b.bad[c]) return;
+    int64_t cb, ce, a0, a1;
+    cluster_bounds(b, c, cb, ce, a0, a1);
+    if (a < a0 || a >= a1) return;
+    const int32_t nch = (int32_t)((ce - cb + kBatchChunk - 1) / kBatchChunk);
+    double v[NC];
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) v[comp] = 0.0;
+    for (int q = 0; q < nch; ++q)
+#pragma unroll
+        for (int comp = 0; comp < NC; ++comp) v[comp] += b.part[((size_t)q * NC + comp) * b.max_active + a];
+    int32_t p = b.aidx[a];
+    if (p < cb || p >= ce) {
+        atomicOr(b.base.flags, BF_FLAG_BADINDEX);
+        return;
+    }
+    if (!__builtin_isfinite(v[0]) || !__builtin_isfinite(v[1]) || !__builtin_isfinite(v[2]))
+        atomicOr(b.base.flags, BF_FLAG_NONFINITE);
+    b.o0[p] = v[0]; b.o1[p] = v[1]; b.o2[p] = v[2];
+}
+
+// kick / drift of the active particles of every cluster
+__global__ __launch_bounds__(256) void k_batch_kick(bf_state S, const Batch b, double h, const double* ax,
+                                                    const double* ay, const double* az, double h2, const double* gx,
+                                                    const double* gy, const double* gz) {
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= b.max_active || a >= b.aoff[b.nclusters]) return;
+    const int32_t p = b.aidx[a];
+    if (p < 0 || p >= S.n) return;  // flagged by the reduction
+    double kx = ax[p], ky = ay[p], kz = az[p];
+    if (gx) {
+        kx = __builtin_fma(h2, gx[p], kx);
+        ky = __builtin_fma(h2, gy[p], ky);
+        kz = __builtin_fma(h2, gz[p], kz);
+    }
+    S.vx[p] = __builtin_fma(h, kx, S.vx[p]);
+    S.vy[p] = __builtin_fma(h, ky, S.vy[p]);
+    S.vz[p] = __builtin_fma(h, kz, S.vz[p]);
+}
+
+__global__ __launch_bounds__(256) void k_batch_drift(bf_state S, const Batch b, double h) {
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= b.max_active || a >= b.aoff[b.nclusters]) return;
+    const int32_t p = b.aidx[a];
+    if (p < 0 || p >= S.n) return;
+    S.x[p] = __builtin_fma(h, S.vx[p], S.x[p]);
+    S.y[p] = __builtin_fma(h, S.vy[p], S.y[p]);
+    S.z[p] = __builtin_fma(h, S.vz[p], S.z[p]);
+}
+
+template <class Op>
+static int batch_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_batch_pairs<Op, kBK, kBW>),
+                                                     64 * kBW, 0) != hipSuccess)
+        return 1;
+    return std::max(nb, 1);
+}
+
+template <class Op>
+static hipError_t launch_batch_op(const Batch& b, int num_cu, hipStream_t st) {
+    const int nblocks = num_cu * batch_blocks_per_cu<Op>();
+    hipLaunchKernelGGL((k_batch_pairs<Op, kBK, kBW>), dim3(nblocks), dim3(64 * kBW), 0, st, b);
+    return hipGetLastError();
+}
+
+}  // namespace bf
+
+// =============================================================================================
+using namespace bf;
+
+// Implemented in capi.hip: scratch growth and error recording shared with the other entry points.
+int bf_internal_ensure(bf_ctx* ctx, int which, size_t need);
+void* bf_internal_scratch(bf_ctx* ctx, int which);
+int bf_internal_fail(int code, const char* msg);
+void bf_internal_swap_scratch(bf_ctx* ctx, void* bufs[3], size_t bytes[3]);
+
+static int batch_setup(bf_ctx* c, const bf_particles* P, int32_t nclusters, const int64_t* coff, const int32_t* aidx,
+                       const int64_t* aoff, int64_t max_active, int64_t max_cluster_n, double G, double eps2, int prec,
+                       double r_fb, int op, Batch& b) {
+    if (!c || !P) return bf_internal_fail(BF_ERR_ARG, "NULL context or particles");
+    if (P->n <= 0 || P->n > INT32_MAX || !P->x || !P->y || !P->z || !P->m)
+        return bf_internal_fail(BF_ERR_ARG, "bad particle arrays");
+    if (nclusters <= 0 || !coff || !aoff || (max_active > 0 && !aidx))
+        return bf_internal_fail(BF_ERR_ARG, "bad cluster description");
+    if (max_active < 0 || max_active > INT32_MAX || max_cluster_n <= 0 || max_cluster_n > P->n)
+        return bf_internal_fail(BF_ERR_ARG, "bad bounds");
+    if (prec != BF_PREC_FP64 && prec != BF_PREC_MIXED) return bf_internal_fail(BF_ERR_ARG, "bad prec");
+    if (!(eps2 >= 0 && eps2 < INFINITY) || !(r_fb >= 0 && r_fb < INFINITY) || !(G > -INFINITY && G < INFINITY))
+        return bf_internal_fail(BF_ERR_ARG, "bad G, eps2 or r_fb");
+    b = Batch{};
+    b.base.P.x = P->x; b.base.P.y = P->y; b.base.P.z = P->z;
+    b.base.P.vx = P->vx; b.base.P.vy = P->vy; b.base.P.vz = P->vz;
+    b.base.P.m = P->m; b.base.P.n = P->n;
+    b.base.G = G;
+    b.base.eps2 = eps2;
+    b.base.eps2f = (float)eps2 + 1e-20f;
+    b.base.rfb2f = prec == BF_PREC_MIXED ? (float)(r_fb * r_fb) : -1.0f;
+    b.base.split = 1;
+    b.nclusters = nclusters;
+    b.coff = coff; b.aidx = aidx; b.aoff = aoff;
+    b.max_active = max_active;
+    b.max_cluster_n = max_cluster_n;
+    b.max_chunks = (int32_t)((max_cluster_n + kBatchChunk - 1) / kBatchChunk);
+    b.pack_bytes = pack_bytes(op, prec);
+    const size_t pack_total = (size_t)P->n * b.pack_bytes;
+    const size_t part_bytes = (size_t)b.max_chunks * 3 * std::max<int64_t>(max_active, 1) * sizeof(double);
+    const size_t off_bytes = ((size_t)(2 * nclusters + 2) * sizeof(int32_t) + 255) & ~size_t(255);
+    if (int rc = bf_internal_ensure(c, 2, pack_total)) return rc;
+    if (int rc = bf_internal_ensure(c, 4, part_bytes + off_bytes)) return rc;
+    b.base.pack = bf_internal_scratch(c, 2);
+    char* s4 = static_cast<char*>(bf_internal_scratch(c, 4));
+    b.part = reinterpret_cast<double*>(s4);
+    b.item_off = reinterpret_cast<int32_t*>(s4 + part_bytes);
+    b.counter = b.item_off + nclusters + 1;
+    b.bad = b.counter + 1;
+    return BF_OK;
+}
+
+// enqueue one batched pass (no allocation, no synchronisation: safe under stream capture)
+static int batch_enqueue(bf_ctx* c, Batch& b, int op, int prec) {
+    hipStream_t st = c->stream;
+    // pack every particle (the clusters' source ranges are sub-ranges of this stream)
+    PairArgs pk = b.base;
+    pk.src = DevSet{nullptr, (int32_t)b.base.P.n, 0};
+    hipError_t e = launch_pack(op, prec, pk, st);
+    if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, st, b);
+    const bool mixed = prec == BF_PREC_MIXED;
+    if (op == OP_ACC) e = mixed ? launch_batch_op<AccMixed>(b, c->num_cu, st) : launch_batch_op<Acc64>(b, c->num_cu, st);
+    else e = mixed ? launch_batch_op<GradMixed>(b, c->num_cu, st) : launch_batch_op<Grad64>(b, c->num_cu, st);
+    if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
+    if (b.max_active > 0)
+        hipLaunchKernelGGL(k_batch_reduce<3>, dim3((unsigned)((b.max_active + 255) / 256)), dim3(256), 0, st, b);
+    e = hipGetLastError();
+    if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
+    return BF_OK;
+}
+
+extern "C" {
+
+BF_API int bf_forces_batched(bf_ctx* c, const bf_particles* P, int32_t nclusters, const int64_t* coff,
+                             const int32_t* aidx, const int64_t* aoff, int64_t max_active, int64_t max_cluster_n,
+                             double G, double eps2, int prec, double r_fb, double* ax, double* ay, double* az) {
+    Batch b;
+    if (int rc = batch_setup(c, P, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, OP_ACC, b))
+        return rc;
+    if (!ax || !ay || !az) return bf_internal_fail(BF_ERR_ARG, "output pointer NULL");
+    b.base.flags = c->d_flags;
+    b.o0 = ax; b.o1 = ay; b.o2 = az;
+    return batch_enqueue(c, b, OP_ACC, prec);
+}
+
+BF_API int bf_force_gradient_batched(bf_ctx* c, const bf_particles* P, int32_t nclusters, const int64_t* coff,
+                                     const int32_t* aidx, const int64_t* aoff, int64_t max_active,
+                                     int64_t max_cluster_n, const double* ax, const double* ay, const double* az,
+                                     double G, double eps2, int prec, double r_fb, double* gx, double* gy,
+                                     double* gz) {
+    Batch b;
+    if (int rc = batch_setup(c, P, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, OP_GRAD, b))
+        return rc;
+    if (!ax || !ay || !az || !gx || !gy || !gz) return bf_internal_fail(BF_ERR_ARG, "array pointer NULL");
+    b.base.P.ax = ax; b.base.P.ay = ay; b.base.P.az = az;
+    b.base.flags = c->d_flags;
+    b.o0 = gx; b.o1 = gy; b.o2 = gz;
+    return batch_enqueue(c, b, OP_GRAD, prec);
+}
+
+// A captured graph owns the scratch its kernels use, so later growth of the context's scratch
+// can never leave a replay pointing at freed memory.
+struct bf_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* owned[3] = {nullptr, nullptr, nullptr};
+};
+
+// prepare the two batch descriptors of a batched FSI cycle (sizes every scratch buffer)
+static int batched_fsi_setup(bf_ctx* c, const bf_state* S, int32_t nclusters, const int64_t* coff, const int32_t* aidx,
+                             const int64_t* aoff, int64_t max_active, int64_t max_cluster_n, double G, double eps2,
+                             int prec, double r_fb, double dt, double* ax, double* ay, double* az, Batch& ba,
+                             Batch& bg) {
+    if (!S) return bf_internal_fail(BF_ERR_ARG, "NULL state");
+    if (!S->x || !S->y || !S->z || !S->vx || !S->vy || !S->vz || !S->m) return bf_internal_fail(BF_ERR_ARG, "state NULL");
+    if (!ax || !ay || !az) return bf_internal_fail(BF_ERR_ARG, "acceleration pointer NULL");
+    if (!(dt > -INFINITY && dt < INFINITY)) return bf_internal_fail(BF_ERR_ARG, "dt not finite");
+    bf_particles P{S->x, S->y, S->z, S->vx, S->vy, S->vz, S->m, S->n};
+    // the gradient pass needs the larger pack: size it first
+    if (int rc = batch_setup(c, &P, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, OP_GRAD, bg))
+        return rc;
+    if (int rc = batch_setup(c, &P, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, OP_ACC, ba))
+        return rc;
+    if (int rc = bf_internal_ensure(c, 3, (size_t)3 * S->n * sizeof(double))) return rc;
+    double* gx = static_cast<double*>(bf_internal_scratch(c, 3));
+    ba.base.flags = bg.base.flags = c->d_flags;
+    ba.o0 = ax; ba.o1 = ay; ba.o2 = az;
+    bg.base.P.ax = ax; bg.base.P.ay = ay; bg.base.P.az = az;
+    bg.o0 = gx; bg.o1 = gx + S->n; bg.o2 = gx + 2 * S->n;
+    return BF_OK;
+}
+
+// enqueue the FSI cycle of the active particles (no allocation, no synchronisation)
+static int batched_fsi_enqueue(bf_ctx* c, const bf_state* S, Batch& ba, Batch& bg, int prec, double dt) {
+    hipStream_t st = c->stream;
+    const unsigned nb = (unsigned)std::max<int64_t>(1, (ba.max_active + 255) / 256);
+    const double *ax = ba.o0, *ay = ba.o1, *az = ba.o2;
+    const double *gx = bg.o0, *gy = bg.o1, *gz = bg.o2;
+    const double* nul = nullptr;
+    hipLaunchKernelGGL(k_batch_kick, dim3(nb), dim3(256), 0, st, *S, ba, dt / 6.0, ax, ay, az, 0.0, nul, nul, nul);
+    hipLaunchKernelGGL(k_batch_drift, dim3(nb), dim3(256), 0, st, *S, ba, 0.5 * dt);
+    if (int rc = batch_enqueue(c, ba, OP_ACC, prec)) return rc;
+    if (int rc = batch_enqueue(c, bg, OP_GRAD, prec)) return rc;
+    hipLaunchKernelGGL(k_batch_kick, dim3(nb), dim3(256), 0, st, *S, ba, 2.0 * dt / 3.0, ax, ay, az, dt * dt / 24.0, gx,
+                       gy, gz);
+    hipLaunchKernelGGL(k_batch_drift, dim3(nb), dim3(256), 0, st, *S, ba, 0.5 * dt);
+    if (int rc = batch_enqueue(c, ba, OP_ACC, prec)) return rc;
+    hipLaunchKernelGGL(k_batch_kick, dim3(nb), dim3(256), 0, st, *S, ba, dt / 6.0, ax, ay, az, 0.0, nul, nul, nul);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
+    return BF_OK;
+}
+
+BF_API int bf_fsi_step_batched(bf_ctx* c, const bf_state* S, int32_t nclusters, const int64_t* coff,
+                               const int32_t* aidx, const int64_t* aoff, int64_t max_active, int64_t max_cluster_n,
+                               double G, double eps2, int prec, double r_fb, double dt, double* ax, double* ay,
+                               double* az) {
+    if (!c) return bf_internal_fail(BF_ERR_ARG, "NULL context");
+    Batch ba, bg;
+    if (int rc = batched_fsi_setup(c, S, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, dt,
+                                   ax, ay, az, ba, bg))
+        return rc;
+    return batched_fsi_enqueue(c, S, ba, bg, prec, dt);
+}
+
+BF_API int bf_graph_capture_batched_fsi(bf_ctx* c, const bf_state* S, int32_t nclusters, const int64_t* coff,
+                                        const int32_t* aidx, const int64_t* aoff, int64_t max_active,
+                                        int64_t max_cluster_n, double G, double eps2, int prec, double r_fb, double dt,
+                                        double* ax, double* ay, double* az, void** graph_exec) {
+    if (!c || !graph_exec) return bf_internal_fail(BF_ERR_ARG, "NULL context or graph pointer");
+    *graph_exec = nullptr;
+    // the graph gets fresh scratch buffers: park the context's own while they are allocated
+    void* saved[3] = {nullptr, nullptr, nullptr};
+    size_t saved_bytes[3] = {0, 0, 0};
+    bf_internal_swap_scratch(c, saved, saved_bytes);
+    Batch ba, bg;
+    if (int rc = batched_fsi_setup(c, S, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, dt,
+                                   ax, ay, az, ba, bg)) {
+        bf_internal_swap_scratch(c, saved, saved_bytes);  // context buffers back, graph ones out
+        for (void* p : saved) if (p) hipFree(p);
+        return rc;
+    }
+    void* mine[3];
+    size_t mine_bytes[3];
+    for (int i = 0; i < 3; ++i) { mine[i] = saved[i]; mine_bytes[i] = saved_bytes[i]; }
+    bf_internal_swap_scratch(c, mine, mine_bytes);  // context has its buffers again; mine = graph's
+    auto free_mine = [&]() { for (void* p : mine) if (p) hipFree(p); };
+    hipStream_t user = c->stream;
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        free_mine();
+        return bf_internal_fail(BF_ERR_HIP, "capture stream creation failed");
+    }
+    if (hipStreamSynchronize(user) != hipSuccess) {
+        hipStreamDestroy(cap);
+        free_mine();
+        return bf_internal_fail(BF_ERR_HIP, "stream synchronisation failed");
+    }
+    int rc = BF_OK;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        hipStreamDestroy(cap);
+        free_mine();
+        return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
+    }
+    c->stream = cap;
+    rc = batched_fsi_enqueue(c, S, ba, bg, prec, dt);
+    c->stream = user;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap, &g);
+    hipStreamDestroy(cap);
+    if (!rc && e != hipSuccess) rc = bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        free_mine();
+        return rc;
+    }
+    bf_graph* h = new bf_graph();
+    h->graph = g;
+    for (int i = 0; i < 3; ++i) h->owned[i] = mine[i];
+    if (hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        free_mine();
+        delete h;
+        return bf_internal_fail(BF_ERR_HIP, "graph instantiation failed");
+    }
+    *graph_exec = h;
+    return BF_OK;
+}
+
+BF_API int bf_graph_launch(bf_ctx* c, void* graph_exec) {
+    if (!c || !graph_exec) return bf_internal_fail(BF_ERR_ARG, "NULL context or graph");
+    bf_graph* h = static_cast<bf_graph*>(graph_exec);
+    hipError_t e = hipGraphLaunch(h->exec, c->stream);
+    if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
+    return BF_OK;
+}
+
+BF_API int bf_graph_destroy(void* graph_exec) {
+    if (!graph_exec) return BF_OK;
+    bf_graph* h = static_cast<bf_graph*>(graph_exec);
+    if (h->exec) hipGraphExecDestroy(h->exec);
+    if (h->graph) hipGraphDestroy(h->graph);
+    hipDeviceSynchronize();  // a replay may still be running on some stream
+    for (void* p : h->owned)
+        if (p) hipFree(p);
+    delete h;
+    return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal declarations of libbifrost_hip: context, kernel argument blocks, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "bifrost.h"
+
+namespace bf {
+
+// ---- argument blocks (passed by value to kernels) ----------------------------------------
+
+// A set as the kernels see it: slot k -> particle idx ? idx[k] : begin + k.
+struct DevSet {
+    const int32_t* idx;
+    int32_t count;
+    int32_t begin;
+};
+
+// FP64 master arrays.
+struct Masters {
+    const double *x, *y, *z, *vx, *vy, *vz, *m;
+    const double *ax, *ay, *az;  // gradient input (particle-indexed), else null
+    int64_t n;
+};
+
+// Everything a pair kernel needs.
+struct PairArgs {
+    Masters P;
+    DevSet tgt;       // targets
+    DevSet src;       // sources
+    const void* pack; // packed source stream (op/precision dependent layout), length src.count
+    double G;
+    double eps2;      // softening (FP64 path)
+    float eps2f;      // eps2 + tiny (FP32 path; tiny keeps the self pair finite)
+    float rfb2f;      // close-pair threshold on s^2 for the FP64 re-evaluation
+    int32_t split;    // number of source chunks
+    int32_t chunk;    // sources per chunk (multiple of the tile size)
+    double* part;     // [split][ncomp][tgt.count] partial results when split > 1
+    double *o0, *o1, *o2;  // particle-indexed outputs when split == 1
+    double eta0, eta1;     // dt_min: eta_ff, eta_fb
+    uint32_t* flags;
+};
+
+enum Op { OP_ACC = 0, OP_GRAD = 1, OP_DT = 2, OP_COUNT = 3 };
+
+struct KernelConfig {
+    int k = 0;      // targets per lane
+    int waves = 0;  // waves per workgroup
+    int split = 0;  // source chunks (0 = automatic)
+};
+
+// Launch one pair kernel (returns the hip error of the launch).
+hipError_t launch_pairs(int op, int prec, const KernelConfig& cfg, const PairArgs& a, int nblocks,
+                        hipStream_t st);
+// Is (k, waves) an instantiated variant?
+bool variant_exists(int op, int prec, int k, int waves);
+// Resident workgroups per CU for a variant (occupancy API), 0 if unknown.
+int variant_blocks_per_cu(int op, int prec, int k, int waves);
+// Bytes per packed source for op/prec.
+int pack_bytes(int op, int prec);
+
+hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st);
+hipError_t launch_reduce(int op, const PairArgs& a, hipStream_t st);
+
+// PN1.0
+struct PnArgs {
+    Masters P;
+    DevSet tgt, src;
+    const int32_t* bh;
+    int32_t nbh;
+    double G, c2inv;
+    double* part;        // [nbh][nchunk][3] partial sums of BH targets over all sources
+    int32_t nchunk, chunk;
+    int32_t* bh_in_src;  // [nbh] 1 if bh[k] is a source
+    double *o0, *o1, *o2;
+    uint32_t* flags;
+};
+hipError_t launch_pn1(const PnArgs& a, hipStream_t st);
+
+// energy
+struct EnergyArgs {
+    Masters P;
+    DevSet set;
+    double G, eps2;
+    double* rows;   // [count] per-row potential sums (pairs with b > a)
+    double* kin;    // [count] per-particle kinetic terms
+    double* out;    // [2] final kinetic, potential
+};
+hipError_t launch_energy(const EnergyArgs& a, hipStream_t st);
+
+// elementwise updates
+hipError_t launch_kick(const bf_state& S, const DevSet& set, double h, const double* ax, const double* ay,
+                       const double* az, double h2, const double* gx, const double* gy, const double* gz,
+                       uint32_t* flags, hipStream_t st);
+hipError_t launch_drift(const bf_state& S, const DevSet& set, double h, uint32_t* flags, hipStream_t st);
+hipError_t launch_validate(const DevSet& set, int64_t n, uint32_t* flags, hipStream_t st);
+
+}  // namespace bf
+
+// ---- the context -------------------------------------------------------------------------
+
+struct bf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 0;
+    uint32_t* d_flags = nullptr;      // device flag word
+    uint32_t* h_flags = nullptr;      // pinned host mirror
+    void* scratch = nullptr;          // general scratch (partials, packs)
+    size_t scratch_bytes = 0;
+    void* scratch2 = nullptr;         // second scratch (packed sources)
+    size_t scratch2_bytes = 0;
+    void* scratch3 = nullptr;         // third scratch (intermediate gradient / a arrays)
+    size_t scratch3_bytes = 0;
+    void* scratch4 = nullptr;         // batched partials, work-item offsets, queue counter
+    size_t scratch4_bytes = 0;
+    // kernel timing: event pairs around pair-kernel launches, per op
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[bf::OP_COUNT];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tpool;
+    // (op, prec) -> forced configuration
+    bf::KernelConfig forced[bf::OP_COUNT][2];
+    // (op, prec, log2 bucket nt, log2 bucket ns) -> tuned configuration
+    std::map<std::tuple<int, int, int, int>, bf::KernelConfig> tuned;
+};

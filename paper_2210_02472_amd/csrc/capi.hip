@@ -1,0 +1,718 @@
+// C ABI of libbifrost_hip: argument checks, context and scratch management, launch planning,
+// the FSI cycle driver and the autotuner.  Every numerical step runs in the kernels of
+// pairs.hip, pn1.hip, energy_update.hip and batch.hip.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "bf_internal.h"
+
+using namespace bf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define BF_HIP(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(BF_ERR_HIP, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_nonneg(double v) { return isfinite(v) && v >= 0.0; }
+
+int check_set(const bf_set* s, int64_t n, const char* what) {
+    if (!s) return fail(BF_ERR_ARG, std::string(what) + " set is NULL");
+    if (s->count < 0) return fail(BF_ERR_ARG, std::string(what) + " count < 0");
+    if (s->idx == nullptr) {
+        if (s->begin < 0 || (int64_t)s->begin + s->count > n)
+            return fail(BF_ERR_ARG, std::string(what) + " range outside [0, n)");
+    }
+    return BF_OK;
+}
+
+int check_particles(const bf_particles* P, bool need_v) {
+    if (!P) return fail(BF_ERR_ARG, "particles NULL");
+    if (P->n <= 0 || P->n > INT32_MAX) return fail(BF_ERR_ARG, "n must be in [1, 2^31)");
+    if (!P->x || !P->y || !P->z || !P->m) return fail(BF_ERR_ARG, "position/mass pointer NULL");
+    if (need_v && (!P->vx || !P->vy || !P->vz)) return fail(BF_ERR_ARG, "velocity pointer NULL");
+    return BF_OK;
+}
+
+Masters masters_of(const bf_particles* P) {
+    Masters M{};
+    M.x = P->x; M.y = P->y; M.z = P->z;
+    M.vx = P->vx; M.vy = P->vy; M.vz = P->vz;
+    M.m = P->m;
+    M.n = P->n;
+    return M;
+}
+
+DevSet devset(const bf_set* s) { return DevSet{s->idx, s->count, s->begin}; }
+
+int ensure(void** buf, size_t* have, size_t need, hipStream_t st) {
+    if (need <= *have) return BF_OK;
+    size_t want = std::max(need, *have + *have / 2);
+    want = (want + 4095) & ~size_t(4095);
+    if (*buf) {
+        BF_HIP(hipStreamSynchronize(st));
+        BF_HIP(hipFree(*buf));
+        *buf = nullptr;
+        *have = 0;
+    }
+    if (hipMalloc(buf, want) != hipSuccess) {
+        *buf = nullptr;
+        return fail(BF_ERR_NOMEM, "scratch allocation of " + std::to_string(want) + " bytes failed");
+    }
+    *have = want;
+    return BF_OK;
+}
+
+int ilog2_bucket(int64_t v) {
+    int b = 0;
+    while (v > 1) { v >>= 1; ++b; }
+    return b;
+}
+
+int ncomp(int op) { return op == OP_DT ? 2 : 3; }
+
+// Default kernel shape: K targets per lane and W waves per workgroup.
+KernelConfig default_config(int op, int prec, int64_t nt) {
+    KernelConfig c;
+    c.waves = 4;
+    if (nt >= 64 * 2 * 4 * 512) c.k = 2;
+    else c.k = 1;
+    if (prec == BF_PREC_FP64 && op != OP_ACC) c.k = 1;
+    return c;
+}
+
+struct Plan {
+    KernelConfig cfg;
+    int split = 1, chunk = 0, nblocks = 0;
+};
+
+int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p) {
+    KernelConfig c = ctx->forced[op][prec];
+    if (c.k == 0) {
+        auto it = ctx->tuned.find(std::make_tuple(op, prec, ilog2_bucket(nt), ilog2_bucket(ns)));
+        if (it != ctx->tuned.end()) c = it->second;
+        else c = default_config(op, prec, nt);
+    }
+    if (!variant_exists(op, prec, c.k, c.waves))
+        return fail(BF_ERR_UNSUPPORTED, "no kernel variant for k=" + std::to_string(c.k) + " waves=" + std::to_string(c.waves));
+    const int T = 64 * c.waves;
+    const int64_t slab = (int64_t)64 * c.k * c.waves;
+    const int64_t nslabs = std::max<int64_t>(1, (nt + slab - 1) / slab);
+    const int64_t ntiles = std::max<int64_t>(1, (ns + T - 1) / T);
+    int64_t split = c.split;
+    if (split <= 0) {
+        int bpc = variant_blocks_per_cu(op, prec, c.k, c.waves);
+        if (bpc <= 0) bpc = 1;
+        const int64_t resident = (int64_t)ctx->num_cu * bpc;
+        // aim for at least four full rounds of resident workgroups
+        const int64_t want = 4 * resident;
+        split = nslabs >= want ? 1 : (want + nslabs - 1) / nslabs;
+        if (split > 8) split = (split + 7) / 8 * 8;  // keep chunks aligned with the 8 XCDs
+    }
+    split = std::min<int64_t>(split, ntiles);
+    split = std::max<int64_t>(split, 1);
+    // sources per chunk: whole tiles
+    const int64_t tiles_per_chunk = (ntiles + split - 1) / split;
+    split = (ntiles + tiles_per_chunk - 1) / tiles_per_chunk;
+    p.cfg = c;
+    p.split = (int)split;
+    p.chunk = (int)(tiles_per_chunk * T);
+    if (nslabs * split > INT32_MAX) return fail(BF_ERR_UNSUPPORTED, "grid too large");
+    p.nblocks = (int)(nslabs * split);
+    return BF_OK;
+}
+
+// Run one pair pass (acc, grad or dt) end to end on the context stream.
+int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg, const bf_set* sr, double G, double eps2,
+              double r_fb, double eta0, double eta1, double* o0, double* o1, double* o2) {
+    if (tg->count == 0) return BF_OK;
+    Plan p;
+    int rc = plan(ctx, op, prec, tg->count, sr->count, p);
+    if (rc) return rc;
+    PairArgs a{};
+    a.P = M;
+    a.tgt = devset(tg);
+    a.src = devset(sr);
+    a.G = G;
+    a.eps2 = eps2;
+    a.eps2f = (float)eps2 + 1e-20f;
+    float rfb2 = (float)(r_fb * r_fb);
+    if (op == OP_DT) rfb2 = std::max(rfb2, 1e-30f);  // the self pair of the FP32 time-step pass
+    a.rfb2f = prec == BF_PREC_MIXED ? rfb2 : -1.0f;
+    a.split = p.split;
+    a.chunk = p.chunk;
+    a.eta0 = eta0;
+    a.eta1 = eta1;
+    a.o0 = o0; a.o1 = o1; a.o2 = o2;
+    a.flags = ctx->d_flags;
+    if (sr->count > 0) {
+        rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)sr->count * pack_bytes(op, prec), ctx->stream);
+        if (rc) return rc;
+        a.pack = ctx->scratch2;
+        BF_HIP(launch_pack(op, prec, a, ctx->stream));
+    }
+    if (p.split > 1) {
+        rc = ensure(&ctx->scratch, &ctx->scratch_bytes, (size_t)p.split * ncomp(op) * tg->count * sizeof(double),
+                    ctx->stream);
+        if (rc) return rc;
+        a.part = static_cast<double*>(ctx->scratch);
+    }
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (ctx->timing) {
+        if (!ctx->tpool.empty()) {
+            ev = ctx->tpool.back();
+            ctx->tpool.pop_back();
+        } else {
+            BF_HIP(hipEventCreate(&ev.first));
+            BF_HIP(hipEventCreate(&ev.second));
+        }
+        BF_HIP(hipEventRecord(ev.first, ctx->stream));
+    }
+    BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
+    if (ctx->timing) {
+        BF_HIP(hipEventRecord(ev.second, ctx->stream));
+        ctx->tev[op].push_back(ev);
+    }
+    if (p.split > 1) BF_HIP(launch_reduce(op, a, ctx->stream));
+    return BF_OK;
+}
+
+int check_ctx(bf_ctx* ctx) {
+    if (!ctx) return fail(BF_ERR_ARG, "context NULL");
+    return BF_OK;
+}
+
+int check_prec(int prec) {
+    if (prec != BF_PREC_FP64 && prec != BF_PREC_MIXED) return fail(BF_ERR_ARG, "prec must be BF_PREC_FP64 or BF_PREC_MIXED");
+    return BF_OK;
+}
+
+}  // namespace
+
+// shared with batch.hip
+int bf_internal_fail(int code, const char* msg) { return fail(code, msg); }
+
+int bf_internal_ensure(bf_ctx* c, int which, size_t need) {
+    switch (which) {
+        case 1: return ensure(&c->scratch, &c->scratch_bytes, need, c->stream);
+        case 2: return ensure(&c->scratch2, &c->scratch2_bytes, need, c->stream);
+        case 3: return ensure(&c->scratch3, &c->scratch3_bytes, need, c->stream);
+        case 4: return ensure(&c->scratch4, &c->scratch4_bytes, need, c->stream);
+    }
+    return fail(BF_ERR_ARG, "bad scratch id");
+}
+
+// exchange scratch buffers 2, 3 and 4 of the context with bufs (used to give graphs their own)
+void bf_internal_swap_scratch(bf_ctx* c, void* bufs[3], size_t bytes[3]) {
+    std::swap(c->scratch2, bufs[0]); std::swap(c->scratch2_bytes, bytes[0]);
+    std::swap(c->scratch3, bufs[1]); std::swap(c->scratch3_bytes, bytes[1]);
+    std::swap(c->scratch4, bufs[2]); std::swap(c->scratch4_bytes, bytes[2]);
+}
+
+void* bf_internal_scratch(bf_ctx* c, int which) {
+    switch (which) {
+        case 1: return c->scratch;
+        case 2: return c->scratch2;
+        case 3: return c->scratch3;
+        case 4: return c->scratch4;
+    }
+    return nullptr;
+}
+
+// =============================================================================================
+extern "C" {
+
+BF_API const char* bf_version(void) { return "bifrost-hip 0.1 (gfx950)"; }
+
+BF_API const char* bf_status_string(int s) {
+    switch (s) {
+        case BF_OK: return "ok";
+        case BF_ERR_ARG: return "invalid argument";
+        case BF_ERR_HIP: return "HIP runtime error";
+        case BF_ERR_NONFINITE: return "non-finite result";
+        case BF_ERR_UNSUPPORTED: return "unsupported request";
+        case BF_ERR_NOMEM: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+BF_API const char* bf_last_error(void) { return g_err.c_str(); }
+
+BF_API int bf_create(bf_ctx** out, int device, void* stream) {
+    g_err.clear();
+    if (!out) return fail(BF_ERR_ARG, "ctx pointer NULL");
+    *out = nullptr;
+    int ndev = 0;
+    BF_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(BF_ERR_ARG, "device out of range");
+    BF_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    BF_HIP(hipGetDeviceProperties(&prop, device));
+    bf_ctx* c = new bf_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->num_cu = prop.multiProcessorCount;
+    if (hipMalloc(&c->d_flags, sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc(&c->h_flags, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(BF_ERR_NOMEM, "flag allocation failed");
+    }
+    if (hipMemsetAsync(c->d_flags, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        hipFree(c->d_flags);
+        hipHostFree(c->h_flags);
+        delete c;
+        return fail(BF_ERR_HIP, "flag initialisation failed");
+    }
+    *out = c;
+    return BF_OK;
+}
+
+static void drop_timing(bf_ctx* c) {
+    for (auto& v : c->tev) {
+        for (auto& e : v) c->tpool.push_back(e);
+        v.clear();
+    }
+}
+
+BF_API int bf_destroy(bf_ctx* c) {
+    if (!c) return BF_OK;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    drop_timing(c);
+    for (auto& e : c->tpool) {
+        hipEventDestroy(e.first);
+        hipEventDestroy(e.second);
+    }
+    if (c->scratch) hipFree(c->scratch);
+    if (c->scratch2) hipFree(c->scratch2);
+    if (c->scratch3) hipFree(c->scratch3);
+    if (c->scratch4) hipFree(c->scratch4);
+    if (c->d_flags) hipFree(c->d_flags);
+    if (c->h_flags) hipHostFree(c->h_flags);
+    delete c;
+    return BF_OK;
+}
+
+BF_API int bf_enable_timing(bf_ctx* c, int on) {
+    if (int rc = check_ctx(c)) return rc;
+    BF_HIP(hipStreamSynchronize(c->stream));
+    drop_timing(c);
+    c->timing = on != 0;
+    return BF_OK;
+}
+
+BF_API int bf_kernel_times(bf_ctx* c, int op, float* ms, int cap, int* count) {
+    if (int rc = check_ctx(c)) return rc;
+    if (op < 0 || op >= OP_COUNT) return fail(BF_ERR_ARG, "bad op");
+    if (!count || (cap > 0 && !ms) || cap < 0) return fail(BF_ERR_ARG, "bad output buffer");
+    BF_HIP(hipStreamSynchronize(c->stream));
+    auto& v = c->tev[op];
+    *count = (int)v.size();
+    for (int i = 0; i < (int)v.size() && i < cap; ++i) BF_HIP(hipEventElapsedTime(&ms[i], v[i].first, v[i].second));
+    for (auto& e : v) c->tpool.push_back(e);
+    v.clear();
+    return BF_OK;
+}
+
+BF_API int bf_set_stream(bf_ctx* c, void* stream) {
+    if (int rc = check_ctx(c)) return rc;
+    c->stream = static_cast<hipStream_t>(stream);
+    return BF_OK;
+}
+
+BF_API int bf_read_flags(bf_ctx* c, uint32_t* flags, int clear) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!flags) return fail(BF_ERR_ARG, "flags NULL");
+    BF_HIP(hipMemcpyAsync(c->h_flags, c->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    BF_HIP(hipStreamSynchronize(c->stream));
+    *flags = *c->h_flags;
+    if (clear) {
+        BF_HIP(hipMemsetAsync(c->d_flags, 0, sizeof(uint32_t), c->stream));
+        BF_HIP(hipStreamSynchronize(c->stream));
+    }
+    return BF_OK;
+}
+
+BF_API int bf_validate_set(bf_ctx* c, const bf_set* s, int64_t n) {
+    if (int rc = check_ctx(c)) return rc;
+    if (n <= 0) return fail(BF_ERR_ARG, "n <= 0");
+    if (int rc = check_set(s, n, "validated")) return rc;
+    if (s->idx == nullptr || s->count == 0) return BF_OK;
+    uint32_t before = 0;
+    if (int rc = bf_read_flags(c, &before, 0)) return rc;
+    BF_HIP(hipMemsetAsync(c->d_flags, 0, sizeof(uint32_t), c->stream));
+    BF_HIP(launch_validate(devset(s), n, c->d_flags, c->stream));
+    uint32_t f = 0;
+    if (int rc = bf_read_flags(c, &f, 0)) return rc;
+    // restore the earlier flags (plus nothing else: the validation itself is not an error source)
+    *c->h_flags = before;
+    BF_HIP(hipMemcpyAsync(c->d_flags, c->h_flags, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+    BF_HIP(hipStreamSynchronize(c->stream));
+    if (f & BF_FLAG_BADINDEX) return fail(BF_ERR_ARG, "index list has entries outside [0, n)");
+    return BF_OK;
+}
+
+BF_API int bf_forces(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf_set* s, double G, double eps2,
+                     int prec, double r_fb, double* ax, double* ay, double* az) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, false)) return rc;
+    if (int rc = check_set(t, P->n, "target")) return rc;
+    if (int rc = check_set(s, P->n, "source")) return rc;
+    if (int rc = check_prec(prec)) return rc;
+    if (!isfinite(G)) return fail(BF_ERR_ARG, "G not finite");
+    if (!finite_nonneg(eps2)) return fail(BF_ERR_ARG, "eps2 must be finite and >= 0");
+    if (!finite_nonneg(r_fb)) return fail(BF_ERR_ARG, "r_fb must be finite and >= 0");
+    if (!ax || !ay || !az) return fail(BF_ERR_ARG, "output pointer NULL");
+    return run_pairs(c, OP_ACC, prec, masters_of(P), t, s, G, eps2, r_fb, 0, 0, ax, ay, az);
+}
+
+BF_API int bf_force_gradient(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf_set* s, const double* ax,
+                             const double* ay, const double* az, double G, double eps2, int prec, double r_fb,
+                             double* gx, double* gy, double* gz) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, false)) return rc;
+    if (int rc = check_set(t, P->n, "target")) return rc;
+    if (int rc = check_set(s, P->n, "source")) return rc;
+    if (int rc = check_prec(prec)) return rc;
+    if (!isfinite(G)) return fail(BF_ERR_ARG, "G not finite");
+    if (!finite_nonneg(eps2)) return fail(BF_ERR_ARG, "eps2 must be finite and >= 0");
+    if (!finite_nonneg(r_fb)) return fail(BF_ERR_ARG, "r_fb must be finite and >= 0");
+    if (!ax || !ay || !az) return fail(BF_ERR_ARG, "acceleration pointer NULL");
+    if (!gx || !gy || !gz) return fail(BF_ERR_ARG, "output pointer NULL");
+    Masters M = masters_of(P);
+    M.ax = ax; M.ay = ay; M.az = az;
+    return run_pairs(c, OP_GRAD, prec, M, t, s, G, eps2, r_fb, 0, 0, gx, gy, gz);
+}
+
+BF_API int bf_dt_min(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf_set* s, double G, double eta_ff,
+                     double eta_fb, int prec, double r_fb, double* dt_ff, double* dt_fb) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, true)) return rc;
+    if (int rc = check_set(t, P->n, "target")) return rc;
+    if (int rc = check_set(s, P->n, "source")) return rc;
+    if (int rc = check_prec(prec)) return rc;
+    if (!(isfinite(G) && G > 0)) return fail(BF_ERR_ARG, "G must be finite and > 0");
+    if (!finite_nonneg(eta_ff) || !finite_nonneg(eta_fb)) return fail(BF_ERR_ARG, "eta must be finite and >= 0");
+    if (!finite_nonneg(r_fb)) return fail(BF_ERR_ARG, "r_fb must be finite and >= 0");
+    if (!dt_ff || !dt_fb) return fail(BF_ERR_ARG, "output pointer NULL");
+    return run_pairs(c, OP_DT, prec, masters_of(P), t, s, G, 0.0, r_fb, eta_ff, eta_fb, dt_ff, dt_fb, nullptr);
+}
+
+static int pn1_impl(bf_ctx* c, const Masters& M, const bf_set* t, const bf_set* s, const int32_t* bh, int32_t nbh,
+                    double G, double cl, double* o0, double* o1, double* o2) {
+    if (t->count == 0) return BF_OK;
+    PnArgs a{};
+    a.P = M;
+    a.tgt = devset(t);
+    a.src = devset(s);
+    a.bh = bh;
+    a.nbh = nbh;
+    a.G = G;
+    a.c2inv = 1.0 / (cl * cl);
+    a.chunk = 4096;
+    a.nchunk = std::max(1, (s->count + a.chunk - 1) / a.chunk);
+    a.o0 = o0; a.o1 = o1; a.o2 = o2;
+    a.flags = c->d_flags;
+    if (nbh > 0) {
+        const size_t part_bytes = (size_t)nbh * a.nchunk * 3 * sizeof(double);
+        const size_t need = part_bytes + (size_t)nbh * sizeof(int32_t) + 256;
+        if (int rc = ensure(&c->scratch, &c->scratch_bytes, need, c->stream)) return rc;
+        a.part = static_cast<double*>(c->scratch);
+        a.bh_in_src = reinterpret_cast<int32_t*>(static_cast<char*>(c->scratch) + ((part_bytes + 255) & ~size_t(255)));
+    }
+    BF_HIP(launch_pn1(a, c->stream));
+    return BF_OK;
+}
+
+BF_API int bf_pn1_bh(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf_set* s, const int32_t* bh_idx,
+                     int32_t n_bh, double G, double cl, double* apx, double* apy, double* apz) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, true)) return rc;
+    if (int rc = check_set(t, P->n, "target")) return rc;
+    if (int rc = check_set(s, P->n, "source")) return rc;
+    if (n_bh < 0 || (n_bh > 0 && !bh_idx)) return fail(BF_ERR_ARG, "bad black-hole list");
+    if (!(isfinite(cl) && cl > 0)) return fail(BF_ERR_ARG, "c must be finite and > 0");
+    if (!isfinite(G)) return fail(BF_ERR_ARG, "G not finite");
+    if (!apx || !apy || !apz) return fail(BF_ERR_ARG, "output pointer NULL");
+    return pn1_impl(c, masters_of(P), t, s, bh_idx, n_bh, G, cl, apx, apy, apz);
+}
+
+BF_API int bf_energy(bf_ctx* c, const bf_particles* P, const bf_set* s, double G, double eps2, double* kinetic,
+                     double* potential) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, true)) return rc;
+    if (int rc = check_set(s, P->n, "energy")) return rc;
+    if (!finite_nonneg(eps2)) return fail(BF_ERR_ARG, "eps2 must be finite and >= 0");
+    if (!kinetic || !potential) return fail(BF_ERR_ARG, "output pointer NULL");
+    if (s->count == 0) { *kinetic = 0; *potential = 0; return BF_OK; }
+    if (s->idx) {
+        if (int rc = bf_validate_set(c, s, P->n)) return rc;
+    }
+    EnergyArgs e{};
+    e.P = masters_of(P);
+    e.set = devset(s);
+    e.G = G;
+    e.eps2 = eps2;
+    const size_t need = (size_t)2 * s->count * sizeof(double) + 2 * sizeof(double);
+    if (int rc = ensure(&c->scratch, &c->scratch_bytes, need, c->stream)) return rc;
+    e.rows = static_cast<double*>(c->scratch);
+    e.kin = e.rows + s->count;
+    e.out = e.kin + s->count;
+    BF_HIP(launch_energy(e, c->stream));
+    double h[2];
+    BF_HIP(hipMemcpyAsync(h, e.out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    BF_HIP(hipStreamSynchronize(c->stream));
+    *kinetic = h[0];
+    *potential = h[1];
+    return BF_OK;
+}
+
+static int check_state(const bf_state* S) {
+    if (!S) return fail(BF_ERR_ARG, "state NULL");
+    if (S->n <= 0 || S->n > INT32_MAX) return fail(BF_ERR_ARG, "n must be in [1, 2^31)");
+    if (!S->x || !S->y || !S->z || !S->vx || !S->vy || !S->vz || !S->m) return fail(BF_ERR_ARG, "state pointer NULL");
+    return BF_OK;
+}
+
+BF_API int bf_kick(bf_ctx* c, const bf_state* S, const bf_set* set, double h, const double* ax, const double* ay,
+                   const double* az, double h2, const double* gx, const double* gy, const double* gz) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_state(S)) return rc;
+    if (int rc = check_set(set, S->n, "kick")) return rc;
+    if (!ax || !ay || !az) return fail(BF_ERR_ARG, "acceleration pointer NULL");
+    if ((gx || gy || gz) && !(gx && gy && gz)) return fail(BF_ERR_ARG, "gradient pointers must be all NULL or all set");
+    if (!isfinite(h) || !isfinite(h2)) return fail(BF_ERR_ARG, "h not finite");
+    BF_HIP(launch_kick(*S, devset(set), h, ax, ay, az, h2, gx, gy, gz, c->d_flags, c->stream));
+    return BF_OK;
+}
+
+BF_API int bf_drift(bf_ctx* c, const bf_state* S, const bf_set* set, double h) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_state(S)) return rc;
+    if (int rc = check_set(set, S->n, "drift")) return rc;
+    if (!isfinite(h)) return fail(BF_ERR_ARG, "h not finite");
+    BF_HIP(launch_drift(*S, devset(set), h, c->d_flags, c->stream));
+    return BF_OK;
+}
+
+BF_API int bf_fsi_step(bf_ctx* c, const bf_state* S, const bf_set* set, double dt, const bf_fsi_params* prm, double* ax,
+                       double* ay, double* az, int flags) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_state(S)) return rc;
+    if (int rc = check_set(set, S->n, "fsi")) return rc;
+    if (!prm) return fail(BF_ERR_ARG, "params NULL");
+    if (int rc = check_prec(prm->prec)) return rc;
+    if (!isfinite(dt)) return fail(BF_ERR_ARG, "dt not finite");
+    if (!isfinite(prm->G) || !finite_nonneg(prm->eps2) || !finite_nonneg(prm->r_fb))
+        return fail(BF_ERR_ARG, "bad G, eps2 or r_fb");
+    if (prm->n_bh < 0 || (prm->n_bh > 0 && (!prm->bh_idx || !(isfinite(prm->c) && prm->c > 0))))
+        return fail(BF_ERR_ARG, "bad PN parameters");
+    if (!ax || !ay || !az) return fail(BF_ERR_ARG, "acceleration pointer NULL");
+    if (set->count == 0) return BF_OK;
+
+    const int64_t n = S->n;
+    if (int rc = ensure(&c->scratch3, &c->scratch3_bytes, (size_t)3 * n * sizeof(double), c->stream)) return rc;
+    double* gx = static_cast<double*>(c->scratch3);
+    double* gy = gx + n;
+    double* gz = gy + n;
+    bf_particles P{S->x, S->y, S->z, S->vx, S->vy, S->vz, S->m, n};
+    const Masters M = masters_of(&P);
+    const DevSet ds = devset(set);
+    const double G = prm->G, e2 = prm->eps2, rfb = prm->r_fb;
+    const int prec = prm->prec;
+    int rc;
+
+    auto pn_half_kick = [&]() -> int {
+        if (prm->n_bh == 0) return BF_OK;
+        if (int r = pn1_impl(c, M, set, set, prm->bh_idx, prm->n_bh, G, prm->c, gx, gy, gz)) return r;
+        BF_HIP(launch_kick(*S, ds, 0.5 * dt, gx, gy, gz, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
+        return BF_OK;
+    };
+    auto acc = [&]() { return run_pairs(c, OP_ACC, prec, M, set, set, G, e2, rfb, 0, 0, ax, ay, az); };
+
+    if ((rc = pn_half_kick())) return rc;
+    if (!(flags & BF_A_VALID))
+        if ((rc = acc())) return rc;
+    BF_HIP(launch_kick(*S, ds, dt / 6.0, ax, ay, az, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
+    BF_HIP(launch_drift(*S, ds, 0.5 * dt, c->d_flags, c->stream));
+    if ((rc = acc())) return rc;
+    Masters Mg = M;
+    Mg.ax = ax; Mg.ay = ay; Mg.az = az;
+    if ((rc = run_pairs(c, OP_GRAD, prec, Mg, set, set, G, e2, rfb, 0, 0, gx, gy, gz))) return rc;
+    BF_HIP(launch_kick(*S, ds, 2.0 * dt / 3.0, ax, ay, az, dt * dt / 24.0, gx, gy, gz, c->d_flags, c->stream));
+    BF_HIP(launch_drift(*S, ds, 0.5 * dt, c->d_flags, c->stream));
+    if ((rc = acc())) return rc;
+    BF_HIP(launch_kick(*S, ds, dt / 6.0, ax, ay, az, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
+    if ((rc = pn_half_kick())) return rc;
+    return BF_OK;
+}
+
+// ---- configuration, tuning -------------------------------------------------------------------
+
+BF_API int bf_query_config(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, int* k, int* waves, int* split) {
+    if (int rc = check_ctx(c)) return rc;
+    if (op < 0 || op >= OP_COUNT) return fail(BF_ERR_ARG, "bad op");
+    if (int rc = check_prec(prec)) return rc;
+    if (nt <= 0 || ns <= 0) return fail(BF_ERR_ARG, "sizes must be > 0");
+    Plan p;
+    if (int rc = plan(c, op, prec, nt, ns, p)) return rc;
+    if (k) *k = p.cfg.k;
+    if (waves) *waves = p.cfg.waves;
+    if (split) *split = p.split;
+    return BF_OK;
+}
+
+BF_API int bf_set_config(bf_ctx* c, int op, int prec, int k, int waves, int split) {
+    if (int rc = check_ctx(c)) return rc;
+    if (op < 0 || op >= OP_COUNT) return fail(BF_ERR_ARG, "bad op");
+    if (int rc = check_prec(prec)) return rc;
+    if (k == 0) { c->forced[op][prec] = KernelConfig{}; return BF_OK; }
+    if (!variant_exists(op, prec, k, waves)) return fail(BF_ERR_UNSUPPORTED, "no such kernel variant");
+    if (split < 0) return fail(BF_ERR_ARG, "split < 0");
+    c->forced[op][prec] = KernelConfig{k, waves, split};
+    return BF_OK;
+}
+
+static int write_cache(bf_ctx* c, const char* path) {
+    std::ofstream f(path);
+    if (!f) return fail(BF_ERR_ARG, std::string("cannot write ") + path);
+    f << "[\n";
+    size_t i = 0;
+    for (const auto& kv : c->tuned) {
+        f << "  {\"op\": " << std::get<0>(kv.first) << ", \"prec\": " << std::get<1>(kv.first)
+          << ", \"nt_log2\": " << std::get<2>(kv.first) << ", \"ns_log2\": " << std::get<3>(kv.first)
+          << ", \"k\": " << kv.second.k << ", \"waves\": " << kv.second.waves << ", \"split\": " << kv.second.split << "}"
+          << (++i < c->tuned.size() ? ",\n" : "\n");
+    }
+    f << "]\n";
+    return BF_OK;
+}
+
+BF_API int bf_autotune_load(bf_ctx* c, const char* path) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!path) return fail(BF_ERR_ARG, "path NULL");
+    std::ifstream f(path);
+    if (!f) return fail(BF_ERR_ARG, std::string("cannot read ") + path);
+    std::string line;
+    while (std::getline(f, line)) {
+        int op, prec, bt, bs, k, w, sp;
+        if (sscanf(line.c_str(), " {\"op\": %d, \"prec\": %d, \"nt_log2\": %d, \"ns_log2\": %d, \"k\": %d, \"waves\": %d, \"split\": %d",
+                   &op, &prec, &bt, &bs, &k, &w, &sp) == 7) {
+            if (op >= 0 && op < OP_COUNT && (prec == 0 || prec == 1) && variant_exists(op, prec, k, w) && sp >= 0)
+                c->tuned[std::make_tuple(op, prec, bt, bs)] = KernelConfig{k, w, sp};
+        }
+    }
+    return BF_OK;
+}
+
+// synthetic particles for tuning: uniform in the unit cube
+__global__ void k_tune_fill(double* x, double* y, double* z, double* v, double* m, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x1234567ull;
+    auto nxt = [&h]() {
+        h ^= h >> 33; h *= 0xff51afd7ed558ccdull; h ^= h >> 33; h *= 0xc4ceb9fe1a85ec53ull; h ^= h >> 33;
+        return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+    };
+    x[i] = nxt(); y[i] = nxt(); z[i] = nxt();
+    v[i] = nxt() - 0.5; v[n + i] = nxt() - 0.5; v[2 * n + i] = nxt() - 0.5;
+    m[i] = 1.0 / (double)n;
+}
+
+BF_API int bf_autotune(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, const char* cache_path) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (op < 0 || op >= OP_COUNT) return fail(BF_ERR_ARG, "bad op");
+    if (int rc = check_prec(prec)) return rc;
+    if (nt <= 0 || ns <= 0 || nt > INT32_MAX || ns > INT32_MAX) return fail(BF_ERR_ARG, "bad sizes");
+    if (cache_path) {
+        std::ifstream probe(cache_path);
+        if (probe) bf_autotune_load(c, cache_path);
+    }
+    const int64_t n = std::max(nt, ns);
+    double* buf = nullptr;
+    // x y z vx vy vz m ax ay az out0 out1 out2
+    if (hipMalloc(&buf, (size_t)13 * n * sizeof(double)) != hipSuccess) return fail(BF_ERR_NOMEM, "tuning buffers");
+    double *x = buf, *y = x + n, *z = y + n, *v = z + n, *m = v + 3 * n, *a = m + n, *o = a + 3 * n;
+    hipLaunchKernelGGL(k_tune_fill, dim3((n + 255) / 256), dim3(256), 0, c->stream, x, y, z, v, m, n);
+    hipLaunchKernelGGL(k_tune_fill, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, a + n, a + 2 * n, o, o + n, n);
+    Masters M{};
+    M.x = x; M.y = y; M.z = z; M.vx = v; M.vy = v + n; M.vz = v + 2 * n; M.m = m;
+    M.ax = a; M.ay = a + n; M.az = a + 2 * n; M.n = n;
+    bf_set tg{nullptr, (int32_t)nt, 0}, sr{nullptr, (int32_t)ns, 0};
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const KernelConfig saved = c->forced[op][prec];
+    KernelConfig best{};
+    float best_ms = 1e30f;
+    int rc = BF_OK;
+    const int ks[] = {1, 2, 4};
+    const int ws[] = {2, 4, 8};
+    const int splits[] = {0, 1, 2, 4, 8, 16, 32, 64, 128};
+    for (int k : ks) {
+        for (int w : ws) {
+            if (!variant_exists(op, prec, k, w)) continue;
+            for (int sp : splits) {
+                c->forced[op][prec] = KernelConfig{k, w, sp};
+                Plan p;
+                if (plan(c, op, prec, nt, ns, p)) continue;
+                if (sp != 0 && p.split != sp) continue;  // clipped to another split: measured elsewhere
+                rc = run_pairs(c, op, prec, M, &tg, &sr, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);  // warm-up
+                if (rc) break;
+                hipEventRecord(e0, c->stream);
+                rc = run_pairs(c, op, prec, M, &tg, &sr, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);
+                hipEventRecord(e1, c->stream);
+                if (rc) break;
+                hipEventSynchronize(e1);
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = KernelConfig{k, w, p.split};
+                }
+            }
+            if (rc) break;
+        }
+        if (rc) break;
+    }
+    c->forced[op][prec] = saved;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamSynchronize(c->stream);
+    hipFree(buf);
+    if (rc) return rc;
+    if (best.k == 0) return fail(BF_ERR_UNSUPPORTED, "no variant ran");
+    c->tuned[std::make_tuple(op, prec, ilog2_bucket(nt), ilog2_bucket(ns))] = best;
+    if (cache_path) return write_cache(c, cache_path);
+    return BF_OK;
+}
+
+}  // extern "C"
