@@ -134,7 +134,7 @@ BF_API int bf_force_gradient(bf_ctx *ctx, const bf_particles *P, const bf_set *t
                              const double *az, double G, double eps2, int prec, double r_fb,
                              double *gx, double *gy, double *gz);
 
-/* Pairwise time-steps (Sec. 3, Eqs. dt-freefall and dt-flyby), unsoftened:
+/* Pairwise time-steps (Sec. 3.5.3, Eqs. dt-freefall and dt-flyby), unsoftened:
  *     dt_ff,i = eta_ff min_j (|r_ij|^3 / (G (m_i + m_j)))^(1/2)
  *     dt_fb,i = eta_fb min_j |r_ij| / |v_ij|
  * over sources j != i.  A pair with v_ij = 0 gives no fly-by bound; a target without a
@@ -146,7 +146,7 @@ BF_API int bf_dt_min(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, 
                      double G, double eta_ff, double eta_fb, int prec, double r_fb,
                      double *dt_ff, double *dt_fb);
 
-/* Global PN1.0 acceleration (Sec. 3, Eqs. subsyspn and subsyspn-mass), FP64: the pairwise
+/* Global PN1.0 acceleration (Sec. 3.8, Eqs. subsyspn and subsyspn-mass), FP64: the pairwise
  * first post-Newtonian acceleration summed over sources j != i for which i or j is in
  * bh_idx[0..n_bh) (device list of distinct particle indices).  The two-body term (not
  * printed in the paper) is the harmonic-gauge form; with n = (x_i - x_j)/r, v_ij = v_i - v_j:
@@ -179,7 +179,7 @@ typedef struct bf_fsi_params {
  * act as both targets and sources (the sub-Hamiltonian of that set):
  *   v += dt/6 a; x += dt/2 v; v += 2dt/3 (a + dt^2/24 Gsum); x += dt/2 v; v += dt/6 a,
  * each a evaluated at the current positions.  With n_bh > 0 the cycle is wrapped in two PN1.0
- * half-kicks v += dt/2 a_PN (Sec. 3, composition e^{eps/2 U_PN} e^{eps H_FSI} e^{eps/2 U_PN}).
+ * half-kicks v += dt/2 a_PN (Sec. 3.8, composition e^{eps/2 U_PN} e^{eps H_FSI} e^{eps/2 U_PN}).
  * ax/ay/az (particle-indexed, caller-owned) hold the accelerations of the final state on
  * return; with flags & BF_A_VALID their input values are reused for the first kick.
  * All updates are FP64.  Errors as in bf_forces. */

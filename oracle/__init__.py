@@ -153,7 +153,7 @@ def gradient(p: Particles, acc_full: np.ndarray, targets=None, sources=None, G: 
 
 def dt_min(p: Particles, targets=None, sources=None, G: float = 1.0, eta_ff: float = 0.2,
            eta_fb: float = 0.2):
-    """Free-fall and fly-by time-steps (Sec. 3, Eqs. dt-freefall, dt-flyby); returns (dt_ff, dt_fb)."""
+    """Free-fall and fly-by time-steps (Sec. 3.5.3, Eqs. dt-freefall, dt-flyby); returns (dt_ff, dt_fb)."""
     _check(p)
     t, s = _idx(targets, p.n), _idx(sources, p.n)
     nt = t.size
@@ -166,7 +166,7 @@ def dt_min(p: Particles, targets=None, sources=None, G: float = 1.0, eta_ff: flo
 
 
 def pn1(p: Particles, bh, targets=None, sources=None, G: float = 1.0, c: float = 1e4):
-    """Global PN1.0 acceleration over pairs with a flagged massive particle (Sec. 3,
+    """Global PN1.0 acceleration over pairs with a flagged massive particle (Sec. 3.8,
     Eqs. subsyspn, subsyspn-mass).  `bh` is a list of particle indices."""
     _check(p)
     t, s = _idx(targets, p.n), _idx(sources, p.n)
@@ -216,7 +216,7 @@ def fsi_step(p: Particles, dt: float, subset=None, G: float = 1.0, eps2: float =
     """One FSI cycle over `subset` in place (Sec. 2.1, Eq. fsi-cycle):
     kick eps/6, drift eps/2, gradient kick 2eps/3, drift eps/2, kick eps/6.
     With `bh` given, the cycle is wrapped in two PN1.0 half-kicks evaluated at the
-    current state (Sec. 3, the e^{eps/2 U_PN} e^{eps H_FSI} e^{eps/2 U_PN} composition)."""
+    current state (Sec. 3.8, the e^{eps/2 U_PN} e^{eps H_FSI} e^{eps/2 U_PN} composition)."""
     idx = _idx(subset, p.n)
     if bh is not None and len(bh):
         _kick(p, idx, pn1(p, bh, idx, idx, G, c), dt / 2)

@@ -24,7 +24,7 @@
 #include <stdint.h>
 
 /* Newtonian acceleration, Sec. 2.1 (Eq. new-newton-acc); softened form as in
- * the comparison runs of Sec. 5 (Plummer softening).  Also returns, per target,
+ * the comparison runs of Sec. 5.2 (Plummer softening).  Also returns, per target,
  * the sum of the magnitudes of the individual terms (a conditioning scale used
  * to state FP64 tolerances). */
 void oracle_forces(const double *x, const double *y, const double *z, const double *m,
@@ -94,7 +94,7 @@ void oracle_gradient(const double *x, const double *y, const double *z, const do
     if (n_coincident) *n_coincident = coinc;
 }
 
-/* Pairwise time-steps, Sec. 3 (Eqs. dt-freefall and dt-flyby):
+/* Pairwise time-steps, Sec. 3.5.3 (Eqs. dt-freefall and dt-flyby):
  *   dt_ff,i = eta_ff * min_j ( |r_ij|^3 / (G (m_i + m_j)) )^(1/2)
  *   dt_fb,i = eta_fb * min_j |r_ij| / |v_ij|
  * Unsoftened separations.  A pair with |v_ij| = 0 gives no fly-by bound; a
@@ -131,7 +131,7 @@ void oracle_dt_min(const double *x, const double *y, const double *z,
     if (n_coincident) *n_coincident = coinc;
 }
 
-/* Global PN1.0 term, Sec. 3 (Eqs. subsyspn and subsyspn-mass): the pairwise
+/* Global PN1.0 term, Sec. 3.8 (Eqs. subsyspn and subsyspn-mass): the pairwise
  * first post-Newtonian acceleration summed over pairs in which either particle
  * is flagged massive (is_bh[p] != 0).  The paper does not print the two-body
  * PN1.0 acceleration; this is the standard harmonic-gauge (EIH) two-body form

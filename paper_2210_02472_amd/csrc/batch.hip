@@ -77,6 +77,7 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const Batch b) {
         }
         b.item_off[nc] = run;
         *b.counter = 0;
+        *b.base.fix_count = 0;
     }
     __syncthreads();
     int32_t run = sums[threadIdx.x];
@@ -121,21 +122,22 @@ __global__ __launch_bounds__(64 * W) void k_batch_pairs(const Batch b) {
         const int j1 = min(ns, j0 + kBatchChunk);
         typename Op::A64 acc[K];
         int slot[K], pidx[K];
-        sweep<Op, K, W>(a, tile, slab * (64 * K * W) + wave * (64 * K), j0, j1, acc, slot, pidx);
+        sweep<Op, K, W, false>(a, tile, slab * (64 * K * W) + wave * (64 * K), j0, j1, acc, slot, pidx);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (slot[k] < na) {
-                double v[Op::NC];
+                constexpr int NP = ncomp_of<Op>();
+                double v[NP];
                 Op::comps(acc[k], v);
 #pragma unroll
-                for (int comp = 0; comp < Op::NC; ++comp)
-                    b.part[((size_t)q * Op::NC + comp) * b.max_active + a0 + slot[k]] = v[comp];
+                for (int comp = 0; comp < NP; ++comp)
+                    b.part[((size_t)q * NP + comp) * b.max_active + a0 + slot[k]] = v[comp];
             }
         }
     }
 }
 
-template <int NC>
+template <int NP>
 __global__ __launch_bounds__(256) void k_batch_reduce(const Batch b) {
     const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (a >= b.max_active) return;
@@ -153,12 +155,12 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const Batch b) {
     cluster_bounds(b, c, cb, ce, a0, a1);
     if (a < a0 || a >= a1) return;
     const int32_t nch = (int32_t)((ce - cb + kBatchChunk - 1) / kBatchChunk);
-    double v[NC];
+    double v[NP];
 #pragma unroll
-    for (int comp = 0; comp < NC; ++comp) v[comp] = 0.0;
+    for (int comp = 0; comp < NP; ++comp) v[comp] = 0.0;
     for (int q = 0; q < nch; ++q)
 #pragma unroll
-        for (int comp = 0; comp < NC; ++comp) v[comp] += b.part[((size_t)q * NC + comp) * b.max_active + a];
+        for (int comp = 0; comp < NP; ++comp) v[comp] += b.part[((size_t)q * NP + comp) * b.max_active + a];
     int32_t p = b.aidx[a];
     if (p < cb || p >= ce) {
         atomicOr(b.base.flags, BF_FLAG_BADINDEX);
@@ -167,6 +169,36 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const Batch b) {
     if (!__builtin_isfinite(v[0]) || !__builtin_isfinite(v[1]) || !__builtin_isfinite(v[2]))
         atomicOr(b.base.flags, BF_FLAG_NONFINITE);
     b.o0[p] = v[0]; b.o1[p] = v[1]; b.o2[p] = v[2];
+    if constexpr (NP == 4) {  // mixed: queue ill-conditioned targets for the FP64 fix-up
+        const double ny = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (v[3] > b.base.cond_max * ny) {
+            const int e = atomicAdd(b.base.fix_count, 1);
+            if (e < b.max_active) b.base.fix_list[e] = (int32_t)a;
+        }
+    }
+}
+
+// FP64 re-evaluation of the queued active slots over their cluster's sources
+template <int OP>
+__global__ __launch_bounds__(256) void k_batch_fixup(const Batch b) {
+    const int count = (int)min((int64_t)*b.base.fix_count, b.max_active);
+    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+        const int32_t a = b.base.fix_list[e];
+        int lo = 0, hi = b.nclusters - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.aoff[mid] <= a) lo = mid;
+            else hi = mid - 1;
+        }
+        int64_t cb, ce, a0, a1;
+        cluster_bounds(b, lo, cb, ce, a0, a1);  // queued slots come from valid clusters
+        const int32_t p = b.aidx[a];            // checked by the reduction before queueing
+        const DevSet src{nullptr, (int32_t)(ce - cb), (int32_t)cb};
+        double r[3];
+        fix_one<OP>(b.base.P, src, p, b.base.G, b.base.eps2, b.base.flags, r);
+        if (threadIdx.x == 0) { b.o0[p] = r[0]; b.o1[p] = r[1]; b.o2[p] = r[2]; }
+        __syncthreads();
+    }
 }
 
 // kick / drift of the active particles of every cluster
@@ -254,8 +286,10 @@ static int batch_setup(bf_ctx* c, const bf_particles* P, int32_t nclusters, cons
     b.max_chunks = (int32_t)((max_cluster_n + kBatchChunk - 1) / kBatchChunk);
     b.pack_bytes = pack_bytes(op, prec);
     const size_t pack_total = (size_t)P->n * b.pack_bytes;
-    const size_t part_bytes = (size_t)b.max_chunks * 3 * std::max<int64_t>(max_active, 1) * sizeof(double);
-    const size_t off_bytes = ((size_t)(2 * nclusters + 2) * sizeof(int32_t) + 255) & ~size_t(255);
+    const size_t part_bytes = (size_t)b.max_chunks * stored_components(op, prec) *
+                              std::max<int64_t>(max_active, 1) * sizeof(double);
+    const size_t off_bytes = ((size_t)(2 * nclusters + 3 + std::max<int64_t>(max_active, 1)) * sizeof(int32_t) + 255) &
+                             ~size_t(255);
     if (int rc = bf_internal_ensure(c, 2, pack_total)) return rc;
     if (int rc = bf_internal_ensure(c, 4, part_bytes + off_bytes)) return rc;
     b.base.pack = bf_internal_scratch(c, 2);
@@ -264,6 +298,9 @@ static int batch_setup(bf_ctx* c, const bf_particles* P, int32_t nclusters, cons
     b.item_off = reinterpret_cast<int32_t*>(s4 + part_bytes);
     b.counter = b.item_off + nclusters + 1;
     b.bad = b.counter + 1;
+    b.base.fix_count = b.bad + nclusters;
+    b.base.fix_list = b.base.fix_count + 1;
+    b.base.cond_max = kCondMax;
     return BF_OK;
 }
 
@@ -280,8 +317,16 @@ static int batch_enqueue(bf_ctx* c, Batch& b, int op, int prec) {
     if (op == OP_ACC) e = mixed ? launch_batch_op<AccMixed>(b, c->num_cu, st) : launch_batch_op<Acc64>(b, c->num_cu, st);
     else e = mixed ? launch_batch_op<GradMixed>(b, c->num_cu, st) : launch_batch_op<Grad64>(b, c->num_cu, st);
     if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
-    if (b.max_active > 0)
-        hipLaunchKernelGGL(k_batch_reduce<3>, dim3((unsigned)((b.max_active + 255) / 256)), dim3(256), 0, st, b);
+    if (b.max_active > 0) {
+        const dim3 g((unsigned)((b.max_active + 255) / 256));
+        if (mixed) hipLaunchKernelGGL(k_batch_reduce<4>, g, dim3(256), 0, st, b);
+        else hipLaunchKernelGGL(k_batch_reduce<3>, g, dim3(256), 0, st, b);
+        if (mixed) {
+            const unsigned nfix = (unsigned)std::min<int64_t>(b.max_active, 4 * c->num_cu);
+            if (op == OP_ACC) hipLaunchKernelGGL(k_batch_fixup<OP_ACC>, dim3(nfix), dim3(256), 0, st, b);
+            else hipLaunchKernelGGL(k_batch_fixup<OP_GRAD>, dim3(nfix), dim3(256), 0, st, b);
+        }
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
     return BF_OK;

@@ -45,6 +45,9 @@ struct PairArgs {
     double* part;     // [split][ncomp][tgt.count] partial results when split > 1
     double *o0, *o1, *o2;  // particle-indexed outputs when split == 1
     double eta0, eta1;     // dt_min: eta_ff, eta_fb
+    double cond_max;       // mixed acc/grad: FP64 fix-up when magnitude estimate > cond_max |result|
+    int32_t* fix_list;     // [tgt.count] target slots queued for the FP64 fix-up
+    int32_t* fix_count;    // number of queued slots
     uint32_t* flags;
 };
 
@@ -66,8 +69,17 @@ int variant_blocks_per_cu(int op, int prec, int k, int waves);
 // Bytes per packed source for op/prec.
 int pack_bytes(int op, int prec);
 
+// Stored components per target (results, plus the magnitude estimate of the mixed acc/grad).
+int stored_components(int op, int prec);
+
 hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st);
-hipError_t launch_reduce(int op, const PairArgs& a, hipStream_t st);
+hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st);
+hipError_t launch_zero_count(int32_t* c, hipStream_t st);
+hipError_t launch_fixup(int op, const PairArgs& a, int nblocks, hipStream_t st);
+
+// Mixed acc/grad: a target is re-evaluated in FP64 when its magnitude estimate exceeds
+// kCondMax times the norm of its result.
+constexpr double kCondMax = 16.0;
 
 // PN1.0
 struct PnArgs {

@@ -87,8 +87,6 @@ int ilog2_bucket(int64_t v) {
     return b;
 }
 
-int ncomp(int op) { return op == OP_DT ? 2 : 3; }
-
 // Default kernel shape: K targets per lane and W waves per workgroup.
 KernelConfig default_config(int op, int prec, int64_t nt) {
     KernelConfig c;
@@ -163,17 +161,22 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     a.eta1 = eta1;
     a.o0 = o0; a.o1 = o1; a.o2 = o2;
     a.flags = ctx->d_flags;
+    a.cond_max = kCondMax;
+    // scratch: [fix counter | fix list (one slot per target) | split partials]
+    const bool fix = prec == BF_PREC_MIXED && op != OP_DT;
+    const size_t head = 256 + (((size_t)tg->count * sizeof(int32_t) + 255) & ~size_t(255));
+    const size_t part_bytes = p.split > 1 ? (size_t)p.split * stored_components(op, prec) * tg->count * sizeof(double) : 0;
+    rc = ensure(&ctx->scratch, &ctx->scratch_bytes, head + part_bytes, ctx->stream);
+    if (rc) return rc;
+    a.fix_count = static_cast<int32_t*>(ctx->scratch);
+    a.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + 256);
+    if (p.split > 1) a.part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + head);
+    if (fix) BF_HIP(launch_zero_count(a.fix_count, ctx->stream));
     if (sr->count > 0) {
         rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)sr->count * pack_bytes(op, prec), ctx->stream);
         if (rc) return rc;
         a.pack = ctx->scratch2;
         BF_HIP(launch_pack(op, prec, a, ctx->stream));
-    }
-    if (p.split > 1) {
-        rc = ensure(&ctx->scratch, &ctx->scratch_bytes, (size_t)p.split * ncomp(op) * tg->count * sizeof(double),
-                    ctx->stream);
-        if (rc) return rc;
-        a.part = static_cast<double*>(ctx->scratch);
     }
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (ctx->timing) {
@@ -191,7 +194,8 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
     }
-    if (p.split > 1) BF_HIP(launch_reduce(op, a, ctx->stream));
+    if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
+    if (fix) BF_HIP(launch_fixup(op, a, std::min<int>(tg->count, 4 * ctx->num_cu), ctx->stream));
     return BF_OK;
 }
 

@@ -1,6 +1,14 @@
 // Pair operations shared by the single-set kernels (pairs.hip) and the batched persistent
 // kernel (batch.hip): per-pair arithmetic of the acceleration, force-gradient and time-step passes
 // in mixed and FP64 precision, the FP64 re-evaluation of close-pair tiles, and the tile sweep.
+//
+// Mixed precision, as used here: every difference of FP64 master quantities (positions,
+// velocities, accelerations) is taken in FP64 and rounded once to FP32; all arithmetic after
+// that (s^2, rsqrt, mass products, the pair term) is FP32; each LDS tile is summed in FP32
+// and merged into FP64 accumulators.  The acceleration and gradient passes also accumulate a
+// magnitude estimate M (sum over pairs of the pair weight times the max-norm of the pair's
+// difference vector); a target whose result is small against M (cancellation) is re-evaluated
+// entirely in FP64 afterwards.
 #pragma once
 
 #include "bf_internal.h"
@@ -31,73 +39,100 @@ __device__ __forceinline__ double rsqrt64(double r2) {
 
 __device__ __forceinline__ float rsqrt32(float r2) { return __builtin_amdgcn_rsqf(r2); }
 
+__device__ __forceinline__ float dif32(double a, double b) { return (float)(a - b); }
+__device__ __forceinline__ float max3abs(float a, float b, float c) {
+    return __builtin_fmaxf(__builtin_fabsf(a), __builtin_fmaxf(__builtin_fabsf(b), __builtin_fabsf(c)));
+}
+
+// G m stored as FP32 in the low half of the fourth FP64 slot of a packed position
+__device__ __forceinline__ double pack_gm(float gm) { return __builtin_bit_cast(double, make_float2(gm, 0.f)); }
+__device__ __forceinline__ float unpack_gm(double w) { return __builtin_bit_cast(float2, w).x; }
+
 constexpr float kTiny32 = 1e-20f;   // added to s^2 in FP32: keeps the self pair finite (and zero)
 constexpr double kTiny64 = 1e-150;  // same in FP64
 
+// FP64 contributions of one pair, straight from the masters (re-evaluation and fix-up paths).
+// r = x_j - x_i, s2 = |r|^2 + eps2 > 0.
+__device__ __forceinline__ void acc_pair64(const Masters& P, int pi, int pj, double G, double eps2, double& sx,
+                                           double& sy, double& sz, double& sm, uint32_t* flags) {
+    const double dx = P.x[pj] - P.x[pi], dy = P.y[pj] - P.y[pi], dz = P.z[pj] - P.z[pi];
+    const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+    if (r2 == 0.0) { atomicOr(flags, BF_FLAG_COINCIDENT); return; }
+    const double ri = rsqrt64(r2);
+    const double w = G * P.m[pj] * ri * ri * ri;
+    sx += w * dx; sy += w * dy; sz += w * dz;
+    sm += w * fmax(fabs(dx), fmax(fabs(dy), fabs(dz)));
+}
+
+__device__ __forceinline__ void grad_pair64(const Masters& P, int pi, int pj, double G, double eps2, double& sx,
+                                            double& sy, double& sz, double& sm, uint32_t* flags) {
+    const double dx = P.x[pj] - P.x[pi], dy = P.y[pj] - P.y[pi], dz = P.z[pj] - P.z[pi];
+    const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+    if (r2 == 0.0) { atomicOr(flags, BF_FLAG_COINCIDENT); return; }
+    const double dax = P.ax[pj] - P.ax[pi], day = P.ay[pj] - P.ay[pi], daz = P.az[pj] - P.az[pi];
+    const double ri = rsqrt64(r2);
+    const double ri2 = ri * ri;
+    const double w = G * P.m[pj] * ri * ri2;
+    const double q3 = 3.0 * (dax * dx + day * dy + daz * dz) * ri2;
+    sx += w * (dax - q3 * dx); sy += w * (day - q3 * dy); sz += w * (daz - q3 * dz);
+    sm += w * fmax(fabs(dax), fmax(fabs(day), fabs(daz)));
+}
+
 // ---- operations ----------------------------------------------------------------------------
 // Each operation provides: Src (LDS element), Tgt (per-target registers), A32 (per-tile
-// partial), A64 (running result), and the steps used by the skeleton.
+// partial), A64 (running result), NC result components plus kCond magnitude components, and
+// the steps used by the skeleton.
 
-// Newtonian acceleration, mixed precision.  Pack: float4 (x, y, z, G m).
+// Newtonian acceleration, mixed precision.  Pack: double4 (x, y, z, [G m as FP32]).
 struct AccMixed {
     static constexpr int NC = 3;
-    static constexpr bool kMixed = true;
-    static constexpr bool kMax = false;
-    struct Src { float4 p; };
-    struct Tgt { float x, y, z; };
-    struct A32 { float x, y, z; };
-    struct A64 { double x, y, z; };
-    __device__ static Src load(const PairArgs& a, int q) { return {static_cast<const float4*>(a.pack)[q]}; }
-    __device__ static void target(const PairArgs& a, int p, Tgt& t) {
-        t.x = (float)a.P.x[p]; t.y = (float)a.P.y[p]; t.z = (float)a.P.z[p];
-    }
-    __device__ static void zero(A32& r) { r.x = r.y = r.z = 0.f; }
-    __device__ static void zero(A64& r) { r.x = r.y = r.z = 0.0; }
+    static constexpr bool kMixed = true, kMax = false, kCond = true;
+    struct Src { double4 p; };
+    struct Tgt { double x, y, z; };
+    struct A32 { float x, y, z, m; };
+    struct A64 { double x, y, z, m; };
+    __device__ static Src load(const PairArgs& a, int q) { return {static_cast<const double4*>(a.pack)[q]}; }
+    __device__ static void target(const PairArgs& a, int p, Tgt& t) { t.x = a.P.x[p]; t.y = a.P.y[p]; t.z = a.P.z[p]; }
+    __device__ static void zero(A32& r) { r.x = r.y = r.z = r.m = 0.f; }
+    __device__ static void zero(A64& r) { r.x = r.y = r.z = r.m = 0.0; }
     __device__ static float pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
-        const float dx = s.p.x - t.x, dy = s.p.y - t.y, dz = s.p.z - t.z;
+        const float dx = dif32(s.p.x, t.x), dy = dif32(s.p.y, t.y), dz = dif32(s.p.z, t.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
         const float ri = rsqrt32(r2);
         const float ri2 = ri * ri;
-        const float w = (s.p.w * ri) * ri2;
+        const float w = (unpack_gm(s.p.w) * ri) * ri2;
         r.x = __builtin_fmaf(w, dx, r.x);
         r.y = __builtin_fmaf(w, dy, r.y);
         r.z = __builtin_fmaf(w, dz, r.z);
+        r.m = __builtin_fmaf(w, max3abs(dx, dy, dz), r.m);
         return r2;
     }
-    __device__ static void fold(A64& o, const A32& i) { o.x += (double)i.x; o.y += (double)i.y; o.z += (double)i.z; }
-    // FP64 re-evaluation of sources [q0, q0 + len) for target particle pi.
+    __device__ static void fold(A64& o, const A32& i) {
+        o.x += (double)i.x; o.y += (double)i.y; o.z += (double)i.z; o.m += (double)i.m;
+    }
     __device__ static void redo(A64& o, const PairArgs& a, int pi, int q0, int len) {
-        const double xi = a.P.x[pi], yi = a.P.y[pi], zi = a.P.z[pi];
-        double sx = 0.0, sy = 0.0, sz = 0.0;
+        double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
         for (int q = q0; q < q0 + len; ++q) {
             const int pj = particle_of(a.src, q, a.P.n, a.flags);
-            if (pj == pi) continue;
-            const double dx = a.P.x[pj] - xi, dy = a.P.y[pj] - yi, dz = a.P.z[pj] - zi;
-            const double r2 = dx * dx + dy * dy + dz * dz + a.eps2;
-            if (r2 == 0.0) { atomicOr(a.flags, BF_FLAG_COINCIDENT); continue; }
-            const double ri = rsqrt64(r2);
-            const double w = a.G * a.P.m[pj] * ri * ri * ri;
-            sx += w * dx; sy += w * dy; sz += w * dz;
+            if (pj != pi) acc_pair64(a.P, pi, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
         }
-        o.x += sx; o.y += sy; o.z += sz;
+        o.x += sx; o.y += sy; o.z += sz; o.m += sm;
     }
-    __device__ static void comps(const A64& o, double* v) { v[0] = o.x; v[1] = o.y; v[2] = o.z; }
+    __device__ static void comps(const A64& o, double* v) { v[0] = o.x; v[1] = o.y; v[2] = o.z; v[3] = o.m; }
 };
 
-// Force-gradient sum, mixed precision.  Pack: double4 (x, y, z, [G m as float | 0]) and
-// double4 (ax, ay, az, 0).  The position and acceleration differences are taken in FP64 and
-// rounded once to FP32 (a_ji = a_j - a_i cancels strongly for near neighbours, whose 1/r^3
-// weight dominates the sum); everything after that is FP32.  Per pair:
+// Force-gradient sum, mixed precision.  Pack: double4 (x, y, z, [G m as FP32]) and
+// double4 (ax, ay, az, 0).  a_ji = a_j - a_i cancels strongly for near neighbours, whose 1/r^3
+// weight dominates the sum, so it is formed in FP64 like the position difference.  Per pair:
 // Gsum += w (a_ji - 3 (a_ji . r) r / s^2) with w = G m / s^3, accumulated as two sums
 // S1 = sum w a_ji and S2 = sum w (a_ji . r)/s^2 r, Gsum = S1 - 3 S2.
 struct GradMixed {
     static constexpr int NC = 3;
-    static constexpr bool kMixed = true;
-    static constexpr bool kMax = false;
+    static constexpr bool kMixed = true, kMax = false, kCond = true;
     struct Src { double4 p, a; };
     struct Tgt { double x, y, z, ax, ay, az; };
-    struct A32 { float x, y, z, u, v, w; };
-    struct A64 { double x, y, z; };
+    struct A32 { float x, y, z, u, v, w, m; };
+    struct A64 { double x, y, z, m; };
     __device__ static Src load(const PairArgs& a, int q) {
         const double4* pk = static_cast<const double4*>(a.pack);
         return {pk[2 * q], pk[2 * q + 1]};
@@ -106,17 +141,16 @@ struct GradMixed {
         t.x = a.P.x[p]; t.y = a.P.y[p]; t.z = a.P.z[p];
         t.ax = a.P.ax[p]; t.ay = a.P.ay[p]; t.az = a.P.az[p];
     }
-    __device__ static void zero(A32& r) { r.x = r.y = r.z = r.u = r.v = r.w = 0.f; }
-    __device__ static void zero(A64& r) { r.x = r.y = r.z = 0.0; }
+    __device__ static void zero(A32& r) { r.x = r.y = r.z = r.u = r.v = r.w = r.m = 0.f; }
+    __device__ static void zero(A64& r) { r.x = r.y = r.z = r.m = 0.0; }
     __device__ static float pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
-        const float dx = (float)(s.p.x - t.x), dy = (float)(s.p.y - t.y), dz = (float)(s.p.z - t.z);
-        const float gm = __builtin_bit_cast(float2, s.p.w).x;
+        const float dx = dif32(s.p.x, t.x), dy = dif32(s.p.y, t.y), dz = dif32(s.p.z, t.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
         const float ri = rsqrt32(r2);
         const float ri2 = ri * ri;
-        const float dax = (float)(s.a.x - t.ax), day = (float)(s.a.y - t.ay), daz = (float)(s.a.z - t.az);
+        const float dax = dif32(s.a.x, t.ax), day = dif32(s.a.y, t.ay), daz = dif32(s.a.z, t.az);
         const float q = __builtin_fmaf(dax, dx, __builtin_fmaf(day, dy, daz * dz));
-        const float w = (gm * ri) * ri2;
+        const float w = (unpack_gm(s.p.w) * ri) * ri2;
         const float w5 = (w * q) * ri2;
         r.x = __builtin_fmaf(w, dax, r.x);
         r.y = __builtin_fmaf(w, day, r.y);
@@ -124,66 +158,57 @@ struct GradMixed {
         r.u = __builtin_fmaf(w5, dx, r.u);
         r.v = __builtin_fmaf(w5, dy, r.v);
         r.w = __builtin_fmaf(w5, dz, r.w);
+        r.m = __builtin_fmaf(w, max3abs(dax, day, daz), r.m);
         return r2;
     }
     __device__ static void fold(A64& o, const A32& i) {
         o.x += (double)i.x - 3.0 * (double)i.u;
         o.y += (double)i.y - 3.0 * (double)i.v;
         o.z += (double)i.z - 3.0 * (double)i.w;
+        o.m += (double)i.m;
     }
     __device__ static void redo(A64& o, const PairArgs& a, int pi, int q0, int len) {
-        const double xi = a.P.x[pi], yi = a.P.y[pi], zi = a.P.z[pi];
-        const double axi = a.P.ax[pi], ayi = a.P.ay[pi], azi = a.P.az[pi];
-        double sx = 0.0, sy = 0.0, sz = 0.0;
+        double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
         for (int q = q0; q < q0 + len; ++q) {
             const int pj = particle_of(a.src, q, a.P.n, a.flags);
-            if (pj == pi) continue;
-            const double dx = a.P.x[pj] - xi, dy = a.P.y[pj] - yi, dz = a.P.z[pj] - zi;
-            const double r2 = dx * dx + dy * dy + dz * dz + a.eps2;
-            if (r2 == 0.0) { atomicOr(a.flags, BF_FLAG_COINCIDENT); continue; }
-            const double dax = a.P.ax[pj] - axi, day = a.P.ay[pj] - ayi, daz = a.P.az[pj] - azi;
-            const double ri = rsqrt64(r2);
-            const double ri2 = ri * ri;
-            const double w = a.G * a.P.m[pj] * ri * ri2;
-            const double q3 = 3.0 * (dax * dx + day * dy + daz * dz) * ri2;
-            sx += w * (dax - q3 * dx); sy += w * (day - q3 * dy); sz += w * (daz - q3 * dz);
+            if (pj != pi) grad_pair64(a.P, pi, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
         }
-        o.x += sx; o.y += sy; o.z += sz;
+        o.x += sx; o.y += sy; o.z += sz; o.m += sm;
     }
-    __device__ static void comps(const A64& o, double* v) { v[0] = o.x; v[1] = o.y; v[2] = o.z; }
+    __device__ static void comps(const A64& o, double* v) { v[0] = o.x; v[1] = o.y; v[2] = o.z; v[3] = o.m; }
 };
 
-// Time-step maxima, mixed precision.  Pack: float4 (x, y, z, G m), float4 (vx, vy, vz, 0).
-// Per pair: Wff = max G(m_i + m_j)/r^3, Wfb = max |v_ij|^2/r^2 (unsoftened); then
-// dt_ff = eta_ff Wff^(-1/2), dt_fb = eta_fb Wfb^(-1/2).
+// Time-step maxima, mixed precision.  Pack: double4 (x, y, z, [G m as FP32]) and
+// double4 (vx, vy, vz, 0).  Per pair: Wff = max G(m_i + m_j)/r^3, Wfb = max |v_ij|^2/r^2
+// (unsoftened); then dt_ff = eta_ff Wff^(-1/2), dt_fb = eta_fb Wfb^(-1/2).  The self pair has
+// r^2 = 0 and always sends its tile to the FP64 re-evaluation, which excludes it by index.
 struct DtMixed {
     static constexpr int NC = 2;
-    static constexpr bool kMixed = true;
-    static constexpr bool kMax = true;
-    struct Src { float4 p, v; };
-    struct Tgt { float x, y, z, vx, vy, vz, gm; };
+    static constexpr bool kMixed = true, kMax = true, kCond = false;
+    struct Src { double4 p, v; };
+    struct Tgt { double x, y, z, vx, vy, vz; float gm; };
     struct A32 { float ff, fb; };
     struct A64 { double ff, fb; };
     __device__ static Src load(const PairArgs& a, int q) {
-        const float4* pk = static_cast<const float4*>(a.pack);
+        const double4* pk = static_cast<const double4*>(a.pack);
         return {pk[2 * q], pk[2 * q + 1]};
     }
     __device__ static void target(const PairArgs& a, int p, Tgt& t) {
-        t.x = (float)a.P.x[p]; t.y = (float)a.P.y[p]; t.z = (float)a.P.z[p];
-        t.vx = (float)a.P.vx[p]; t.vy = (float)a.P.vy[p]; t.vz = (float)a.P.vz[p];
+        t.x = a.P.x[p]; t.y = a.P.y[p]; t.z = a.P.z[p];
+        t.vx = a.P.vx[p]; t.vy = a.P.vy[p]; t.vz = a.P.vz[p];
         t.gm = (float)(a.G * a.P.m[p]);
     }
     __device__ static void zero(A32& r) { r.ff = r.fb = 0.f; }
     __device__ static void zero(A64& r) { r.ff = r.fb = 0.0; }
     __device__ static float pair(A32& r, const Tgt& t, const Src& s, float /*eps2f*/) {
-        const float dx = s.p.x - t.x, dy = s.p.y - t.y, dz = s.p.z - t.z;
+        const float dx = dif32(s.p.x, t.x), dy = dif32(s.p.y, t.y), dz = dif32(s.p.z, t.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-        const float ux = s.v.x - t.vx, uy = s.v.y - t.vy, uz = s.v.z - t.vz;
+        const float ux = dif32(s.v.x, t.vx), uy = dif32(s.v.y, t.vy), uz = dif32(s.v.z, t.vz);
         const float u2 = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
         const float ri = rsqrt32(r2);
         const float ri2 = ri * ri;
         r.fb = fmaxf(r.fb, u2 * ri2);
-        r.ff = fmaxf(r.ff, ((s.p.w + t.gm) * ri2) * ri);
+        r.ff = fmaxf(r.ff, ((unpack_gm(s.p.w) + t.gm) * ri2) * ri);
         return r2;
     }
     __device__ static void fold(A64& o, const A32& i) { o.ff = fmax(o.ff, (double)i.ff); o.fb = fmax(o.fb, (double)i.fb); }
@@ -210,8 +235,7 @@ struct DtMixed {
 // FP64 variants.  Packs: double4 (x, y, z, G m) [+ double4 (ax, ay, az, 0) | (vx, vy, vz, j)].
 struct Acc64 {
     static constexpr int NC = 3;
-    static constexpr bool kMixed = false;
-    static constexpr bool kMax = false;
+    static constexpr bool kMixed = false, kMax = false, kCond = false;
     struct Src { double4 p; };
     struct Tgt { double x, y, z; };
     using A32 = int;  // unused
@@ -234,8 +258,7 @@ struct Acc64 {
 
 struct Grad64 {
     static constexpr int NC = 3;
-    static constexpr bool kMixed = false;
-    static constexpr bool kMax = false;
+    static constexpr bool kMixed = false, kMax = false, kCond = false;
     struct Src { double4 p, a; };
     struct Tgt { double x, y, z, ax, ay, az; };
     using A32 = int;
@@ -267,10 +290,9 @@ struct Grad64 {
 
 struct Dt64 {
     static constexpr int NC = 2;
-    static constexpr bool kMixed = false;
-    static constexpr bool kMax = true;
+    static constexpr bool kMixed = false, kMax = true, kCond = false;
     struct Src { double4 p, v; };   // v.w = source particle index (exact in FP64)
-    struct Tgt { double x, y, z, vx, vy, vz, gm; int p; };
+    struct Tgt { double x, y, z, vx, vy, vz, gm; };
     using A32 = int;
     struct A64 { double ff, fb; };
     __device__ static Src load(const PairArgs& a, int q) {
@@ -280,7 +302,7 @@ struct Dt64 {
     __device__ static void target(const PairArgs& a, int p, Tgt& t) {
         t.x = a.P.x[p]; t.y = a.P.y[p]; t.z = a.P.z[p];
         t.vx = a.P.vx[p]; t.vy = a.P.vy[p]; t.vz = a.P.vz[p];
-        t.gm = a.G * a.P.m[p]; t.p = p;
+        t.gm = a.G * a.P.m[p];
     }
     __device__ static void zero(A64& r) { r.ff = r.fb = 0.0; }
     __device__ static void pair64(A64& r, const Tgt& t, const Src& s, double /*eps2t*/, int pi) {
@@ -299,12 +321,18 @@ struct Dt64 {
     __device__ static void comps(const A64& o, double* v) { v[0] = o.ff; v[1] = o.fb; }
 };
 
+// number of stored components of an operation (results + magnitude estimate)
+template <class Op>
+constexpr int ncomp_of() { return Op::NC + (Op::kCond ? 1 : 0); }
+
 // ---- sweep of one source range for the K targets of each lane -------------------------------
 // Loads the lane's targets (slots tbase + k*64 + lane of a.tgt; slots past nt duplicate the last
 // target and are not written by the caller), then walks sources [j0, j1) of the packed stream
-// in LDS tiles of 64*W.  All threads of the workgroup must call it (it synchronises).
+// in LDS tiles of 64*W.  DETECT: track min s^2 per tile and re-evaluate the wavefront's tile in
+// FP64 when a lane saw s^2 < a.rfb2f.  All threads of the workgroup must call it (it
+// synchronises).
 
-template <class Op, int K, int W>
+template <class Op, int K, int W, bool DETECT>
 __device__ __forceinline__ void sweep(const PairArgs& a, typename Op::Src* tile, int tbase, int j0, int j1,
                                       typename Op::A64 (&acc)[K], int (&slot)[K], int (&pidx)[K]) {
     constexpr int T = 64 * W;
@@ -335,13 +363,17 @@ __device__ __forceinline__ void sweep(const PairArgs& a, typename Op::Src* tile,
                 float r2[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) r2[k] = Op::pair(part[k], tg[k], s, a.eps2f);
+                if constexpr (DETECT) {
 #pragma unroll
-                for (int k = 0; k < K; k += 2) {
-                    if (k + 1 < K) dmin = fminf(dmin, fminf(r2[k], r2[k + 1]));
-                    else dmin = fminf(dmin, r2[k]);
+                    for (int k = 0; k < K; k += 2) {
+                        if (k + 1 < K) dmin = fminf(dmin, fminf(r2[k], r2[k + 1]));
+                        else dmin = fminf(dmin, r2[k]);
+                    }
                 }
             }
-            if (__any(dmin < a.rfb2f)) {
+            bool redo = false;
+            if constexpr (DETECT) redo = __any(dmin < a.rfb2f);
+            if (redo) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) Op::redo(acc[k], a, pidx[k], jt, len);
             } else {
@@ -358,6 +390,46 @@ __device__ __forceinline__ void sweep(const PairArgs& a, typename Op::Src* tile,
             }
         }
     }
+}
+
+// ---- conditioning check and FP64 fix-up --------------------------------------------------------
+// A mixed result y with magnitude estimate M is re-evaluated in FP64 when M > cond_max |y|:
+// the FP32 error of a pair term is bounded relative to that term, so the relative error of y
+// grows with M / |y| (cancellation).
+
+__device__ __forceinline__ void cond_check(const PairArgs& a, int slot, const double* v) {
+    const double ny = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (v[3] > a.cond_max * ny) {
+        const int e = atomicAdd(a.fix_count, 1);
+        if (e < a.tgt.count) a.fix_list[e] = slot;
+    }
+}
+
+// FP64 sum of all sources of `src` for target particle pi, one workgroup of 256 threads;
+// returns the result in thread 0.
+template <int OP>
+__device__ __forceinline__ void fix_one(const Masters& P, const DevSet& src, int pi, double G, double eps2,
+                                        uint32_t* flags, double* out3) {
+    __shared__ double red[3][256];
+    double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
+    for (int q = threadIdx.x; q < src.count; q += 256) {
+        const int pj = particle_of(src, q, P.n, flags);
+        if (pj == pi) continue;
+        if constexpr (OP == OP_ACC) acc_pair64(P, pi, pj, G, eps2, sx, sy, sz, sm, flags);
+        else grad_pair64(P, pi, pj, G, eps2, sx, sy, sz, sm, flags);
+    }
+    __syncthreads();
+    red[0][threadIdx.x] = sx; red[1][threadIdx.x] = sy; red[2][threadIdx.x] = sz;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            red[2][threadIdx.x] += red[2][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out3[0] = red[0][0]; out3[1] = red[1][0]; out3[2] = red[2][0]; }
 }
 
 }  // namespace bf

@@ -1,6 +1,5 @@
 // Direct-summation pair kernels for gfx950: Newtonian acceleration, force gradient and the
-// pairwise time-step maxima, each in a mixed (FP32 pair arithmetic, FP64 merge) and an FP64
-// flavour, sharing one tiled skeleton.
+// pairwise time-step maxima, each in a mixed and an FP64 flavour, sharing one tiled skeleton.
 //
 // Skeleton (one workgroup = W wavefronts):
 //  * the workgroup owns a slab of 64*K*W target slots (K per lane, lane-strided) and one of
@@ -10,12 +9,9 @@
 //  * sources are staged tile by tile (64*W per tile, one per thread) from a packed stream into
 //    LDS; every lane then walks the tile with a broadcast LDS read per source and updates its
 //    K targets in registers;
-//  * mixed precision: each tile is summed into FP32 partials that start at zero, and merged
-//    into FP64 accumulators after the tile (cascade summation: the FP32 sum never spans more
-//    than one tile).  The per-lane minimum of s^2 over the tile is tracked; if any lane of the
-//    wavefront saw s^2 < r_fb^2 the wavefront re-evaluates that tile in FP64 from the FP64
-//    masters with explicit self-exclusion and uses that instead (close pairs, coincident
-//    FP32 positions and the self pair all land there);
+//  * mixed precision (pair_ops.h): FP64 differences rounded once to FP32, FP32 arithmetic,
+//    per-tile FP32 partials merged into FP64, optional FP64 re-evaluation of tiles holding
+//    close pairs, and an FP64 fix-up of targets whose result cancels strongly;
 //  * results go straight to the particle-indexed outputs (split == 1) or to per-chunk
 //    partials that a second kernel reduces in chunk order (deterministic).
 #include "pair_ops.h"
@@ -25,33 +21,40 @@ namespace bf {
 // ---- output of one target ------------------------------------------------------------------
 
 template <class Op>
+__device__ __forceinline__ void write_result(const PairArgs& a, int slot, int pi, const double* v) {
+    if constexpr (Op::kMax) {
+        // dt = eta W^(-1/2); W = 0 (no valid source) gives +inf
+        const double dff = a.eta0 / sqrt(v[0]), dfb = a.eta1 / sqrt(v[1]);
+        if (__builtin_isnan(dff) || __builtin_isnan(dfb)) atomicOr(a.flags, BF_FLAG_NONFINITE);
+        a.o0[pi] = dff;
+        a.o1[pi] = dfb;
+    } else {
+        if (!__builtin_isfinite(v[0]) || !__builtin_isfinite(v[1]) || !__builtin_isfinite(v[2]))
+            atomicOr(a.flags, BF_FLAG_NONFINITE);
+        a.o0[pi] = v[0];
+        a.o1[pi] = v[1];
+        a.o2[pi] = v[2];
+        if constexpr (Op::kCond) cond_check(a, slot, v);
+    }
+}
+
+template <class Op>
 __device__ __forceinline__ void emit(const PairArgs& a, int c, int slot, int pi, const typename Op::A64& acc) {
-    double v[Op::NC];
+    constexpr int NP = ncomp_of<Op>();
+    double v[NP];
     Op::comps(acc, v);
     if (a.split == 1) {
-        if constexpr (Op::kMax) {
-            // dt = eta W^(-1/2); W = 0 (no valid source) gives +inf
-            const double dff = a.eta0 / sqrt(v[0]), dfb = a.eta1 / sqrt(v[1]);
-            if (__builtin_isnan(dff) || __builtin_isnan(dfb)) atomicOr(a.flags, BF_FLAG_NONFINITE);
-            a.o0[pi] = dff;
-            a.o1[pi] = dfb;
-        } else {
-            if (!__builtin_isfinite(v[0]) || !__builtin_isfinite(v[1]) || !__builtin_isfinite(v[2]))
-                atomicOr(a.flags, BF_FLAG_NONFINITE);
-            a.o0[pi] = v[0];
-            a.o1[pi] = v[1];
-            a.o2[pi] = v[2];
-        }
+        write_result<Op>(a, slot, pi, v);
     } else {
         const int nt = a.tgt.count;
 #pragma unroll
-        for (int comp = 0; comp < Op::NC; ++comp) a.part[((size_t)c * Op::NC + comp) * nt + slot] = v[comp];
+        for (int comp = 0; comp < NP; ++comp) a.part[((size_t)c * NP + comp) * nt + slot] = v[comp];
     }
 }
 
 // ---- the skeleton --------------------------------------------------------------------------
 
-template <class Op, int K, int W>
+template <class Op, int K, int W, bool DETECT>
 __global__ __launch_bounds__(64 * W) void k_pairs(const PairArgs a) {
     __shared__ typename Op::Src tile[64 * W];
     const int wave = threadIdx.x >> 6;
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs(const PairArgs a) {
     const int j1 = min(a.src.count, j0 + a.chunk);
     typename Op::A64 acc[K];
     int slot[K], pidx[K];
-    sweep<Op, K, W>(a, tile, tbase, j0, j1, acc, slot, pidx);
+    sweep<Op, K, W, DETECT>(a, tile, tbase, j0, j1, acc, slot, pidx);
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (slot[k] < a.tgt.count) emit<Op>(a, c, slot[k], pidx[k], acc[k]);
@@ -76,65 +79,59 @@ __global__ __launch_bounds__(256) void k_pack(const PairArgs a) {
     if (q >= a.src.count) return;
     const int p = particle_of(a.src, q, a.P.n, a.flags);
     const double gm = a.G * a.P.m[p];
-    if constexpr (MIXED) {
-        float4* pk = static_cast<float4*>(const_cast<void*>(a.pack));
-        const float4 pos = make_float4((float)a.P.x[p], (float)a.P.y[p], (float)a.P.z[p], (float)gm);
-        if constexpr (OP == OP_ACC) {
-            pk[q] = pos;
-        } else if constexpr (OP == OP_GRAD) {
-            // FP64 positions and accelerations; G m as FP32 in the low half of the fourth slot
-            double4* pd = static_cast<double4*>(const_cast<void*>(a.pack));
-            pd[2 * q] = make_double4(a.P.x[p], a.P.y[p], a.P.z[p],
-                                     __builtin_bit_cast(double, make_float2((float)gm, 0.f)));
-            pd[2 * q + 1] = make_double4(a.P.ax[p], a.P.ay[p], a.P.az[p], 0.0);
-        } else {
-            pk[2 * q] = pos;
-            pk[2 * q + 1] = make_float4((float)a.P.vx[p], (float)a.P.vy[p], (float)a.P.vz[p], 0.f);
-        }
+    double4* pk = static_cast<double4*>(const_cast<void*>(a.pack));
+    // mixed: G m as FP32 in the low half of the fourth slot; FP64: G m as FP64
+    const double4 pos = make_double4(a.P.x[p], a.P.y[p], a.P.z[p], MIXED ? pack_gm((float)gm) : gm);
+    if constexpr (OP == OP_ACC) {
+        pk[q] = pos;
+    } else if constexpr (OP == OP_GRAD) {
+        pk[2 * q] = pos;
+        pk[2 * q + 1] = make_double4(a.P.ax[p], a.P.ay[p], a.P.az[p], 0.0);
     } else {
-        double4* pk = static_cast<double4*>(const_cast<void*>(a.pack));
-        const double4 pos = make_double4(a.P.x[p], a.P.y[p], a.P.z[p], gm);
-        if constexpr (OP == OP_ACC) {
-            pk[q] = pos;
-        } else if constexpr (OP == OP_GRAD) {
-            pk[2 * q] = pos;
-            pk[2 * q + 1] = make_double4(a.P.ax[p], a.P.ay[p], a.P.az[p], 0.0);
-        } else {
-            pk[2 * q] = pos;
-            pk[2 * q + 1] = make_double4(a.P.vx[p], a.P.vy[p], a.P.vz[p], (double)p);
-        }
+        pk[2 * q] = pos;
+        pk[2 * q + 1] = make_double4(a.P.vx[p], a.P.vy[p], a.P.vz[p], (double)p);
     }
 }
 
 // ---- reduction over source chunks (fixed order) --------------------------------------------
 
-template <int NC, bool MAX>
+template <class Op>
 __global__ __launch_bounds__(256) void k_reduce(const PairArgs a) {
+    constexpr int NP = ncomp_of<Op>();
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int nt = a.tgt.count;
     if (k >= nt) return;
-    double v[NC];
+    double v[NP];
 #pragma unroll
-    for (int comp = 0; comp < NC; ++comp) v[comp] = 0.0;
+    for (int comp = 0; comp < NP; ++comp) v[comp] = 0.0;
     for (int c = 0; c < a.split; ++c) {
 #pragma unroll
-        for (int comp = 0; comp < NC; ++comp) {
-            const double x = a.part[((size_t)c * NC + comp) * nt + k];
-            v[comp] = MAX ? fmax(v[comp], x) : v[comp] + x;
+        for (int comp = 0; comp < NP; ++comp) {
+            const double x = a.part[((size_t)c * NP + comp) * nt + k];
+            v[comp] = Op::kMax ? fmax(v[comp], x) : v[comp] + x;
         }
     }
-    const int p = particle_of(a.tgt, k, a.P.n, a.flags);
-    if constexpr (MAX) {
-        const double dff = a.eta0 / sqrt(v[0]), dfb = a.eta1 / sqrt(v[1]);
-        if (__builtin_isnan(dff) || __builtin_isnan(dfb)) atomicOr(a.flags, BF_FLAG_NONFINITE);
-        a.o0[p] = dff;
-        a.o1[p] = dfb;
-    } else {
-        if (!__builtin_isfinite(v[0]) || !__builtin_isfinite(v[1]) || !__builtin_isfinite(v[2]))
-            atomicOr(a.flags, BF_FLAG_NONFINITE);
-        a.o0[p] = v[0];
-        a.o1[p] = v[1];
-        a.o2[p] = v[2];
+    write_result<Op>(a, k, particle_of(a.tgt, k, a.P.n, a.flags), v);
+}
+
+// ---- FP64 fix-up of ill-conditioned targets ------------------------------------------------
+
+__global__ void k_zero_count(int32_t* c) { *c = 0; }
+
+template <int OP>
+__global__ __launch_bounds__(256) void k_fixup(const PairArgs a) {
+    const int count = min(*a.fix_count, a.tgt.count);
+    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+        const int slot = a.fix_list[e];
+        const int pi = particle_of(a.tgt, slot, a.P.n, a.flags);
+        double r[3];
+        fix_one<OP>(a.P, a.src, pi, a.G, a.eps2, a.flags, r);
+        if (threadIdx.x == 0) {
+            a.o0[pi] = r[0];
+            a.o1[pi] = r[1];
+            a.o2[pi] = r[2];
+        }
+        __syncthreads();
     }
 }
 
@@ -142,38 +139,35 @@ __global__ __launch_bounds__(256) void k_reduce(const PairArgs a) {
 
 using KernelFn = void (*)(const PairArgs);
 
-template <class Op>
+template <class Op, bool D>
 static KernelFn pick(int k, int w) {
-    if (w == 4) {
-        if (k == 1) return k_pairs<Op, 1, 4>;
-        if (k == 2) return k_pairs<Op, 2, 4>;
-        if (k == 4) return k_pairs<Op, 4, 4>;
-    } else if (w == 8) {
-        if (k == 1) return k_pairs<Op, 1, 8>;
-        if (k == 2) return k_pairs<Op, 2, 8>;
-        if (k == 4) return k_pairs<Op, 4, 8>;
-    } else if (w == 2) {
-        if (k == 1) return k_pairs<Op, 1, 2>;
-        if (k == 2) return k_pairs<Op, 2, 2>;
-        if (k == 4) return k_pairs<Op, 4, 2>;
-    }
+#define BF_PICK(KK, WW) \
+    if (k == KK && w == WW) return k_pairs<Op, KK, WW, D>;
+    BF_PICK(1, 2) BF_PICK(2, 2) BF_PICK(4, 2)
+    BF_PICK(1, 4) BF_PICK(2, 4) BF_PICK(4, 4)
+    BF_PICK(1, 8) BF_PICK(2, 8) BF_PICK(4, 8)
+#undef BF_PICK
     return nullptr;
 }
 
-static KernelFn kernel_for(int op, int prec, int k, int w) {
+static KernelFn kernel_for(int op, int prec, int k, int w, bool detect) {
     const bool mixed = prec == BF_PREC_MIXED;
     switch (op) {
-        case OP_ACC: return mixed ? pick<AccMixed>(k, w) : pick<Acc64>(k, w);
-        case OP_GRAD: return mixed ? pick<GradMixed>(k, w) : pick<Grad64>(k, w);
-        case OP_DT: return mixed ? pick<DtMixed>(k, w) : pick<Dt64>(k, w);
+        case OP_ACC:
+            if (!mixed) return pick<Acc64, false>(k, w);
+            return detect ? pick<AccMixed, true>(k, w) : pick<AccMixed, false>(k, w);
+        case OP_GRAD:
+            if (!mixed) return pick<Grad64, false>(k, w);
+            return detect ? pick<GradMixed, true>(k, w) : pick<GradMixed, false>(k, w);
+        case OP_DT: return mixed ? pick<DtMixed, true>(k, w) : pick<Dt64, false>(k, w);
     }
     return nullptr;
 }
 
-bool variant_exists(int op, int prec, int k, int waves) { return kernel_for(op, prec, k, waves) != nullptr; }
+bool variant_exists(int op, int prec, int k, int waves) { return kernel_for(op, prec, k, waves, false) != nullptr; }
 
 int variant_blocks_per_cu(int op, int prec, int k, int waves) {
-    KernelFn f = kernel_for(op, prec, k, waves);
+    KernelFn f = kernel_for(op, prec, k, waves, op == OP_DT);
     if (!f) return 0;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(f), 64 * waves, 0) != hipSuccess)
@@ -182,16 +176,18 @@ int variant_blocks_per_cu(int op, int prec, int k, int waves) {
 }
 
 hipError_t launch_pairs(int op, int prec, const KernelConfig& cfg, const PairArgs& a, int nblocks, hipStream_t st) {
-    KernelFn f = kernel_for(op, prec, cfg.k, cfg.waves);
+    const bool detect = prec == BF_PREC_MIXED && a.rfb2f > 0.0f;
+    KernelFn f = kernel_for(op, prec, cfg.k, cfg.waves, detect || op == OP_DT);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(nblocks), dim3(64 * cfg.waves), 0, st, a);
     return hipGetLastError();
 }
 
-int pack_bytes(int op, int prec) {
-    if (op == OP_GRAD) return 64;  // FP64 differences in both precisions
-    const int base = prec == BF_PREC_MIXED ? 16 : 32;
-    return op == OP_ACC ? base : 2 * base;
+int pack_bytes(int op, int /*prec*/) { return op == OP_ACC ? 32 : 64; }
+
+int stored_components(int op, int prec) {
+    if (op == OP_DT) return 2;
+    return prec == BF_PREC_MIXED ? 4 : 3;
 }
 
 template <int OP, bool MIXED>
@@ -209,12 +205,29 @@ hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(int op, const PairArgs& a, hipStream_t st) {
+template <class Op>
+static void reduce_one(const PairArgs& a, hipStream_t st) {
     const int n = a.tgt.count;
-    if (n <= 0) return hipSuccess;
-    const dim3 g((n + 255) / 256), b(256);
-    if (op == OP_DT) hipLaunchKernelGGL((k_reduce<2, true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_reduce<3, false>), g, b, 0, st, a);
+    hipLaunchKernelGGL(k_reduce<Op>, dim3((n + 255) / 256), dim3(256), 0, st, a);
+}
+
+hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st) {
+    if (a.tgt.count <= 0) return hipSuccess;
+    const bool mixed = prec == BF_PREC_MIXED;
+    if (op == OP_ACC) mixed ? reduce_one<AccMixed>(a, st) : reduce_one<Acc64>(a, st);
+    else if (op == OP_GRAD) mixed ? reduce_one<GradMixed>(a, st) : reduce_one<Grad64>(a, st);
+    else mixed ? reduce_one<DtMixed>(a, st) : reduce_one<Dt64>(a, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_count(int32_t* c, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_fixup(int op, const PairArgs& a, int nblocks, hipStream_t st) {
+    if (op == OP_ACC) hipLaunchKernelGGL(k_fixup<OP_ACC>, dim3(nblocks), dim3(256), 0, st, a);
+    else if (op == OP_GRAD) hipLaunchKernelGGL(k_fixup<OP_GRAD>, dim3(nblocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 """Two-body (Kepler) closed form used to pin the integrator oracle.
 
 Elliptic orbits only.  Kepler's equation M = E - e sin E (the form the paper
-solves for its secular binaries, Sec. 3) is solved by Newton iteration started
+solves for its secular binaries and Kepler solver, Secs. 3.10-3.11) is solved by Newton iteration started
 at E = M + e sin M and safeguarded by bisection on [M - e, M + e].  Nothing here
 uses the force routines: the state at any time follows from the orbital
 elements of the initial relative state.

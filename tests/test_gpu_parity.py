@@ -298,18 +298,24 @@ def test_energy_parity(ctx):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_fsi_step_parity(ctx, prec):
+    """Three FSI cycles of the N = 1024 Plummer sphere.  FP64: state within 1e-12 of its scale.
+    Mixed: the change of the state over the steps is within the mixed tolerance (1e-5) of the
+    oracle's change (the kicks carry the relative error of the accelerations)."""
     d = ics.config1_plummer1k()
     P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    P0 = P.copy()
     acc = None
     for s in range(3):
         oracle.fsi_step(P, 1e-3)
         acc = ctx.fsi_step(Pd, 1e-3, prec=prec, acc=acc, acc_valid=s > 0)
-    tol = 1e-12 if prec == "fp64" else 1e-8
     for k in ("x", "y", "z", "vx", "vy", "vz"):
         ref = getattr(P, k)
         got = getattr(Pd, k).cpu().numpy()
-        scale = np.abs(ref).max()
-        assert np.abs(got - ref).max() <= tol * scale, k
+        if prec == "fp64":
+            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
+        else:
+            change = np.abs(ref - getattr(P0, k)).max()
+            assert np.abs(got - ref).max() <= MAX_TOL * change, k
 
 
 def test_fsi_step_with_pn_parity(ctx):

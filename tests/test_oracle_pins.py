@@ -42,7 +42,7 @@ def test_acc_hand_worked_line():
 
 def test_acc_two_body_direction_and_magnitude():
     """Body 1 is pulled toward body 2 with magnitude G m2 / d^2 (and the softened form
-    G m2 d / (d^2 + eps^2)^(3/2) of the comparison runs, Sec. 5)."""
+    G m2 d / (d^2 + eps^2)^(3/2) of the comparison runs, Sec. 5.2)."""
     G, m1, m2, d = 1.7, 0.3, 2.5, 1.9
     u = np.array([0.48, -0.6, 0.64])
     d1 = {"x": np.array([0.1, 0.1 + d * u[0]]), "y": np.array([-0.2, -0.2 + d * u[1]]),
@@ -153,17 +153,17 @@ def test_grad_momentum_balance():
 
 
 # --------------------------------------------------------------------------------------------
-# Pairwise time-steps (Sec. 3, Eqs. dt-freefall, dt-flyby)
+# Pairwise time-steps (Sec. 3.5.3, Eqs. dt-freefall, dt-flyby)
 # --------------------------------------------------------------------------------------------
 
 def test_dt_circular_binary_ff_equals_fb():
-    """The free-fall and fly-by criteria agree for a circular binary (Sec. 3)."""
+    """The free-fall and fly-by criteria agree for a circular binary (Sec. 3.5.3)."""
     d = _kepler.binary_state(0.6, 0.4, 0.8, 1e-12 + 0.0, G=1.0)
     # e -> 0 exactly: rebuild with a circular velocity
     P = Particles.from_dict(d)
     ff, fb = oracle.dt_min(P, G=1.0, eta_ff=1.0, eta_fb=1.0)
     np.testing.assert_allclose(ff, fb, rtol=1e-9)
-    # eccentric binary at periapsis: fly-by is the smaller one (Sec. 3)
+    # eccentric binary at periapsis: fly-by is the smaller one (Sec. 3.5.3)
     P = Particles.from_dict(_kepler.binary_state(0.6, 0.4, 0.8, 0.7, phase_E=0.0))
     ff, fb = oracle.dt_min(P, eta_ff=1.0, eta_fb=1.0)
     assert np.all(fb < ff)
@@ -192,7 +192,7 @@ def test_dt_minimum_over_sources_and_edge_cases():
 
 
 # --------------------------------------------------------------------------------------------
-# PN1.0 (Sec. 3, global PN1.0 term)
+# PN1.0 (Sec. 3.8, global PN1.0 term)
 # --------------------------------------------------------------------------------------------
 
 def _pn_energy(P, G, c):
@@ -271,7 +271,7 @@ def test_pn_circular_orbit_frequency():
 @pytest.mark.slow
 def test_pn_periapsis_advance():
     """FSI with PN1.0 half-kicks reproduces the periapsis advance 6 pi G M / (c^2 a (1 - e^2))
-    per orbit (Sec. 3, first term of Eq. secular_omega times the period)."""
+    per orbit (Sec. 3.10, first term of Eq. secular_omega times the period)."""
     m1, m2, a0, e0, G = 0.5, 0.5, 1.0, 0.5, 1.0
     c = 50.0
     d = _kepler.binary_state(m1, m2, a0, e0)
@@ -361,7 +361,7 @@ def test_fsi_kepler_fourth_order():
 
 
 def test_fsi_energy_error_fourth_order():
-    """Relative energy error ~ dt^4 (Sec. 5, Eq. fourthorder)."""
+    """Relative energy error ~ dt^4 (Sec. 5.1, Eq. fourthorder)."""
     d = _kepler.binary_state(0.5, 0.5, 1.0, 0.3)
     P0 = Particles.from_dict(d)
     E0 = sum(oracle.energy(P0))
@@ -410,7 +410,7 @@ def test_hhs_conserves_momentum():
 
 
 def test_hhs_fourth_order_energy():
-    """HHS-FSI with fixed levels stays fourth order (Sec. 2.2; Eq. fourthorder)."""
+    """HHS-FSI with fixed levels stays fourth order (Sec. 2.2; Sec. 5.1, Eq. fourthorder)."""
     d = _kepler.binary_state(0.5, 0.5, 0.2, 0.2)
     # a tight binary on the fast level inside a wide third body on the slow level
     d = {k: np.concatenate([v, [0.0]]) for k, v in d.items()}
