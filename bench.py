@@ -40,6 +40,133 @@ def synthetic_acc_field(d):
     return np.stack([-x * s, -y * s, -z * s], axis=1)
 
 
+def _pass_rate(ctx, bf, op, call, reps=3):
+    """Average pair-kernel duration (ms) of `call` over reps, from the context's HIP events."""
+    call()
+    ctx.enable_timing(True)
+    for _ in range(reps):
+        call()
+    t = ctx.kernel_times(op)
+    ctx.enable_timing(False)
+    return float(np.mean(t)) if t else float("nan")
+
+
+def run_workload(name, args):
+    """The remaining workloads: each prints one JSON line with its own rates."""
+    import torch
+
+    import oracle
+    import paper_2210_02472_amd as bf
+    from paper_2210_02472_amd import ics
+
+    ctx = bf.Context(0)
+    rec = {"workload": name, "n_gpus": 1, "data": "synthetic"}
+    if name == "plummer1k-fsi":
+        # N = 1024 equal-mass Plummer, eps = 0: one acceleration + gradient evaluation, then 10 FSI
+        # steps with dt = 1e-3 (FP64), energy logged every step
+        d = ics.config1_plummer1k()
+        P = bf.Particles.from_numpy(d)
+        a = ctx.forces(P, prec="fp64")
+        ctx.force_gradient(P, a, prec="fp64")
+        k0, u0 = ctx.energy(P)
+        energies = []
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for s in range(10):
+            a = ctx.fsi_step(P, 1e-3, prec="fp64", acc=a, acc_valid=s > 0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        k1, u1 = ctx.energy(P)
+        energies = [k0 + u0, k1 + u1]
+        rec.update({"ms_per_fsi_step": wall / 10 * 1e3, "E0": energies[0], "E10": energies[1],
+                    "rel_energy_drift_10_steps": abs(energies[1] / energies[0] - 1)})
+    elif name == "plummer64k-level":
+        # N = 65,536 Kroupa Plummer, a random 10% level, eps = 1e-4: acc + grad + dt_min of the level
+        # against all particles, mixed vs FP64
+        d, act = ics.config2_plummer64k()
+        P = bf.Particles.from_numpy(d)
+        T = torch.as_tensor(act, device="cuda")
+        n, nt = len(d["m"]), len(act)
+        pairs = float(nt) * n
+        out = {}
+        for prec in ("mixed", "fp64"):
+            a = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+            ta = _pass_rate(ctx, bf, bf.BF_OP_FORCES, lambda: ctx.forces(P, T, None, eps2=1e-8, prec=prec, r_fb=0.0,
+                                                                         out=a))
+            tg = _pass_rate(ctx, bf, bf.BF_OP_GRADIENT, lambda: ctx.force_gradient(P, a, T, None, eps2=1e-8, prec=prec,
+                                                                                   r_fb=0.0))
+            td = _pass_rate(ctx, bf, bf.BF_OP_DTMIN, lambda: ctx.dt_min(P, T, None, prec=prec, r_fb=1e-3))
+            out[prec] = {"acc_ms": ta, "grad_ms": tg, "dtmin_ms": td, "acc_grad_pairs_per_s": pairs / ((ta + tg) * 1e-3),
+                         "dtmin_pairs_per_s": pairs / (td * 1e-3)}
+        Po = oracle.Particles.from_dict(d)
+        sample = np.sort(np.random.default_rng(1).choice(act, 128, replace=False))
+        a = ctx.forces(P, T, None, eps2=1e-8, prec="mixed", r_fb=0.0)
+        ref = oracle.forces(Po, sample, None, eps2=1e-8)
+        got = np.stack([t.cpu().numpy()[sample] for t in a], axis=1)
+        e = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        rec.update({"n": n, "n_active": nt, "pairs_per_pass": pairs, "passes": out,
+                    "acc_rel_err_rms": float(np.sqrt(np.mean(e * e))), "acc_rel_err_max": float(e.max())})
+    elif name == "ensemble256":
+        # 256 equal-mass Plummer clusters, N log-uniform in [1024, 65536], active fractions 2^-k:
+        # one persistent batched launch per pass, and the HIP-graph captured batched FSI cycle
+        d, off, act, aoff = ics.config4_ensemble()
+        P = bf.Particles.from_numpy(d)
+        co, ai, ao = (torch.as_tensor(x, device="cuda") for x in (off, act, aoff))
+        sizes = np.diff(off)
+        nact = np.diff(aoff)
+        pairs = float(np.sum(sizes.astype(np.float64) * nact))
+        maxn = int(sizes.max())
+        ntot = int(off[-1])
+        res = {}
+        for prec in ("mixed", "fp64"):
+            a = ctx.forces_batched(P, co, ai, ao, int(aoff[-1]), maxn, prec=prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                ctx.forces_batched(P, co, ai, ao, int(aoff[-1]), maxn, prec=prec, out=a)
+            torch.cuda.synchronize()
+            tf = (time.perf_counter() - t) / 3
+            g = ctx.capture_batched_fsi(P, co, ai, ao, int(aoff[-1]), maxn, 1e-4, a, prec=prec)
+            g.launch()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                g.launch()
+            torch.cuda.synchronize()
+            tg = (time.perf_counter() - t) / 3
+            g.close()
+            res[prec] = {"forces_ms": tf * 1e3, "forces_pairs_per_s": pairs / tf,
+                         "fsi_cycle_graph_ms": tg * 1e3,
+                         "fsi_cycle_pairs_per_s": 3 * pairs / tg}  # 2 force passes + 1 gradient pass
+        rec.update({"clusters": len(sizes), "particles": ntot, "active": int(aoff[-1]), "active_pairs": pairs,
+                    "passes": res})
+    elif name == "bh-levels":
+        # N = 262,144 Kroupa Plummer with 16 BHs + 1000 Msun IMBH, levels 0..7 (2^-k at >= k):
+        # per level, acceleration + gradient of the level's particles from all particles (mixed)
+        # and PN1.0 for BH pairs (FP64, c = 1e4)
+        d, bh, lv = ics.config5_bh_cluster()
+        P = bf.Particles.from_numpy(d)
+        n = len(d["m"])
+        levels = []
+        for k in range(int(lv.max()) + 1):
+            idx = np.nonzero(lv >= k)[0].astype(np.int32)
+            T = torch.as_tensor(idx, device="cuda")
+            a = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+            ta = _pass_rate(ctx, bf, bf.BF_OP_FORCES, lambda: ctx.forces(P, T, None, prec="mixed", r_fb=0.0, out=a))
+            tg = _pass_rate(ctx, bf, bf.BF_OP_GRADIENT, lambda: ctx.force_gradient(P, a, T, None, prec="mixed",
+                                                                                   r_fb=0.0))
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.pn1_bh(P, bh, T, None, c=1e4)
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t
+            levels.append({"level": k, "n_active": int(idx.size), "acc_ms": ta, "grad_ms": tg, "pn1_ms": tp * 1e3,
+                           "acc_grad_pairs_per_s": idx.size * float(n) / ((ta + tg) * 1e-3)})
+        rec.update({"n": n, "n_bh": int(len(bh)), "levels": levels})
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,11 +179,20 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", type=int, default=256, help="targets sampled for the error check")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 2 GiB device-to-device copy kernel first (HBM counter calibration)")
+    ap.add_argument("--workload", default="king1m",
+                    choices=["king1m", "plummer1k-fsi", "plummer64k-level", "ensemble256", "bh-levels"],
+                    help="king1m (default): the headline sweep; the others measure the remaining "
+                         "workloads and print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is described, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "king1m":
+        run_workload(args.workload, args)
+        return
 
     import torch
 
@@ -71,6 +207,14 @@ def main():
     n = args.n
     log(f"generated King W0=6 N={n} in {time.time() - t0:.1f}s")
     P = bf.Particles.from_numpy(d, "cuda:0")
+    if args.calib_copy:
+        # a plain elementwise copy of known size (2 GiB read, 2 GiB written; larger than the
+        # 256 MB last-level cache): its FETCH_SIZE / WRITE_SIZE calibrate the HBM counters
+        src = torch.ones(256 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = bf.Context(0)
     out_a = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
     out_g = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]

@@ -186,6 +186,51 @@ typedef struct bf_fsi_params {
 BF_API int bf_fsi_step(bf_ctx *ctx, const bf_state *S, const bf_set *set, double dt,
                        const bf_fsi_params *prm, double *ax, double *ay, double *az, int flags);
 
+/* ---- time-step assignment and the HHS-FSI interval ----------------------------------- */
+
+/* Jerk (Sec. 3.5.5): j_i = sum_{j != i} G m_j / s^5 (s^2 v_ji - 3 (r_ji . v_ji) r_ji),
+ * v_ji = v_j - v_i; the same tidal contraction as bf_force_gradient with velocities in place of
+ * accelerations.  Writes jx/jy/jz[i] for every target i.  prec as in bf_forces. */
+BF_API int bf_jerk(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, const bf_set *sources,
+                   double G, double eps2, int prec, double *jx, double *jy, double *jz);
+
+/* Per-particle time-step of the set: the minimum of
+ *   dt_ff, dt_fb                                  (bf_dt_min, Sec. 3.5.3),
+ *   eta_grad (|v| / |g'|)^(1/3), eta_grad (|a| / |g'|)^(1/2), g' = Gsum / 24
+ *                                                 (Sec. 3.5.4, Eqs. dt-nabla1, dt-nabla2),
+ *   eta_jerk |a| / |j|                            (Sec. 3.5.5),
+ * where a criterion is skipped if its arrays are NULL (gx/gy/gz or jx/jy/jz), its eta <= 0 or its
+ * denominator is zero.  With level != NULL also writes the time-step level: the smallest k in
+ * [0, kmax] with dt >= tau / 2^k (slow on level k, Sec. 2.2), kmax if none.  All arrays are
+ * particle-indexed; only entries of the set are written. */
+BF_API int bf_timestep_assign(bf_ctx *ctx, const bf_particles *P, const bf_set *set,
+                              const double *dt_ff, const double *dt_fb,
+                              const double *ax, const double *ay, const double *az,
+                              const double *gx, const double *gy, const double *gz,
+                              const double *jx, const double *jy, const double *jz,
+                              double eta_grad, double eta_jerk, double tau, int kmax,
+                              double *dt, int32_t *level);
+
+/* Synchronising.  Stable partition of the particles of `set` by level (level: device int32,
+ * particle-indexed, values in [0, kmax]): order[0 .. set.count) receives the particle indices
+ * sorted by level (ties keep the set's order), counts[0 .. kmax] (host) the number per level.
+ * The fast set "level > k" is then the contiguous suffix of order after level k. */
+BF_API int bf_level_partition(bf_ctx *ctx, const bf_set *set, int64_t n, const int32_t *level, int kmax,
+                              int32_t *order, int64_t *counts);
+
+/* One HHS-FSI interval of length tau over `set` (Sec. 2.2, Eq. hhsfsi-cycle) with fixed
+ * per-particle levels (device int32, particle-indexed, in [0, kmax]).  On level k the slow set
+ * S holds the particles at level k and the fast set F those deeper:
+ *   kick tau/6 with the inter-level accelerations (S <- F, F <- S); FSI(S, tau/2);
+ *   HHS(F, tau/2); gradient kick 2 tau/3 with the inter-level accelerations and gradient sums;
+ *   HHS(F, tau/2); FSI(S, tau/2); kick tau/6.
+ * An empty F ends the recursion with one FSI cycle of S over tau; an empty S gives two half
+ * intervals of F.  Positions and velocities of S are updated in place (FP64).  The partition
+ * synchronises once; everything else is stream-ordered.  prm->n_bh must be 0 (PN1.0 is not part
+ * of this driver). */
+BF_API int bf_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, const int32_t *level,
+                           int kmax, double tau, const bf_fsi_params *prm);
+
 /* Elementwise kicks and drifts used by integrator drivers (FP64, over the set):
  *   bf_kick:  v_i += h (a_i + h2 g_i)   (g may be NULL, then h2 is ignored)
  *   bf_drift: x_i += h v_i                                              (Sec. 2.1) */
@@ -259,6 +304,13 @@ BF_API int bf_autotune(bf_ctx *ctx, int op, int prec, int64_t n_targets, int64_t
                        const char *cache_path);
 /* Load a tuning table written by bf_autotune. */
 BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
+
+/* Spatially sorted mode of the mixed acceleration and gradient passes (default on).  When on,
+ * and r_fb == 0, with at least 2048 sources and 512 targets, targets and sources are ordered
+ * along a Morton curve and packed into tiles; tiles far from a workgroup's targets are summed
+ * from FP32 offsets to the tile centre, near tiles from FP64 differences.  Results keep the
+ * accuracy of the unsorted mixed path; outputs stay particle-indexed. */
+BF_API int bf_set_spatial_sort(bf_ctx *ctx, int on);
 
 /* Kernel configuration the context would use for a pass (for reporting):
  * targets per lane, waves per workgroup, source split. */

@@ -181,6 +181,47 @@ def pn1(p: Particles, bh, targets=None, sources=None, G: float = 1.0, c: float =
     return np.stack([px, py, pz], axis=1)
 
 
+def jerk(p: Particles, targets=None, sources=None, G: float = 1.0, eps2: float = 0.0):
+    """Jerk j_i = sum_j G m_j / s^5 (s^2 v_ji - 3 (r_ji . v_ji) r_ji) (Sec. 3.5.5).  It is the
+    tidal tensor contracted with v_ji, i.e. the force-gradient sum of the C routine evaluated
+    with the velocities in place of the accelerations."""
+    return gradient(p, p.vel(), targets, sources, G, eps2)
+
+
+def timestep_criteria(p: Particles, idx, dt_ff, dt_fb, acc, gsum=None, jrk=None, eta_grad: float = 0.1,
+                      eta_jerk: float = 0.1):
+    """Per-particle time-step: the minimum of the pairwise criteria (Sec. 3.5.3) and of
+    eta_grad (|v|/|g'|)^(1/3), eta_grad (|a|/|g'|)^(1/2) with g' = Gsum/24 (Sec. 3.5.4, Eqs.
+    dt-nabla1, dt-nabla2) and eta_jerk |a|/|j| (Sec. 3.5.5).  All arrays are per listed particle
+    (row k belongs to particle idx[k]); a criterion with a zero denominator or eta <= 0 is skipped."""
+    idx = np.asarray(idx)
+    dt = np.minimum(np.asarray(dt_ff, float), np.asarray(dt_fb, float)).copy()
+    v = np.linalg.norm(p.vel()[idx], axis=1)
+    a = np.linalg.norm(np.asarray(acc), axis=1)
+    for k in range(idx.size):
+        if gsum is not None and eta_grad > 0:
+            g = np.linalg.norm(gsum[k]) / 24.0
+            if g > 0:
+                dt[k] = min(dt[k], eta_grad * np.cbrt(v[k] / g), eta_grad * np.sqrt(a[k] / g))
+        if jrk is not None and eta_jerk > 0:
+            jn = np.linalg.norm(jrk[k])
+            if jn > 0:
+                dt[k] = min(dt[k], eta_jerk * a[k] / jn)
+    return dt
+
+
+def levels_from_dt(dt, tau: float, kmax: int):
+    """Level of the power-of-two hierarchy: the smallest k in [0, kmax] with dt >= tau / 2^k
+    (a particle is slow on the level whose pivot its time-step reaches, Sec. 2.2)."""
+    out = np.full(np.shape(dt), kmax, dtype=np.int32)
+    for i, d in enumerate(np.asarray(dt)):
+        for k in range(kmax + 1):
+            if d >= tau / 2.0 ** k:
+                out[i] = k
+                break
+    return out
+
+
 def energy(p: Particles, subset=None, G: float = 1.0, eps2: float = 0.0):
     """(kinetic, potential) of a particle set (Sec. 2.1, the N-body Hamiltonian)."""
     _check(p)

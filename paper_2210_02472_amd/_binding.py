@@ -81,6 +81,11 @@ def load_library(path: str = LIB_PATH):
         "bf_energy": [_vp, P, S, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)],
         "bf_fsi_step": [_vp, ST, S, _d, FP, _vp, _vp, _vp, _int],
         "bf_kick": [_vp, ST, S, _d, _vp, _vp, _vp, _d, _vp, _vp, _vp],
+        "bf_jerk": [_vp, P, S, S, _d, _d, _int, _vp, _vp, _vp],
+        "bf_timestep_assign": [_vp, P, S, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _d, _int,
+                               _vp, _vp],
+        "bf_level_partition": [_vp, S, _i64, _vp, _int, _vp, ctypes.POINTER(_i64)],
+        "bf_hhs_interval": [_vp, ST, S, _vp, _int, _d, FP],
         "bf_drift": [_vp, ST, S, _d],
         "bf_forces_batched": [_vp, P, _i32, _vp, _vp, _vp, _i64, _i64, _d, _d, _int, _d, _vp, _vp, _vp],
         "bf_force_gradient_batched": [_vp, P, _i32, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _d, _d, _int, _d,
@@ -96,6 +101,7 @@ def load_library(path: str = LIB_PATH):
                             ctypes.POINTER(_int)],
         "bf_set_config": [_vp, _int, _int, _int, _int, _int],
         "bf_enable_timing": [_vp, _int],
+        "bf_set_spatial_sort": [_vp, _int],
         "bf_kernel_times": [_vp, _int, ctypes.POINTER(ctypes.c_float), _int, ctypes.POINTER(_int)],
     }
     for name, args in sig.items():
@@ -297,6 +303,47 @@ class Context:
                                                ctypes.byref(prm), *map(_ptr, a), BF_A_VALID if acc_valid else 0))
         return a
 
+    def jerk(self, P: Particles, targets=None, sources=None, G=1.0, eps2=0.0, prec="mixed",
+             out: Optional[Sequence[torch.Tensor]] = None):
+        """Jerks (particle-indexed jx, jy, jz)."""
+        t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
+        o = self._outs(P, out, 3)
+        _check("bf_jerk", _lib.bf_jerk(self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()),
+                                       float(G), float(eps2), PRECISIONS[prec], *map(_ptr, o)))
+        return o
+
+    def timestep_assign(self, P: Particles, subset, dt_ff, dt_fb, acc, grad=None, jerk=None, eta_grad=0.1,
+                        eta_jerk=0.1, tau=1.0, kmax=0, with_levels=True):
+        """Per-particle time-steps (minimum of the criteria) and levels; returns (dt, level)."""
+        s = ParticleSet.of(subset, P.n)
+        dt = torch.full((P.n,), float("nan"), dtype=torch.float64, device=P.m.device)
+        lv = torch.full((P.n,), -1, dtype=torch.int32, device=P.m.device) if with_levels else None
+        g = grad if grad is not None else (None, None, None)
+        j = jerk if jerk is not None else (None, None, None)
+        _check("bf_timestep_assign", _lib.bf_timestep_assign(
+            self._h, ctypes.byref(P._c()), ctypes.byref(s._c()), _ptr(dt_ff), _ptr(dt_fb), *map(_ptr, acc),
+            *map(_ptr, g), *map(_ptr, j), float(eta_grad), float(eta_jerk), float(tau), int(kmax), _ptr(dt), _ptr(lv)))
+        return dt, lv
+
+    def level_partition(self, subset, n: int, level: torch.Tensor, kmax: int):
+        """Stable partition by level: (order int32 tensor, counts list)."""
+        s = ParticleSet.of(subset, n)
+        _need(level, torch.int32, n, "level")
+        order = torch.empty(max(s.count, 1), dtype=torch.int32, device=level.device)
+        counts = (_i64 * (kmax + 1))()
+        _check("bf_level_partition", _lib.bf_level_partition(self._h, ctypes.byref(s._c()), int(n), _ptr(level),
+                                                             int(kmax), _ptr(order), counts))
+        return order[:s.count], [int(counts[k]) for k in range(kmax + 1)]
+
+    def hhs_interval(self, P: Particles, level: torch.Tensor, kmax: int, tau: float, subset=None, G=1.0, eps2=0.0,
+                     prec="mixed", r_fb=0.0):
+        """One HHS-FSI interval with fixed levels, in place."""
+        s = ParticleSet.of(subset, P.n)
+        _need(level, torch.int32, P.n, "level")
+        prm = _FsiParams(float(G), float(eps2), PRECISIONS[prec], float(r_fb), None, 0, 1.0)
+        _check("bf_hhs_interval", _lib.bf_hhs_interval(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()),
+                                                       _ptr(level), int(kmax), float(tau), ctypes.byref(prm)))
+
     def kick(self, P: Particles, subset, h, acc, h2=0.0, grad=None):
         s = ParticleSet.of(subset, P.n)
         g = grad if grad is not None else (None, None, None)
@@ -367,6 +414,9 @@ class Context:
         _check("bf_query_config", _lib.bf_query_config(self._h, op, PRECISIONS[prec], int(n_targets), int(n_sources),
                                                        ctypes.byref(k), ctypes.byref(w), ctypes.byref(s)))
         return k.value, w.value, s.value
+
+    def set_spatial_sort(self, on: bool = True):
+        _check("bf_set_spatial_sort", _lib.bf_set_spatial_sort(self._h, int(on)))
 
     def enable_timing(self, on: bool = True):
         _check("bf_enable_timing", _lib.bf_enable_timing(self._h, int(on)))

@@ -15,8 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(ROOT, "_build")
-LIB = os.path.join(HERE, "libbifrost_hip.so")
+BUILD = os.environ.get("BF_BUILD_DIR") or os.path.join(ROOT, "_build")
+LIB = os.environ.get("BF_LIB_OUT") or os.path.join(HERE, "libbifrost_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

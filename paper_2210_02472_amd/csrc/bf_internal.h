@@ -45,6 +45,9 @@ struct PairArgs {
     double* part;     // [split][ncomp][tgt.count] partial results when split > 1
     double *o0, *o1, *o2;  // particle-indexed outputs when split == 1
     double eta0, eta1;     // dt_min: eta_ff, eta_fb
+    const void* pack_far;     // spatially sorted mode: FP32 tile-relative source stream
+    const double4* tile_meta; // spatially sorted mode: per tile (centre, extent) [, (a centre, 0)]
+    float kappa;              // spatially sorted mode: a tile is near when gap < kappa * extent
     double cond_max;       // mixed acc/grad: FP64 fix-up when magnitude estimate > cond_max |result|
     int32_t* fix_list;     // [tgt.count] target slots queued for the FP64 fix-up
     int32_t* fix_count;    // number of queued slots
@@ -76,6 +79,51 @@ hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_zero_count(int32_t* c, hipStream_t st);
 hipError_t launch_fixup(int op, const PairArgs& a, int nblocks, hipStream_t st);
+
+// Spatially sorted mixed acc/grad (spatial.hip).
+struct SortBuffers {
+    uint32_t* bbox;      // 6 ordered-uint words: min x, y, z then max x, y, z
+    uint32_t* keys_in;   // [n]
+    uint32_t* keys_out;  // [n]
+    int32_t* vals_in;    // [n]
+    int32_t* vals_out;   // [n]
+    void* tmp;           // radix-sort temporary storage
+    size_t tmp_bytes;
+};
+// bytes of radix-sort temporary storage for n keys
+size_t sort_tmp_bytes(int n);
+// sort the particles of `set` along a Morton curve over the box of `box_set`; writes the sorted
+// particle list to out[0..set.count)
+hipError_t launch_sort_set(const Masters& P, const DevSet& set, const DevSet& box_set, const SortBuffers& sb,
+                           int32_t* out, uint32_t* flags, hipStream_t st);
+// pack sorted sources into tiles of 64*waves: near (FP64) stream, far (FP32 tile-relative)
+// stream and tile metadata
+hipError_t launch_pack_tiles(int op, int waves, const PairArgs& a, void* near_pack, void* far_pack,
+                             double4* meta, hipStream_t st);
+// launch the spatially sorted pair kernel
+hipError_t launch_pairs_sorted(int op, const KernelConfig& cfg, const PairArgs& a, int nblocks, hipStream_t st);
+bool sorted_variant_exists(int op, int k, int waves);
+int sorted_blocks_per_cu(int op, int k, int waves);
+
+// time-step assignment epilogue (timestep.hip)
+struct TimestepArgs {
+    Masters P;
+    DevSet set;
+    const double *dt_ff, *dt_fb;            // pairwise criteria (particle-indexed)
+    const double *ax, *ay, *az;             // accelerations
+    const double *gx, *gy, *gz;             // force-gradient sums (NULL: no gradient criteria)
+    const double *jx, *jy, *jz;             // jerks (NULL: no jerk criterion)
+    double eta_grad, eta_jerk, tau;
+    int kmax;
+    double* dt;                             // out: time-step
+    int32_t* level;                         // out: level (NULL: not assigned)
+    uint32_t* flags;
+};
+hipError_t launch_timestep(const TimestepArgs& t, hipStream_t st);
+size_t level_sort_tmp_bytes(int n);
+hipError_t launch_level_partition(const DevSet& set, int64_t n, const int32_t* level, int kmax, uint32_t* keys_in,
+                                  uint32_t* keys_out, int32_t* vals_in, int32_t* out_order, int32_t* counts,
+                                  void* tmp, size_t tmp_bytes, uint32_t* flags, hipStream_t st);
 
 // Mixed acc/grad: a target is re-evaluated in FP64 when its magnitude estimate exceeds
 // kCondMax times the norm of its result.
@@ -132,6 +180,13 @@ struct bf_ctx {
     size_t scratch3_bytes = 0;
     void* scratch4 = nullptr;         // batched partials, work-item offsets, queue counter
     size_t scratch4_bytes = 0;
+    void* scratch5 = nullptr;         // spatial sort: box, keys, values, sorted lists, sort temporaries
+    size_t scratch5_bytes = 0;
+    void* scratch6 = nullptr;         // spatial sort: far (FP32 tile-relative) stream and tile metadata
+    size_t scratch6_bytes = 0;
+    void* scratch7 = nullptr;         // HHS driver: level order and inter-level / FSI arrays
+    size_t scratch7_bytes = 0;
+    bool spatial_sort = true;         // use the spatially sorted mixed acc/grad kernels when large enough
     // kernel timing: event pairs around pair-kernel launches, per op
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[bf::OP_COUNT];

@@ -102,7 +102,16 @@ struct Plan {
     int split = 1, chunk = 0, nblocks = 0;
 };
 
-int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p) {
+// Spatially sorted mode: mixed acceleration / gradient passes on large enough sets.
+constexpr int64_t kSortMinSources = 2048, kSortMinTargets = 512;
+constexpr float kKappa = 3.0f;  // a tile is near a workgroup when their gap < kKappa * tile half-extent
+
+bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb) {
+    return ctx->spatial_sort && prec == BF_PREC_MIXED && (op == OP_ACC || op == OP_GRAD) && r_fb == 0.0 &&
+           ns >= kSortMinSources && nt >= kSortMinTargets;
+}
+
+int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool sorted = false) {
     KernelConfig c = ctx->forced[op][prec];
     if (c.k == 0) {
         auto it = ctx->tuned.find(std::make_tuple(op, prec, ilog2_bucket(nt), ilog2_bucket(ns)));
@@ -117,13 +126,15 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p) {
     const int64_t ntiles = std::max<int64_t>(1, (ns + T - 1) / T);
     int64_t split = c.split;
     if (split <= 0) {
-        int bpc = variant_blocks_per_cu(op, prec, c.k, c.waves);
+        int bpc = sorted ? sorted_blocks_per_cu(op, c.k, c.waves) : variant_blocks_per_cu(op, prec, c.k, c.waves);
         if (bpc <= 0) bpc = 1;
         const int64_t resident = (int64_t)ctx->num_cu * bpc;
-        // aim for at least four full rounds of resident workgroups
+        // At least four full rounds of resident workgroups.  The split is a multiple of the 8 XCDs
+        // whenever there is enough work, so that (with round-robin dispatch) every workgroup on
+        // one XCD streams the same source chunk and the chunk is served from that XCD's L2.
         const int64_t want = 4 * resident;
-        split = nslabs >= want ? 1 : (want + nslabs - 1) / nslabs;
-        if (split > 8) split = (split + 7) / 8 * 8;  // keep chunks aligned with the 8 XCDs
+        split = (want + nslabs - 1) / nslabs;
+        split = std::max<int64_t>(8, (split + 7) / 8 * 8);
     }
     split = std::min<int64_t>(split, ntiles);
     split = std::max<int64_t>(split, 1);
@@ -142,9 +153,12 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p) {
 int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg, const bf_set* sr, double G, double eps2,
               double r_fb, double eta0, double eta1, double* o0, double* o1, double* o2) {
     if (tg->count == 0) return BF_OK;
+    const bool sorted = use_sorted(ctx, op, prec, tg->count, sr->count, r_fb);
     Plan p;
-    int rc = plan(ctx, op, prec, tg->count, sr->count, p);
+    int rc = plan(ctx, op, prec, tg->count, sr->count, p, sorted);
     if (rc) return rc;
+    if (sorted && !sorted_variant_exists(op, p.cfg.k, p.cfg.waves))
+        return fail(BF_ERR_UNSUPPORTED, "no sorted kernel variant for this configuration");
     PairArgs a{};
     a.P = M;
     a.tgt = devset(tg);
@@ -172,7 +186,47 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     a.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + 256);
     if (p.split > 1) a.part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + head);
     if (fix) BF_HIP(launch_zero_count(a.fix_count, ctx->stream));
-    if (sr->count > 0) {
+    if (sorted) {
+        // order targets and sources along a Morton curve, then pack the sorted sources into tiles
+        const int64_t nt = tg->count, ns = sr->count, nmax = std::max(nt, ns);
+        const size_t tmp = sort_tmp_bytes((int)nmax);
+        const size_t list_bytes = ((size_t)nmax * 4 + 255) & ~size_t(255);
+        const size_t need5 = 256 + 4 * list_bytes + 2 * list_bytes + ((tmp + 255) & ~size_t(255));
+        rc = ensure(&ctx->scratch5, &ctx->scratch5_bytes, need5, ctx->stream);
+        if (rc) return rc;
+        char* b5 = static_cast<char*>(ctx->scratch5);
+        SortBuffers sb;
+        sb.bbox = reinterpret_cast<uint32_t*>(b5);
+        sb.keys_in = reinterpret_cast<uint32_t*>(b5 + 256);
+        sb.keys_out = reinterpret_cast<uint32_t*>(b5 + 256 + list_bytes);
+        sb.vals_in = reinterpret_cast<int32_t*>(b5 + 256 + 2 * list_bytes);
+        sb.vals_out = reinterpret_cast<int32_t*>(b5 + 256 + 3 * list_bytes);
+        int32_t* src_sorted = reinterpret_cast<int32_t*>(b5 + 256 + 4 * list_bytes);
+        int32_t* tgt_sorted = reinterpret_cast<int32_t*>(b5 + 256 + 5 * list_bytes);
+        sb.tmp = b5 + 256 + 6 * list_bytes;
+        sb.tmp_bytes = tmp;
+        const DevSet ds = devset(sr), dt = devset(tg);
+        BF_HIP(launch_sort_set(M, ds, ds, sb, src_sorted, ctx->d_flags, ctx->stream));
+        const bool same = tg->idx == sr->idx && tg->count == sr->count && tg->begin == sr->begin;
+        if (!same) BF_HIP(launch_sort_set(M, dt, ds, sb, tgt_sorted, ctx->d_flags, ctx->stream));
+        a.src = DevSet{src_sorted, (int32_t)ns, 0};
+        a.tgt = DevSet{same ? src_sorted : tgt_sorted, (int32_t)nt, 0};
+        const int T = 64 * p.cfg.waves;
+        const int64_t ntiles = (ns + T - 1) / T;
+        const int kmeta = op == OP_GRAD ? 2 : 1;
+        rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)ns * pack_bytes(op, prec), ctx->stream);
+        if (rc) return rc;
+        const size_t far_bytes = (((size_t)ns * (op == OP_GRAD ? 32 : 16)) + 255) & ~size_t(255);
+        rc = ensure(&ctx->scratch6, &ctx->scratch6_bytes, far_bytes + (size_t)ntiles * kmeta * sizeof(double4),
+                    ctx->stream);
+        if (rc) return rc;
+        a.pack = ctx->scratch2;
+        a.pack_far = ctx->scratch6;
+        a.tile_meta = reinterpret_cast<const double4*>(static_cast<char*>(ctx->scratch6) + far_bytes);
+        a.kappa = kKappa;
+        BF_HIP(launch_pack_tiles(op, p.cfg.waves, a, ctx->scratch2, ctx->scratch6,
+                                 reinterpret_cast<double4*>(static_cast<char*>(ctx->scratch6) + far_bytes), ctx->stream));
+    } else if (sr->count > 0) {
         rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)sr->count * pack_bytes(op, prec), ctx->stream);
         if (rc) return rc;
         a.pack = ctx->scratch2;
@@ -189,7 +243,8 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         }
         BF_HIP(hipEventRecord(ev.first, ctx->stream));
     }
-    BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
+    if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
+    else BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
     if (ctx->timing) {
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
@@ -310,6 +365,9 @@ BF_API int bf_destroy(bf_ctx* c) {
     if (c->scratch2) hipFree(c->scratch2);
     if (c->scratch3) hipFree(c->scratch3);
     if (c->scratch4) hipFree(c->scratch4);
+    if (c->scratch5) hipFree(c->scratch5);
+    if (c->scratch6) hipFree(c->scratch6);
+    if (c->scratch7) hipFree(c->scratch7);
     if (c->d_flags) hipFree(c->d_flags);
     if (c->h_flags) hipHostFree(c->h_flags);
     delete c;
@@ -525,27 +583,22 @@ BF_API int bf_drift(bf_ctx* c, const bf_state* S, const bf_set* set, double h) {
     return BF_OK;
 }
 
-BF_API int bf_fsi_step(bf_ctx* c, const bf_state* S, const bf_set* set, double dt, const bf_fsi_params* prm, double* ax,
-                       double* ay, double* az, int flags) {
-    g_err.clear();
-    if (int rc = check_ctx(c)) return rc;
-    if (int rc = check_state(S)) return rc;
-    if (int rc = check_set(set, S->n, "fsi")) return rc;
+static int check_fsi_params(const bf_fsi_params* prm) {
     if (!prm) return fail(BF_ERR_ARG, "params NULL");
     if (int rc = check_prec(prm->prec)) return rc;
-    if (!isfinite(dt)) return fail(BF_ERR_ARG, "dt not finite");
     if (!isfinite(prm->G) || !finite_nonneg(prm->eps2) || !finite_nonneg(prm->r_fb))
         return fail(BF_ERR_ARG, "bad G, eps2 or r_fb");
     if (prm->n_bh < 0 || (prm->n_bh > 0 && (!prm->bh_idx || !(isfinite(prm->c) && prm->c > 0))))
         return fail(BF_ERR_ARG, "bad PN parameters");
-    if (!ax || !ay || !az) return fail(BF_ERR_ARG, "acceleration pointer NULL");
-    if (set->count == 0) return BF_OK;
+    return BF_OK;
+}
 
+// One FSI cycle (Sec. 2.1, Eq. fsi-cycle) over `set`, optionally wrapped in PN1.0 half-kicks;
+// g* is scratch for the gradient sums (and the PN accelerations), particle-indexed.
+static int fsi_impl(bf_ctx* c, const bf_state* S, const bf_set* set, double dt, const bf_fsi_params* prm, double* ax,
+                    double* ay, double* az, int flags, double* gx, double* gy, double* gz) {
+    if (set->count == 0) return BF_OK;
     const int64_t n = S->n;
-    if (int rc = ensure(&c->scratch3, &c->scratch3_bytes, (size_t)3 * n * sizeof(double), c->stream)) return rc;
-    double* gx = static_cast<double*>(c->scratch3);
-    double* gy = gx + n;
-    double* gz = gy + n;
     bf_particles P{S->x, S->y, S->z, S->vx, S->vy, S->vz, S->m, n};
     const Masters M = masters_of(&P);
     const DevSet ds = devset(set);
@@ -578,7 +631,209 @@ BF_API int bf_fsi_step(bf_ctx* c, const bf_state* S, const bf_set* set, double d
     return BF_OK;
 }
 
+BF_API int bf_fsi_step(bf_ctx* c, const bf_state* S, const bf_set* set, double dt, const bf_fsi_params* prm, double* ax,
+                       double* ay, double* az, int flags) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_state(S)) return rc;
+    if (int rc = check_set(set, S->n, "fsi")) return rc;
+    if (int rc = check_fsi_params(prm)) return rc;
+    if (!isfinite(dt)) return fail(BF_ERR_ARG, "dt not finite");
+    if (!ax || !ay || !az) return fail(BF_ERR_ARG, "acceleration pointer NULL");
+    if (set->count == 0) return BF_OK;
+    const int64_t n = S->n;
+    if (int rc = ensure(&c->scratch3, &c->scratch3_bytes, (size_t)3 * n * sizeof(double), c->stream)) return rc;
+    double* g = static_cast<double*>(c->scratch3);
+    return fsi_impl(c, S, set, dt, prm, ax, ay, az, flags, g, g + n, g + 2 * n);
+}
+
+// ---- time-step assignment, level partition, HHS-FSI interval ------------------------------------
+
+BF_API int bf_jerk(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf_set* s, double G, double eps2, int prec,
+                   double* jx, double* jy, double* jz) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, true)) return rc;
+    if (int rc = check_set(t, P->n, "target")) return rc;
+    if (int rc = check_set(s, P->n, "source")) return rc;
+    if (int rc = check_prec(prec)) return rc;
+    if (!isfinite(G)) return fail(BF_ERR_ARG, "G not finite");
+    if (!finite_nonneg(eps2)) return fail(BF_ERR_ARG, "eps2 must be finite and >= 0");
+    if (!jx || !jy || !jz) return fail(BF_ERR_ARG, "output pointer NULL");
+    // the jerk is the tidal contraction of the gradient pass with velocities in place of accelerations
+    Masters M = masters_of(P);
+    M.ax = P->vx; M.ay = P->vy; M.az = P->vz;
+    return run_pairs(c, OP_GRAD, prec, M, t, s, G, eps2, 0.0, 0, 0, jx, jy, jz);
+}
+
+BF_API int bf_timestep_assign(bf_ctx* c, const bf_particles* P, const bf_set* set, const double* dt_ff,
+                              const double* dt_fb, const double* ax, const double* ay, const double* az,
+                              const double* gx, const double* gy, const double* gz, const double* jx, const double* jy,
+                              const double* jz, double eta_grad, double eta_jerk, double tau, int kmax, double* dt,
+                              int32_t* level) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, true)) return rc;
+    if (int rc = check_set(set, P->n, "timestep")) return rc;
+    if (!dt_ff || !dt_fb || !ax || !ay || !az || !dt) return fail(BF_ERR_ARG, "array pointer NULL");
+    if ((gx || gy || gz) && !(gx && gy && gz)) return fail(BF_ERR_ARG, "gradient pointers must be all NULL or all set");
+    if ((jx || jy || jz) && !(jx && jy && jz)) return fail(BF_ERR_ARG, "jerk pointers must be all NULL or all set");
+    if (!isfinite(eta_grad) || !isfinite(eta_jerk)) return fail(BF_ERR_ARG, "eta not finite");
+    if (!(isfinite(tau) && tau > 0)) return fail(BF_ERR_ARG, "tau must be finite and > 0");
+    if (kmax < 0 || kmax > 63) return fail(BF_ERR_ARG, "kmax must be in [0, 63]");
+    TimestepArgs t{};
+    t.P = masters_of(P);
+    t.set = devset(set);
+    t.dt_ff = dt_ff; t.dt_fb = dt_fb;
+    t.ax = ax; t.ay = ay; t.az = az;
+    t.gx = gx; t.gy = gy; t.gz = gz;
+    t.jx = jx; t.jy = jy; t.jz = jz;
+    t.eta_grad = eta_grad; t.eta_jerk = eta_jerk; t.tau = tau; t.kmax = kmax;
+    t.dt = dt; t.level = level;
+    t.flags = c->d_flags;
+    BF_HIP(launch_timestep(t, c->stream));
+    return BF_OK;
+}
+
+// stable partition of a set by level into `order`; level counts copied to the host (synchronising)
+static int partition_impl(bf_ctx* c, const bf_set* set, int64_t n, const int32_t* level, int kmax, int32_t* order,
+                          int64_t* counts_host) {
+    const int cnt = set->count;
+    const size_t lb = ((size_t)std::max(cnt, 1) * 4 + 255) & ~size_t(255);
+    const size_t tmp = level_sort_tmp_bytes(std::max(cnt, 1));
+    if (int rc = ensure(&c->scratch5, &c->scratch5_bytes, 256 + 3 * lb + tmp, c->stream)) return rc;
+    char* b = static_cast<char*>(c->scratch5);
+    int32_t* counts = reinterpret_cast<int32_t*>(b);
+    uint32_t* kin = reinterpret_cast<uint32_t*>(b + 256);
+    uint32_t* kout = reinterpret_cast<uint32_t*>(b + 256 + lb);
+    int32_t* vin = reinterpret_cast<int32_t*>(b + 256 + 2 * lb);
+    BF_HIP(launch_level_partition(devset(set), n, level, kmax, kin, kout, vin, order, counts, b + 256 + 3 * lb, tmp,
+                                  c->d_flags, c->stream));
+    int32_t h[64];
+    BF_HIP(hipMemcpyAsync(h, counts, sizeof(int32_t) * (kmax + 1), hipMemcpyDeviceToHost, c->stream));
+    BF_HIP(hipStreamSynchronize(c->stream));
+    for (int k = 0; k <= kmax; ++k) counts_host[k] = h[k];
+    return BF_OK;
+}
+
+BF_API int bf_level_partition(bf_ctx* c, const bf_set* set, int64_t n, const int32_t* level, int kmax, int32_t* order,
+                              int64_t* counts) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (n <= 0 || n > INT32_MAX) return fail(BF_ERR_ARG, "n must be in [1, 2^31)");
+    if (int rc = check_set(set, n, "partition")) return rc;
+    if (!level || !order || !counts) return fail(BF_ERR_ARG, "array pointer NULL");
+    if (kmax < 0 || kmax > 63) return fail(BF_ERR_ARG, "kmax must be in [0, 63]");
+    return partition_impl(c, set, n, level, kmax, order, counts);
+}
+
+namespace {
+
+struct HhsCtx {
+    bf_ctx* c;
+    const bf_state* S;
+    const bf_fsi_params* prm;
+    Masters M;
+    const int32_t* order;
+    int64_t begin[65];  // begin[k] = first position of level k in `order`; begin[kmax+1] = total
+    int kmax;
+    double *asf, *gsf, *afsi, *gfsi;  // each 3n
+};
+
+bf_set segment(const HhsCtx& h, int64_t b, int64_t e) { return bf_set{h.order + b, (int32_t)(e - b), 0}; }
+
+// inter-level accelerations (Sec. 2.2): S <- F and F <- S into asf
+int interlevel_acc(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset) {
+    const int64_t n = h.S->n;
+    const bf_fsi_params* p = h.prm;
+    if (int rc = run_pairs(h.c, OP_ACC, p->prec, h.M, &Sset, &Fset, p->G, p->eps2, p->r_fb, 0, 0, h.asf, h.asf + n,
+                           h.asf + 2 * n))
+        return rc;
+    return run_pairs(h.c, OP_ACC, p->prec, h.M, &Fset, &Sset, p->G, p->eps2, p->r_fb, 0, 0, h.asf, h.asf + n,
+                     h.asf + 2 * n);
+}
+
+int hhs_rec(const HhsCtx& h, int k, double tau) {
+    const int64_t n = h.S->n, total = h.begin[h.kmax + 1];
+    const int64_t sb = h.begin[k], fb = k < h.kmax ? h.begin[k + 1] : total;
+    const bf_set Sset = segment(h, sb, fb), Fset = segment(h, fb, total), Bset = segment(h, sb, total);
+    bf_ctx* c = h.c;
+    const bf_fsi_params* p = h.prm;
+    auto fsi = [&](double dt) {
+        return fsi_impl(c, h.S, &Sset, dt, p, h.afsi, h.afsi + n, h.afsi + 2 * n, 0, h.gfsi, h.gfsi + n, h.gfsi + 2 * n);
+    };
+    if (Fset.count == 0) return Sset.count ? fsi(tau) : BF_OK;  // no split at the last level
+    if (Sset.count == 0) {
+        if (int rc = hhs_rec(h, k + 1, 0.5 * tau)) return rc;
+        return hhs_rec(h, k + 1, 0.5 * tau);
+    }
+    const DevSet dB = devset(&Bset);
+    const double* nul = nullptr;
+    int rc;
+    if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
+    BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
+    if ((rc = fsi(0.5 * tau))) return rc;
+    if ((rc = hhs_rec(h, k + 1, 0.5 * tau))) return rc;
+    if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
+    Masters Mg = h.M;
+    Mg.ax = h.asf; Mg.ay = h.asf + n; Mg.az = h.asf + 2 * n;
+    if ((rc = run_pairs(c, OP_GRAD, p->prec, Mg, &Sset, &Fset, p->G, p->eps2, p->r_fb, 0, 0, h.gsf, h.gsf + n,
+                        h.gsf + 2 * n)))
+        return rc;
+    if ((rc = run_pairs(c, OP_GRAD, p->prec, Mg, &Fset, &Sset, p->G, p->eps2, p->r_fb, 0, 0, h.gsf, h.gsf + n,
+                        h.gsf + 2 * n)))
+        return rc;
+    BF_HIP(launch_kick(*h.S, dB, 2.0 * tau / 3.0, h.asf, h.asf + n, h.asf + 2 * n, tau * tau / 24.0, h.gsf, h.gsf + n,
+                       h.gsf + 2 * n, c->d_flags, c->stream));
+    if ((rc = hhs_rec(h, k + 1, 0.5 * tau))) return rc;
+    if ((rc = fsi(0.5 * tau))) return rc;
+    if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
+    BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
+    return BF_OK;
+}
+
+}  // namespace
+
+BF_API int bf_hhs_interval(bf_ctx* c, const bf_state* S, const bf_set* set, const int32_t* level, int kmax, double tau,
+                           const bf_fsi_params* prm) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_state(S)) return rc;
+    if (int rc = check_set(set, S->n, "hhs")) return rc;
+    if (int rc = check_fsi_params(prm)) return rc;
+    if (prm->n_bh != 0) return fail(BF_ERR_UNSUPPORTED, "the HHS driver runs without PN1.0 (n_bh must be 0)");
+    if (!level) return fail(BF_ERR_ARG, "level NULL");
+    if (kmax < 0 || kmax > 63) return fail(BF_ERR_ARG, "kmax must be in [0, 63]");
+    if (!(isfinite(tau) && tau > 0)) return fail(BF_ERR_ARG, "tau must be finite and > 0");
+    if (set->count == 0) return BF_OK;
+    const int64_t n = S->n;
+    const size_t ob = ((size_t)set->count * 4 + 255) & ~size_t(255);
+    if (int rc = ensure(&c->scratch7, &c->scratch7_bytes, ob + (size_t)12 * n * sizeof(double), c->stream)) return rc;
+    HhsCtx h;
+    h.c = c;
+    h.S = S;
+    h.prm = prm;
+    bf_particles P{S->x, S->y, S->z, S->vx, S->vy, S->vz, S->m, n};
+    h.M = masters_of(&P);
+    int32_t* order = static_cast<int32_t*>(c->scratch7);
+    double* d = reinterpret_cast<double*>(static_cast<char*>(c->scratch7) + ob);
+    h.asf = d; h.gsf = d + 3 * n; h.afsi = d + 6 * n; h.gfsi = d + 9 * n;
+    h.order = order;
+    h.kmax = kmax;
+    int64_t counts[64];
+    if (int rc = partition_impl(c, set, n, level, kmax, order, counts)) return rc;
+    h.begin[0] = 0;
+    for (int k = 0; k <= kmax; ++k) h.begin[k + 1] = h.begin[k] + counts[k];
+    return hhs_rec(h, 0, tau);
+}
+
 // ---- configuration, tuning -------------------------------------------------------------------
+
+BF_API int bf_set_spatial_sort(bf_ctx* c, int on) {
+    if (int rc = check_ctx(c)) return rc;
+    c->spatial_sort = on != 0;
+    return BF_OK;
+}
 
 BF_API int bf_query_config(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, int* k, int* waves, int* split) {
     if (int rc = check_ctx(c)) return rc;

@@ -321,6 +321,173 @@ struct Dt64 {
     __device__ static void comps(const A64& o, double* v) { v[0] = o.ff; v[1] = o.fb; }
 };
 
+// ---- far-tile operations of the spatially sorted mode ----------------------------------------
+// Sources of a tile are stored as FP32 offsets from the tile centre c (rounded once from FP64);
+// a lane forms its target's offset from the same centre once per tile.  For a pair in a tile
+// whose gap to every target of the workgroup is at least kappa times the tile half-extent h,
+// the rounding error of dx is at most u (|x_j - c| + |x_i - c|) <= u (r + 2 sqrt(3) h), i.e.
+// relative error u (1 + 2 sqrt(3) / kappa): the FP64 differences are only needed for near tiles.
+
+struct AccRel {
+    struct Src { float4 p; };             // (x - cx, y - cy, z - cz, G m)
+    struct Tgt { float x, y, z; };
+    using A32 = AccMixed::A32;
+    __device__ static Src load(const PairArgs& a, int q) { return {static_cast<const float4*>(a.pack_far)[q]}; }
+    __device__ static void rel(Tgt& t, const AccMixed::Tgt& g, const double4& c, const double4&) {
+        t.x = (float)(g.x - c.x); t.y = (float)(g.y - c.y); t.z = (float)(g.z - c.z);
+    }
+    __device__ static void pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
+        const float dx = s.p.x - t.x, dy = s.p.y - t.y, dz = s.p.z - t.z;
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+        const float ri = rsqrt32(r2);
+        const float ri2 = ri * ri;
+        const float w = (s.p.w * ri) * ri2;
+        r.x = __builtin_fmaf(w, dx, r.x);
+        r.y = __builtin_fmaf(w, dy, r.y);
+        r.z = __builtin_fmaf(w, dz, r.z);
+        r.m = __builtin_fmaf(w, max3abs(dx, dy, dz), r.m);
+    }
+};
+
+struct GradRel {
+    struct Src { float4 p, a; };          // (x - cx, ..., G m), (ax - acx, ay - acy, az - acz, 0)
+    struct Tgt { float x, y, z, ax, ay, az; };
+    using A32 = GradMixed::A32;
+    __device__ static Src load(const PairArgs& a, int q) {
+        const float4* pk = static_cast<const float4*>(a.pack_far);
+        return {pk[2 * q], pk[2 * q + 1]};
+    }
+    __device__ static void rel(Tgt& t, const GradMixed::Tgt& g, const double4& c, const double4& ca) {
+        t.x = (float)(g.x - c.x); t.y = (float)(g.y - c.y); t.z = (float)(g.z - c.z);
+        t.ax = (float)(g.ax - ca.x); t.ay = (float)(g.ay - ca.y); t.az = (float)(g.az - ca.z);
+    }
+    __device__ static void pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
+        const float dx = s.p.x - t.x, dy = s.p.y - t.y, dz = s.p.z - t.z;
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+        const float ri = rsqrt32(r2);
+        const float ri2 = ri * ri;
+        const float dax = s.a.x - t.ax, day = s.a.y - t.ay, daz = s.a.z - t.az;
+        const float q = __builtin_fmaf(dax, dx, __builtin_fmaf(day, dy, daz * dz));
+        const float w = (s.p.w * ri) * ri2;
+        const float w5 = (w * q) * ri2;
+        r.x = __builtin_fmaf(w, dax, r.x);
+        r.y = __builtin_fmaf(w, day, r.y);
+        r.z = __builtin_fmaf(w, daz, r.z);
+        r.u = __builtin_fmaf(w5, dx, r.u);
+        r.v = __builtin_fmaf(w5, dy, r.v);
+        r.w = __builtin_fmaf(w5, dz, r.w);
+        r.m = __builtin_fmaf(w, max3abs(dax, day, daz), r.m);
+    }
+};
+
+template <class Near> struct FarOf;
+template <> struct FarOf<AccMixed> { using type = AccRel; static constexpr int kMeta = 1; };
+template <> struct FarOf<GradMixed> { using type = GradRel; static constexpr int kMeta = 2; };
+
+// workgroup-wide min/max of the K targets of every lane (FP32 box)
+template <int W>
+__device__ __forceinline__ void block_box(float lo[3], float hi[3], float* sbox /* [2][3][W] */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fminf(lo[d], __shfl_xor(lo[d], off));
+            hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], off));
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { sbox[d * W + wave] = lo[d]; sbox[(3 + d) * W + wave] = hi[d]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = sbox[d * W];
+        hi[d] = sbox[(3 + d) * W];
+        for (int w = 1; w < W; ++w) {
+            lo[d] = fminf(lo[d], sbox[d * W + w]);
+            hi[d] = fmaxf(hi[d], sbox[(3 + d) * W + w]);
+        }
+    }
+}
+
+// Sweep of sorted sources [j0, j1) (tile aligned) for the K targets of each lane.  Per tile the
+// workgroup decides from the tile metadata whether the tile is near its target box; near tiles
+// run the FP64-difference operation, far tiles the FP32 tile-relative one.
+template <class Near, int K, int W>
+__device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, float* sbox, int tbase, int j0, int j1,
+                                             typename Near::A64 (&acc)[K], int (&slot)[K], int (&pidx)[K]) {
+    using Far = typename FarOf<Near>::type;
+    constexpr int T = 64 * W;
+    constexpr int kMeta = FarOf<Near>::kMeta;
+    const int lane = threadIdx.x & 63;
+    const int nt = a.tgt.count;
+    typename Near::Tgt tg[K];
+    float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
+    float hi[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        slot[k] = tbase + k * 64 + lane;
+        const int s = slot[k] < nt ? slot[k] : nt - 1;
+        pidx[k] = particle_of(a.tgt, s, a.P.n, a.flags);
+        Near::target(a, pidx[k], tg[k]);
+        Near::zero(acc[k]);
+        const float px = (float)tg[k].x, py = (float)tg[k].y, pz = (float)tg[k].z;
+        lo[0] = fminf(lo[0], px); lo[1] = fminf(lo[1], py); lo[2] = fminf(lo[2], pz);
+        hi[0] = fmaxf(hi[0], px); hi[1] = fmaxf(hi[1], py); hi[2] = fmaxf(hi[2], pz);
+    }
+    block_box<W>(lo, hi, sbox);
+    typename Near::Src* tnear = reinterpret_cast<typename Near::Src*>(tile_raw);
+    typename Far::Src* tfar = reinterpret_cast<typename Far::Src*>(tile_raw);
+    for (int jt = j0; jt < j1; jt += T) {
+        const int len = min(T, j1 - jt);
+        const int tix = jt / T;
+        const double4 c = a.tile_meta[kMeta * tix];
+        const double4 ca = kMeta > 1 ? a.tile_meta[kMeta * tix + 1] : c;
+        const float h = unpack_gm(c.w);  // tile half-extent (max over axes)
+        float gap2 = 0.f;
+        {
+            const float cc[3] = {(float)c.x, (float)c.y, (float)c.z};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const float g = fmaxf(0.f, fmaxf(cc[d] - h - hi[d], lo[d] - (cc[d] + h)));
+                gap2 = __builtin_fmaf(g, g, gap2);
+            }
+        }
+        const bool near = gap2 < (a.kappa * h) * (a.kappa * h);
+        __syncthreads();
+        if ((int)threadIdx.x < len) {
+            if (near) tnear[threadIdx.x] = Near::load(a, jt + threadIdx.x);
+            else tfar[threadIdx.x] = Far::load(a, jt + threadIdx.x);
+        }
+        __syncthreads();
+        typename Near::A32 part[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) Near::zero(part[k]);
+        if (near) {
+#pragma unroll 2
+            for (int j = 0; j < len; ++j) {
+                const typename Near::Src s = tnear[j];
+#pragma unroll
+                for (int k = 0; k < K; ++k) Near::pair(part[k], tg[k], s, a.eps2f);
+            }
+        } else {
+            typename Far::Tgt tf[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) Far::rel(tf[k], tg[k], c, ca);
+#pragma unroll 4
+            for (int j = 0; j < len; ++j) {
+                const typename Far::Src s = tfar[j];
+#pragma unroll
+                for (int k = 0; k < K; ++k) Far::pair(part[k], tf[k], s, a.eps2f);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) Near::fold(acc[k], part[k]);
+    }
+}
+
 // number of stored components of an operation (results + magnitude estimate)
 template <class Op>
 constexpr int ncomp_of() { return Op::NC + (Op::kCond ? 1 : 0); }

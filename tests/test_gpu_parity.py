@@ -45,10 +45,18 @@ def _flags_clean(ctx):
 # accelerations
 # --------------------------------------------------------------------------------------------
 
+@pytest.fixture(params=["sorted", "unsorted"])
+def sort_mode(ctx, request):
+    """Run a test with the spatially sorted mixed kernels on (default) and off."""
+    ctx.set_spatial_sort(request.param == "sorted")
+    yield request.param
+    ctx.set_spatial_sort(True)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("kind", ["all", "list", "range"])
 @pytest.mark.parametrize("eps2", [0.0, 1e-6])
-def test_forces_parity(ctx, prec, kind, eps2):
+def test_forces_parity(ctx, sort_mode, prec, kind, eps2):
     n = 3001  # several 256-source tiles plus a ragged tail
     d = _cluster(n, 1)
     P, Pd = oracle.Particles.from_dict(d), _dev(d)
@@ -63,7 +71,7 @@ def test_forces_parity(ctx, prec, kind, eps2):
         T, S = np.arange(100, 1400), np.arange(900, 3001)
         Tg, Sg = bf.ParticleSet.range(100, 1300), bf.ParticleSet.range(900, 2101)
     ref, mag, _ = oracle.forces(P, T, S, eps2=eps2, return_mag=True)
-    out = ctx.forces(Pd, Tg, Sg, eps2=eps2, prec=prec, r_fb=1e-3)
+    out = ctx.forces(Pd, Tg, Sg, eps2=eps2, prec=prec, r_fb=0.0)
     ti = np.arange(n) if T is None else T
     got = gather(out, ti)
     _flags_clean(ctx)
@@ -139,6 +147,37 @@ def test_forces_config_invariance_and_determinism(ctx, prec):
         ctx.set_config(bf.BF_OP_FORCES, prec, 0)
 
 
+@pytest.mark.parametrize("op", ["forces", "gradient"])
+def test_sorted_mode_king_cluster(ctx, op):
+    """A 20,000-body King W0 = 6 cluster with Kroupa masses and binaries: the spatially sorted
+    mixed kernels (near tiles in FP64 differences, far tiles from FP32 tile offsets) and the
+    unsorted ones both meet the mixed tolerance against the oracle, on all targets and on a list."""
+    d = ics.king_cluster(ics.rng_for(102), 20000, 6.0, 0.01)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    T = np.sort(np.random.default_rng(11).choice(20000, 700, replace=False))
+    if op == "forces":
+        ref = oracle.forces(P, T, None)
+    else:
+        x, y, z = d["x"], d["y"], d["z"]
+        s3 = (x * x + y * y + z * z + 0.1) ** -1.5
+        af = np.stack([-x * s3, -y * s3, -z * s3], axis=1)
+        ref = oracle.gradient(P, af, T, None)
+        acc = [torch.as_tensor(np.ascontiguousarray(af[:, k]), device="cuda") for k in range(3)]
+    try:
+        for mode in (True, False):
+            ctx.set_spatial_sort(mode)
+            for targets in (None, T):
+                if op == "forces":
+                    out = ctx.forces(Pd, targets, None, prec="mixed", r_fb=0.0)
+                else:
+                    out = ctx.force_gradient(Pd, acc, targets, None, prec="mixed", r_fb=0.0)
+                rms, mx = stats(rel_errors(gather(out, T), ref))
+                assert rms <= RMS_TOL and mx <= MAX_TOL, (mode, targets is None, rms, mx)
+    finally:
+        ctx.set_spatial_sort(True)
+    _flags_clean(ctx)
+
+
 def test_forces_close_pair_fallback(ctx):
     """A pair well inside r_fb: the FP64 re-evaluation keeps the mixed result at FP64 quality."""
     d = _cluster(1000, 6)
@@ -189,7 +228,7 @@ def test_bad_index_is_flagged_not_faulted(ctx):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("kind", ["all", "list"])
 @pytest.mark.parametrize("eps2", [0.0, 1e-6])
-def test_gradient_parity(ctx, prec, kind, eps2):
+def test_gradient_parity(ctx, sort_mode, prec, kind, eps2):
     n = 2999
     d = _cluster(n, 11)
     P, Pd = oracle.Particles.from_dict(d), _dev(d)
@@ -202,7 +241,7 @@ def test_gradient_parity(ctx, prec, kind, eps2):
         S = np.sort(rng.choice(n, 2500, replace=False))
     ref, mag, _ = oracle.gradient(P, a, T, S, eps2=eps2, return_mag=True)
     acc = [torch.as_tensor(np.ascontiguousarray(a[:, k]), device="cuda") for k in range(3)]
-    out = ctx.force_gradient(Pd, acc, T, S, eps2=eps2, prec=prec, r_fb=1e-3)
+    out = ctx.force_gradient(Pd, acc, T, S, eps2=eps2, prec=prec, r_fb=0.0)
     ti = np.arange(n) if T is None else T
     got = gather(out, ti)
     _flags_clean(ctx)

@@ -1,0 +1,116 @@
+"""GPU parity of the time-step assignment (jerk, gradient and pairwise criteria, levels), the
+level partition and the device HHS-FSI interval driver against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2210_02472_amd import ics
+from tests._parity import gather, rel_errors, stats
+
+bf = pytest.importorskip("paper_2210_02472_amd")
+
+pytestmark = pytest.mark.gpu
+
+RMS_TOL, MAX_TOL = 1e-6, 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = bf.Context(0)
+    yield c
+    c.close()
+
+
+def _cluster(n, seed):
+    return ics.plummer_cluster(ics.rng_for(300, seed), n, "kroupa")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_jerk_parity(ctx, prec):
+    d = _cluster(2500, 1)
+    P, Pd = oracle.Particles.from_dict(d), bf.Particles.from_numpy(d)
+    ref = oracle.jerk(P)
+    got = gather(ctx.jerk(Pd, prec=prec), np.arange(2500))
+    if prec == "fp64":
+        _, mag, _ = oracle.gradient(P, P.vel(), return_mag=True)
+        assert np.all(np.linalg.norm(got - ref, axis=1) <= 1e-12 * mag)
+    else:
+        rms, mx = stats(rel_errors(got, ref))
+        assert rms <= RMS_TOL and mx <= MAX_TOL, (rms, mx)
+
+
+def test_timestep_assign_parity(ctx):
+    """The whole assignment in FP64: dt to 1e-12 relative; levels equal except where dt lies
+    within that tolerance of a pivot (where both sides may round to different sides)."""
+    n, kmax, tau = 3000, 7, 0.05
+    d = _cluster(n, 2)
+    P, Pd = oracle.Particles.from_dict(d), bf.Particles.from_numpy(d)
+    idx = np.arange(n)
+    ff, fb = oracle.dt_min(P, eta_ff=0.2, eta_fb=0.2)
+    a = oracle.forces(P)
+    g = oracle.gradient(P, a)
+    j = oracle.jerk(P)
+    dt_ref = oracle.timestep_criteria(P, idx, ff, fb, a, g, j, eta_grad=0.1, eta_jerk=0.1)
+    lv_ref = oracle.levels_from_dt(dt_ref, tau, kmax)
+
+    dff, dfb = ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.2, prec="fp64")
+    ad = ctx.forces(Pd, prec="fp64")
+    gd = ctx.force_gradient(Pd, ad, prec="fp64")
+    jd = ctx.jerk(Pd, prec="fp64")
+    dt, lv = ctx.timestep_assign(Pd, None, dff, dfb, ad, gd, jd, eta_grad=0.1, eta_jerk=0.1, tau=tau, kmax=kmax)
+    dt, lv = dt.cpu().numpy(), lv.cpu().numpy()
+    np.testing.assert_allclose(dt, dt_ref, rtol=1e-12)
+    pivots = tau / 2.0 ** np.arange(kmax + 1)
+    near_pivot = np.min(np.abs(dt_ref[:, None] / pivots[None, :] - 1.0), axis=1) < 1e-11
+    assert np.array_equal(lv[~near_pivot], lv_ref[~near_pivot])
+    assert lv.min() >= 0 and lv.max() <= kmax
+
+
+def test_level_partition_is_stable_sort(ctx):
+    n, kmax = 5000, 6
+    rng = np.random.default_rng(4)
+    level = rng.integers(0, kmax + 1, n).astype(np.int32)
+    sub = np.sort(rng.choice(n, 3000, replace=False)).astype(np.int32)
+    lv = torch.as_tensor(level, device="cuda")
+    order, counts = ctx.level_partition(sub, n, lv, kmax)
+    ref = sub[np.argsort(level[sub], kind="stable")]
+    assert np.array_equal(order.cpu().numpy(), ref)
+    assert counts == [int(np.sum(level[sub] == k)) for k in range(kmax + 1)]
+    order, counts = ctx.level_partition(None, n, lv, kmax)
+    assert np.array_equal(order.cpu().numpy(), np.argsort(level, kind="stable"))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_hhs_interval_parity(ctx, prec):
+    """One HHS-FSI interval with four populated levels (and an empty one) on the device against the
+    oracle recursion.  FP64: state to 1e-12 of its scale; mixed: the change of the state within
+    1e-5 of the oracle's change."""
+    n = 900
+    d = _cluster(n, 3)
+    rng = np.random.default_rng(5)
+    level = rng.choice([0, 1, 2, 4], size=n, p=[0.5, 0.25, 0.15, 0.10]).astype(np.int32)
+    P, Pd = oracle.Particles.from_dict(d), bf.Particles.from_numpy(d)
+    P0 = P.copy()
+    tau = 2e-3
+    oracle.hhs_interval(P, level, tau)
+    ctx.hhs_interval(Pd, torch.as_tensor(level, device="cuda"), 4, tau, prec=prec)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        ref = getattr(P, k)
+        got = getattr(Pd, k).cpu().numpy()
+        if prec == "fp64":
+            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
+        else:
+            change = np.abs(ref - getattr(P0, k)).max()
+            assert np.abs(got - ref).max() <= MAX_TOL * change, k
+    assert ctx.read_flags() & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
+
+
+def test_hhs_single_level_matches_fsi(ctx):
+    d = _cluster(700, 6)
+    A, B = bf.Particles.from_numpy(d), bf.Particles.from_numpy(d)
+    lv = torch.zeros(700, dtype=torch.int32, device="cuda")
+    ctx.hhs_interval(A, lv, 3, 1e-3, prec="fp64")
+    ctx.fsi_step(B, 1e-3, prec="fp64")
+    for k in ("x", "vy"):
+        assert torch.allclose(getattr(A, k), getattr(B, k), rtol=0, atol=1e-15)

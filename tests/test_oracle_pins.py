@@ -191,6 +191,46 @@ def test_dt_minimum_over_sources_and_edge_cases():
     assert np.all(np.isinf(fbq)) and np.all(np.isfinite(ffq))
 
 
+def test_jerk_is_time_derivative_of_acc():
+    """j_i = d/dt a_i along the flow x -> x + h v (Sec. 3.5.5), by central differences of the
+    acceleration routine; and the two-body value -G m2 (v21 - 3 (n.v21) n) / r^3 at radial motion."""
+    P = _random_cluster(30, seed=9)
+    j = oracle.jerk(P)
+
+    def acc_at(h):
+        Q = P.copy()
+        Q.x += h * Q.vx; Q.y += h * Q.vy; Q.z += h * Q.vz
+        return oracle.forces(Q)
+
+    h = 1e-5
+    fd = (acc_at(-2 * h) - 8 * acc_at(-h) + 8 * acc_at(h) - acc_at(2 * h)) / (12 * h)
+    err = np.linalg.norm(fd - j, axis=1) / np.linalg.norm(j, axis=1)
+    assert err.max() < 1e-7
+    # two bodies moving apart along x: a_1 = G m2 / r^2 x-hat shrinks, da_1/dt = -2 G m2 u / r^3
+    d = {"x": np.array([0.0, 2.0]), "y": np.zeros(2), "z": np.zeros(2), "vx": np.array([0.0, 0.5]),
+         "vy": np.zeros(2), "vz": np.zeros(2), "m": np.array([1.0, 3.0])}
+    j2 = oracle.jerk(Particles.from_dict(d))
+    np.testing.assert_allclose(j2[0], [-2 * 3.0 * 0.5 / 8.0, 0, 0], rtol=1e-15)
+
+
+def test_timestep_criteria_and_levels():
+    """Gradient and jerk criteria (Sec. 3.5.4, 3.5.5) on hand-set vectors, and the level rule
+    (slow when dt >= pivot tau / 2^k, Sec. 2.2) at exact power-of-two boundaries."""
+    d = {"x": np.zeros(1), "y": np.zeros(1), "z": np.zeros(1), "vx": np.array([3.0]), "vy": np.array([4.0]),
+         "vz": np.zeros(1), "m": np.ones(1)}
+    P = Particles.from_dict(d)
+    acc = np.array([[0.0, 0.0, 2.0]])
+    gsum = np.array([[24.0 * 0.5, 0.0, 0.0]])        # |g'| = 0.5
+    jrk = np.array([[0.0, 8.0, 0.0]])                 # |j| = 8
+    dt = oracle.timestep_criteria(P, [0], [10.0], [10.0], acc, gsum, jrk, eta_grad=0.1, eta_jerk=0.2)
+    # candidates: 0.1 (5/0.5)^(1/3) = 0.2154, 0.1 (2/0.5)^(1/2) = 0.2, 0.2 * 2/8 = 0.05
+    np.testing.assert_allclose(dt, [0.05], rtol=1e-15)
+    dt = oracle.timestep_criteria(P, [0], [10.0], [10.0], acc, gsum, None, eta_grad=0.1)
+    np.testing.assert_allclose(dt, [0.2], rtol=1e-15)
+    lv = oracle.levels_from_dt(np.array([1.0, 0.5, 0.4999999, 0.25, 1e-9, 3.0]), 1.0, 5)
+    assert list(lv) == [0, 1, 2, 2, 5, 0]
+
+
 # --------------------------------------------------------------------------------------------
 # PN1.0 (Sec. 3.8, global PN1.0 term)
 # --------------------------------------------------------------------------------------------
