@@ -33,6 +33,38 @@ PEAK_FP32_TFLOPS = 256 * 128 * 2 * 2.4e9 / 1e12  # 157.29
 PEAK_FP64_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.64
 
 
+# HBM traffic of the dominant kernel, measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE)
+# and scaled by the same counters' reading for a copy kernel of known size.  The figure is used
+# only while the kernel sources hash to the value recorded with it.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_GradMixed_king1m_hbm_traffic.txt")
+KERNEL_SOURCES = ["pair_ops.h", "pairs.hip", "bf_internal.h", "capi.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2210_02472_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n):
+    """Bytes per launch from the committed counter summary, or None if absent or stale."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != kernel_source_hash() or int(kv.get("n", -1)) != n:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def synthetic_acc_field(d):
     """Smooth input accelerations for the gradient parity sample (any field is a valid input)."""
     x, y, z = d["x"], d["y"], d["z"]
@@ -175,10 +207,18 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--r-fb", type=float, default=0.0,
-                    help="FP64 re-evaluation radius; 0: every pair difference is already formed in FP64")
+                    help="radius below which whole tiles are re-evaluated in FP64 (0: off; every pair's "
+                         "separation is formed in FP64 in any case)")
+    ap.add_argument("--rfb-variant", type=float, default=1e-3,
+                    help="also time the sweep with this re-evaluation radius (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", type=int, default=256, help="targets sampled for the error check")
+    ap.add_argument("--spatial-sort", default="default", choices=["default", "off", "acc", "grad", "both"],
+                    help="passes that use the spatially sorted mixed kernels (default: the library's)")
+    ap.add_argument("--kappa", type=float, default=0.0, help="near-tile threshold (0: the library's)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library autotuner for both passes before timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 2 GiB device-to-device copy kernel first (HBM counter calibration)")
     ap.add_argument("--workload", default="king1m",
@@ -216,22 +256,31 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ctx = bf.Context(0)
+    if args.spatial_sort != "default" or args.kappa:
+        mode = {"default": (False, True), "off": (False, False), "acc": (True, False), "grad": (False, True),
+                "both": (True, True)}[args.spatial_sort]
+        ctx.set_spatial_sort(forces=mode[0], gradient=mode[1], kappa=args.kappa)
+    if args.autotune:
+        t1 = time.time()
+        for op in (bf.BF_OP_FORCES, bf.BF_OP_GRADIENT):
+            ctx.autotune(op, "mixed", n, n)
+        log(f"autotuned in {time.time() - t1:.1f}s")
     out_a = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
     out_g = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
 
-    def sweep(prec):
-        ctx.forces(P, None, None, G=1.0, eps2=0.0, prec=prec, r_fb=args.r_fb, out=out_a)
-        ctx.force_gradient(P, out_a, None, None, G=1.0, eps2=0.0, prec=prec, r_fb=args.r_fb, out=out_g)
+    def sweep(prec, r_fb):
+        ctx.forces(P, None, None, G=1.0, eps2=0.0, prec=prec, r_fb=r_fb, out=out_a)
+        ctx.force_gradient(P, out_a, None, None, G=1.0, eps2=0.0, prec=prec, r_fb=r_fb, out=out_g)
 
-    def timed(prec, steps, warmup):
+    def timed(prec, steps, warmup, r_fb=args.r_fb):
         for _ in range(warmup):
-            sweep(prec)
+            sweep(prec, r_fb)
         torch.cuda.synchronize()
         ctx.enable_timing(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
-            sweep(prec)
+            sweep(prec, r_fb)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
         ka = ctx.kernel_times(bf.BF_OP_FORCES)
@@ -247,19 +296,31 @@ def main():
     acc_m = [t.clone() for t in out_a]
     grad_m = [t.clone() for t in out_g]
     log(f"mixed: {ms_step:.1f} ms/step, {value:.4e} pairs/s")
+    stats_m = ctx.last_pass_stats()
+    rfb_var = None
+    if args.rfb_variant > 0:
+        log(f"mixed sweep with r_fb = {args.rfb_variant} ...")
+        wall_v, ka_v, kg_v = timed("mixed", 2, 1, r_fb=args.rfb_variant)
+        rfb_var = {"r_fb": args.rfb_variant, "value": pairs / (wall_v / 2), "ms_per_step": wall_v / 2 * 1e3,
+                   "acc_kernel_ms": float(np.mean(ka_v)), "grad_kernel_ms": float(np.mean(kg_v))}
     log("fp64 sweep ...")
     wall_d, ka_d, kg_d = timed("fp64", args.fp64_steps, 0)
     ms_fp64 = wall_d / args.fp64_steps * 1e3
     log(f"fp64: {ms_fp64:.1f} ms/step")
 
-    # mixed sweep vs FP64 GPU sweep, all targets (relative per-target error)
+    # mixed vs FP64 GPU, all 2^20 targets, per-target relative error.  The acceleration passes
+    # see the same positions; the gradient is compared on the same input accelerations (the
+    # mixed ones), and separately end to end (each precision on its own accelerations).
     def rel(a, b):
         da = torch.sqrt(sum((x - y) ** 2 for x, y in zip(a, b)))
         nb = torch.sqrt(sum(y ** 2 for y in b))
         e = (da / nb).cpu().numpy()
-        return float(np.sqrt(np.mean(e * e))), float(e.max())
+        return float(np.sqrt(np.mean(e * e))), float(e.max()), int(np.sum(e > 1e-5))
     acc_vs64 = rel(acc_m, out_a)
-    grad_vs64 = rel(grad_m, out_g)
+    grad_e2e = rel(grad_m, out_g)
+    g64_same = ctx.force_gradient(P, acc_m, None, None, G=1.0, eps2=0.0, prec="fp64")
+    grad_vs64 = rel(grad_m, g64_same)
+    del g64_same
 
     # mixed vs the FP64 CPU oracle on sampled targets (same inputs on both sides)
     import oracle
@@ -279,6 +340,10 @@ def main():
 
     cfg_a = ctx.query_config(bf.BF_OP_FORCES, "mixed", n, n)
     cfg_g = ctx.query_config(bf.BF_OP_GRADIENT, "mixed", n, n)
+    sorted_g = stats_m[1] + stats_m[2] > 0
+    ctx.forces(P, None, None, prec="mixed", r_fb=args.r_fb, out=out_a)
+    stats_a = ctx.last_pass_stats()
+    sorted_a = stats_a[1] + stats_a[2] > 0
     avg = lambda v: float(np.mean(v)) if v else float("nan")  # noqa: E731
     ka, kg = avg(ka_m), avg(kg_m)
     grad_tflops = pairs * FLOPS_GRAD / (kg * 1e-3) / 1e12
@@ -317,14 +382,17 @@ def main():
         "dtype": "f32 pair arithmetic, f64 accumulate",
         "data": "synthetic",
         "config": {"workload": f"King W0=6 cluster N={n}, Kroupa IMF + 1% binaries as COM particles, Henon units, "
-                               f"eps=0, all active; acceleration + force-gradient sweep, mixed precision (FP64 "
-                               f"differences, FP32 pair arithmetic, FP64 merge and cancellation fix-up)",
+                               f"eps=0, all active; acceleration + force-gradient sweep, mixed precision (every "
+                               f"pair separation formed in FP64 and rounded once, FP32 pair arithmetic, FP64 "
+                               f"merge and cancellation fix-up)",
                    "n": n, "eps": 0.0, "r_fb": args.r_fb,
+                   "fp64_differences": "all pairs (covers pairs at r < 1e-3)",
+                   "spatial_sort": {"forces": sorted_a, "gradient": sorted_g}, "autotuned": bool(args.autotune),
                    "acc_kernel": {"k_per_lane": cfg_a[0], "waves": cfg_a[1], "split": cfg_a[2]},
                    "grad_kernel": {"k_per_lane": cfg_g[0], "waves": cfg_g[1], "split": cfg_g[2]}},
         "roofline": {"bound": "alu", "kernel": "k_pairs<GradMixed> (force-gradient pass)",
                      "achieved": grad_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": grad_tflops / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": grad_tflops / PEAK_FP32_TFLOPS, "traffic": measured_traffic(n),
                      "flops_per_pair": FLOPS_GRAD, "pairs_per_launch": pairs, "avg_kernel_ms": kg},
         "acc_pass": {"avg_kernel_ms": ka, "tflops": acc_tflops, "frac": acc_tflops / PEAK_FP32_TFLOPS,
                      "pairs_per_s": pairs / (ka * 1e-3)},
@@ -337,7 +405,12 @@ def main():
                     "grad_vs_oracle_rms": float(np.sqrt(np.mean(e_g ** 2))), "grad_vs_oracle_max": float(e_g.max()),
                     "oracle_sample_targets": int(args.sample),
                     "acc_vs_fp64_gpu_rms": acc_vs64[0], "acc_vs_fp64_gpu_max": acc_vs64[1],
-                    "grad_vs_fp64_gpu_rms": grad_vs64[0], "grad_vs_fp64_gpu_max": grad_vs64[1]},
+                    "acc_vs_fp64_gpu_n_above_1e-5": acc_vs64[2],
+                    "grad_vs_fp64_gpu_rms": grad_vs64[0], "grad_vs_fp64_gpu_max": grad_vs64[1],
+                    "grad_vs_fp64_gpu_n_above_1e-5": grad_vs64[2],
+                    "grad_end_to_end_vs_fp64_gpu_rms": grad_e2e[0], "grad_end_to_end_vs_fp64_gpu_max": grad_e2e[1]},
+        "fixups": {"acc": stats_a[0], "grad": stats_m[0]},
+        "rfb_variant": rfb_var,
         "device_flags": flags,
         "cpu_baseline": cpu,
     }

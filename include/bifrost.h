@@ -231,6 +231,21 @@ BF_API int bf_level_partition(bf_ctx *ctx, const bf_set *set, int64_t n, const i
 BF_API int bf_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, const int32_t *level,
                            int kmax, double tau, const bf_fsi_params *prm);
 
+/* One HHS-FSI interval of length tau over `set` with time-steps assigned on every hierarchy
+ * level (Sec. 2.2: each level starts by assigning time-steps and splitting its particles at the
+ * pivot; Sec. 3.5.1: a time-step cannot grow within the interval).  dt0 (device FP64,
+ * particle-indexed) holds the time-steps assigned at the start of the interval from all
+ * particles (e.g. bf_timestep_assign); it splits level 0.  On a deeper level k with particle set
+ * P and pivot tau / 2^k, a particle's time-step is min(dt0, dt_ff, dt_fb) with the pairwise
+ * free-fall / fly-by time-steps over P (eta_ff, eta_fb > 0, precision prm->prec); particles
+ * with time-step >= pivot are slow, the others fast; on level kmax all are slow.  The cycle on
+ * each level is the one of bf_hhs_interval.  Synchronises once per visited level (the split
+ * sizes); max_level / n_levels (host, may be NULL) receive the deepest level reached and the
+ * number of levels visited.  prm->n_bh must be 0. */
+BF_API int bf_hhs_interval_adaptive(bf_ctx *ctx, const bf_state *S, const bf_set *set, const double *dt0,
+                                    int kmax, double tau, double eta_ff, double eta_fb,
+                                    const bf_fsi_params *prm, int *max_level, int64_t *n_levels);
+
 /* Elementwise kicks and drifts used by integrator drivers (FP64, over the set):
  *   bf_kick:  v_i += h (a_i + h2 g_i)   (g may be NULL, then h2 is ignored)
  *   bf_drift: x_i += h v_i                                              (Sec. 2.1) */
@@ -305,12 +320,21 @@ BF_API int bf_autotune(bf_ctx *ctx, int op, int prec, int64_t n_targets, int64_t
 /* Load a tuning table written by bf_autotune. */
 BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
 
-/* Spatially sorted mode of the mixed acceleration and gradient passes (default on).  When on,
- * and r_fb == 0, with at least 2048 sources and 512 targets, targets and sources are ordered
- * along a Morton curve and packed into tiles; tiles far from a workgroup's targets are summed
- * from FP32 offsets to the tile centre, near tiles from FP64 differences.  Results keep the
- * accuracy of the unsorted mixed path; outputs stay particle-indexed. */
-BF_API int bf_set_spatial_sort(bf_ctx *ctx, int on);
+/* Spatially sorted mode of the mixed acceleration and gradient passes.  ops_mask selects the
+ * passes that use it: bit (1 << BF_OP_FORCES) and/or bit (1 << BF_OP_GRADIENT); the default is
+ * the gradient pass only.  When selected, and r_fb == 0, with at least 2048 sources and 512
+ * targets, targets and sources are ordered along a Morton curve and the sources packed into
+ * tiles; a tile whose gap to a workgroup's target box is at least kappa times its half-extent
+ * is summed from FP32 offsets to the tile centre (pair separation rounding error at most
+ * u (1 + 2 sqrt(3) / kappa) relative), nearer tiles from FP64 differences.  kappa = 0 keeps the
+ * current value (default 3); otherwise it must lie in [0.5, 64] (BF_ERR_ARG).  Outputs stay
+ * particle-indexed; results keep the accuracy of the unsorted mixed path. */
+BF_API int bf_set_spatial_sort(bf_ctx *ctx, int ops_mask, double kappa);
+
+/* Synchronising.  Counters of the most recent acceleration / gradient / time-step pass: targets
+ * re-evaluated in FP64 by the cancellation fix-up, and (spatially sorted mode) tile visits that
+ * took the near (FP64-difference) and far (FP32 tile-offset) paths. */
+BF_API int bf_last_pass_stats(bf_ctx *ctx, int64_t *fixups, int64_t *near_tiles, int64_t *far_tiles);
 
 /* Kernel configuration the context would use for a pass (for reporting):
  * targets per lane, waves per workgroup, source split. */

@@ -321,3 +321,54 @@ def hhs_interval(p: Particles, levels: np.ndarray, tau: float, subset=None, leve
     a = _interlevel_acc(p, S, F, G, eps2)
     _kick(p, both, a[both], tau / 6)
     return p
+
+
+def hhs_interval_adaptive(p: Particles, dt0: np.ndarray, tau: float, kmax: int, eta_ff: float = 0.2,
+                          eta_fb: float = 0.2, subset=None, level: int = 0, G: float = 1.0,
+                          eps2: float = 0.0, trace=None) -> Particles:
+    """One HHS-FSI interval of length tau over `subset` in which every hierarchy level begins by
+    assigning time-steps and dividing its particles into slow (dt >= pivot) and fast (dt < pivot)
+    sets (Sec. 2.2).  `dt0` (particle-indexed) holds the time-steps assigned at the start of the
+    interval from all particles; on deeper levels a particle's time-step is the pairwise
+    free-fall / fly-by time-step over the particles of that level, capped by its dt0 so that it
+    cannot grow within the interval (Sec. 3.5.1, the level-0 minimum).  Particles on level kmax
+    are all slow.  `trace`, if a list, receives (level, pivot, slow count, fast count, smallest
+    distance of a time-step to the pivot relative to the pivot) per visited level."""
+    idx = _idx(subset, p.n)
+    if level == 0:
+        dt = np.asarray(dt0, float)[idx]
+    else:
+        ff, fb = dt_min(p, idx, idx, G, eta_ff, eta_fb)
+        dt = np.minimum(np.minimum(ff, fb), np.asarray(dt0, float)[idx])
+    if level >= kmax:
+        slow = np.ones(idx.size, dtype=bool)
+    else:
+        slow = dt >= tau
+    S, F = idx[slow], idx[~slow]
+    if trace is not None:
+        gap = float(np.min(np.abs(dt / tau - 1.0))) if idx.size else np.inf
+        trace.append((level, tau, S.size, F.size, gap))
+    sub = dict(eta_ff=eta_ff, eta_fb=eta_fb, G=G, eps2=eps2, trace=trace)
+    if F.size == 0:
+        if S.size:
+            fsi_step(p, tau, S, G, eps2)
+        return p
+    if S.size == 0:
+        hhs_interval_adaptive(p, dt0, tau / 2, kmax, subset=F, level=level + 1, **sub)
+        hhs_interval_adaptive(p, dt0, tau / 2, kmax, subset=F, level=level + 1, **sub)
+        return p
+    both = np.concatenate([S, F])
+    a = _interlevel_acc(p, S, F, G, eps2)
+    _kick(p, both, a[both], tau / 6)
+    fsi_step(p, tau / 2, S, G, eps2)
+    hhs_interval_adaptive(p, dt0, tau / 2, kmax, subset=F, level=level + 1, **sub)
+    a = _interlevel_acc(p, S, F, G, eps2)
+    g = np.zeros((p.n, 3))
+    g[S] = gradient(p, a, S, F, G, eps2)
+    g[F] = gradient(p, a, F, S, G, eps2)
+    _kick(p, both, a[both] + (tau * tau / 24.0) * g[both], 2.0 * tau / 3.0)
+    hhs_interval_adaptive(p, dt0, tau / 2, kmax, subset=F, level=level + 1, **sub)
+    fsi_step(p, tau / 2, S, G, eps2)
+    a = _interlevel_acc(p, S, F, G, eps2)
+    _kick(p, both, a[both], tau / 6)
+    return p

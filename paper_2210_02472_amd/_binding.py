@@ -86,6 +86,8 @@ def load_library(path: str = LIB_PATH):
                                _vp, _vp],
         "bf_level_partition": [_vp, S, _i64, _vp, _int, _vp, ctypes.POINTER(_i64)],
         "bf_hhs_interval": [_vp, ST, S, _vp, _int, _d, FP],
+        "bf_hhs_interval_adaptive": [_vp, ST, S, _vp, _int, _d, _d, _d, FP, ctypes.POINTER(_int),
+                                     ctypes.POINTER(_i64)],
         "bf_drift": [_vp, ST, S, _d],
         "bf_forces_batched": [_vp, P, _i32, _vp, _vp, _vp, _i64, _i64, _d, _d, _int, _d, _vp, _vp, _vp],
         "bf_force_gradient_batched": [_vp, P, _i32, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _d, _d, _int, _d,
@@ -101,7 +103,8 @@ def load_library(path: str = LIB_PATH):
                             ctypes.POINTER(_int)],
         "bf_set_config": [_vp, _int, _int, _int, _int, _int],
         "bf_enable_timing": [_vp, _int],
-        "bf_set_spatial_sort": [_vp, _int],
+        "bf_set_spatial_sort": [_vp, _int, ctypes.c_double],
+        "bf_last_pass_stats": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
         "bf_kernel_times": [_vp, _int, ctypes.POINTER(ctypes.c_float), _int, ctypes.POINTER(_int)],
     }
     for name, args in sig.items():
@@ -344,6 +347,20 @@ class Context:
         _check("bf_hhs_interval", _lib.bf_hhs_interval(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()),
                                                        _ptr(level), int(kmax), float(tau), ctypes.byref(prm)))
 
+    def hhs_interval_adaptive(self, P: Particles, dt0: torch.Tensor, kmax: int, tau: float, eta_ff=0.2, eta_fb=0.2,
+                              subset=None, G=1.0, eps2=0.0, prec="fp64", r_fb=0.0):
+        """One HHS-FSI interval with time-steps assigned on every level (capped by dt0), in
+        place.  Returns (deepest level reached, number of levels visited)."""
+        s = ParticleSet.of(subset, P.n)
+        _need(dt0, torch.float64, P.n, "dt0")
+        prm = _FsiParams(float(G), float(eps2), PRECISIONS[prec], float(r_fb), None, 0, 1.0)
+        ml, nl = _int(0), _i64(0)
+        _check("bf_hhs_interval_adaptive",
+               _lib.bf_hhs_interval_adaptive(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()), _ptr(dt0),
+                                             int(kmax), float(tau), float(eta_ff), float(eta_fb), ctypes.byref(prm),
+                                             ctypes.byref(ml), ctypes.byref(nl)))
+        return ml.value, nl.value
+
     def kick(self, P: Particles, subset, h, acc, h2=0.0, grad=None):
         s = ParticleSet.of(subset, P.n)
         g = grad if grad is not None else (None, None, None)
@@ -415,8 +432,18 @@ class Context:
                                                        ctypes.byref(k), ctypes.byref(w), ctypes.byref(s)))
         return k.value, w.value, s.value
 
-    def set_spatial_sort(self, on: bool = True):
-        _check("bf_set_spatial_sort", _lib.bf_set_spatial_sort(self._h, int(on)))
+    def last_pass_stats(self):
+        """(fix-ups, near tile visits, far tile visits) of the most recent pass."""
+        f, nn, nf = _i64(0), _i64(0), _i64(0)
+        _check("bf_last_pass_stats", _lib.bf_last_pass_stats(self._h, ctypes.byref(f), ctypes.byref(nn),
+                                                             ctypes.byref(nf)))
+        return f.value, nn.value, nf.value
+
+    def set_spatial_sort(self, forces: bool = False, gradient: bool = True, kappa: float = 0.0):
+        """Select the passes that use the spatially sorted mixed kernels; kappa = 0 keeps the
+        near-tile threshold (default 3)."""
+        mask = (int(bool(forces)) << BF_OP_FORCES) | (int(bool(gradient)) << BF_OP_GRADIENT)
+        _check("bf_set_spatial_sort", _lib.bf_set_spatial_sort(self._h, mask, float(kappa)))
 
     def enable_timing(self, on: bool = True):
         _check("bf_enable_timing", _lib.bf_enable_timing(self._h, int(on)))

@@ -51,6 +51,7 @@ struct PairArgs {
     double cond_max;       // mixed acc/grad: FP64 fix-up when magnitude estimate > cond_max |result|
     int32_t* fix_list;     // [tgt.count] target slots queued for the FP64 fix-up
     int32_t* fix_count;    // number of queued slots
+    unsigned long long* tile_stats;  // sorted mode: [near tiles, far tiles] visited (NULL: not counted)
     uint32_t* flags;
 };
 
@@ -78,6 +79,7 @@ int stored_components(int op, int prec);
 hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_zero_count(int32_t* c, hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st);
 hipError_t launch_fixup(int op, const PairArgs& a, int nblocks, hipStream_t st);
 
 // Spatially sorted mixed acc/grad (spatial.hip).
@@ -121,6 +123,8 @@ struct TimestepArgs {
 };
 hipError_t launch_timestep(const TimestepArgs& t, hipStream_t st);
 size_t level_sort_tmp_bytes(int n);
+hipError_t launch_pivot_flags(const DevSet& set, int64_t n, const double* dt0, const double* ff, const double* fb,
+                              double tau, bool all_slow, int32_t* flag, uint32_t* flags, hipStream_t st);
 hipError_t launch_level_partition(const DevSet& set, int64_t n, const int32_t* level, int kmax, uint32_t* keys_in,
                                   uint32_t* keys_out, int32_t* vals_in, int32_t* out_order, int32_t* counts,
                                   void* tmp, size_t tmp_bytes, uint32_t* flags, hipStream_t st);
@@ -186,7 +190,10 @@ struct bf_ctx {
     size_t scratch6_bytes = 0;
     void* scratch7 = nullptr;         // HHS driver: level order and inter-level / FSI arrays
     size_t scratch7_bytes = 0;
-    bool spatial_sort = true;         // use the spatially sorted mixed acc/grad kernels when large enough
+    unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass
+    // spatially sorted mixed passes: bit op set = use them for that operation when large enough
+    int sort_ops = 1 << 1;            // the force-gradient pass
+    float kappa = 3.0f;               // a tile is near a workgroup when their gap < kappa * tile half-extent
     // kernel timing: event pairs around pair-kernel launches, per op
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[bf::OP_COUNT];

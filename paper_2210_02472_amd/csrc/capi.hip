@@ -104,10 +104,10 @@ struct Plan {
 
 // Spatially sorted mode: mixed acceleration / gradient passes on large enough sets.
 constexpr int64_t kSortMinSources = 2048, kSortMinTargets = 512;
-constexpr float kKappa = 3.0f;  // a tile is near a workgroup when their gap < kKappa * tile half-extent
+constexpr double kKappaMin = 0.5, kKappaMax = 64.0;
 
 bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb) {
-    return ctx->spatial_sort && prec == BF_PREC_MIXED && (op == OP_ACC || op == OP_GRAD) && r_fb == 0.0 &&
+    return (ctx->sort_ops >> op & 1) && prec == BF_PREC_MIXED && (op == OP_ACC || op == OP_GRAD) && r_fb == 0.0 &&
            ns >= kSortMinSources && nt >= kSortMinTargets;
 }
 
@@ -186,6 +186,8 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     a.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + 256);
     if (p.split > 1) a.part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + head);
     if (fix) BF_HIP(launch_zero_count(a.fix_count, ctx->stream));
+    BF_HIP(launch_zero_u64(ctx->d_stats, 3, ctx->stream));
+    a.tile_stats = ctx->d_stats + 1;
     if (sorted) {
         // order targets and sources along a Morton curve, then pack the sorted sources into tiles
         const int64_t nt = tg->count, ns = sr->count, nmax = std::max(nt, ns);
@@ -223,7 +225,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         a.pack = ctx->scratch2;
         a.pack_far = ctx->scratch6;
         a.tile_meta = reinterpret_cast<const double4*>(static_cast<char*>(ctx->scratch6) + far_bytes);
-        a.kappa = kKappa;
+        a.kappa = ctx->kappa;
         BF_HIP(launch_pack_tiles(op, p.cfg.waves, a, ctx->scratch2, ctx->scratch6,
                                  reinterpret_cast<double4*>(static_cast<char*>(ctx->scratch6) + far_bytes), ctx->stream));
     } else if (sr->count > 0) {
@@ -251,6 +253,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     }
     if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
     if (fix) BF_HIP(launch_fixup(op, a, std::min<int>(tg->count, 4 * ctx->num_cu), ctx->stream));
+    if (fix) BF_HIP(hipMemcpyAsync(ctx->d_stats, a.fix_count, sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
     return BF_OK;
 }
 
@@ -329,7 +332,8 @@ BF_API int bf_create(bf_ctx** out, int device, void* stream) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
     c->num_cu = prop.multiProcessorCount;
-    if (hipMalloc(&c->d_flags, sizeof(uint32_t)) != hipSuccess ||
+    if (hipMalloc(&c->d_stats, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->d_flags, sizeof(uint32_t)) != hipSuccess ||
         hipHostMalloc(&c->h_flags, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(BF_ERR_NOMEM, "flag allocation failed");
@@ -369,6 +373,7 @@ BF_API int bf_destroy(bf_ctx* c) {
     if (c->scratch6) hipFree(c->scratch6);
     if (c->scratch7) hipFree(c->scratch7);
     if (c->d_flags) hipFree(c->d_flags);
+    if (c->d_stats) hipFree(c->d_stats);
     if (c->h_flags) hipHostFree(c->h_flags);
     delete c;
     return BF_OK;
@@ -753,10 +758,12 @@ int interlevel_acc(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset) {
                      h.asf + 2 * n);
 }
 
-int hhs_rec(const HhsCtx& h, int k, double tau) {
-    const int64_t n = h.S->n, total = h.begin[h.kmax + 1];
-    const int64_t sb = h.begin[k], fb = k < h.kmax ? h.begin[k + 1] : total;
-    const bf_set Sset = segment(h, sb, fb), Fset = segment(h, fb, total), Bset = segment(h, sb, total);
+// One level of the HHS-FSI cycle (Sec. 2.2, Eq. hhsfsi-cycle) for slow set Sset and fast set
+// Fset (Bset = both, contiguous); `fast` advances F by tau/2 (the next level).
+extern "C++" {
+template <class Fast>
+int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_set& Bset, double tau, Fast&& fast) {
+    const int64_t n = h.S->n;
     bf_ctx* c = h.c;
     const bf_fsi_params* p = h.prm;
     auto fsi = [&](double dt) {
@@ -764,8 +771,8 @@ int hhs_rec(const HhsCtx& h, int k, double tau) {
     };
     if (Fset.count == 0) return Sset.count ? fsi(tau) : BF_OK;  // no split at the last level
     if (Sset.count == 0) {
-        if (int rc = hhs_rec(h, k + 1, 0.5 * tau)) return rc;
-        return hhs_rec(h, k + 1, 0.5 * tau);
+        if (int rc = fast()) return rc;
+        return fast();
     }
     const DevSet dB = devset(&Bset);
     const double* nul = nullptr;
@@ -773,7 +780,7 @@ int hhs_rec(const HhsCtx& h, int k, double tau) {
     if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
     BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
     if ((rc = fsi(0.5 * tau))) return rc;
-    if ((rc = hhs_rec(h, k + 1, 0.5 * tau))) return rc;
+    if ((rc = fast())) return rc;
     if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
     Masters Mg = h.M;
     Mg.ax = h.asf; Mg.ay = h.asf + n; Mg.az = h.asf + 2 * n;
@@ -785,11 +792,57 @@ int hhs_rec(const HhsCtx& h, int k, double tau) {
         return rc;
     BF_HIP(launch_kick(*h.S, dB, 2.0 * tau / 3.0, h.asf, h.asf + n, h.asf + 2 * n, tau * tau / 24.0, h.gsf, h.gsf + n,
                        h.gsf + 2 * n, c->d_flags, c->stream));
-    if ((rc = hhs_rec(h, k + 1, 0.5 * tau))) return rc;
+    if ((rc = fast())) return rc;
     if ((rc = fsi(0.5 * tau))) return rc;
     if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
     BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
     return BF_OK;
+}
+}  // extern "C++"
+
+// fixed levels: level k's slow set is the k-th segment of the level order
+int hhs_rec(const HhsCtx& h, int k, double tau) {
+    const int64_t total = h.begin[h.kmax + 1];
+    const int64_t sb = h.begin[k], fb = k < h.kmax ? h.begin[k + 1] : total;
+    const bf_set Sset = segment(h, sb, fb), Fset = segment(h, fb, total), Bset = segment(h, sb, total);
+    return hhs_cycle(h, Sset, Fset, Bset, tau, [&]() { return hhs_rec(h, k + 1, 0.5 * tau); });
+}
+
+// adaptive levels: every level assigns time-steps to its particles P and splits them at the
+// pivot tau (Sec. 2.2); below the top level a time-step is the pairwise free-fall / fly-by
+// time-step over P capped by the interval's initial one (Sec. 3.5.1, the level-0 minimum).
+struct HhsAdapt {
+    const double* dt0;
+    double eta_ff, eta_fb;
+    double *dtff, *dtfb;  // particle-indexed
+    int32_t* flag;        // particle-indexed: 0 slow, 1 fast
+    int32_t* lists;       // (kmax + 1) buffers of `cap` entries: the split of the level-k set
+    int64_t cap;
+    int max_level;
+    int64_t nodes;
+};
+
+int hhs_adapt(const HhsCtx& h, HhsAdapt& A, const bf_set& P, int k, double tau) {
+    if (P.count == 0) return BF_OK;
+    bf_ctx* c = h.c;
+    const int64_t n = h.S->n;
+    const bf_fsi_params* p = h.prm;
+    const bool top = k == 0;
+    if (!top) {
+        if (int rc = run_pairs(c, OP_DT, p->prec, h.M, &P, &P, p->G, 0.0, 0.0, A.eta_ff, A.eta_fb, A.dtff, A.dtfb,
+                               nullptr))
+            return rc;
+    }
+    BF_HIP(launch_pivot_flags(devset(&P), n, A.dt0, top ? nullptr : A.dtff, top ? nullptr : A.dtfb, tau,
+                              k >= h.kmax, A.flag, c->d_flags, c->stream));
+    int32_t* mine = A.lists + (size_t)k * A.cap;
+    int64_t cnt[2];
+    if (int rc = partition_impl(c, &P, n, A.flag, 1, mine, cnt)) return rc;
+    A.max_level = std::max(A.max_level, k);
+    ++A.nodes;
+    const bf_set Sset{mine, (int32_t)cnt[0], 0}, Fset{mine + cnt[0], (int32_t)cnt[1], 0};
+    const bf_set Bset{mine, (int32_t)(cnt[0] + cnt[1]), 0};
+    return hhs_cycle(h, Sset, Fset, Bset, tau, [&]() { return hhs_adapt(h, A, Fset, k + 1, 0.5 * tau); });
 }
 
 }  // namespace
@@ -827,11 +880,76 @@ BF_API int bf_hhs_interval(bf_ctx* c, const bf_state* S, const bf_set* set, cons
     return hhs_rec(h, 0, tau);
 }
 
+BF_API int bf_hhs_interval_adaptive(bf_ctx* c, const bf_state* S, const bf_set* set, const double* dt0, int kmax,
+                                    double tau, double eta_ff, double eta_fb, const bf_fsi_params* prm,
+                                    int* max_level, int64_t* n_levels) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_state(S)) return rc;
+    if (int rc = check_set(set, S->n, "hhs")) return rc;
+    if (int rc = check_fsi_params(prm)) return rc;
+    if (prm->n_bh != 0) return fail(BF_ERR_UNSUPPORTED, "the HHS driver runs without PN1.0 (n_bh must be 0)");
+    if (!dt0) return fail(BF_ERR_ARG, "dt0 NULL");
+    if (kmax < 0 || kmax > 63) return fail(BF_ERR_ARG, "kmax must be in [0, 63]");
+    if (!(isfinite(tau) && tau > 0)) return fail(BF_ERR_ARG, "tau must be finite and > 0");
+    if (!(isfinite(eta_ff) && eta_ff > 0) || !(isfinite(eta_fb) && eta_fb > 0))
+        return fail(BF_ERR_ARG, "eta must be finite and > 0");
+    if (max_level) *max_level = -1;
+    if (n_levels) *n_levels = 0;
+    if (set->count == 0) return BF_OK;
+    const int64_t n = S->n, cap = set->count;
+    const size_t lb = ((size_t)(kmax + 1) * cap * 4 + 255) & ~size_t(255);
+    const size_t fb = ((size_t)n * 4 + 255) & ~size_t(255);
+    if (int rc = ensure(&c->scratch7, &c->scratch7_bytes, lb + fb + (size_t)14 * n * sizeof(double), c->stream))
+        return rc;
+    HhsCtx h;
+    h.c = c;
+    h.S = S;
+    h.prm = prm;
+    bf_particles P{S->x, S->y, S->z, S->vx, S->vy, S->vz, S->m, n};
+    h.M = masters_of(&P);
+    h.order = nullptr;
+    h.kmax = kmax;
+    char* base = static_cast<char*>(c->scratch7);
+    double* d = reinterpret_cast<double*>(base + lb + fb);
+    h.asf = d; h.gsf = d + 3 * n; h.afsi = d + 6 * n; h.gfsi = d + 9 * n;
+    HhsAdapt A;
+    A.dt0 = dt0;
+    A.eta_ff = eta_ff;
+    A.eta_fb = eta_fb;
+    A.dtff = d + 12 * n;
+    A.dtfb = d + 13 * n;
+    A.flag = reinterpret_cast<int32_t*>(base + lb);
+    A.lists = reinterpret_cast<int32_t*>(base);
+    A.cap = cap;
+    A.max_level = -1;
+    A.nodes = 0;
+    const int rc = hhs_adapt(h, A, *set, 0, tau);
+    if (max_level) *max_level = A.max_level;
+    if (n_levels) *n_levels = A.nodes;
+    return rc;
+}
+
 // ---- configuration, tuning -------------------------------------------------------------------
 
-BF_API int bf_set_spatial_sort(bf_ctx* c, int on) {
+BF_API int bf_last_pass_stats(bf_ctx* c, int64_t* fixups, int64_t* near_tiles, int64_t* far_tiles) {
     if (int rc = check_ctx(c)) return rc;
-    c->spatial_sort = on != 0;
+    unsigned long long h[3];
+    BF_HIP(hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    BF_HIP(hipStreamSynchronize(c->stream));
+    if (fixups) *fixups = (int64_t)(h[0] & 0xffffffffull);
+    if (near_tiles) *near_tiles = (int64_t)h[1];
+    if (far_tiles) *far_tiles = (int64_t)h[2];
+    return BF_OK;
+}
+
+BF_API int bf_set_spatial_sort(bf_ctx* c, int ops_mask, double kappa) {
+    if (int rc = check_ctx(c)) return rc;
+    if (ops_mask & ~((1 << OP_ACC) | (1 << OP_GRAD))) return fail(BF_ERR_ARG, "ops_mask: only the force and gradient passes");
+    if (kappa != 0.0 && !(kappa >= kKappaMin && kappa <= kKappaMax))
+        return fail(BF_ERR_ARG, "kappa must be 0 (keep) or in [0.5, 64]");
+    c->sort_ops = ops_mask;
+    if (kappa != 0.0) c->kappa = (float)kappa;
     return BF_OK;
 }
 
@@ -841,7 +959,7 @@ BF_API int bf_query_config(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, 
     if (int rc = check_prec(prec)) return rc;
     if (nt <= 0 || ns <= 0) return fail(BF_ERR_ARG, "sizes must be > 0");
     Plan p;
-    if (int rc = plan(c, op, prec, nt, ns, p)) return rc;
+    if (int rc = plan(c, op, prec, nt, ns, p, use_sorted(c, op, prec, nt, ns, 0.0))) return rc;
     if (k) *k = p.cfg.k;
     if (waves) *waves = p.cfg.waves;
     if (split) *split = p.split;
@@ -925,7 +1043,11 @@ BF_API int bf_autotune(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, cons
     Masters M{};
     M.x = x; M.y = y; M.z = z; M.vx = v; M.vy = v + n; M.vz = v + 2 * n; M.m = m;
     M.ax = a; M.ay = a + n; M.az = a + 2 * n; M.n = n;
-    bf_set tg{nullptr, (int32_t)nt, 0}, sr{nullptr, (int32_t)ns, 0};
+    // Candidates: targets per lane x waves per workgroup, each with the automatic source split.
+    // Large target sets are timed on a leading sample of targets (the rate per pair is what is
+    // compared); the split is recomputed for the real size when the configuration is used.
+    const int64_t nt_time = std::min<int64_t>(nt, (int64_t)1 << 17);
+    bf_set tg{nullptr, (int32_t)nt_time, 0}, sr{nullptr, (int32_t)ns, 0};
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
@@ -935,30 +1057,24 @@ BF_API int bf_autotune(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, cons
     int rc = BF_OK;
     const int ks[] = {1, 2, 4};
     const int ws[] = {2, 4, 8};
-    const int splits[] = {0, 1, 2, 4, 8, 16, 32, 64, 128};
+    const bool sorted = use_sorted(c, op, prec, nt_time, ns, 0.0);
     for (int k : ks) {
         for (int w : ws) {
-            if (!variant_exists(op, prec, k, w)) continue;
-            for (int sp : splits) {
-                c->forced[op][prec] = KernelConfig{k, w, sp};
-                Plan p;
-                if (plan(c, op, prec, nt, ns, p)) continue;
-                if (sp != 0 && p.split != sp) continue;  // clipped to another split: measured elsewhere
-                rc = run_pairs(c, op, prec, M, &tg, &sr, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);  // warm-up
-                if (rc) break;
-                hipEventRecord(e0, c->stream);
-                rc = run_pairs(c, op, prec, M, &tg, &sr, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);
-                hipEventRecord(e1, c->stream);
-                if (rc) break;
-                hipEventSynchronize(e1);
-                float ms = 0;
-                hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = KernelConfig{k, w, p.split};
-                }
-            }
+            if (!variant_exists(op, prec, k, w) || (sorted && !sorted_variant_exists(op, k, w))) continue;
+            c->forced[op][prec] = KernelConfig{k, w, 0};
+            rc = run_pairs(c, op, prec, M, &tg, &sr, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);  // warm-up
             if (rc) break;
+            hipEventRecord(e0, c->stream);
+            rc = run_pairs(c, op, prec, M, &tg, &sr, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);
+            hipEventRecord(e1, c->stream);
+            if (rc) break;
+            hipEventSynchronize(e1);
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = KernelConfig{k, w, 0};
+            }
         }
         if (rc) break;
     }

@@ -6,9 +6,9 @@
 // velocities, accelerations) is taken in FP64 and rounded once to FP32; all arithmetic after
 // that (s^2, rsqrt, mass products, the pair term) is FP32; each LDS tile is summed in FP32
 // and merged into FP64 accumulators.  The acceleration and gradient passes also accumulate a
-// magnitude estimate M (sum over pairs of the pair weight times the max-norm of the pair's
-// difference vector); a target whose result is small against M (cancellation) is re-evaluated
-// entirely in FP64 afterwards.
+// magnitude estimate M of sum_j |term_j| (acceleration: sum G m / s^2; gradient: sum of the
+// pair weight times the max-norm of a_ji); a target whose result is small against M
+// (cancellation) is re-evaluated entirely in FP64 afterwards.
 #pragma once
 
 #include "bf_internal.h"
@@ -59,9 +59,10 @@ __device__ __forceinline__ void acc_pair64(const Masters& P, int pi, int pj, dou
     const double r2 = dx * dx + dy * dy + dz * dz + eps2;
     if (r2 == 0.0) { atomicOr(flags, BF_FLAG_COINCIDENT); return; }
     const double ri = rsqrt64(r2);
-    const double w = G * P.m[pj] * ri * ri * ri;
+    const double t = G * P.m[pj] * ri * ri;
+    const double w = t * ri;
     sx += w * dx; sy += w * dy; sz += w * dz;
-    sm += w * fmax(fabs(dx), fmax(fabs(dy), fabs(dz)));
+    sm += t;
 }
 
 __device__ __forceinline__ void grad_pair64(const Masters& P, int pi, int pj, double G, double eps2, double& sx,
@@ -99,12 +100,12 @@ struct AccMixed {
         const float dx = dif32(s.p.x, t.x), dy = dif32(s.p.y, t.y), dz = dif32(s.p.z, t.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
         const float ri = rsqrt32(r2);
-        const float ri2 = ri * ri;
-        const float w = (unpack_gm(s.p.w) * ri) * ri2;
+        const float gs = unpack_gm(s.p.w) * (ri * ri);  // G m / s^2, at least the term's norm
+        const float w = gs * ri;
         r.x = __builtin_fmaf(w, dx, r.x);
         r.y = __builtin_fmaf(w, dy, r.y);
         r.z = __builtin_fmaf(w, dz, r.z);
-        r.m = __builtin_fmaf(w, max3abs(dx, dy, dz), r.m);
+        r.m += gs;
         return r2;
     }
     __device__ static void fold(A64& o, const A32& i) {
@@ -336,6 +337,14 @@ struct AccRel {
     __device__ static void rel(Tgt& t, const AccMixed::Tgt& g, const double4& c, const double4&) {
         t.x = (float)(g.x - c.x); t.y = (float)(g.y - c.y); t.z = (float)(g.z - c.z);
     }
+    // upper bound of sum_j |term_j| over the tile for this target: every source lies within
+    // sqrt(3) h of the centre, so r >= d - sqrt(3) h and |term| = G m r / s^3 <= G m / r^2
+    static constexpr bool kTileBound = true;
+    __device__ static float bound(const Tgt& t, float h, float gm_tile, float) {
+        const float d = __builtin_sqrtf(__builtin_fmaf(t.x, t.x, __builtin_fmaf(t.y, t.y, t.z * t.z)));
+        const float r = fmaxf(d - 1.7320509f * h, 1e-30f);
+        return gm_tile / (r * r);
+    }
     __device__ static void pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
         const float dx = s.p.x - t.x, dy = s.p.y - t.y, dz = s.p.z - t.z;
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
@@ -345,7 +354,6 @@ struct AccRel {
         r.x = __builtin_fmaf(w, dx, r.x);
         r.y = __builtin_fmaf(w, dy, r.y);
         r.z = __builtin_fmaf(w, dz, r.z);
-        r.m = __builtin_fmaf(w, max3abs(dx, dy, dz), r.m);
     }
 };
 
@@ -361,6 +369,10 @@ struct GradRel {
         t.x = (float)(g.x - c.x); t.y = (float)(g.y - c.y); t.z = (float)(g.z - c.z);
         t.ax = (float)(g.ax - ca.x); t.ay = (float)(g.ay - ca.y); t.az = (float)(g.az - ca.z);
     }
+    // the gradient terms have no useful tile-wide bound (a_ji does not shrink with distance), so
+    // the magnitude estimate is accumulated per pair as in the FP64-difference operation
+    static constexpr bool kTileBound = false;
+    __device__ static float bound(const Tgt&, float, float, float) { return 0.f; }
     __device__ static void pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
         const float dx = s.p.x - t.x, dy = s.p.y - t.y, dz = s.p.z - t.z;
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
@@ -440,12 +452,15 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
     block_box<W>(lo, hi, sbox);
     typename Near::Src* tnear = reinterpret_cast<typename Near::Src*>(tile_raw);
     typename Far::Src* tfar = reinterpret_cast<typename Far::Src*>(tile_raw);
+    unsigned long long n_near = 0, n_far = 0;
     for (int jt = j0; jt < j1; jt += T) {
         const int len = min(T, j1 - jt);
         const int tix = jt / T;
         const double4 c = a.tile_meta[kMeta * tix];
         const double4 ca = kMeta > 1 ? a.tile_meta[kMeta * tix + 1] : c;
-        const float h = unpack_gm(c.w);  // tile half-extent (max over axes)
+        const float2 hm = __builtin_bit_cast(float2, c.w);  // (tile half-extent, G * tile mass)
+        const float h = hm.x;
+        const float ha = kMeta > 1 ? unpack_gm(ca.w) : 0.f;  // half-extent of the tile's accelerations
         float gap2 = 0.f;
         {
             const float cc[3] = {(float)c.x, (float)c.y, (float)c.z};
@@ -456,6 +471,8 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
             }
         }
         const bool near = gap2 < (a.kappa * h) * (a.kappa * h);
+        n_near += near ? 1 : 0;
+        n_far += near ? 0 : 1;
         __syncthreads();
         if ((int)threadIdx.x < len) {
             if (near) tnear[threadIdx.x] = Near::load(a, jt + threadIdx.x);
@@ -475,7 +492,10 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
         } else {
             typename Far::Tgt tf[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) Far::rel(tf[k], tg[k], c, ca);
+            for (int k = 0; k < K; ++k) {
+                Far::rel(tf[k], tg[k], c, ca);
+                if (Far::kTileBound) part[k].m = Far::bound(tf[k], h, hm.y, ha);  // estimate of the whole tile
+            }
 #pragma unroll 4
             for (int j = 0; j < len; ++j) {
                 const typename Far::Src s = tfar[j];
@@ -485,6 +505,10 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) Near::fold(acc[k], part[k]);
+    }
+    if (a.tile_stats && threadIdx.x == 0) {
+        atomicAdd(&a.tile_stats[0], n_near);
+        atomicAdd(&a.tile_stats[1], n_far);
     }
 }
 

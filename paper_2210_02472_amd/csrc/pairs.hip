@@ -117,6 +117,9 @@ __global__ __launch_bounds__(256) void k_reduce(const PairArgs a) {
 // ---- FP64 fix-up of ill-conditioned targets ------------------------------------------------
 
 __global__ void k_zero_count(int32_t* c) { *c = 0; }
+__global__ void k_zero_u64(unsigned long long* c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
 
 template <int OP>
 __global__ __launch_bounds__(256) void k_fixup(const PairArgs a) {
@@ -222,6 +225,11 @@ hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st) {
 
 hipError_t launch_zero_count(int32_t* c, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, c, n);
     return hipGetLastError();
 }
 

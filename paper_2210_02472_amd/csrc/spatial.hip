@@ -179,12 +179,26 @@ __global__ __launch_bounds__(T) void k_pack_tiles(const PairArgs a, double4* nea
     const double acy = 0.5 * ((double)w[1] + (double)w[4]);
     const double acz = 0.5 * ((double)w[2] + (double)w[5]);
     constexpr int kMeta = OP == OP_GRAD ? 2 : 1;
+    // G * tile mass (for the far-tile magnitude bound) and the half-extent of the accelerations
+    const float gm = (float)(a.G * a.P.m[p]);
+    float gsum = ok ? gm : 0.f;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) gsum += __shfl_xor(gsum, off);
+    __shared__ float redM[T / 64];
+    if (lane == 0) redM[wave] = gsum;
+    __syncthreads();
+    float gm_tile = 0.f;
+    for (int u = 0; u < T / 64; ++u) gm_tile += redM[u];
+    gm_tile *= 1.0f + 1e-5f;  // rounding margin of the FP32 sum
+    float ha = fmaxf(fmaxf(w[3] - w[0], w[4] - w[1]), w[5] - w[2]) * 0.5f;
+    const float amaxa = fmaxf(fmaxf(fabsf(w[0]), fabsf(w[3])),
+                              fmaxf(fmaxf(fabsf(w[1]), fabsf(w[4])), fmaxf(fabsf(w[2]), fabsf(w[5]))));
+    ha = ha * (1.0f + 1e-6f) + amaxa * 1.2e-7f;
     if (threadIdx.x == 0) {
-        meta[kMeta * blockIdx.x] = make_double4(cx, cy, cz, pack_gm(h));
-        if constexpr (OP == OP_GRAD) meta[kMeta * blockIdx.x + 1] = make_double4(acx, acy, acz, 0.0);
+        meta[kMeta * blockIdx.x] = make_double4(cx, cy, cz, __builtin_bit_cast(double, make_float2(h, gm_tile)));
+        if constexpr (OP == OP_GRAD) meta[kMeta * blockIdx.x + 1] = make_double4(acx, acy, acz, pack_gm(ha));
     }
     if (!ok) return;
-    const float gm = (float)(a.G * a.P.m[p]);
     constexpr int S = OP == OP_GRAD ? 2 : 1;
     near_pack[S * s] = make_double4(x, y, z, pack_gm(gm));
     far_pack[S * s] = make_float4((float)(x - cx), (float)(y - cy), (float)(z - cz), gm);

@@ -47,10 +47,12 @@ def _flags_clean(ctx):
 
 @pytest.fixture(params=["sorted", "unsorted"])
 def sort_mode(ctx, request):
-    """Run a test with the spatially sorted mixed kernels on (default) and off."""
-    ctx.set_spatial_sort(request.param == "sorted")
+    """Run a test with the spatially sorted mixed kernels on for both passes and off for both
+    (the default is the gradient pass only)."""
+    on = request.param == "sorted"
+    ctx.set_spatial_sort(forces=on, gradient=on)
     yield request.param
-    ctx.set_spatial_sort(True)
+    ctx.set_spatial_sort(forces=False, gradient=True, kappa=3.0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -150,8 +152,9 @@ def test_forces_config_invariance_and_determinism(ctx, prec):
 @pytest.mark.parametrize("op", ["forces", "gradient"])
 def test_sorted_mode_king_cluster(ctx, op):
     """A 20,000-body King W0 = 6 cluster with Kroupa masses and binaries: the spatially sorted
-    mixed kernels (near tiles in FP64 differences, far tiles from FP32 tile offsets) and the
-    unsorted ones both meet the mixed tolerance against the oracle, on all targets and on a list."""
+    mixed kernels (near tiles in FP64 differences, far tiles from FP32 tile offsets), at the
+    default near threshold and at the smallest one accepted, and the unsorted ones all meet the
+    mixed tolerance against the oracle, on all targets and on a list."""
     d = ics.king_cluster(ics.rng_for(102), 20000, 6.0, 0.01)
     P, Pd = oracle.Particles.from_dict(d), _dev(d)
     T = np.sort(np.random.default_rng(11).choice(20000, 700, replace=False))
@@ -164,17 +167,19 @@ def test_sorted_mode_king_cluster(ctx, op):
         ref = oracle.gradient(P, af, T, None)
         acc = [torch.as_tensor(np.ascontiguousarray(af[:, k]), device="cuda") for k in range(3)]
     try:
-        for mode in (True, False):
-            ctx.set_spatial_sort(mode)
+        for mode, kappa in ((True, 3.0), (True, 0.5), (False, 3.0)):
+            ctx.set_spatial_sort(forces=mode, gradient=mode, kappa=kappa)
             for targets in (None, T):
                 if op == "forces":
                     out = ctx.forces(Pd, targets, None, prec="mixed", r_fb=0.0)
                 else:
                     out = ctx.force_gradient(Pd, acc, targets, None, prec="mixed", r_fb=0.0)
                 rms, mx = stats(rel_errors(gather(out, T), ref))
-                assert rms <= RMS_TOL and mx <= MAX_TOL, (mode, targets is None, rms, mx)
+                assert rms <= RMS_TOL and mx <= MAX_TOL, (mode, kappa, targets is None, rms, mx)
+        with pytest.raises(bf.BifrostError):
+            ctx.set_spatial_sort(gradient=True, kappa=0.25)
     finally:
-        ctx.set_spatial_sort(True)
+        ctx.set_spatial_sort(forces=False, gradient=True, kappa=3.0)
     _flags_clean(ctx)
 
 

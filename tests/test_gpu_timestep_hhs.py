@@ -114,3 +114,51 @@ def test_hhs_single_level_matches_fsi(ctx):
     ctx.fsi_step(B, 1e-3, prec="fp64")
     for k in ("x", "vy"):
         assert torch.allclose(getattr(A, k), getattr(B, k), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_hhs_adaptive_parity(ctx, prec):
+    """The adaptive interval (time-steps assigned on every level, capped by the initial ones)
+    against the oracle recursion on a softened Kroupa Plummer sphere.  Both sides must take the
+    same slow / fast decisions, so the case is one where every time-step the oracle compares
+    lies clear of its pivot (relative gap > 1e-9 in FP64, > 1e-4 in mixed precision)."""
+    n, kmax, tau, eta, eps2 = 700, 6, 1.0 / 64, 0.05, 1e-6
+    d = _cluster(n, 9)
+    P, Pd = oracle.Particles.from_dict(d), bf.Particles.from_numpy(d)
+    ff, fb = oracle.dt_min(P, eta_ff=eta, eta_fb=eta)
+    dt0 = np.minimum(ff, fb)
+    P0 = P.copy()
+    trace = []
+    oracle.hhs_interval_adaptive(P, dt0, tau, kmax, eta, eta, eps2=eps2, trace=trace)
+    gap = min(t[4] for t in trace)
+    assert gap > (1e-9 if prec == "fp64" else 1e-4), gap
+    assert max(t[0] for t in trace) >= 3
+    ml, nl = ctx.hhs_interval_adaptive(Pd, torch.as_tensor(dt0, device="cuda"), kmax, tau, eta, eta, eps2=eps2,
+                                       prec=prec)
+    assert (ml, nl) == (max(t[0] for t in trace), len(trace))
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        ref = getattr(P, k)
+        got = getattr(Pd, k).cpu().numpy()
+        if prec == "fp64":
+            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
+        else:
+            change = np.abs(ref - getattr(P0, k)).max()
+            assert np.abs(got - ref).max() <= MAX_TOL * change, k
+    assert ctx.read_flags() & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
+
+
+def test_hhs_adaptive_fixed_level_equivalence(ctx):
+    """With huge eta the level-0 cap decides every level, and the adaptive driver reproduces the
+    fixed-level driver on the device (to FP64 rounding: the fast sets are held in a different
+    order, so sums run in a different order)."""
+    n, tau = 800, 2e-3
+    d = _cluster(n, 10)
+    lv = np.random.default_rng(12).choice([0, 1, 2, 3], size=n, p=[0.4, 0.3, 0.2, 0.1]).astype(np.int32)
+    A, B = bf.Particles.from_numpy(d), bf.Particles.from_numpy(d)
+    dt0 = torch.as_tensor(1.5 * tau / 2.0 ** lv, device="cuda")
+    ml, _ = ctx.hhs_interval_adaptive(A, dt0, 5, tau, 1e9, 1e9, prec="fp64")
+    ctx.hhs_interval(B, torch.as_tensor(lv, device="cuda"), 5, tau, prec="fp64")
+    assert ml == 3
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        a, b = getattr(A, k), getattr(B, k)
+        assert (a - b).abs().max().item() <= 1e-13 * b.abs().max().item(), k

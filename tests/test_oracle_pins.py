@@ -466,3 +466,69 @@ def test_hhs_fourth_order_energy():
             oracle.hhs_interval(P, lv, tau)
         errs.append(abs(sum(oracle.energy(P)) / E0 - 1))
     assert 11 < errs[0] / errs[1] < 21, errs
+
+
+# --------------------------------------------------------------------------------------------
+# HHS-FSI with time-steps assigned on every level (Sec. 2.2; Sec. 3.5.1, level-0 minimum)
+# --------------------------------------------------------------------------------------------
+
+def test_hhs_adaptive_reduces_to_fixed_levels():
+    """When the pairwise time-steps on every level exceed the interval's initial ones (huge eta),
+    the level-0 cap keeps each particle at the level its initial time-step gives, and the
+    adaptive interval is the fixed-level interval, bit for bit."""
+    P0 = Particles.from_dict(ics.plummer_cluster(ics.rng_for(57), 90, "kroupa"))
+    tau, kmax = 4e-3, 5
+    lv = np.random.default_rng(8).choice([0, 1, 2, 4], size=P0.n, p=[0.4, 0.3, 0.2, 0.1])
+    dt0 = 1.5 * tau / 2.0 ** lv
+    A, B = P0.copy(), P0.copy()
+    trace = []
+    oracle.hhs_interval_adaptive(A, dt0, tau, kmax, eta_ff=1e9, eta_fb=1e9, trace=trace)
+    oracle.hhs_interval(B, lv, tau)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        np.testing.assert_array_equal(getattr(A, k), getattr(B, k))
+    assert max(t[0] for t in trace) == 4
+
+
+def test_hhs_adaptive_all_slow_is_fsi():
+    P0 = Particles.from_dict(ics.plummer_cluster(ics.rng_for(58), 40, "equal"))
+    A, B = P0.copy(), P0.copy()
+    oracle.hhs_interval_adaptive(A, np.full(P0.n, 1.0), 1e-3, 6)
+    oracle.fsi_step(B, 1e-3)
+    np.testing.assert_array_equal(A.x, B.x)
+    np.testing.assert_array_equal(A.vz, B.vz)
+
+
+def test_hhs_adaptive_level_zero_cap():
+    """A particle whose pairwise time-step on a deeper level would exceed its initial one stays
+    fast on the level its initial time-step gives: with eta huge, dt0 alone decides."""
+    P0 = Particles.from_dict(ics.plummer_cluster(ics.rng_for(59), 30, "equal"))
+    dt0 = np.full(P0.n, 1.0)
+    dt0[3] = 0.3e-3  # fast at pivots 1e-3 and 0.5e-3, slow at 0.25e-3
+    trace = []
+    oracle.hhs_interval_adaptive(P0.copy(), dt0, 1e-3, 6, eta_ff=1e9, eta_fb=1e9, trace=trace)
+    assert [(t[0], t[2], t[3]) for t in trace] == [(0, 29, 1), (1, 0, 1), (2, 1, 0), (2, 1, 0),
+                                                   (1, 0, 1), (2, 1, 0), (2, 1, 0)]
+
+
+def test_hhs_adaptive_energy_error_scales_as_eta_to_the_fourth():
+    """Time-steps proportional to eta on every level: the energy error of the fourth-order
+    HHS-FSI falls as eta^4 (Sec. 5.1, Eq. fourthorder).  Softened 64-body Plummer sphere,
+    eight intervals; log-log slope of the largest relative energy error against eta."""
+    d = ics.plummer_cluster(ics.rng_for(301, 0), 64, "equal")
+    eps2, tau, kmax = 1e-2, 1.0 / 8, 12
+    etas = (0.4, 0.2, 0.1, 0.05)
+    errs, momenta = [], []
+    for eta in etas:
+        P = Particles.from_dict(d)
+        E0 = sum(oracle.energy(P, eps2=eps2))
+        p0 = (P.m[:, None] * P.vel()).sum(axis=0)
+        emax = 0.0
+        for _ in range(8):
+            ff, fb = oracle.dt_min(P, eta_ff=eta, eta_fb=eta)
+            oracle.hhs_interval_adaptive(P, np.minimum(ff, fb), tau, kmax, eta, eta, eps2=eps2)
+            emax = max(emax, abs(sum(oracle.energy(P, eps2=eps2)) / E0 - 1))
+        errs.append(emax)
+        momenta.append(np.abs((P.m[:, None] * P.vel()).sum(axis=0) - p0).max())
+    slope = np.polyfit(np.log(etas), np.log(errs), 1)[0]
+    assert 3.3 < slope < 4.8, (slope, errs)
+    assert max(momenta) < 1e-15
