@@ -36,8 +36,8 @@ PEAK_FP64_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.64
 # HBM traffic of the dominant kernel, measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE)
 # and scaled by the same counters' reading for a copy kernel of known size.  The figure is used
 # only while the kernel sources hash to the value recorded with it.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_GradMixed_king1m_hbm_traffic.txt")
-KERNEL_SOURCES = ["pair_ops.h", "pairs.hip", "bf_internal.h", "capi.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_sorted_GradMixed_king1m_hbm_traffic.txt")
+KERNEL_SOURCES = ["pair_ops.h", "pairs.hip", "spatial.hip", "bf_internal.h", "capi.hip"]
 
 
 def kernel_source_hash():
@@ -257,7 +257,7 @@ def main():
         del src, dst
     ctx = bf.Context(0)
     if args.spatial_sort != "default" or args.kappa:
-        mode = {"default": (False, True), "off": (False, False), "acc": (True, False), "grad": (False, True),
+        mode = {"default": (True, True), "off": (False, False), "acc": (True, False), "grad": (False, True),
                 "both": (True, True)}[args.spatial_sort]
         ctx.set_spatial_sort(forces=mode[0], gradient=mode[1], kappa=args.kappa)
     if args.autotune:
@@ -390,9 +390,11 @@ def main():
                    "spatial_sort": {"forces": sorted_a, "gradient": sorted_g}, "autotuned": bool(args.autotune),
                    "acc_kernel": {"k_per_lane": cfg_a[0], "waves": cfg_a[1], "split": cfg_a[2]},
                    "grad_kernel": {"k_per_lane": cfg_g[0], "waves": cfg_g[1], "split": cfg_g[2]}},
-        "roofline": {"bound": "alu", "kernel": "k_pairs<GradMixed> (force-gradient pass)",
+        "roofline": {"bound": "alu",
+                     "kernel": ("k_pairs_sorted<GradMixed>" if sorted_g else "k_pairs<GradMixed>") +
+                               " (force-gradient pass)",
                      "achieved": grad_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": grad_tflops / PEAK_FP32_TFLOPS, "traffic": measured_traffic(n),
+                     "frac": grad_tflops / PEAK_FP32_TFLOPS, "traffic": measured_traffic(n) if sorted_g else None,
                      "flops_per_pair": FLOPS_GRAD, "pairs_per_launch": pairs, "avg_kernel_ms": kg},
         "acc_pass": {"avg_kernel_ms": ka, "tflops": acc_tflops, "frac": acc_tflops / PEAK_FP32_TFLOPS,
                      "pairs_per_s": pairs / (ka * 1e-3)},

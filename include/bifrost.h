@@ -42,7 +42,7 @@ typedef enum {
     BF_ERR_HIP = -2,         /* a HIP runtime call failed (message in bf_last_error) */
     BF_ERR_NONFINITE = -3,   /* reserved for callers that turn BF_FLAG_NONFINITE into an error */
     BF_ERR_UNSUPPORTED = -4, /* no kernel variant for this request */
-    BF_ERR_NOMEM = -5        /* scratch allocation failed */
+    BF_ERR_NOMEM = -5        /* scratch allocation failed, or a caller buffer is too small */
 } bf_status;
 
 typedef enum {
@@ -307,6 +307,42 @@ BF_API int bf_graph_launch(bf_ctx *ctx, void *graph_exec);
 /* Free a captured graph (NULL accepted). */
 BF_API int bf_graph_destroy(void *graph_exec);
 
+/* ---- subsystems (Sec. 3.3) ------------------------------------------------------------ */
+
+/* Synchronising.  Neighbour pairs of the subsystem search (Sec. 3.3, Eqs. ngb-bound and
+ * ngb-unbound), FP64.  For every target i and source j != i closer than r_max, with
+ * mu = G (m_i + m_j), relative separation r, relative velocity v, E = v^2/2 - mu/r and
+ * h = |r x v|: a bound pair (E < 0, a = -mu / (2E)) is a neighbour if a < r_ngb or r < r_ngb;
+ * an unbound pair if r < r_ngb, or if its periapsis h^2 / (mu (1 + e)),
+ * e = sqrt(1 + 2 E h^2 / mu^2), lies below r_ngb and C r / |v| < tau (tau: the pivot time-step
+ * of the level, C < 1 a safety factor).  edges (device int32, 2 * cap entries, caller-owned)
+ * receives the pairs as rows (i, j), sorted by i then j; *n_edges (host) the number found.
+ * With targets = sources every pair appears in both orders.  If more than cap pairs are found,
+ * returns BF_ERR_NOMEM with *n_edges set to the number needed (edges then undefined).
+ * Distinct particles at zero separation are skipped and raise BF_FLAG_COINCIDENT. */
+BF_API int bf_neighbours(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, const bf_set *sources,
+                         double G, double r_ngb, double r_max, double C, double tau,
+                         int32_t *edges, int64_t cap, int64_t *n_edges);
+
+/* Synchronising.  Subsystems as the connected components of a neighbour graph (Sec. 3.3):
+ * label (device int32, n entries, caller-owned) receives for every particle the smallest
+ * particle index of its component, so a particle without neighbours carries its own index.
+ * edges: device int32 rows (i, j), m rows, indices in [0, n) (others raise BF_FLAG_BADINDEX
+ * and are ignored).  *n_subsystems (host, may be NULL): components with two or more members. */
+BF_API int bf_subsystems(bf_ctx *ctx, int64_t n, const int32_t *edges, int64_t m, int32_t *label,
+                         int64_t *n_subsystems);
+
+/* Exclude intra-subsystem pairs (Sec. 3.3, Alg. 1: accelerations ignore intra-subsystem
+ * contributions; time-steps of subsystem members ignore their own subsystem).  label: device
+ * int32, particle-indexed (n entries), e.g. from bf_subsystems; a pair (i, j) is skipped in the
+ * acceleration, force-gradient and time-step passes (and everything built on them: jerk, FSI,
+ * HHS) when label[i] == label[j].  The array is read by later calls and must stay valid until
+ * cleared with label = NULL.  Passes on a particle set of another size fail with BF_ERR_ARG;
+ * the batched ensemble calls fail with BF_ERR_UNSUPPORTED while labels are set.  bf_pn1_bh and
+ * bf_energy do not apply the exclusion.  The subsystems' own integration is outside this
+ * library. */
+BF_API int bf_set_subsystems(bf_ctx *ctx, const int32_t *label, int64_t n);
+
 /* ---- tuning ------------------------------------------------------------------------- */
 
 typedef enum { BF_OP_FORCES = 0, BF_OP_GRADIENT = 1, BF_OP_DTMIN = 2 } bf_op;
@@ -322,12 +358,12 @@ BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
 
 /* Spatially sorted mode of the mixed acceleration and gradient passes.  ops_mask selects the
  * passes that use it: bit (1 << BF_OP_FORCES) and/or bit (1 << BF_OP_GRADIENT); the default is
- * the gradient pass only.  When selected, and r_fb == 0, with at least 2048 sources and 512
+ * both.  When selected, and r_fb == 0, with at least 2048 sources and 512
  * targets, targets and sources are ordered along a Morton curve and the sources packed into
  * tiles; a tile whose gap to a workgroup's target box is at least kappa times its half-extent
  * is summed from FP32 offsets to the tile centre (pair separation rounding error at most
  * u (1 + 2 sqrt(3) / kappa) relative), nearer tiles from FP64 differences.  kappa = 0 keeps the
- * current value (default 3); otherwise it must lie in [0.5, 64] (BF_ERR_ARG).  Outputs stay
+ * current value (default 1); otherwise it must lie in [0.5, 64] (BF_ERR_ARG).  Outputs stay
  * particle-indexed; results keep the accuracy of the unsorted mixed path. */
 BF_API int bf_set_spatial_sort(bf_ctx *ctx, int ops_mask, double kappa);
 

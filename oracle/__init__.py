@@ -43,9 +43,10 @@ def _load():
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         D = ctypes.c_double
-        lib.oracle_forces.argtypes = [P, P, P, P, I64, P, I64, P, D, D, P, P, P, P, P]
-        lib.oracle_gradient.argtypes = [P, P, P, P, P, P, P, I64, P, I64, P, D, D, P, P, P, P, P]
-        lib.oracle_dt_min.argtypes = [P, P, P, P, P, P, P, I64, P, I64, P, D, D, D, P, P, P]
+        lib.oracle_forces.argtypes = [P, P, P, P, I64, P, I64, P, P, D, D, P, P, P, P, P]
+        lib.oracle_gradient.argtypes = [P, P, P, P, P, P, P, I64, P, I64, P, P, D, D, P, P, P, P, P]
+        lib.oracle_dt_min.argtypes = [P, P, P, P, P, P, P, I64, P, I64, P, P, D, D, D, P, P, P]
+        lib.oracle_neighbours.argtypes = [P, P, P, P, P, P, P, I64, P, I64, P, D, D, D, D, D, P]
         lib.oracle_pn1.argtypes = [P, P, P, P, P, P, P, P, I64, P, I64, P, D, D, P, P, P, P]
         lib.oracle_energy.argtypes = [P, P, P, P, P, P, P, I64, P, D, D, P, P, P]
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -112,18 +113,30 @@ def _check(p: Particles):
         assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == (p.n,)
 
 
+def _sub(sub, n: int):
+    """Particle-indexed subsystem labels as int64 (or None: no exclusion)."""
+    if sub is None:
+        return None
+    a = np.ascontiguousarray(sub, dtype=np.int64)
+    assert a.shape == (n,)
+    return a
+
+
 def forces(p: Particles, targets=None, sources=None, G: float = 1.0, eps2: float = 0.0,
-           return_mag: bool = False):
+           return_mag: bool = False, sub=None):
     """Newtonian accelerations of `targets` from `sources` (Sec. 2.1, Eq. new-newton-acc).
 
     Returns an (nt, 3) array indexed by target slot (and optionally the per-target
-    sum of term magnitudes and the count of coincident distinct pairs)."""
+    sum of term magnitudes and the count of coincident distinct pairs).  With `sub`
+    (particle-indexed subsystem labels) pairs inside one subsystem are left out (Alg. 1)."""
     _check(p)
     t, s = _idx(targets, p.n), _idx(sources, p.n)
+    sb = _sub(sub, p.n)
     nt = t.size
     ax, ay, az, mag = (np.zeros(nt) for _ in range(4))
     nco = ctypes.c_int64(0)
     _load().oracle_forces(_ptr(p.x), _ptr(p.y), _ptr(p.z), _ptr(p.m), nt, _ptr(t), s.size, _ptr(s),
+                          _ptr(sb) if sb is not None else None,
                           float(G), float(eps2), _ptr(ax), _ptr(ay), _ptr(az), _ptr(mag),
                           ctypes.byref(nco))
     a = np.stack([ax, ay, az], axis=1)
@@ -131,7 +144,7 @@ def forces(p: Particles, targets=None, sources=None, G: float = 1.0, eps2: float
 
 
 def gradient(p: Particles, acc_full: np.ndarray, targets=None, sources=None, G: float = 1.0,
-             eps2: float = 0.0, return_mag: bool = False):
+             eps2: float = 0.0, return_mag: bool = False, sub=None):
     """Force-gradient sum Gsum (Sec. 2.1, Eq. new-grad-acc; inter-level form Sec. 2.2).
 
     `acc_full` is an (n, 3) particle-indexed array of the accelerations that enter
@@ -144,23 +157,27 @@ def gradient(p: Particles, acc_full: np.ndarray, targets=None, sources=None, G: 
     nt = t.size
     gx, gy, gz, mag = (np.zeros(nt) for _ in range(4))
     nco = ctypes.c_int64(0)
+    sb = _sub(sub, p.n)
     _load().oracle_gradient(_ptr(p.x), _ptr(p.y), _ptr(p.z), _ptr(p.m), _ptr(axf), _ptr(ayf), _ptr(azf),
-                            nt, _ptr(t), s.size, _ptr(s), float(G), float(eps2),
+                            nt, _ptr(t), s.size, _ptr(s), _ptr(sb) if sb is not None else None,
+                            float(G), float(eps2),
                             _ptr(gx), _ptr(gy), _ptr(gz), _ptr(mag), ctypes.byref(nco))
     g = np.stack([gx, gy, gz], axis=1)
     return (g, mag, int(nco.value)) if return_mag else g
 
 
 def dt_min(p: Particles, targets=None, sources=None, G: float = 1.0, eta_ff: float = 0.2,
-           eta_fb: float = 0.2):
+           eta_fb: float = 0.2, sub=None):
     """Free-fall and fly-by time-steps (Sec. 3.5.3, Eqs. dt-freefall, dt-flyby); returns (dt_ff, dt_fb)."""
     _check(p)
     t, s = _idx(targets, p.n), _idx(sources, p.n)
     nt = t.size
     ff, fb = np.zeros(nt), np.zeros(nt)
     nco = ctypes.c_int64(0)
+    sb = _sub(sub, p.n)
     _load().oracle_dt_min(_ptr(p.x), _ptr(p.y), _ptr(p.z), _ptr(p.vx), _ptr(p.vy), _ptr(p.vz), _ptr(p.m),
-                          nt, _ptr(t), s.size, _ptr(s), float(G), float(eta_ff), float(eta_fb),
+                          nt, _ptr(t), s.size, _ptr(s), _ptr(sb) if sb is not None else None,
+                          float(G), float(eta_ff), float(eta_fb),
                           _ptr(ff), _ptr(fb), ctypes.byref(nco))
     return ff, fb
 
@@ -253,24 +270,27 @@ def _drift(p: Particles, idx: np.ndarray, h: float):
 
 
 def fsi_step(p: Particles, dt: float, subset=None, G: float = 1.0, eps2: float = 0.0,
-             bh=None, c: float = 1e4) -> Particles:
+             bh=None, c: float = 1e4, sub=None) -> Particles:
     """One FSI cycle over `subset` in place (Sec. 2.1, Eq. fsi-cycle):
     kick eps/6, drift eps/2, gradient kick 2eps/3, drift eps/2, kick eps/6.
     With `bh` given, the cycle is wrapped in two PN1.0 half-kicks evaluated at the
-    current state (Sec. 3.8, the e^{eps/2 U_PN} e^{eps H_FSI} e^{eps/2 U_PN} composition)."""
+    current state (Sec. 3.8, the e^{eps/2 U_PN} e^{eps H_FSI} e^{eps/2 U_PN} composition).
+    With `sub` (subsystem labels) the accelerations and gradient sums leave out intra-subsystem
+    pairs (Alg. 1); every particle still drifts (the subsystems' own integration, which would
+    replace their drift, is outside this oracle)."""
     idx = _idx(subset, p.n)
     if bh is not None and len(bh):
         _kick(p, idx, pn1(p, bh, idx, idx, G, c), dt / 2)
-    a = forces(p, idx, idx, G, eps2)
+    a = forces(p, idx, idx, G, eps2, sub=sub)
     _kick(p, idx, a, dt / 6)
     _drift(p, idx, dt / 2)
-    a = forces(p, idx, idx, G, eps2)
+    a = forces(p, idx, idx, G, eps2, sub=sub)
     full = np.zeros((p.n, 3))
     full[idx] = a
-    g = gradient(p, full, idx, idx, G, eps2)
+    g = gradient(p, full, idx, idx, G, eps2, sub=sub)
     _kick(p, idx, a + (dt * dt / 24.0) * g, 2.0 * dt / 3.0)
     _drift(p, idx, dt / 2)
-    a = forces(p, idx, idx, G, eps2)
+    a = forces(p, idx, idx, G, eps2, sub=sub)
     _kick(p, idx, a, dt / 6)
     if bh is not None and len(bh):
         _kick(p, idx, pn1(p, bh, idx, idx, G, c), dt / 2)
@@ -372,3 +392,49 @@ def hhs_interval_adaptive(p: Particles, dt0: np.ndarray, tau: float, kmax: int, 
     a = _interlevel_acc(p, S, F, G, eps2)
     _kick(p, both, a[both], tau / 6)
     return p
+
+
+
+# ---------------------------------------------------------------------------------------------
+# Subsystems (Sec. 3.3): neighbour search and connected components.
+# ---------------------------------------------------------------------------------------------
+
+def neighbours(p: Particles, targets=None, sources=None, G: float = 1.0, r_ngb: float = 1e-3,
+               r_max: float = 0.1, C: float = 0.5, tau: float = 1e-3) -> np.ndarray:
+    """Neighbour pairs (Sec. 3.3, Eqs. ngb-bound, ngb-unbound): an (m, 2) int64 array of
+    (target particle, source particle) rows, sorted, for every pair closer than r_max that
+    meets the bound or unbound criterion."""
+    _check(p)
+    t, s = _idx(targets, p.n), _idx(sources, p.n)
+    out = np.zeros(t.size * s.size, dtype=np.uint8)
+    _load().oracle_neighbours(_ptr(p.x), _ptr(p.y), _ptr(p.z), _ptr(p.vx), _ptr(p.vy), _ptr(p.vz), _ptr(p.m),
+                              t.size, _ptr(t), s.size, _ptr(s), float(G), float(r_ngb), float(r_max), float(C),
+                              float(tau), out.ctypes.data_as(ctypes.c_void_p))
+    k, q = np.nonzero(out.reshape(t.size, s.size))
+    e = np.stack([t[k], s[q]], axis=1)
+    return e[np.lexsort((e[:, 1], e[:, 0]))] if e.size else e.reshape(0, 2)
+
+
+def subsystems(n: int, edges: np.ndarray) -> np.ndarray:
+    """Subsystem label of every particle: the components of the neighbour graph, found by
+    depth-first search from each particle not yet visited (Sec. 3.3).  A component's label is
+    its smallest particle index, so a particle without neighbours is labelled by itself."""
+    adj = [[] for _ in range(n)]
+    for i, j in np.asarray(edges, dtype=np.int64):
+        adj[i].append(j)
+        adj[j].append(i)
+    label = np.full(n, -1, dtype=np.int64)
+    for start in range(n):
+        if label[start] >= 0:
+            continue
+        comp, stack = [], [start]
+        label[start] = start
+        while stack:
+            v = stack.pop()
+            comp.append(v)
+            for w in adj[v]:
+                if label[w] < 0:
+                    label[w] = start
+                    stack.append(w)
+        label[comp] = min(comp)
+    return label

@@ -17,6 +17,11 @@
  *     zero separation (only possible with eps2 == 0) contributes nothing and
  *     increments *n_coincident (reading of an undefined case).
  *
+ *   - `sub` (particle-indexed subsystem labels, or NULL): a pair whose two
+ *     particles carry the same label is skipped.  Accelerations, gradient
+ *     sums and time-steps ignore intra-subsystem pairs (Sec. 3.3, Alg. 1 and
+ *     the time-step assignment of subsystem particles).
+ *
  * Each target is independent, so the outer loop carries an OpenMP pragma; the
  * inner loop is the definition summed in source order.
  */
@@ -29,7 +34,7 @@
  * to state FP64 tolerances). */
 void oracle_forces(const double *x, const double *y, const double *z, const double *m,
                    int64_t nt, const int64_t *tgt, int64_t ns, const int64_t *src,
-                   double G, double eps2,
+                   const int64_t *sub, double G, double eps2,
                    double *ax, double *ay, double *az, double *mag, int64_t *n_coincident)
 {
     int64_t coinc = 0;
@@ -40,6 +45,7 @@ void oracle_forces(const double *x, const double *y, const double *z, const doub
         for (int64_t q = 0; q < ns; ++q) {
             const int64_t j = src[q];
             if (j == i) continue;
+            if (sub && sub[j] == sub[i]) continue;  /* same subsystem */
             const double rx = x[j] - x[i], ry = y[j] - y[i], rz = z[j] - z[i];
             const double s2 = rx * rx + ry * ry + rz * rz + eps2;
             if (s2 == 0.0) { ++coinc; continue; }
@@ -63,7 +69,7 @@ void oracle_forces(const double *x, const double *y, const double *z, const doub
 void oracle_gradient(const double *x, const double *y, const double *z, const double *m,
                      const double *ax, const double *ay, const double *az,
                      int64_t nt, const int64_t *tgt, int64_t ns, const int64_t *src,
-                     double G, double eps2,
+                     const int64_t *sub, double G, double eps2,
                      double *gx, double *gy, double *gz, double *mag, int64_t *n_coincident)
 {
     int64_t coinc = 0;
@@ -74,6 +80,7 @@ void oracle_gradient(const double *x, const double *y, const double *z, const do
         for (int64_t q = 0; q < ns; ++q) {
             const int64_t j = src[q];
             if (j == i) continue;
+            if (sub && sub[j] == sub[i]) continue;  /* same subsystem */
             const double rx = x[j] - x[i], ry = y[j] - y[i], rz = z[j] - z[i];
             const double s2 = rx * rx + ry * ry + rz * rz + eps2;
             if (s2 == 0.0) { ++coinc; continue; }
@@ -102,7 +109,7 @@ void oracle_gradient(const double *x, const double *y, const double *z, const do
 void oracle_dt_min(const double *x, const double *y, const double *z,
                    const double *vx, const double *vy, const double *vz, const double *m,
                    int64_t nt, const int64_t *tgt, int64_t ns, const int64_t *src,
-                   double G, double eta_ff, double eta_fb,
+                   const int64_t *sub, double G, double eta_ff, double eta_fb,
                    double *dt_ff, double *dt_fb, int64_t *n_coincident)
 {
     int64_t coinc = 0;
@@ -113,6 +120,7 @@ void oracle_dt_min(const double *x, const double *y, const double *z,
         for (int64_t q = 0; q < ns; ++q) {
             const int64_t j = src[q];
             if (j == i) continue;
+            if (sub && sub[j] == sub[i]) continue;  /* same subsystem */
             const double rx = x[j] - x[i], ry = y[j] - y[i], rz = z[j] - z[i];
             const double r = sqrt(rx * rx + ry * ry + rz * rz);
             if (r == 0.0) { ++coinc; continue; }
@@ -228,3 +236,48 @@ void oracle_set_num_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 int oracle_num_threads(void) { return 1; }
 void oracle_set_num_threads(int n) { (void)n; }
 #endif
+
+/* Subsystem neighbour criterion (Sec. 3.3, Eqs. ngb-bound and ngb-unbound) for
+ * every target/source pair: out[k * ns + q] = 1 if source src[q] is a neighbour
+ * of target tgt[k], else 0.  Only pairs closer than r_max are examined.  With
+ * mu = G (m_i + m_j), relative separation r and velocity v, specific energy
+ * E = v^2/2 - mu/r and specific angular momentum h = |r x v|:
+ *   bound (E < 0), semi-major axis a = -mu / (2E):  a < r_ngb  or  r < r_ngb;
+ *   unbound (E >= 0): periapsis r_p = h^2 / (mu (1 + e)), e = sqrt(1 + 2 E h^2 / mu^2);
+ *     r < r_ngb,  or  r_p < r_ngb and C r / |v| < tau.                            */
+void oracle_neighbours(const double *x, const double *y, const double *z,
+                       const double *vx, const double *vy, const double *vz, const double *m,
+                       int64_t nt, const int64_t *tgt, int64_t ns, const int64_t *src,
+                       double G, double r_ngb, double r_max, double C, double tau,
+                       unsigned char *out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        const int64_t i = tgt[k];
+        for (int64_t q = 0; q < ns; ++q) {
+            const int64_t j = src[q];
+            unsigned char nb = 0;
+            if (j != i) {
+                const double rx = x[j] - x[i], ry = y[j] - y[i], rz = z[j] - z[i];
+                const double ux = vx[j] - vx[i], uy = vy[j] - vy[i], uz = vz[j] - vz[i];
+                const double r = sqrt(rx * rx + ry * ry + rz * rz);
+                if (r < r_max) {
+                    const double mu = G * (m[i] + m[j]);
+                    const double v2 = ux * ux + uy * uy + uz * uz;
+                    const double E = 0.5 * v2 - mu / r;
+                    if (E < 0.0) {
+                        const double a = -mu / (2.0 * E);
+                        nb = (a < r_ngb) || (r < r_ngb);
+                    } else {
+                        const double hx = ry * uz - rz * uy, hy = rz * ux - rx * uz, hz = rx * uy - ry * ux;
+                        const double h2 = hx * hx + hy * hy + hz * hz;
+                        const double e = sqrt(1.0 + 2.0 * E * h2 / (mu * mu));
+                        const double rp = h2 / (mu * (1.0 + e));
+                        nb = (r < r_ngb) || (rp < r_ngb && C * r / sqrt(v2) < tau);
+                    }
+                }
+            }
+            out[k * ns + q] = nb;
+        }
+    }
+}

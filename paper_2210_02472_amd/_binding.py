@@ -23,6 +23,7 @@ BF_FLAG_NONFINITE = 0x1
 BF_FLAG_COINCIDENT = 0x2
 BF_FLAG_BADINDEX = 0x4
 BF_A_VALID = 0x1
+BF_ERR_NOMEM = -5
 BF_OP_FORCES, BF_OP_GRADIENT, BF_OP_DTMIN = 0, 1, 2
 
 PRECISIONS = {"fp64": BF_PREC_FP64, "mixed": BF_PREC_MIXED}
@@ -104,6 +105,9 @@ def load_library(path: str = LIB_PATH):
         "bf_set_config": [_vp, _int, _int, _int, _int, _int],
         "bf_enable_timing": [_vp, _int],
         "bf_set_spatial_sort": [_vp, _int, ctypes.c_double],
+        "bf_neighbours": [_vp, P, S, S, _d, _d, _d, _d, _d, _vp, _i64, ctypes.POINTER(_i64)],
+        "bf_subsystems": [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i64)],
+        "bf_set_subsystems": [_vp, _vp, _i64],
         "bf_last_pass_stats": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
         "bf_kernel_times": [_vp, _int, ctypes.POINTER(ctypes.c_float), _int, ctypes.POINTER(_int)],
     }
@@ -439,11 +443,52 @@ class Context:
                                                              ctypes.byref(nf)))
         return f.value, nn.value, nf.value
 
-    def set_spatial_sort(self, forces: bool = False, gradient: bool = True, kappa: float = 0.0):
-        """Select the passes that use the spatially sorted mixed kernels; kappa = 0 keeps the
-        near-tile threshold (default 3)."""
+    def set_spatial_sort(self, forces: bool = True, gradient: bool = True, kappa: float = 0.0):
+        """Select the passes that use the spatially sorted mixed kernels (default: both); kappa = 0
+        keeps the near-tile threshold (default 1)."""
         mask = (int(bool(forces)) << BF_OP_FORCES) | (int(bool(gradient)) << BF_OP_GRADIENT)
         _check("bf_set_spatial_sort", _lib.bf_set_spatial_sort(self._h, mask, float(kappa)))
+
+    # ---- subsystems --------------------------------------------------------------------------
+
+    def neighbours(self, P: Particles, targets=None, sources=None, G=1.0, r_ngb=1e-3, r_max=0.1, C=0.5, tau=1e-3,
+                   cap: int = 1 << 16) -> torch.Tensor:
+        """Neighbour pairs (i, j) as an (m, 2) int32 device tensor, sorted (Sec. 3.3)."""
+        t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
+        while True:
+            edges = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=P.m.device)
+            m = _i64(0)
+            rc = _lib.bf_neighbours(self._h, ctypes.byref(P._c()), ctypes.byref(t._c()),
+                                    ctypes.byref(s._c()), float(G), float(r_ngb), float(r_max), float(C),
+                                    float(tau), _ptr(edges), int(cap), ctypes.byref(m))
+            if rc == BF_ERR_NOMEM and m.value > cap:
+                cap = m.value
+                continue
+            _check("bf_neighbours", rc)
+            return edges[:m.value]
+
+    def subsystems(self, n: int, edges: torch.Tensor):
+        """(labels, number of subsystems): components of the neighbour graph, each labelled by
+        its smallest particle index."""
+        e = edges.contiguous()
+        _need(e, torch.int32, None, "edges")
+        label = torch.empty(n, dtype=torch.int32, device=e.device)
+        ns = _i64(0)
+        _check("bf_subsystems", _lib.bf_subsystems(self._h, int(n), _ptr(e) if e.numel() else None,
+                                                   int(e.shape[0]) if e.numel() else 0, _ptr(label),
+                                                   ctypes.byref(ns)))
+        return label, ns.value
+
+    def set_subsystems(self, label: Optional[torch.Tensor]):
+        """Exclude pairs with equal labels from later acc / gradient / time-step passes (None clears).
+        The context keeps a reference to the tensor until cleared."""
+        if label is None:
+            self._sub = None
+            _check("bf_set_subsystems", _lib.bf_set_subsystems(self._h, None, 0))
+            return
+        _need(label, torch.int32, None, "label")
+        self._sub = label
+        _check("bf_set_subsystems", _lib.bf_set_subsystems(self._h, _ptr(label), int(label.numel())))
 
     def enable_timing(self, on: bool = True):
         _check("bf_enable_timing", _lib.bf_enable_timing(self._h, int(on)))

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_batch_fixup(const Batch b) {
         const int32_t p = b.aidx[a];            // checked by the reduction before queueing
         const DevSet src{nullptr, (int32_t)(ce - cb), (int32_t)cb};
         double r[3];
-        fix_one<OP>(b.base.P, src, p, b.base.G, b.base.eps2, b.base.flags, r);
+        fix_one<OP>(b.base.P, src, nullptr, p, b.base.G, b.base.eps2, b.base.flags, r);
         if (threadIdx.x == 0) { b.o0[p] = r[0]; b.o1[p] = r[1]; b.o2[p] = r[2]; }
         __syncthreads();
     }
@@ -268,6 +268,9 @@ static int batch_setup(bf_ctx* c, const bf_particles* P, int32_t nclusters, cons
     if (max_active < 0 || max_active > INT32_MAX || max_cluster_n <= 0 || max_cluster_n > P->n)
         return bf_internal_fail(BF_ERR_ARG, "bad bounds");
     if (prec != BF_PREC_FP64 && prec != BF_PREC_MIXED) return bf_internal_fail(BF_ERR_ARG, "bad prec");
+    if (c->sub)
+        return bf_internal_fail(BF_ERR_UNSUPPORTED, "batched ensembles take no subsystem exclusion "
+                                                    "(clear it with bf_set_subsystems(ctx, NULL, 0))");
     if (!(eps2 >= 0 && eps2 < INFINITY) || !(r_fb >= 0 && r_fb < INFINITY) || !(G > -INFINITY && G < INFINITY))
         return bf_internal_fail(BF_ERR_ARG, "bad G, eps2 or r_fb");
     b = Batch{};
@@ -300,7 +303,7 @@ static int batch_setup(bf_ctx* c, const bf_particles* P, int32_t nclusters, cons
     b.bad = b.counter + 1;
     b.base.fix_count = b.bad + nclusters;
     b.base.fix_list = b.base.fix_count + 1;
-    b.base.cond_max = kCondMax;
+    b.base.cond_max = cond_max_for(op);
     return BF_OK;
 }
 

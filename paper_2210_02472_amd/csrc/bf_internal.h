@@ -52,6 +52,7 @@ struct PairArgs {
     int32_t* fix_list;     // [tgt.count] target slots queued for the FP64 fix-up
     int32_t* fix_count;    // number of queued slots
     unsigned long long* tile_stats;  // sorted mode: [near tiles, far tiles] visited (NULL: not counted)
+    const int32_t* sub;    // particle-indexed subsystem labels (NULL: no exclusion)
     uint32_t* flags;
 };
 
@@ -67,9 +68,9 @@ struct KernelConfig {
 hipError_t launch_pairs(int op, int prec, const KernelConfig& cfg, const PairArgs& a, int nblocks,
                         hipStream_t st);
 // Is (k, waves) an instantiated variant?
-bool variant_exists(int op, int prec, int k, int waves);
+bool variant_exists(int op, int prec, int k, int waves, bool excl = false);
 // Resident workgroups per CU for a variant (occupancy API), 0 if unknown.
-int variant_blocks_per_cu(int op, int prec, int k, int waves);
+int variant_blocks_per_cu(int op, int prec, int k, int waves, bool excl = false);
 // Bytes per packed source for op/prec.
 int pack_bytes(int op, int prec);
 
@@ -80,7 +81,9 @@ hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_zero_count(int32_t* c, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st);
-hipError_t launch_fixup(int op, const PairArgs& a, int nblocks, hipStream_t st);
+// FP64 fix-up of queued targets; part: kFixChunks * 3 * kFixTiled doubles of scratch.
+constexpr int kFixTiled = 32768, kFixChunks = 32;
+hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hipStream_t st);
 
 // Spatially sorted mixed acc/grad (spatial.hip).
 struct SortBuffers {
@@ -122,6 +125,26 @@ struct TimestepArgs {
     uint32_t* flags;
 };
 hipError_t launch_timestep(const TimestepArgs& t, hipStream_t st);
+// Subsystem neighbour search (ngb.hip).
+struct NgbArgs {
+    Masters P;
+    DevSet tgt, src;
+    double G, r_ngb, r_max2, C, tau;
+    int32_t split, chunk;         // source chunks per target slab, sources per chunk
+    unsigned long long* keys;     // [cap] found pairs (i << 32 | j), unordered
+    int64_t cap;
+    unsigned long long* count;    // pairs found (may exceed cap)
+    uint32_t* flags;
+};
+hipError_t launch_ngb(const NgbArgs& a, int waves, int nblocks, hipStream_t st);
+size_t ngb_sort_tmp_bytes(int64_t m);
+hipError_t launch_ngb_finish(unsigned long long* keys_in, unsigned long long* keys_out, int64_t m, void* tmp,
+                             size_t tmp_bytes, int32_t* edges, hipStream_t st);
+hipError_t launch_label_init(int32_t* label, int64_t n, int32_t* changed, hipStream_t st);
+hipError_t launch_label_round(const int32_t* edges, int64_t m, int64_t n, int32_t* label, int32_t* changed,
+                              uint32_t* flags, hipStream_t st);
+hipError_t launch_label_count(const int32_t* label, int64_t n, int32_t* mark, int32_t* count, hipStream_t st);
+
 size_t level_sort_tmp_bytes(int n);
 hipError_t launch_pivot_flags(const DevSet& set, int64_t n, const double* dt0, const double* ff, const double* fb,
                               double tau, bool all_slow, int32_t* flag, uint32_t* flags, hipStream_t st);
@@ -129,9 +152,15 @@ hipError_t launch_level_partition(const DevSet& set, int64_t n, const int32_t* l
                                   uint32_t* keys_out, int32_t* vals_in, int32_t* out_order, int32_t* counts,
                                   void* tmp, size_t tmp_bytes, uint32_t* flags, hipStream_t st);
 
-// Mixed acc/grad: a target is re-evaluated in FP64 when its magnitude estimate exceeds
-// kCondMax times the norm of its result.
+// Mixed acc / grad: a target is re-evaluated in FP64 when its magnitude estimate M exceeds
+// cond_max times the norm of its result.  Acceleration: M = sum w max|r| lies within a factor
+// sqrt(3) of the sum of the term norms; threshold 16.  Gradient: M = sum w max|a_ji| falls
+// short of the sum of the term norms by up to a factor 2 sqrt(3) (|term| <= 2 w |a_ji|), and
+// the two partial sums S1 = sum w a_ji and S2 = sum w (a_ji . r) r / s^2 are carried
+// separately; threshold 8.
 constexpr double kCondMax = 16.0;
+constexpr double kCondMaxGrad = 8.0;
+inline double cond_max_for(int op) { return op == OP_GRAD ? kCondMaxGrad : kCondMax; }
 
 // PN1.0
 struct PnArgs {
@@ -190,10 +219,14 @@ struct bf_ctx {
     size_t scratch6_bytes = 0;
     void* scratch7 = nullptr;         // HHS driver: level order and inter-level / FSI arrays
     size_t scratch7_bytes = 0;
+    void* scratch8 = nullptr;         // FP64 fix-up partial sums
+    size_t scratch8_bytes = 0;
     unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass
     // spatially sorted mixed passes: bit op set = use them for that operation when large enough
-    int sort_ops = 1 << 1;            // the force-gradient pass
-    float kappa = 3.0f;               // a tile is near a workgroup when their gap < kappa * tile half-extent
+    int sort_ops = (1 << 0) | (1 << 1);  // acceleration and force-gradient passes
+    const int32_t* sub = nullptr;     // subsystem labels applied to acc / grad / dt passes (NULL: none)
+    int64_t sub_n = 0;
+    float kappa = 1.0f;               // a tile is near a workgroup when their gap < kappa * tile half-extent
     // kernel timing: event pairs around pair-kernel launches, per op
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[bf::OP_COUNT];

@@ -107,7 +107,8 @@ constexpr int64_t kSortMinSources = 2048, kSortMinTargets = 512;
 constexpr double kKappaMin = 0.5, kKappaMax = 64.0;
 
 bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb) {
-    return (ctx->sort_ops >> op & 1) && prec == BF_PREC_MIXED && (op == OP_ACC || op == OP_GRAD) && r_fb == 0.0 &&
+    return (ctx->sort_ops >> op & 1) && ctx->sub == nullptr && prec == BF_PREC_MIXED && (op == OP_ACC || op == OP_GRAD) &&
+           r_fb == 0.0 &&
            ns >= kSortMinSources && nt >= kSortMinTargets;
 }
 
@@ -117,8 +118,14 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool so
         auto it = ctx->tuned.find(std::make_tuple(op, prec, ilog2_bucket(nt), ilog2_bucket(ns)));
         if (it != ctx->tuned.end()) c = it->second;
         else c = default_config(op, prec, nt);
+        if (it == ctx->tuned.end() && sorted) c.k = 1;  // measured best for the sorted kernels
     }
-    if (!variant_exists(op, prec, c.k, c.waves))
+    const bool excl = ctx->sub != nullptr && !sorted;
+    if (excl) {  // the exclusion variants exist for 4 waves and 1 or 2 targets per lane
+        c.waves = 4;
+        c.k = std::min(c.k, 2);
+    }
+    if (!variant_exists(op, prec, c.k, c.waves, excl))
         return fail(BF_ERR_UNSUPPORTED, "no kernel variant for k=" + std::to_string(c.k) + " waves=" + std::to_string(c.waves));
     const int T = 64 * c.waves;
     const int64_t slab = (int64_t)64 * c.k * c.waves;
@@ -126,7 +133,7 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool so
     const int64_t ntiles = std::max<int64_t>(1, (ns + T - 1) / T);
     int64_t split = c.split;
     if (split <= 0) {
-        int bpc = sorted ? sorted_blocks_per_cu(op, c.k, c.waves) : variant_blocks_per_cu(op, prec, c.k, c.waves);
+        int bpc = sorted ? sorted_blocks_per_cu(op, c.k, c.waves) : variant_blocks_per_cu(op, prec, c.k, c.waves, excl);
         if (bpc <= 0) bpc = 1;
         const int64_t resident = (int64_t)ctx->num_cu * bpc;
         // At least four full rounds of resident workgroups.  The split is a multiple of the 8 XCDs
@@ -153,6 +160,9 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool so
 int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg, const bf_set* sr, double G, double eps2,
               double r_fb, double eta0, double eta1, double* o0, double* o1, double* o2) {
     if (tg->count == 0) return BF_OK;
+    if (ctx->sub && ctx->sub_n != M.n)
+        return fail(BF_ERR_ARG, "subsystem labels were set for n=" + std::to_string(ctx->sub_n) +
+                                    " particles, this pass has n=" + std::to_string(M.n));
     const bool sorted = use_sorted(ctx, op, prec, tg->count, sr->count, r_fb);
     Plan p;
     int rc = plan(ctx, op, prec, tg->count, sr->count, p, sorted);
@@ -175,7 +185,8 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     a.eta1 = eta1;
     a.o0 = o0; a.o1 = o1; a.o2 = o2;
     a.flags = ctx->d_flags;
-    a.cond_max = kCondMax;
+    a.cond_max = cond_max_for(op);
+    a.sub = ctx->sub;
     // scratch: [fix counter | fix list (one slot per target) | split partials]
     const bool fix = prec == BF_PREC_MIXED && op != OP_DT;
     const size_t head = 256 + (((size_t)tg->count * sizeof(int32_t) + 255) & ~size_t(255));
@@ -252,7 +263,12 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         ctx->tev[op].push_back(ev);
     }
     if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
-    if (fix) BF_HIP(launch_fixup(op, a, std::min<int>(tg->count, 4 * ctx->num_cu), ctx->stream));
+    if (fix) {
+        const size_t fb = (size_t)kFixChunks * 3 * kFixTiled * sizeof(double);
+        rc = ensure(&ctx->scratch8, &ctx->scratch8_bytes, fb, ctx->stream);
+        if (rc) return rc;
+        BF_HIP(launch_fixup(op, a, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
+    }
     if (fix) BF_HIP(hipMemcpyAsync(ctx->d_stats, a.fix_count, sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
     return BF_OK;
 }
@@ -372,6 +388,7 @@ BF_API int bf_destroy(bf_ctx* c) {
     if (c->scratch5) hipFree(c->scratch5);
     if (c->scratch6) hipFree(c->scratch6);
     if (c->scratch7) hipFree(c->scratch7);
+    if (c->scratch8) hipFree(c->scratch8);
     if (c->d_flags) hipFree(c->d_flags);
     if (c->d_stats) hipFree(c->d_stats);
     if (c->h_flags) hipHostFree(c->h_flags);
@@ -953,6 +970,98 @@ BF_API int bf_set_spatial_sort(bf_ctx* c, int ops_mask, double kappa) {
     return BF_OK;
 }
 
+BF_API int bf_neighbours(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf_set* s, double G, double r_ngb,
+                         double r_max, double C, double tau, int32_t* edges, int64_t cap, int64_t* n_edges) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, true)) return rc;
+    if (int rc = check_set(t, P->n, "target")) return rc;
+    if (int rc = check_set(s, P->n, "source")) return rc;
+    if (!(isfinite(G) && G > 0)) return fail(BF_ERR_ARG, "G must be finite and > 0");
+    if (!(isfinite(r_ngb) && r_ngb > 0) || !(isfinite(r_max) && r_max > 0))
+        return fail(BF_ERR_ARG, "r_ngb and r_max must be finite and > 0");
+    if (!(isfinite(C) && C > 0) || !(isfinite(tau) && tau > 0)) return fail(BF_ERR_ARG, "C and tau must be finite and > 0");
+    if (!n_edges) return fail(BF_ERR_ARG, "n_edges NULL");
+    if (cap < 0 || (cap > 0 && !edges)) return fail(BF_ERR_ARG, "bad edge buffer");
+    *n_edges = 0;
+    if (t->count == 0 || s->count == 0) return BF_OK;
+    const int64_t capk = std::max<int64_t>(cap, 1);
+    const size_t kb = ((size_t)capk * 8 + 255) & ~size_t(255);
+    const size_t tmp = ngb_sort_tmp_bytes(capk);
+    if (int rc = ensure(&c->scratch4, &c->scratch4_bytes, 256 + 2 * kb + tmp, c->stream)) return rc;
+    char* b = static_cast<char*>(c->scratch4);
+    NgbArgs a{};
+    a.P = masters_of(P);
+    a.tgt = devset(t);
+    a.src = devset(s);
+    a.G = G;
+    a.r_ngb = r_ngb;
+    a.r_max2 = r_max * r_max;
+    a.C = C;
+    a.tau = tau;
+    a.count = reinterpret_cast<unsigned long long*>(b);
+    a.keys = reinterpret_cast<unsigned long long*>(b + 256);
+    a.cap = cap;
+    a.flags = c->d_flags;
+    constexpr int T = 256;
+    const int64_t nslabs = (t->count + T - 1) / T, ntiles = (s->count + T - 1) / T;
+    int64_t split = std::max<int64_t>(1, (8 * (int64_t)c->num_cu + nslabs - 1) / nslabs);
+    split = std::min(split, ntiles);
+    const int64_t tiles_per_chunk = (ntiles + split - 1) / split;
+    split = (ntiles + tiles_per_chunk - 1) / tiles_per_chunk;
+    a.split = (int32_t)split;
+    a.chunk = (int32_t)(tiles_per_chunk * T);
+    if (nslabs * split > INT32_MAX) return fail(BF_ERR_UNSUPPORTED, "grid too large");
+    BF_HIP(launch_zero_u64(a.count, 1, c->stream));
+    BF_HIP(launch_ngb(a, 4, (int)(nslabs * split), c->stream));
+    unsigned long long found = 0;
+    BF_HIP(hipMemcpyAsync(&found, a.count, sizeof(found), hipMemcpyDeviceToHost, c->stream));
+    BF_HIP(hipStreamSynchronize(c->stream));
+    *n_edges = (int64_t)found;
+    if ((int64_t)found > cap) return fail(BF_ERR_NOMEM, "edge buffer too small: " + std::to_string(found) + " pairs found");
+    BF_HIP(launch_ngb_finish(a.keys, reinterpret_cast<unsigned long long*>(b + 256 + kb), (int64_t)found,
+                             b + 256 + 2 * kb, tmp, edges, c->stream));
+    return BF_OK;
+}
+
+BF_API int bf_subsystems(bf_ctx* c, int64_t n, const int32_t* edges, int64_t m, int32_t* label, int64_t* n_sub) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (n <= 0 || n > INT32_MAX) return fail(BF_ERR_ARG, "n must be in [1, 2^31)");
+    if (m < 0 || (m > 0 && !edges)) return fail(BF_ERR_ARG, "bad edge list");
+    if (!label) return fail(BF_ERR_ARG, "label NULL");
+    const size_t mb = ((size_t)n * 4 + 255) & ~size_t(255);
+    if (int rc = ensure(&c->scratch4, &c->scratch4_bytes, 256 + mb, c->stream)) return rc;
+    int32_t* word = static_cast<int32_t*>(c->scratch4);
+    int32_t* mark = reinterpret_cast<int32_t*>(static_cast<char*>(c->scratch4) + 256);
+    BF_HIP(launch_label_init(label, n, word, c->stream));
+    // every round that changes something lowers at least one label, so this ends
+    for (int64_t round = 0;; ++round) {
+        if (round > n + 64) return fail(BF_ERR_HIP, "label propagation did not settle");
+        BF_HIP(launch_label_round(edges, m, n, label, word, c->d_flags, c->stream));
+        int32_t changed = 0;
+        BF_HIP(hipMemcpyAsync(&changed, word, sizeof(changed), hipMemcpyDeviceToHost, c->stream));
+        BF_HIP(hipStreamSynchronize(c->stream));
+        if (!changed) break;
+    }
+    if (n_sub) {
+        BF_HIP(launch_label_count(label, n, mark, word, c->stream));
+        int32_t cnt = 0;
+        BF_HIP(hipMemcpyAsync(&cnt, word, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+        BF_HIP(hipStreamSynchronize(c->stream));
+        *n_sub = cnt;
+    }
+    return BF_OK;
+}
+
+BF_API int bf_set_subsystems(bf_ctx* c, const int32_t* label, int64_t n) {
+    if (int rc = check_ctx(c)) return rc;
+    if (label && (n <= 0 || n > INT32_MAX)) return fail(BF_ERR_ARG, "n must be in [1, 2^31)");
+    c->sub = label;
+    c->sub_n = label ? n : 0;
+    return BF_OK;
+}
+
 BF_API int bf_query_config(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, int* k, int* waves, int* split) {
     if (int rc = check_ctx(c)) return rc;
     if (op < 0 || op >= OP_COUNT) return fail(BF_ERR_ARG, "bad op");
@@ -1052,6 +1161,8 @@ BF_API int bf_autotune(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, cons
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     const KernelConfig saved = c->forced[op][prec];
+    const int32_t* saved_sub = c->sub;
+    c->sub = nullptr;  // tuning runs on its own synthetic particles
     KernelConfig best{};
     float best_ms = 1e30f;
     int rc = BF_OK;
@@ -1079,6 +1190,7 @@ BF_API int bf_autotune(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, cons
         if (rc) break;
     }
     c->forced[op][prec] = saved;
+    c->sub = saved_sub;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     hipStreamSynchronize(c->stream);

@@ -6,9 +6,9 @@
 // velocities, accelerations) is taken in FP64 and rounded once to FP32; all arithmetic after
 // that (s^2, rsqrt, mass products, the pair term) is FP32; each LDS tile is summed in FP32
 // and merged into FP64 accumulators.  The acceleration and gradient passes also accumulate a
-// magnitude estimate M of sum_j |term_j| (acceleration: sum G m / s^2; gradient: sum of the
-// pair weight times the max-norm of a_ji); a target whose result is small against M
-// (cancellation) is re-evaluated entirely in FP64 afterwards.
+// magnitude estimate M of sum_j |term_j| (the pair weight times the max-norm of the pair's
+// difference vector: r for the acceleration, a_ji for the gradient); a target whose result is
+// small against M (cancellation) is re-evaluated entirely in FP64 afterwards.
 #pragma once
 
 #include "bf_internal.h"
@@ -39,6 +39,10 @@ __device__ __forceinline__ double rsqrt64(double r2) {
 
 __device__ __forceinline__ float rsqrt32(float r2) { return __builtin_amdgcn_rsqf(r2); }
 
+// pairs inside one subsystem (equal labels) are left out of every pair sum (Alg. 1: the
+// accelerations ignore intra-subsystem contributions)
+__device__ __forceinline__ bool same_sub(const int32_t* sub, int pi, int pj) { return sub != nullptr && sub[pi] == sub[pj]; }
+
 __device__ __forceinline__ float dif32(double a, double b) { return (float)(a - b); }
 __device__ __forceinline__ float max3abs(float a, float b, float c) {
     return __builtin_fmaxf(__builtin_fabsf(a), __builtin_fmaxf(__builtin_fabsf(b), __builtin_fabsf(c)));
@@ -48,6 +52,7 @@ __device__ __forceinline__ float max3abs(float a, float b, float c) {
 __device__ __forceinline__ double pack_gm(float gm) { return __builtin_bit_cast(double, make_float2(gm, 0.f)); }
 __device__ __forceinline__ float unpack_gm(double w) { return __builtin_bit_cast(float2, w).x; }
 
+constexpr int kFold = 64;           // sources per FP32 partial before the FP64 merge
 constexpr float kTiny32 = 1e-20f;   // added to s^2 in FP32: keeps the self pair finite (and zero)
 constexpr double kTiny64 = 1e-150;  // same in FP64
 
@@ -59,10 +64,9 @@ __device__ __forceinline__ void acc_pair64(const Masters& P, int pi, int pj, dou
     const double r2 = dx * dx + dy * dy + dz * dz + eps2;
     if (r2 == 0.0) { atomicOr(flags, BF_FLAG_COINCIDENT); return; }
     const double ri = rsqrt64(r2);
-    const double t = G * P.m[pj] * ri * ri;
-    const double w = t * ri;
+    const double w = G * P.m[pj] * ri * ri * ri;
     sx += w * dx; sy += w * dy; sz += w * dz;
-    sm += t;
+    sm += w * fmax(fabs(dx), fmax(fabs(dy), fabs(dz)));
 }
 
 __device__ __forceinline__ void grad_pair64(const Masters& P, int pi, int pj, double G, double eps2, double& sx,
@@ -96,16 +100,18 @@ struct AccMixed {
     __device__ static void target(const PairArgs& a, int p, Tgt& t) { t.x = a.P.x[p]; t.y = a.P.y[p]; t.z = a.P.z[p]; }
     __device__ static void zero(A32& r) { r.x = r.y = r.z = r.m = 0.f; }
     __device__ static void zero(A64& r) { r.x = r.y = r.z = r.m = 0.0; }
+    __device__ static void exclude(Src& s) { s.p.w = 0.0; }  // zero mass: no term
     __device__ static float pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
         const float dx = dif32(s.p.x, t.x), dy = dif32(s.p.y, t.y), dz = dif32(s.p.z, t.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
         const float ri = rsqrt32(r2);
-        const float gs = unpack_gm(s.p.w) * (ri * ri);  // G m / s^2, at least the term's norm
-        const float w = gs * ri;
+        const float ri2 = ri * ri;
+        const float w = (unpack_gm(s.p.w) * ri) * ri2;
         r.x = __builtin_fmaf(w, dx, r.x);
         r.y = __builtin_fmaf(w, dy, r.y);
         r.z = __builtin_fmaf(w, dz, r.z);
-        r.m += gs;
+        // the self pair has dx = 0 and adds nothing here (a form without dx would count it)
+        r.m = __builtin_fmaf(w, max3abs(dx, dy, dz), r.m);
         return r2;
     }
     __device__ static void fold(A64& o, const A32& i) {
@@ -115,7 +121,7 @@ struct AccMixed {
         double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
         for (int q = q0; q < q0 + len; ++q) {
             const int pj = particle_of(a.src, q, a.P.n, a.flags);
-            if (pj != pi) acc_pair64(a.P, pi, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
+            if (pj != pi && !same_sub(a.sub, pi, pj)) acc_pair64(a.P, pi, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
         }
         o.x += sx; o.y += sy; o.z += sz; o.m += sm;
     }
@@ -144,6 +150,7 @@ struct GradMixed {
     }
     __device__ static void zero(A32& r) { r.x = r.y = r.z = r.u = r.v = r.w = r.m = 0.f; }
     __device__ static void zero(A64& r) { r.x = r.y = r.z = r.m = 0.0; }
+    __device__ static void exclude(Src& s) { s.p.w = 0.0; }
     __device__ static float pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
         const float dx = dif32(s.p.x, t.x), dy = dif32(s.p.y, t.y), dz = dif32(s.p.z, t.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
@@ -172,7 +179,7 @@ struct GradMixed {
         double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
         for (int q = q0; q < q0 + len; ++q) {
             const int pj = particle_of(a.src, q, a.P.n, a.flags);
-            if (pj != pi) grad_pair64(a.P, pi, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
+            if (pj != pi && !same_sub(a.sub, pi, pj)) grad_pair64(a.P, pi, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
         }
         o.x += sx; o.y += sy; o.z += sz; o.m += sm;
     }
@@ -201,6 +208,8 @@ struct DtMixed {
     }
     __device__ static void zero(A32& r) { r.ff = r.fb = 0.f; }
     __device__ static void zero(A64& r) { r.ff = r.fb = 0.0; }
+    // moved out of reach: s^2 overflows to +inf in FP32, so both maxima get zero
+    __device__ static void exclude(Src& s) { s.p.x = 1e150; }
     __device__ static float pair(A32& r, const Tgt& t, const Src& s, float /*eps2f*/) {
         const float dx = dif32(s.p.x, t.x), dy = dif32(s.p.y, t.y), dz = dif32(s.p.z, t.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
@@ -219,7 +228,7 @@ struct DtMixed {
         double ff = o.ff, fb = o.fb;
         for (int q = q0; q < q0 + len; ++q) {
             const int pj = particle_of(a.src, q, a.P.n, a.flags);
-            if (pj == pi) continue;
+            if (pj == pi || same_sub(a.sub, pi, pj)) continue;
             const double dx = a.P.x[pj] - xi, dy = a.P.y[pj] - yi, dz = a.P.z[pj] - zi;
             const double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 == 0.0) { atomicOr(a.flags, BF_FLAG_COINCIDENT); continue; }
@@ -337,13 +346,15 @@ struct AccRel {
     __device__ static void rel(Tgt& t, const AccMixed::Tgt& g, const double4& c, const double4&) {
         t.x = (float)(g.x - c.x); t.y = (float)(g.y - c.y); t.z = (float)(g.z - c.z);
     }
-    // upper bound of sum_j |term_j| over the tile for this target: every source lies within
-    // sqrt(3) h of the centre, so r >= d - sqrt(3) h and |term| = G m r / s^3 <= G m / r^2
+    // upper bound of sum_j |term_j| over the tile for this target: every source lies in the
+    // cube of half-extent h about the centre, so r is at least the target's distance to that
+    // cube (positive for a far tile) and |term| = G m r / s^3 <= G m / r^2
     static constexpr bool kTileBound = true;
     __device__ static float bound(const Tgt& t, float h, float gm_tile, float) {
-        const float d = __builtin_sqrtf(__builtin_fmaf(t.x, t.x, __builtin_fmaf(t.y, t.y, t.z * t.z)));
-        const float r = fmaxf(d - 1.7320509f * h, 1e-30f);
-        return gm_tile / (r * r);
+        const float gx = fmaxf(__builtin_fabsf(t.x) - h, 0.f), gy = fmaxf(__builtin_fabsf(t.y) - h, 0.f),
+                    gz = fmaxf(__builtin_fabsf(t.z) - h, 0.f);
+        const float r2 = fmaxf(__builtin_fmaf(gx, gx, __builtin_fmaf(gy, gy, gz * gz)), 1e-30f);
+        return gm_tile / r2;
     }
     __device__ static void pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
         const float dx = s.p.x - t.x, dy = s.p.y - t.y, dz = s.p.z - t.z;
@@ -479,32 +490,43 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
             else tfar[threadIdx.x] = Far::load(a, jt + threadIdx.x);
         }
         __syncthreads();
-        typename Near::A32 part[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) Near::zero(part[k]);
         if (near) {
-#pragma unroll 2
-            for (int j = 0; j < len; ++j) {
-                const typename Near::Src s = tnear[j];
+            for (int js = 0; js < len; js += kFold) {
+                const int je = min(len, js + kFold);
+                typename Near::A32 part[K];
 #pragma unroll
-                for (int k = 0; k < K; ++k) Near::pair(part[k], tg[k], s, a.eps2f);
+                for (int k = 0; k < K; ++k) Near::zero(part[k]);
+#pragma unroll 2
+                for (int j = js; j < je; ++j) {
+                    const typename Near::Src s = tnear[j];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) Near::pair(part[k], tg[k], s, a.eps2f);
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) Near::fold(acc[k], part[k]);
             }
         } else {
             typename Far::Tgt tf[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 Far::rel(tf[k], tg[k], c, ca);
-                if (Far::kTileBound) part[k].m = Far::bound(tf[k], h, hm.y, ha);  // estimate of the whole tile
+                if (Far::kTileBound) acc[k].m += (double)Far::bound(tf[k], h, hm.y, ha);  // the whole tile
             }
-#pragma unroll 4
-            for (int j = 0; j < len; ++j) {
-                const typename Far::Src s = tfar[j];
+            for (int js = 0; js < len; js += kFold) {
+                const int je = min(len, js + kFold);
+                typename Near::A32 part[K];
 #pragma unroll
-                for (int k = 0; k < K; ++k) Far::pair(part[k], tf[k], s, a.eps2f);
+                for (int k = 0; k < K; ++k) Near::zero(part[k]);
+#pragma unroll 4
+                for (int j = js; j < je; ++j) {
+                    const typename Far::Src s = tfar[j];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) Far::pair(part[k], tf[k], s, a.eps2f);
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) Near::fold(acc[k], part[k]);
             }
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k) Near::fold(acc[k], part[k]);
     }
     if (a.tile_stats && threadIdx.x == 0) {
         atomicAdd(&a.tile_stats[0], n_near);
@@ -523,13 +545,15 @@ constexpr int ncomp_of() { return Op::NC + (Op::kCond ? 1 : 0); }
 // FP64 when a lane saw s^2 < a.rfb2f.  All threads of the workgroup must call it (it
 // synchronises).
 
-template <class Op, int K, int W, bool DETECT>
+template <class Op, int K, int W, bool DETECT, bool EXCL = false>
 __device__ __forceinline__ void sweep(const PairArgs& a, typename Op::Src* tile, int tbase, int j0, int j1,
-                                      typename Op::A64 (&acc)[K], int (&slot)[K], int (&pidx)[K]) {
+                                      typename Op::A64 (&acc)[K], int (&slot)[K], int (&pidx)[K],
+                                      int32_t* tsub = nullptr) {
     constexpr int T = 64 * W;
     const int lane = threadIdx.x & 63;
     const int nt = a.tgt.count;
     typename Op::Tgt tg[K];
+    int32_t sid[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         slot[k] = tbase + k * 64 + lane;
@@ -537,47 +561,73 @@ __device__ __forceinline__ void sweep(const PairArgs& a, typename Op::Src* tile,
         pidx[k] = particle_of(a.tgt, s, a.P.n, a.flags);
         Op::target(a, pidx[k], tg[k]);
         Op::zero(acc[k]);
+        if constexpr (EXCL) sid[k] = a.sub[pidx[k]];
     }
     for (int jt = j0; jt < j1; jt += T) {
         const int len = min(T, j1 - jt);
         __syncthreads();
-        if ((int)threadIdx.x < len) tile[threadIdx.x] = Op::load(a, jt + threadIdx.x);
+        if ((int)threadIdx.x < len) {
+            tile[threadIdx.x] = Op::load(a, jt + threadIdx.x);
+            if constexpr (EXCL) tsub[threadIdx.x] = a.sub[particle_of(a.src, jt + threadIdx.x, a.P.n, a.flags)];
+        }
         __syncthreads();
         if constexpr (Op::kMixed) {
-            typename Op::A32 part[K];
+            // FP32 partials span at most kFold sources before they are merged in FP64; a
+            // close pair re-evaluates only its kFold-source slice in FP64
+            for (int js = 0; js < len; js += kFold) {
+                const int je = min(len, js + kFold);
+                typename Op::A32 part[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) Op::zero(part[k]);
-            float dmin = __builtin_huge_valf();
+                for (int k = 0; k < K; ++k) Op::zero(part[k]);
+                float dmin = __builtin_huge_valf();
 #pragma unroll 4
-            for (int j = 0; j < len; ++j) {
-                const typename Op::Src s = tile[j];
-                float r2[K];
+                for (int j = js; j < je; ++j) {
+                    const typename Op::Src s = tile[j];
+                    float r2[K];
+                    if constexpr (EXCL) {
+                        const int32_t sj = tsub[j];
 #pragma unroll
-                for (int k = 0; k < K; ++k) r2[k] = Op::pair(part[k], tg[k], s, a.eps2f);
-                if constexpr (DETECT) {
+                        for (int k = 0; k < K; ++k) {
+                            typename Op::Src sk = s;
+                            if (sj == sid[k]) Op::exclude(sk);
+                            r2[k] = Op::pair(part[k], tg[k], sk, a.eps2f);
+                        }
+                    } else {
 #pragma unroll
-                    for (int k = 0; k < K; k += 2) {
-                        if (k + 1 < K) dmin = fminf(dmin, fminf(r2[k], r2[k + 1]));
-                        else dmin = fminf(dmin, r2[k]);
+                        for (int k = 0; k < K; ++k) r2[k] = Op::pair(part[k], tg[k], s, a.eps2f);
+                    }
+                    if constexpr (DETECT) {
+#pragma unroll
+                        for (int k = 0; k < K; k += 2) {
+                            if (k + 1 < K) dmin = fminf(dmin, fminf(r2[k], r2[k + 1]));
+                            else dmin = fminf(dmin, r2[k]);
+                        }
                     }
                 }
-            }
-            bool redo = false;
-            if constexpr (DETECT) redo = __any(dmin < a.rfb2f);
-            if (redo) {
+                bool redo = false;
+                if constexpr (DETECT) redo = __any(dmin < a.rfb2f);
+                if (redo) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) Op::redo(acc[k], a, pidx[k], jt, len);
-            } else {
+                    for (int k = 0; k < K; ++k) Op::redo(acc[k], a, pidx[k], jt + js, je - js);
+                } else {
 #pragma unroll
-                for (int k = 0; k < K; ++k) Op::fold(acc[k], part[k]);
+                    for (int k = 0; k < K; ++k) Op::fold(acc[k], part[k]);
+                }
             }
         } else {
             const double eps2t = a.eps2 + kTiny64;
 #pragma unroll 2
             for (int j = 0; j < len; ++j) {
                 const typename Op::Src s = tile[j];
+                if constexpr (EXCL) {
+                    const int32_t sj = tsub[j];
 #pragma unroll
-                for (int k = 0; k < K; ++k) Op::pair64(acc[k], tg[k], s, eps2t, pidx[k]);
+                    for (int k = 0; k < K; ++k)
+                        if (sj != sid[k]) Op::pair64(acc[k], tg[k], s, eps2t, pidx[k]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) Op::pair64(acc[k], tg[k], s, eps2t, pidx[k]);
+                }
             }
         }
     }
@@ -599,13 +649,13 @@ __device__ __forceinline__ void cond_check(const PairArgs& a, int slot, const do
 // FP64 sum of all sources of `src` for target particle pi, one workgroup of 256 threads;
 // returns the result in thread 0.
 template <int OP>
-__device__ __forceinline__ void fix_one(const Masters& P, const DevSet& src, int pi, double G, double eps2,
-                                        uint32_t* flags, double* out3) {
+__device__ __forceinline__ void fix_one(const Masters& P, const DevSet& src, const int32_t* sub, int pi, double G,
+                                        double eps2, uint32_t* flags, double* out3) {
     __shared__ double red[3][256];
     double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
     for (int q = threadIdx.x; q < src.count; q += 256) {
         const int pj = particle_of(src, q, P.n, flags);
-        if (pj == pi) continue;
+        if (pj == pi || same_sub(sub, pi, pj)) continue;
         if constexpr (OP == OP_ACC) acc_pair64(P, pi, pj, G, eps2, sx, sy, sz, sm, flags);
         else grad_pair64(P, pi, pj, G, eps2, sx, sy, sz, sm, flags);
     }

@@ -54,9 +54,10 @@ __device__ __forceinline__ void emit(const PairArgs& a, int c, int slot, int pi,
 
 // ---- the skeleton --------------------------------------------------------------------------
 
-template <class Op, int K, int W, bool DETECT>
+template <class Op, int K, int W, bool DETECT, bool EXCL = false>
 __global__ __launch_bounds__(64 * W) void k_pairs(const PairArgs a) {
     __shared__ typename Op::Src tile[64 * W];
+    __shared__ int32_t tsub[EXCL ? 64 * W : 1];
     const int wave = threadIdx.x >> 6;
     const int c = blockIdx.x % a.split;
     const int slab = blockIdx.x / a.split;
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs(const PairArgs a) {
     const int j1 = min(a.src.count, j0 + a.chunk);
     typename Op::A64 acc[K];
     int slot[K], pidx[K];
-    sweep<Op, K, W, DETECT>(a, tile, tbase, j0, j1, acc, slot, pidx);
+    sweep<Op, K, W, DETECT, EXCL>(a, tile, tbase, j0, j1, acc, slot, pidx, tsub);
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (slot[k] < a.tgt.count) emit<Op>(a, c, slot[k], pidx[k], acc[k]);
@@ -121,14 +122,87 @@ __global__ void k_zero_u64(unsigned long long* c, int n) {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
+// Tiled form for up to kFixTiled queued targets: a workgroup takes 256 queued targets (one per
+// thread) against one of kFixChunks source chunks staged through LDS, and writes FP64 partial
+// sums; k_fixup_reduce adds the chunks in order.  Queued targets beyond kFixTiled (never seen
+// in practice) take k_fixup, one workgroup per target.
+template <int OP>
+__global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* part) {
+    const int count = min(min(*a.fix_count, a.tgt.count), kFixTiled);
+    const int items = (count + 255) / 256 * kFixChunks;
+    const int ns = a.src.count;
+    const int chunk = (ns + kFixChunks - 1) / kFixChunks;
+    __shared__ double4 sp[256];  // (x, y, z, G m)
+    __shared__ double4 sa[256];  // (ax, ay, az, particle index)
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int slab = it / kFixChunks, c = it % kFixChunks;
+        const int e = slab * 256 + (int)threadIdx.x;
+        const bool act = e < count;
+        const int pi = particle_of(a.tgt, a.fix_list[act ? e : 0], a.P.n, a.flags);
+        const double xi = a.P.x[pi], yi = a.P.y[pi], zi = a.P.z[pi];
+        double axi = 0.0, ayi = 0.0, azi = 0.0;
+        if constexpr (OP == OP_GRAD) { axi = a.P.ax[pi]; ayi = a.P.ay[pi]; azi = a.P.az[pi]; }
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        const int j0 = c * chunk, j1 = min(ns, j0 + chunk);
+        for (int jt = j0; jt < j1; jt += 256) {
+            const int len = min(256, j1 - jt);
+            __syncthreads();
+            if ((int)threadIdx.x < len) {
+                const int p = particle_of(a.src, jt + threadIdx.x, a.P.n, a.flags);
+                sp[threadIdx.x] = make_double4(a.P.x[p], a.P.y[p], a.P.z[p], a.G * a.P.m[p]);
+                if constexpr (OP == OP_GRAD) sa[threadIdx.x] = make_double4(a.P.ax[p], a.P.ay[p], a.P.az[p], (double)p);
+                else sa[threadIdx.x] = make_double4(0.0, 0.0, 0.0, (double)p);
+            }
+            __syncthreads();
+            if (!act) continue;
+            for (int j = 0; j < len; ++j) {
+                const int pj = (int)sa[j].w;
+                if (pj == pi || same_sub(a.sub, pi, pj)) continue;
+                const double4 q = sp[j];
+                const double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+                const double r2 = dx * dx + dy * dy + dz * dz + a.eps2;
+                if (r2 == 0.0) { atomicOr(a.flags, BF_FLAG_COINCIDENT); continue; }
+                const double ri = rsqrt64(r2);
+                const double ri2 = ri * ri;
+                const double w = q.w * ri * ri2;
+                if constexpr (OP == OP_ACC) {
+                    sx += w * dx; sy += w * dy; sz += w * dz;
+                } else {
+                    const double dax = sa[j].x - axi, day = sa[j].y - ayi, daz = sa[j].z - azi;
+                    const double q3 = 3.0 * (dax * dx + day * dy + daz * dz) * ri2;
+                    sx += w * (dax - q3 * dx); sy += w * (day - q3 * dy); sz += w * (daz - q3 * dz);
+                }
+            }
+        }
+        if (act) {
+            part[((size_t)c * 3 + 0) * kFixTiled + e] = sx;
+            part[((size_t)c * 3 + 1) * kFixTiled + e] = sy;
+            part[((size_t)c * 3 + 2) * kFixTiled + e] = sz;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part) {
+    const int count = min(min(*a.fix_count, a.tgt.count), kFixTiled);
+    for (int e = blockIdx.x * 256 + (int)threadIdx.x; e < count; e += gridDim.x * 256) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < kFixChunks; ++c)
+            for (int k = 0; k < 3; ++k) v[k] += part[((size_t)c * 3 + k) * kFixTiled + e];
+        const int pi = particle_of(a.tgt, a.fix_list[e], a.P.n, a.flags);
+        a.o0[pi] = v[0];
+        a.o1[pi] = v[1];
+        a.o2[pi] = v[2];
+    }
+}
+
 template <int OP>
 __global__ __launch_bounds__(256) void k_fixup(const PairArgs a) {
     const int count = min(*a.fix_count, a.tgt.count);
-    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+    for (int e = kFixTiled + blockIdx.x; e < count; e += gridDim.x) {
         const int slot = a.fix_list[e];
         const int pi = particle_of(a.tgt, slot, a.P.n, a.flags);
         double r[3];
-        fix_one<OP>(a.P, a.src, pi, a.G, a.eps2, a.flags, r);
+        fix_one<OP>(a.P, a.src, a.sub, pi, a.G, a.eps2, a.flags, r);
         if (threadIdx.x == 0) {
             a.o0[pi] = r[0];
             a.o1[pi] = r[1];
@@ -153,7 +227,31 @@ static KernelFn pick(int k, int w) {
     return nullptr;
 }
 
-static KernelFn kernel_for(int op, int prec, int k, int w, bool detect) {
+// variants with intra-subsystem exclusion: one block shape (4 waves), 1 or 2 targets per lane
+template <class Op, bool D>
+static KernelFn pick_excl(int k, int w) {
+    if (w != 4) return nullptr;
+    if (k == 1) return k_pairs<Op, 1, 4, D, true>;
+    if (k == 2) return k_pairs<Op, 2, 4, D, true>;
+    return nullptr;
+}
+
+static KernelFn kernel_for_excl(int op, int prec, int k, int w, bool detect) {
+    const bool mixed = prec == BF_PREC_MIXED;
+    switch (op) {
+        case OP_ACC:
+            if (!mixed) return pick_excl<Acc64, false>(k, w);
+            return detect ? pick_excl<AccMixed, true>(k, w) : pick_excl<AccMixed, false>(k, w);
+        case OP_GRAD:
+            if (!mixed) return pick_excl<Grad64, false>(k, w);
+            return detect ? pick_excl<GradMixed, true>(k, w) : pick_excl<GradMixed, false>(k, w);
+        case OP_DT: return mixed ? pick_excl<DtMixed, true>(k, w) : pick_excl<Dt64, false>(k, w);
+    }
+    return nullptr;
+}
+
+static KernelFn kernel_for(int op, int prec, int k, int w, bool detect, bool excl = false) {
+    if (excl) return kernel_for_excl(op, prec, k, w, detect);
     const bool mixed = prec == BF_PREC_MIXED;
     switch (op) {
         case OP_ACC:
@@ -167,10 +265,12 @@ static KernelFn kernel_for(int op, int prec, int k, int w, bool detect) {
     return nullptr;
 }
 
-bool variant_exists(int op, int prec, int k, int waves) { return kernel_for(op, prec, k, waves, false) != nullptr; }
+bool variant_exists(int op, int prec, int k, int waves, bool excl) {
+    return kernel_for(op, prec, k, waves, false, excl) != nullptr;
+}
 
-int variant_blocks_per_cu(int op, int prec, int k, int waves) {
-    KernelFn f = kernel_for(op, prec, k, waves, op == OP_DT);
+int variant_blocks_per_cu(int op, int prec, int k, int waves, bool excl) {
+    KernelFn f = kernel_for(op, prec, k, waves, op == OP_DT, excl);
     if (!f) return 0;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(f), 64 * waves, 0) != hipSuccess)
@@ -180,7 +280,7 @@ int variant_blocks_per_cu(int op, int prec, int k, int waves) {
 
 hipError_t launch_pairs(int op, int prec, const KernelConfig& cfg, const PairArgs& a, int nblocks, hipStream_t st) {
     const bool detect = prec == BF_PREC_MIXED && a.rfb2f > 0.0f;
-    KernelFn f = kernel_for(op, prec, cfg.k, cfg.waves, detect || op == OP_DT);
+    KernelFn f = kernel_for(op, prec, cfg.k, cfg.waves, detect || op == OP_DT, a.sub != nullptr);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(nblocks), dim3(64 * cfg.waves), 0, st, a);
     return hipGetLastError();
@@ -233,9 +333,21 @@ hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_fixup(int op, const PairArgs& a, int nblocks, hipStream_t st) {
-    if (op == OP_ACC) hipLaunchKernelGGL(k_fixup<OP_ACC>, dim3(nblocks), dim3(256), 0, st, a);
-    else if (op == OP_GRAD) hipLaunchKernelGGL(k_fixup<OP_GRAD>, dim3(nblocks), dim3(256), 0, st, a);
+hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hipStream_t st) {
+    const int nt = a.tgt.count;
+    if (nt <= 0) return hipSuccess;
+    const int items = (std::min(nt, kFixTiled) + 255) / 256 * kFixChunks;
+    const int g1 = std::min(items, 4 * num_cu);
+    const int g2 = std::min((std::min(nt, kFixTiled) + 255) / 256, 4 * num_cu);
+    if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_tiled<OP_ACC>, dim3(g1), dim3(256), 0, st, a, part);
+    else if (op == OP_GRAD) hipLaunchKernelGGL(k_fixup_tiled<OP_GRAD>, dim3(g1), dim3(256), 0, st, a, part);
+    else return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fixup_reduce, dim3(g2), dim3(256), 0, st, a, (const double*)part);
+    if (nt > kFixTiled) {
+        const int g3 = std::min(nt - kFixTiled, 4 * num_cu);
+        if (op == OP_ACC) hipLaunchKernelGGL(k_fixup<OP_ACC>, dim3(g3), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(k_fixup<OP_GRAD>, dim3(g3), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -532,3 +532,124 @@ def test_hhs_adaptive_energy_error_scales_as_eta_to_the_fourth():
     slope = np.polyfit(np.log(etas), np.log(errs), 1)[0]
     assert 3.3 < slope < 4.8, (slope, errs)
     assert max(momenta) < 1e-15
+
+
+# --------------------------------------------------------------------------------------------
+# Subsystems (Sec. 3.3): neighbour criterion, components, exclusion of intra-subsystem pairs
+# --------------------------------------------------------------------------------------------
+
+def _pair_state(rel, vrel, m1=1e-3, m2=2e-3):
+    """Two particles with the given relative position and velocity (second minus first)."""
+    M = m1 + m2
+    x1, x2 = -m2 / M * np.asarray(rel, float), m1 / M * np.asarray(rel, float)
+    v1, v2 = -m2 / M * np.asarray(vrel, float), m1 / M * np.asarray(vrel, float)
+    return Particles.from_dict({"x": np.array([x1[0], x2[0]]), "y": np.array([x1[1], x2[1]]),
+                                "z": np.array([x1[2], x2[2]]), "vx": np.array([v1[0], v2[0]]),
+                                "vy": np.array([v1[1], v2[1]]), "vz": np.array([v1[2], v2[2]]),
+                                "m": np.array([m1, m2])})
+
+
+def _hyperbola(q, e, f, GM):
+    """Relative state on a hyperbolic orbit of periapsis q and eccentricity e > 1 at true
+    anomaly f (conic r = p / (1 + e cos f), p = q (1 + e))."""
+    p = q * (1 + e)
+    r = p / (1 + e * math.cos(f))
+    vr, vt = math.sqrt(GM / p) * e * math.sin(f), math.sqrt(GM / p) * (1 + e * math.cos(f))
+    c, s = math.cos(f), math.sin(f)
+    return np.array([r * c, r * s, 0.0]), np.array([vr * c - vt * s, vr * s + vt * c, 0.0]), r
+
+
+def _is_ngb(P, **kw):
+    return len(oracle.neighbours(P, **kw)) == 2  # both directions
+
+
+def test_ngb_bound_criteria():
+    """Sec. 3.3, Eq. ngb-bound: a bound pair is a neighbour if a < r_ngb (anywhere on the orbit)
+    or if it is closer than r_ngb (a distant binary near periapsis)."""
+    r_ngb = 1e-3
+    m1, m2 = 1e-3, 2e-3
+    # close binary seen at apoapsis, r = 1.2 r_ngb > r_ngb
+    P = Particles.from_dict(_kepler.binary_state(m1, m2, 0.8 * r_ngb, 0.5, phase_E=math.pi))
+    assert np.hypot(*(P.pos()[1] - P.pos()[0])[:2]) > r_ngb * 1.1
+    assert _is_ngb(P, r_ngb=r_ngb)
+    # distant eccentric binary: neighbour at periapsis (r = 0.5 r_ngb), not at apoapsis (9.5 r_ngb)
+    assert _is_ngb(Particles.from_dict(_kepler.binary_state(m1, m2, 5 * r_ngb, 0.9, phase_E=0.0)), r_ngb=r_ngb)
+    assert not _is_ngb(Particles.from_dict(_kepler.binary_state(m1, m2, 5 * r_ngb, 0.9, phase_E=math.pi)),
+                       r_ngb=r_ngb)
+    # beyond r_max nothing is examined, even a slow bound pair
+    assert not _is_ngb(_pair_state([0.3, 0, 0], [0, 1e-4, 0]), r_ngb=r_ngb, r_max=0.1)
+
+
+def test_ngb_unbound_criteria():
+    """Sec. 3.3, Eq. ngb-unbound: an unbound pair with periapsis below r_ngb is a neighbour when
+    closer than r_ngb, or when C r / |v| < tau; a periapsis at or beyond r_ngb never is."""
+    r_ngb, C, GM = 1e-3, 0.5, 3e-3
+    rel, vrel, r = _hyperbola(0.5 * r_ngb, 1.5, -2.0, GM)
+    assert r > 3 * r_ngb
+    P = _pair_state(rel, vrel)
+    t_fb = C * r / np.linalg.norm(vrel)
+    assert _is_ngb(P, r_ngb=r_ngb, C=C, tau=2 * t_fb)
+    assert not _is_ngb(P, r_ngb=r_ngb, C=C, tau=0.5 * t_fb)
+    rel, vrel, r = _hyperbola(2 * r_ngb, 1.5, -1.0, GM)
+    assert not _is_ngb(_pair_state(rel, vrel), r_ngb=r_ngb, C=C, tau=1e9)
+    # a close fly-by inside r_ngb
+    rel, vrel, r = _hyperbola(0.2 * r_ngb, 3.0, 0.3, GM)
+    assert r < r_ngb
+    assert _is_ngb(_pair_state(rel, vrel), r_ngb=r_ngb, C=C, tau=1e-30)
+
+
+def test_subsystems_are_graph_components():
+    """Components of random graphs against a boolean transitive closure (repeated squaring of
+    the reachability matrix), which shares nothing with the depth-first search."""
+    rng = np.random.default_rng(21)
+    for n, m in ((1, 0), (7, 0), (30, 12), (60, 45), (40, 200)):
+        e = rng.integers(0, n, size=(m, 2)) if m else np.zeros((0, 2), dtype=np.int64)
+        e = e[e[:, 0] != e[:, 1]]
+        R = np.eye(n, dtype=bool)
+        R[e[:, 0], e[:, 1]] = R[e[:, 1], e[:, 0]] = True
+        for _ in range(int(np.ceil(np.log2(max(n, 2)))) + 1):
+            R = (R.astype(np.int64) @ R.astype(np.int64)) > 0
+        expect = np.array([np.flatnonzero(R[i]).min() for i in range(n)])
+        np.testing.assert_array_equal(oracle.subsystems(n, e), expect)
+
+
+def test_subsystem_chain_through_a_common_neighbour():
+    """The construction of Fig. ngb: a target joins a particle far beyond r_ngb through a shared
+    neighbour, while a closer particle that is no neighbour of any of them stays single."""
+    r_ngb = 1e-3
+    d = {k: np.zeros(4) for k in ("x", "y", "z", "vx", "vy", "vz")}
+    d["m"] = np.full(4, 1e-6)  # mu = 2e-6 for every pair
+    # T at rest and F at rest 0.9 r_ngb away: bound with a = 0.45 r_ngb (close binary)
+    # G 0.9 r_ngb beyond F moving at 0.055 across: bound to F with a = 1.41 r_ngb inside r_ngb
+    #   (distant binary near periapsis), unbound from T with periapsis 1.8 r_ngb (no neighbour)
+    # H 1.5 r_ngb on the other side moving fast across: periapsis about its distance from all
+    d["x"][:] = [0.0, 0.9e-3, 1.8e-3, -1.5e-3]
+    d["vy"][:] = [0.0, 0.0, 0.055, 1.0]
+    P = Particles.from_dict(d)
+    e = oracle.neighbours(P, r_ngb=r_ngb, tau=1e-3)
+    lab = oracle.subsystems(4, e)
+    assert lab[0] == lab[1] == lab[2] == 0 and lab[3] == 3
+    assert not np.any((e[:, 0] == 0) & (e[:, 1] == 2))  # T and G are no direct neighbours
+
+
+def test_exclusion_removes_intra_subsystem_pairs():
+    """Accelerations, gradient sums and time-steps with subsystem labels equal those computed
+    with each particle's subsystem partners dropped from its sources, and the excluded
+    accelerations still balance momentum (pairs are removed symmetrically)."""
+    P = Particles.from_dict(ics.plummer_cluster(ics.rng_for(60), 120, "kroupa"))
+    lab = np.arange(P.n)
+    lab[[5, 17, 40]] = 5
+    lab[[60, 61]] = 60
+    af = oracle.forces(P)
+    a_ex = oracle.forces(P, sub=lab)
+    g_ex = oracle.gradient(P, af, sub=lab)
+    ff_ex, fb_ex = oracle.dt_min(P, sub=lab)
+    for i in range(P.n):
+        src = np.flatnonzero(lab != lab[i])
+        np.testing.assert_array_equal(a_ex[i], oracle.forces(P, [i], src)[0])
+        np.testing.assert_array_equal(g_ex[i], oracle.gradient(P, af, [i], src)[0])
+        ff, fb = oracle.dt_min(P, [i], src)
+        assert ff_ex[i] == ff[0] and fb_ex[i] == fb[0]
+    f = (P.m[:, None] * a_ex).sum(axis=0)
+    assert np.abs(f).max() < 1e-14 * (P.m[:, None] * np.abs(a_ex)).sum()
+    assert not np.allclose(a_ex[[5, 17, 40, 60, 61]], af[[5, 17, 40, 60, 61]])
