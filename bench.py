@@ -352,18 +352,18 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         nthreads = oracle.num_threads()
-        probe = np.sort(rng.choice(n, 16, replace=False))
-        t1 = time.perf_counter()
-        oracle.forces(Po, probe, None)
-        oracle.gradient(Po, af, probe, None)
-        tp = time.perf_counter() - t1
-        k = int(min(8192, max(16, 16 * args.cpu_seconds / max(tp, 1e-3))))
-        Ts = np.sort(rng.choice(n, k, replace=False))
-        log(f"cpu oracle sample: {k} targets x {n} sources on {nthreads} threads ...")
-        t1 = time.perf_counter()
-        oracle.forces(Po, Ts, None)
-        oracle.gradient(Po, af, Ts, None)
-        tc = time.perf_counter() - t1
+        warm = np.sort(rng.choice(n, 16, replace=False))
+        oracle.forces(Po, warm, None)  # thread pool start-up, not timed
+        # batches of random targets against all sources until about cpu_seconds have passed
+        log(f"cpu oracle sample: batches of 1024 targets x {n} sources on {nthreads} threads ...")
+        k, tc = 0, 0.0
+        while tc < args.cpu_seconds and k < 65536:
+            Ts = np.sort(rng.choice(n, 1024, replace=False))
+            t1 = time.perf_counter()
+            oracle.forces(Po, Ts, None)
+            oracle.gradient(Po, af, Ts, None)
+            tc += time.perf_counter() - t1
+            k += Ts.size
         cpu = {"value": k * (n - 1) / tc, "unit": "pair interactions/s", "cores": nthreads, "kind": "oracle",
                "sample": f"{k} random targets x all {n} sources, acceleration + force-gradient passes, FP64, "
                          f"{tc:.1f} s"}

@@ -231,6 +231,17 @@ BF_API int bf_level_partition(bf_ctx *ctx, const bf_set *set, int64_t n, const i
 BF_API int bf_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, const int32_t *level,
                            int kmax, double tau, const bf_fsi_params *prm);
 
+/* Capture one fixed-level HHS-FSI interval (the recursion of bf_hhs_interval, Sec. 2.2) into a
+ * HIP graph: *graph_exec receives a handle for bf_graph_launch / bf_graph_destroy.  Each launch
+ * advances the state in S by one interval with the level structure given here (the partition
+ * is taken once, at capture; recapture when levels change).  Synchronising; the graph owns its
+ * scratch buffers, so later calls on the context never invalidate it.  Inside the graph the
+ * mixed passes run unsorted (the spatially sorted mode and kernel timing are off while
+ * capturing); results equal an eager bf_hhs_interval with the sorted mode off.  Errors as
+ * bf_hhs_interval; an empty set is BF_ERR_ARG. */
+BF_API int bf_graph_capture_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, const int32_t *level,
+                                         int kmax, double tau, const bf_fsi_params *prm, void **graph_exec);
+
 /* One HHS-FSI interval of length tau over `set` with time-steps assigned on every hierarchy
  * level (Sec. 2.2: each level starts by assigning time-steps and splitting its particles at the
  * pivot; Sec. 3.5.1: a time-step cannot grow within the interval).  dt0 (device FP64,

@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
                                _vp, _vp],
         "bf_level_partition": [_vp, S, _i64, _vp, _int, _vp, ctypes.POINTER(_i64)],
         "bf_hhs_interval": [_vp, ST, S, _vp, _int, _d, FP],
+        "bf_graph_capture_hhs_interval": [_vp, ST, S, _vp, _int, _d, FP, ctypes.POINTER(_vp)],
         "bf_hhs_interval_adaptive": [_vp, ST, S, _vp, _int, _d, _d, _d, FP, ctypes.POINTER(_int),
                                      ctypes.POINTER(_i64)],
         "bf_drift": [_vp, ST, S, _d],
@@ -351,6 +352,18 @@ class Context:
         _check("bf_hhs_interval", _lib.bf_hhs_interval(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()),
                                                        _ptr(level), int(kmax), float(tau), ctypes.byref(prm)))
 
+    def capture_hhs_interval(self, P: Particles, level: torch.Tensor, kmax: int, tau: float, subset=None, G=1.0,
+                             eps2=0.0, prec="mixed", r_fb=0.0) -> "Graph":
+        """Capture one fixed-level HHS-FSI interval into a HIP graph (launch to advance P)."""
+        s = ParticleSet.of(subset, P.n)
+        _need(level, torch.int32, P.n, "level")
+        prm = _FsiParams(float(G), float(eps2), PRECISIONS[prec], float(r_fb), None, 0, 1.0)
+        h = _vp()
+        _check("bf_graph_capture_hhs_interval",
+               _lib.bf_graph_capture_hhs_interval(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()), _ptr(level),
+                                                  int(kmax), float(tau), ctypes.byref(prm), ctypes.byref(h)))
+        return Graph(self, h, keep=(P, level, s))
+
     def hhs_interval_adaptive(self, P: Particles, dt0: torch.Tensor, kmax: int, tau: float, eta_ff=0.2, eta_fb=0.2,
                               subset=None, G=1.0, eps2=0.0, prec="fp64", r_fb=0.0):
         """One HHS-FSI interval with time-steps assigned on every level (capped by dt0), in
@@ -419,7 +432,7 @@ class Context:
             self._h, ctypes.byref(P._state()), nc, _ptr(cluster_off), _ptr(active_idx), _ptr(active_off),
             int(max_active_total), int(max_cluster_n), float(G), float(eps2), PRECISIONS[prec], float(r_fb),
             float(dt), *map(_ptr, acc), ctypes.byref(g)))
-        return Graph(self, g)
+        return Graph(self, g, keep=(P, cluster_off, active_idx, active_off, tuple(acc)))
 
     # ---- configuration -----------------------------------------------------------------------
 
@@ -507,8 +520,9 @@ class Context:
 class Graph:
     """A captured HIP graph (opaque handle) replayed on the context's stream."""
 
-    def __init__(self, ctx: Context, handle):
-        self.ctx, self._g = ctx, handle
+    def __init__(self, ctx: Context, handle, keep=()):
+        # the graph reads and writes the captured tensors: keep them alive as long as it exists
+        self.ctx, self._g, self._keep = ctx, handle, keep
 
     def launch(self):
         _check("bf_graph_launch", _lib.bf_graph_launch(self.ctx.handle, self._g))

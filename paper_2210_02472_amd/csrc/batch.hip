@@ -366,11 +366,6 @@ BF_API int bf_force_gradient_batched(bf_ctx* c, const bf_particles* P, int32_t n
 
 // A captured graph owns the scratch its kernels use, so later growth of the context's scratch
 // can never leave a replay pointing at freed memory.
-struct bf_graph {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    void* owned[3] = {nullptr, nullptr, nullptr};
-};
 
 // prepare the two batch descriptors of a batched FSI cycle (sizes every scratch buffer)
 static int batched_fsi_setup(bf_ctx* c, const bf_state* S, int32_t nclusters, const int64_t* coff, const int32_t* aidx,

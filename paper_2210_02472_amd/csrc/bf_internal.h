@@ -81,8 +81,15 @@ hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_zero_count(int32_t* c, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st);
+// A captured graph and the scratch buffers it owns (freed with it).
+struct bf_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* owned[8] = {};
+};
+
 // FP64 fix-up of queued targets; part: kFixChunks * 3 * kFixTiled doubles of scratch.
-constexpr int kFixTiled = 32768, kFixChunks = 32;
+constexpr int kFixTiled = 16384, kFixChunks = 128;
 hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hipStream_t st);
 
 // Spatially sorted mixed acc/grad (spatial.hip).
@@ -221,6 +228,8 @@ struct bf_ctx {
     size_t scratch7_bytes = 0;
     void* scratch8 = nullptr;         // FP64 fix-up partial sums
     size_t scratch8_bytes = 0;
+    bool capturing = false;           // a graph capture is recording this context's work
+    bool dry = false;                 // size scratch only, launch nothing (before a capture)
     unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass
     // spatially sorted mixed passes: bit op set = use them for that operation when large enough
     int sort_ops = (1 << 0) | (1 << 1);  // acceleration and force-gradient passes

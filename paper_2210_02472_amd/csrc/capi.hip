@@ -107,7 +107,8 @@ constexpr int64_t kSortMinSources = 2048, kSortMinTargets = 512;
 constexpr double kKappaMin = 0.5, kKappaMax = 64.0;
 
 bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb) {
-    return (ctx->sort_ops >> op & 1) && ctx->sub == nullptr && prec == BF_PREC_MIXED && (op == OP_ACC || op == OP_GRAD) &&
+    return (ctx->sort_ops >> op & 1) && ctx->sub == nullptr && !ctx->capturing && prec == BF_PREC_MIXED &&
+           (op == OP_ACC || op == OP_GRAD) &&
            r_fb == 0.0 &&
            ns >= kSortMinSources && nt >= kSortMinTargets;
 }
@@ -193,6 +194,19 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     const size_t part_bytes = p.split > 1 ? (size_t)p.split * stored_components(op, prec) * tg->count * sizeof(double) : 0;
     rc = ensure(&ctx->scratch, &ctx->scratch_bytes, head + part_bytes, ctx->stream);
     if (rc) return rc;
+    if (fix) {
+        rc = ensure(&ctx->scratch8, &ctx->scratch8_bytes, (size_t)kFixChunks * 3 * kFixTiled * sizeof(double),
+                    ctx->stream);
+        if (rc) return rc;
+    }
+    if (!sorted && sr->count > 0) {
+        rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)sr->count * pack_bytes(op, prec), ctx->stream);
+        if (rc) return rc;
+    }
+    if (ctx->dry) {  // sizing before a capture: every buffer of this pass now exists
+        if (sorted) return fail(BF_ERR_UNSUPPORTED, "sorted passes are not captured");
+        return BF_OK;
+    }
     a.fix_count = static_cast<int32_t*>(ctx->scratch);
     a.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + 256);
     if (p.split > 1) a.part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + head);
@@ -240,13 +254,12 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         BF_HIP(launch_pack_tiles(op, p.cfg.waves, a, ctx->scratch2, ctx->scratch6,
                                  reinterpret_cast<double4*>(static_cast<char*>(ctx->scratch6) + far_bytes), ctx->stream));
     } else if (sr->count > 0) {
-        rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)sr->count * pack_bytes(op, prec), ctx->stream);
-        if (rc) return rc;
         a.pack = ctx->scratch2;
         BF_HIP(launch_pack(op, prec, a, ctx->stream));
     }
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    if (ctx->timing) {
+    const bool timed = ctx->timing && !ctx->capturing;
+    if (timed) {
         if (!ctx->tpool.empty()) {
             ev = ctx->tpool.back();
             ctx->tpool.pop_back();
@@ -258,17 +271,12 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     }
     if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
     else BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
-    if (ctx->timing) {
+    if (timed) {
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
     }
     if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
-    if (fix) {
-        const size_t fb = (size_t)kFixChunks * 3 * kFixTiled * sizeof(double);
-        rc = ensure(&ctx->scratch8, &ctx->scratch8_bytes, fb, ctx->stream);
-        if (rc) return rc;
-        BF_HIP(launch_fixup(op, a, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
-    }
+    if (fix) BF_HIP(launch_fixup(op, a, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
     if (fix) BF_HIP(hipMemcpyAsync(ctx->d_stats, a.fix_count, sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
     return BF_OK;
 }
@@ -630,6 +638,7 @@ static int fsi_impl(bf_ctx* c, const bf_state* S, const bf_set* set, double dt, 
 
     auto pn_half_kick = [&]() -> int {
         if (prm->n_bh == 0) return BF_OK;
+        if (c->dry) return fail(BF_ERR_UNSUPPORTED, "PN1.0 kicks are not captured");
         if (int r = pn1_impl(c, M, set, set, prm->bh_idx, prm->n_bh, G, prm->c, gx, gy, gz)) return r;
         BF_HIP(launch_kick(*S, ds, 0.5 * dt, gx, gy, gz, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
         return BF_OK;
@@ -639,16 +648,17 @@ static int fsi_impl(bf_ctx* c, const bf_state* S, const bf_set* set, double dt, 
     if ((rc = pn_half_kick())) return rc;
     if (!(flags & BF_A_VALID))
         if ((rc = acc())) return rc;
-    BF_HIP(launch_kick(*S, ds, dt / 6.0, ax, ay, az, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
-    BF_HIP(launch_drift(*S, ds, 0.5 * dt, c->d_flags, c->stream));
+    const bool go = !c->dry;  // a sizing pass before a capture launches nothing
+    if (go) BF_HIP(launch_kick(*S, ds, dt / 6.0, ax, ay, az, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
+    if (go) BF_HIP(launch_drift(*S, ds, 0.5 * dt, c->d_flags, c->stream));
     if ((rc = acc())) return rc;
     Masters Mg = M;
     Mg.ax = ax; Mg.ay = ay; Mg.az = az;
     if ((rc = run_pairs(c, OP_GRAD, prec, Mg, set, set, G, e2, rfb, 0, 0, gx, gy, gz))) return rc;
-    BF_HIP(launch_kick(*S, ds, 2.0 * dt / 3.0, ax, ay, az, dt * dt / 24.0, gx, gy, gz, c->d_flags, c->stream));
-    BF_HIP(launch_drift(*S, ds, 0.5 * dt, c->d_flags, c->stream));
+    if (go) BF_HIP(launch_kick(*S, ds, 2.0 * dt / 3.0, ax, ay, az, dt * dt / 24.0, gx, gy, gz, c->d_flags, c->stream));
+    if (go) BF_HIP(launch_drift(*S, ds, 0.5 * dt, c->d_flags, c->stream));
     if ((rc = acc())) return rc;
-    BF_HIP(launch_kick(*S, ds, dt / 6.0, ax, ay, az, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
+    if (go) BF_HIP(launch_kick(*S, ds, dt / 6.0, ax, ay, az, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
     if ((rc = pn_half_kick())) return rc;
     return BF_OK;
 }
@@ -794,8 +804,9 @@ int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_
     const DevSet dB = devset(&Bset);
     const double* nul = nullptr;
     int rc;
+    const bool go = !c->dry;
     if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
-    BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
+    if (go) BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
     if ((rc = fsi(0.5 * tau))) return rc;
     if ((rc = fast())) return rc;
     if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
@@ -807,12 +818,13 @@ int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_
     if ((rc = run_pairs(c, OP_GRAD, p->prec, Mg, &Fset, &Sset, p->G, p->eps2, p->r_fb, 0, 0, h.gsf, h.gsf + n,
                         h.gsf + 2 * n)))
         return rc;
-    BF_HIP(launch_kick(*h.S, dB, 2.0 * tau / 3.0, h.asf, h.asf + n, h.asf + 2 * n, tau * tau / 24.0, h.gsf, h.gsf + n,
-                       h.gsf + 2 * n, c->d_flags, c->stream));
+    if (go)
+        BF_HIP(launch_kick(*h.S, dB, 2.0 * tau / 3.0, h.asf, h.asf + n, h.asf + 2 * n, tau * tau / 24.0, h.gsf,
+                           h.gsf + n, h.gsf + 2 * n, c->d_flags, c->stream));
     if ((rc = fast())) return rc;
     if ((rc = fsi(0.5 * tau))) return rc;
     if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
-    BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
+    if (go) BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
     return BF_OK;
 }
 }  // extern "C++"
@@ -864,9 +876,8 @@ int hhs_adapt(const HhsCtx& h, HhsAdapt& A, const bf_set& P, int k, double tau) 
 
 }  // namespace
 
-BF_API int bf_hhs_interval(bf_ctx* c, const bf_state* S, const bf_set* set, const int32_t* level, int kmax, double tau,
-                           const bf_fsi_params* prm) {
-    g_err.clear();
+static int hhs_setup(bf_ctx* c, const bf_state* S, const bf_set* set, const int32_t* level, int kmax, double tau,
+                     const bf_fsi_params* prm, HhsCtx& h) {
     if (int rc = check_ctx(c)) return rc;
     if (int rc = check_state(S)) return rc;
     if (int rc = check_set(set, S->n, "hhs")) return rc;
@@ -875,11 +886,9 @@ BF_API int bf_hhs_interval(bf_ctx* c, const bf_state* S, const bf_set* set, cons
     if (!level) return fail(BF_ERR_ARG, "level NULL");
     if (kmax < 0 || kmax > 63) return fail(BF_ERR_ARG, "kmax must be in [0, 63]");
     if (!(isfinite(tau) && tau > 0)) return fail(BF_ERR_ARG, "tau must be finite and > 0");
-    if (set->count == 0) return BF_OK;
     const int64_t n = S->n;
-    const size_t ob = ((size_t)set->count * 4 + 255) & ~size_t(255);
+    const size_t ob = ((size_t)std::max(set->count, 1) * 4 + 255) & ~size_t(255);
     if (int rc = ensure(&c->scratch7, &c->scratch7_bytes, ob + (size_t)12 * n * sizeof(double), c->stream)) return rc;
-    HhsCtx h;
     h.c = c;
     h.S = S;
     h.prm = prm;
@@ -891,10 +900,99 @@ BF_API int bf_hhs_interval(bf_ctx* c, const bf_state* S, const bf_set* set, cons
     h.order = order;
     h.kmax = kmax;
     int64_t counts[64];
-    if (int rc = partition_impl(c, set, n, level, kmax, order, counts)) return rc;
+    for (int k = 0; k < 64; ++k) counts[k] = 0;
+    if (set->count > 0)
+        if (int rc = partition_impl(c, set, n, level, kmax, order, counts)) return rc;
     h.begin[0] = 0;
     for (int k = 0; k <= kmax; ++k) h.begin[k + 1] = h.begin[k] + counts[k];
+    return BF_OK;
+}
+
+BF_API int bf_hhs_interval(bf_ctx* c, const bf_state* S, const bf_set* set, const int32_t* level, int kmax, double tau,
+                           const bf_fsi_params* prm) {
+    g_err.clear();
+    HhsCtx h;
+    if (int rc = hhs_setup(c, S, set, level, kmax, tau, prm, h)) return rc;
+    if (set->count == 0) return BF_OK;
     return hhs_rec(h, 0, tau);
+}
+
+BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_set* set, const int32_t* level,
+                                         int kmax, double tau, const bf_fsi_params* prm, void** graph_exec) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (!graph_exec) return fail(BF_ERR_ARG, "graph pointer NULL");
+    *graph_exec = nullptr;
+    // The graph gets buffers of its own: park the context's while the interval is sized and
+    // captured, then hand the new ones to the graph and give the context its own back.
+    void** slot[4] = {&c->scratch, &c->scratch2, &c->scratch7, &c->scratch8};
+    size_t* slot_bytes[4] = {&c->scratch_bytes, &c->scratch2_bytes, &c->scratch7_bytes, &c->scratch8_bytes};
+    void* parked[4];
+    size_t parked_bytes[4];
+    for (int i = 0; i < 4; ++i) {
+        parked[i] = *slot[i];
+        parked_bytes[i] = *slot_bytes[i];
+        *slot[i] = nullptr;
+        *slot_bytes[i] = 0;
+    }
+    auto unpark = [&](bool free_new) {
+        for (int i = 0; i < 4; ++i) {
+            if (free_new && *slot[i]) hipFree(*slot[i]);
+            *slot[i] = parked[i];
+            *slot_bytes[i] = parked_bytes[i];
+        }
+    };
+    HhsCtx h;
+    int rc = hhs_setup(c, S, set, level, kmax, tau, prm, h);
+    if (!rc && set->count == 0) rc = fail(BF_ERR_ARG, "empty set: nothing to capture");
+    if (rc) {
+        hipStreamSynchronize(c->stream);
+        unpark(true);
+        return rc;
+    }
+    c->capturing = true;  // no sorted passes, no timing events inside the graph
+    c->dry = true;
+    rc = hhs_rec(h, 0, tau);
+    c->dry = false;
+    hipStream_t user = c->stream, cap = nullptr;
+    hipGraph_t g = nullptr;
+    if (!rc && hipStreamSynchronize(user) != hipSuccess) rc = fail(BF_ERR_HIP, "stream synchronisation failed");
+    if (!rc && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(BF_ERR_HIP, "capture stream creation failed");
+    if (!rc) {
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            rc = fail(BF_ERR_HIP, hipGetErrorString(e));
+        } else {
+            c->stream = cap;
+            rc = hhs_rec(h, 0, tau);
+            c->stream = user;
+            e = hipStreamEndCapture(cap, &g);
+            if (!rc && e != hipSuccess) rc = fail(BF_ERR_HIP, hipGetErrorString(e));
+        }
+    }
+    if (cap) hipStreamDestroy(cap);
+    c->capturing = false;
+    bf_graph* gr = nullptr;
+    if (!rc) {
+        gr = new bf_graph();
+        gr->graph = g;
+        if (hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            rc = fail(BF_ERR_HIP, "graph instantiation failed");
+            delete gr;
+            gr = nullptr;
+        }
+    }
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        hipStreamSynchronize(user);
+        unpark(true);
+        return rc;
+    }
+    for (int i = 0; i < 4; ++i) gr->owned[i] = *slot[i];
+    unpark(false);
+    *graph_exec = gr;
+    return BF_OK;
 }
 
 BF_API int bf_hhs_interval_adaptive(bf_ctx* c, const bf_state* S, const bf_set* set, const double* dt0, int kmax,

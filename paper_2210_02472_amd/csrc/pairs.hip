@@ -123,19 +123,26 @@ __global__ void k_zero_u64(unsigned long long* c, int n) {
 }
 
 // Tiled form for up to kFixTiled queued targets: a workgroup takes 256 queued targets (one per
-// thread) against one of kFixChunks source chunks staged through LDS, and writes FP64 partial
-// sums; k_fixup_reduce adds the chunks in order.  Queued targets beyond kFixTiled (never seen
-// in practice) take k_fixup, one workgroup per target.
+// thread) against one source chunk staged through LDS and writes FP64 partial sums;
+// k_fixup_reduce adds the chunks in order.  The number of chunks follows the queue length (at
+// most kFixChunks), so that short queues still fill the chip.  Queued targets beyond kFixTiled
+// take k_fixup, one workgroup per target.
+__device__ __forceinline__ int fix_chunks(int count) {
+    const int slabs = (count + 255) / 256;
+    return max(8, min(kFixChunks, 2048 / max(slabs, 1)));
+}
+
 template <int OP>
 __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* part) {
     const int count = min(min(*a.fix_count, a.tgt.count), kFixTiled);
-    const int items = (count + 255) / 256 * kFixChunks;
+    const int nch = fix_chunks(count);
+    const int items = (count + 255) / 256 * nch;
     const int ns = a.src.count;
-    const int chunk = (ns + kFixChunks - 1) / kFixChunks;
+    const int chunk = (ns + nch - 1) / nch;
     __shared__ double4 sp[256];  // (x, y, z, G m)
     __shared__ double4 sa[256];  // (ax, ay, az, particle index)
     for (int it = blockIdx.x; it < items; it += gridDim.x) {
-        const int slab = it / kFixChunks, c = it % kFixChunks;
+        const int slab = it / nch, c = it % nch;
         const int e = slab * 256 + (int)threadIdx.x;
         const bool act = e < count;
         const int pi = particle_of(a.tgt, a.fix_list[act ? e : 0], a.P.n, a.flags);
@@ -184,9 +191,10 @@ __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* p
 
 __global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part) {
     const int count = min(min(*a.fix_count, a.tgt.count), kFixTiled);
+    const int nch = fix_chunks(count);
     for (int e = blockIdx.x * 256 + (int)threadIdx.x; e < count; e += gridDim.x * 256) {
         double v[3] = {0.0, 0.0, 0.0};
-        for (int c = 0; c < kFixChunks; ++c)
+        for (int c = 0; c < nch; ++c)
             for (int k = 0; k < 3; ++k) v[k] += part[((size_t)c * 3 + k) * kFixTiled + e];
         const int pi = particle_of(a.tgt, a.fix_list[e], a.P.n, a.flags);
         a.o0[pi] = v[0];
@@ -336,8 +344,7 @@ hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st) {
 hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hipStream_t st) {
     const int nt = a.tgt.count;
     if (nt <= 0) return hipSuccess;
-    const int items = (std::min(nt, kFixTiled) + 255) / 256 * kFixChunks;
-    const int g1 = std::min(items, 4 * num_cu);
+    const int g1 = std::min(((std::min(nt, kFixTiled) + 255) / 256) * kFixChunks, 8 * num_cu);
     const int g2 = std::min((std::min(nt, kFixTiled) + 255) / 256, 4 * num_cu);
     if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_tiled<OP_ACC>, dim3(g1), dim3(256), 0, st, a, part);
     else if (op == OP_GRAD) hipLaunchKernelGGL(k_fixup_tiled<OP_GRAD>, dim3(g1), dim3(256), 0, st, a, part);
