@@ -89,7 +89,7 @@ struct bf_graph {
 };
 
 // FP64 fix-up of queued targets; part: kFixChunks * 3 * kFixTiled doubles of scratch.
-constexpr int kFixTiled = 16384, kFixChunks = 128;
+constexpr int kFixTiled = 32768, kFixChunks = 64;
 hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hipStream_t st);
 
 // Spatially sorted mixed acc/grad (spatial.hip).

@@ -349,7 +349,8 @@ struct AccRel {
     // upper bound of sum_j |term_j| over the tile for this target: every source lies in the
     // cube of half-extent h about the centre, so r is at least the target's distance to that
     // cube (positive for a far tile) and |term| = G m r / s^3 <= G m / r^2
-    static constexpr bool kTileBound = true;
+    static constexpr bool kTileBound = true, kWeightSum = false;
+    __device__ static float factor(const Tgt&, float) { return 1.f; }
     __device__ static float bound(const Tgt& t, float h, float gm_tile, float) {
         const float gx = fmaxf(__builtin_fabsf(t.x) - h, 0.f), gy = fmaxf(__builtin_fabsf(t.y) - h, 0.f),
                     gz = fmaxf(__builtin_fabsf(t.z) - h, 0.f);
@@ -380,10 +381,12 @@ struct GradRel {
         t.x = (float)(g.x - c.x); t.y = (float)(g.y - c.y); t.z = (float)(g.z - c.z);
         t.ax = (float)(g.ax - ca.x); t.ay = (float)(g.ay - ca.y); t.az = (float)(g.az - ca.z);
     }
-    // the gradient terms have no useful tile-wide bound (a_ji does not shrink with distance), so
-    // the magnitude estimate is accumulated per pair as in the FP64-difference operation
-    static constexpr bool kTileBound = false;
+    // magnitude estimate per pair, as in the FP64-difference operation: a tile-wide bound (sum
+    // of w times h_a + |a_c - a_i|) sent 60 times as many targets of a King W0 = 6 cluster to
+    // the FP64 fix-up
+    static constexpr bool kTileBound = false, kWeightSum = false;
     __device__ static float bound(const Tgt&, float, float, float) { return 0.f; }
+    __device__ static float factor(const Tgt&, float) { return 1.f; }
     __device__ static void pair(A32& r, const Tgt& t, const Src& s, float eps2f) {
         const float dx = s.p.x - t.x, dy = s.p.y - t.y, dz = s.p.z - t.z;
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
@@ -507,10 +510,12 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
             }
         } else {
             typename Far::Tgt tf[K];
+            float fac[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 Far::rel(tf[k], tg[k], c, ca);
                 if (Far::kTileBound) acc[k].m += (double)Far::bound(tf[k], h, hm.y, ha);  // the whole tile
+                fac[k] = Far::factor(tf[k], ha);
             }
             for (int js = 0; js < len; js += kFold) {
                 const int je = min(len, js + kFold);
@@ -524,7 +529,10 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
                     for (int k = 0; k < K; ++k) Far::pair(part[k], tf[k], s, a.eps2f);
                 }
 #pragma unroll
-                for (int k = 0; k < K; ++k) Near::fold(acc[k], part[k]);
+                for (int k = 0; k < K; ++k) {
+                    if (Far::kWeightSum) part[k].m *= fac[k];
+                    Near::fold(acc[k], part[k]);
+                }
             }
         }
     }

@@ -122,19 +122,24 @@ __global__ void k_zero_u64(unsigned long long* c, int n) {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
-// Tiled form for up to kFixTiled queued targets: a workgroup takes 256 queued targets (one per
-// thread) against one source chunk staged through LDS and writes FP64 partial sums;
-// k_fixup_reduce adds the chunks in order.  The number of chunks follows the queue length (at
-// most kFixChunks), so that short queues still fill the chip.  Queued targets beyond kFixTiled
-// take k_fixup, one workgroup per target.
+// The queue is worked in rounds of up to kFixTiled targets.  In a round a workgroup takes 256
+// queued targets (one per thread) against one source chunk staged through LDS and writes FP64
+// partial sums; k_fixup_reduce adds the chunks in order.  The number of chunks follows the
+// round's length (at most kFixChunks), so that short queues still fill the chip.  Rounds past
+// the queue's end exit at once.
 __device__ __forceinline__ int fix_chunks(int count) {
     const int slabs = (count + 255) / 256;
     return max(8, min(kFixChunks, 2048 / max(slabs, 1)));
 }
 
+__device__ __forceinline__ int fix_round_count(const PairArgs& a, int base) {
+    return min(min(*a.fix_count, a.tgt.count) - base, kFixTiled);
+}
+
 template <int OP>
-__global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* part) {
-    const int count = min(min(*a.fix_count, a.tgt.count), kFixTiled);
+__global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* part, int base) {
+    const int count = fix_round_count(a, base);
+    if (count <= 0) return;
     const int nch = fix_chunks(count);
     const int items = (count + 255) / 256 * nch;
     const int ns = a.src.count;
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* p
         const int slab = it / nch, c = it % nch;
         const int e = slab * 256 + (int)threadIdx.x;
         const bool act = e < count;
-        const int pi = particle_of(a.tgt, a.fix_list[act ? e : 0], a.P.n, a.flags);
+        const int pi = particle_of(a.tgt, a.fix_list[base + (act ? e : 0)], a.P.n, a.flags);
         const double xi = a.P.x[pi], yi = a.P.y[pi], zi = a.P.z[pi];
         double axi = 0.0, ayi = 0.0, azi = 0.0;
         if constexpr (OP == OP_GRAD) { axi = a.P.ax[pi]; ayi = a.P.ay[pi]; azi = a.P.az[pi]; }
@@ -189,34 +194,18 @@ __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* p
     }
 }
 
-__global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part) {
-    const int count = min(min(*a.fix_count, a.tgt.count), kFixTiled);
+__global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part, int base) {
+    const int count = fix_round_count(a, base);
+    if (count <= 0) return;
     const int nch = fix_chunks(count);
     for (int e = blockIdx.x * 256 + (int)threadIdx.x; e < count; e += gridDim.x * 256) {
         double v[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < nch; ++c)
             for (int k = 0; k < 3; ++k) v[k] += part[((size_t)c * 3 + k) * kFixTiled + e];
-        const int pi = particle_of(a.tgt, a.fix_list[e], a.P.n, a.flags);
+        const int pi = particle_of(a.tgt, a.fix_list[base + e], a.P.n, a.flags);
         a.o0[pi] = v[0];
         a.o1[pi] = v[1];
         a.o2[pi] = v[2];
-    }
-}
-
-template <int OP>
-__global__ __launch_bounds__(256) void k_fixup(const PairArgs a) {
-    const int count = min(*a.fix_count, a.tgt.count);
-    for (int e = kFixTiled + blockIdx.x; e < count; e += gridDim.x) {
-        const int slot = a.fix_list[e];
-        const int pi = particle_of(a.tgt, slot, a.P.n, a.flags);
-        double r[3];
-        fix_one<OP>(a.P, a.src, a.sub, pi, a.G, a.eps2, a.flags, r);
-        if (threadIdx.x == 0) {
-            a.o0[pi] = r[0];
-            a.o1[pi] = r[1];
-            a.o2[pi] = r[2];
-        }
-        __syncthreads();
     }
 }
 
@@ -344,16 +333,14 @@ hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st) {
 hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hipStream_t st) {
     const int nt = a.tgt.count;
     if (nt <= 0) return hipSuccess;
-    const int g1 = std::min(((std::min(nt, kFixTiled) + 255) / 256) * kFixChunks, 8 * num_cu);
-    const int g2 = std::min((std::min(nt, kFixTiled) + 255) / 256, 4 * num_cu);
-    if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_tiled<OP_ACC>, dim3(g1), dim3(256), 0, st, a, part);
-    else if (op == OP_GRAD) hipLaunchKernelGGL(k_fixup_tiled<OP_GRAD>, dim3(g1), dim3(256), 0, st, a, part);
-    else return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fixup_reduce, dim3(g2), dim3(256), 0, st, a, (const double*)part);
-    if (nt > kFixTiled) {
-        const int g3 = std::min(nt - kFixTiled, 4 * num_cu);
-        if (op == OP_ACC) hipLaunchKernelGGL(k_fixup<OP_ACC>, dim3(g3), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL(k_fixup<OP_GRAD>, dim3(g3), dim3(256), 0, st, a);
+    if (op != OP_ACC && op != OP_GRAD) return hipErrorInvalidValue;
+    for (int base = 0; base < nt; base += kFixTiled) {  // rounds past the queue's end exit at once
+        const int len = std::min(nt - base, kFixTiled);
+        const int g1 = std::min((len + 255) / 256 * kFixChunks, 8 * num_cu);
+        const int g2 = std::min((len + 255) / 256, 4 * num_cu);
+        if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_tiled<OP_ACC>, dim3(g1), dim3(256), 0, st, a, part, base);
+        else hipLaunchKernelGGL(k_fixup_tiled<OP_GRAD>, dim3(g1), dim3(256), 0, st, a, part, base);
+        hipLaunchKernelGGL(k_fixup_reduce, dim3(g2), dim3(256), 0, st, a, (const double*)part, base);
     }
     return hipGetLastError();
 }

@@ -250,7 +250,10 @@ __device__ __forceinline__ void emit_sorted(const PairArgs& a, int c, int slot, 
 }
 
 template <class Op, int K, int W>
-__global__ __launch_bounds__(64 * W) void k_pairs_sorted(const PairArgs a) {
+// one target per lane: ask for six waves per SIMD (the gradient variant then fits 76 VGPRs
+// without spills, 2% faster at N = 2^20 than at its natural 92)
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 1 ? 6 : 1))) void k_pairs_sorted(
+    const PairArgs a) {
     constexpr int T = 64 * W;
     using Far = typename FarOf<Op>::type;
     constexpr size_t kBytes = sizeof(typename Op::Src) > sizeof(typename Far::Src) ? sizeof(typename Op::Src)
