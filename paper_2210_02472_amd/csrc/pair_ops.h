@@ -53,6 +53,21 @@ __device__ __forceinline__ double pack_gm(float gm) { return __builtin_bit_cast(
 __device__ __forceinline__ float unpack_gm(double w) { return __builtin_bit_cast(float2, w).x; }
 
 constexpr int kFold = 64;           // sources per FP32 partial before the FP64 merge
+
+// Read-only data whose address is the same for every lane of a wavefront (a source of the
+// sorted far stream, tile metadata): read through the constant address space, so that the
+// compiler issues scalar loads and the operands arrive in SGPRs, once per wavefront, with no
+// LDS staging.  The data must not be written while the kernel runs.
+typedef __attribute__((address_space(4))) const float cfloat;
+typedef __attribute__((address_space(4))) const double cdouble;
+__device__ __forceinline__ float4 load_uniform4(const void* base, int q) {
+    const cfloat* f = (const cfloat*)(base) + 4 * (size_t)q;
+    return make_float4(f[0], f[1], f[2], f[3]);
+}
+__device__ __forceinline__ double4 load_uniform4d(const void* base, int q) {
+    const cdouble* f = (const cdouble*)(base) + 4 * (size_t)q;
+    return make_double4(f[0], f[1], f[2], f[3]);
+}
 constexpr float kTiny32 = 1e-20f;   // added to s^2 in FP32: keeps the self pair finite (and zero)
 constexpr double kTiny64 = 1e-150;  // same in FP64
 
@@ -343,6 +358,7 @@ struct AccRel {
     struct Tgt { float x, y, z; };
     using A32 = AccMixed::A32;
     __device__ static Src load(const PairArgs& a, int q) { return {static_cast<const float4*>(a.pack_far)[q]}; }
+    __device__ static Src load_uniform(const PairArgs& a, int q) { return {load_uniform4(a.pack_far, q)}; }
     __device__ static void rel(Tgt& t, const AccMixed::Tgt& g, const double4& c, const double4&) {
         t.x = (float)(g.x - c.x); t.y = (float)(g.y - c.y); t.z = (float)(g.z - c.z);
     }
@@ -376,6 +392,9 @@ struct GradRel {
     __device__ static Src load(const PairArgs& a, int q) {
         const float4* pk = static_cast<const float4*>(a.pack_far);
         return {pk[2 * q], pk[2 * q + 1]};
+    }
+    __device__ static Src load_uniform(const PairArgs& a, int q) {
+        return {load_uniform4(a.pack_far, 2 * q), load_uniform4(a.pack_far, 2 * q + 1)};
     }
     __device__ static void rel(Tgt& t, const GradMixed::Tgt& g, const double4& c, const double4& ca) {
         t.x = (float)(g.x - c.x); t.y = (float)(g.y - c.y); t.z = (float)(g.z - c.z);
@@ -465,13 +484,12 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
     }
     block_box<W>(lo, hi, sbox);
     typename Near::Src* tnear = reinterpret_cast<typename Near::Src*>(tile_raw);
-    typename Far::Src* tfar = reinterpret_cast<typename Far::Src*>(tile_raw);
     unsigned long long n_near = 0, n_far = 0;
     for (int jt = j0; jt < j1; jt += T) {
         const int len = min(T, j1 - jt);
         const int tix = jt / T;
-        const double4 c = a.tile_meta[kMeta * tix];
-        const double4 ca = kMeta > 1 ? a.tile_meta[kMeta * tix + 1] : c;
+        const double4 c = load_uniform4d(a.tile_meta, kMeta * tix);
+        const double4 ca = kMeta > 1 ? load_uniform4d(a.tile_meta, kMeta * tix + 1) : c;
         const float2 hm = __builtin_bit_cast(float2, c.w);  // (tile half-extent, G * tile mass)
         const float h = hm.x;
         const float ha = kMeta > 1 ? unpack_gm(ca.w) : 0.f;  // half-extent of the tile's accelerations
@@ -487,13 +505,12 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
         const bool near = gap2 < (a.kappa * h) * (a.kappa * h);
         n_near += near ? 1 : 0;
         n_far += near ? 0 : 1;
-        __syncthreads();
-        if ((int)threadIdx.x < len) {
-            if (near) tnear[threadIdx.x] = Near::load(a, jt + threadIdx.x);
-            else tfar[threadIdx.x] = Far::load(a, jt + threadIdx.x);
-        }
-        __syncthreads();
         if (near) {
+            // near tiles are staged through LDS (FP64 sources); the decision is uniform over
+            // the workgroup, so the barriers are too
+            __syncthreads();
+            if ((int)threadIdx.x < len) tnear[threadIdx.x] = Near::load(a, jt + threadIdx.x);
+            __syncthreads();
             for (int js = 0; js < len; js += kFold) {
                 const int je = min(len, js + kFold);
                 typename Near::A32 part[K];
@@ -524,7 +541,7 @@ __device__ __forceinline__ void sweep_sorted(const PairArgs& a, char* tile_raw, 
                 for (int k = 0; k < K; ++k) Near::zero(part[k]);
 #pragma unroll 4
                 for (int j = js; j < je; ++j) {
-                    const typename Far::Src s = tfar[j];
+                    const typename Far::Src s = Far::load_uniform(a, jt + j);  // scalar loads
 #pragma unroll
                     for (int k = 0; k < K; ++k) Far::pair(part[k], tf[k], s, a.eps2f);
                 }
@@ -573,6 +590,9 @@ __device__ __forceinline__ void sweep(const PairArgs& a, typename Op::Src* tile,
     }
     for (int jt = j0; jt < j1; jt += T) {
         const int len = min(T, j1 - jt);
+        // The tile is staged through LDS.  (Wavefront-uniform scalar loads, which the sorted far
+        // path uses, measured slower here: the FP64 sources take twice the SGPR traffic and the
+        // close-pair variants lost occupancy.)
         __syncthreads();
         if ((int)threadIdx.x < len) {
             tile[threadIdx.x] = Op::load(a, jt + threadIdx.x);
