@@ -195,6 +195,43 @@ def run_workload(name, args):
             levels.append({"level": k, "n_active": int(idx.size), "acc_ms": ta, "grad_ms": tg, "pn1_ms": tp * 1e3,
                            "acc_grad_pairs_per_s": idx.size * float(n) / ((ta + tg) * 1e-3)})
         rec.update({"n": n, "n_bh": int(len(bh)), "levels": levels})
+    elif name == "bh-hhs":
+        # One HHS-FSI interval over the same cluster and levels (Newtonian part, mixed precision):
+        # eager device driver, the same interval replayed from a HIP graph, and the interval
+        # with time-steps reassigned on every level (the initial time-steps put each particle on
+        # its level; pairwise time-steps over each level's particles may move it deeper)
+        d, bh, lv = ics.config5_bh_cluster()
+        n = len(d["m"])
+        kmax = int(lv.max())
+        tau = 1.0 / 4096
+        level = torch.as_tensor(lv.astype(np.int32), device="cuda")
+        P = bf.Particles.from_numpy(d)
+
+        def wall(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / reps * 1e3
+
+        eager = wall(lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed"), 3)
+        ctx.set_spatial_sort(False, False)  # what the graph records: the unsorted passes
+        eager_unsorted = wall(lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed"), 3)
+        g = ctx.capture_hhs_interval(P, level, kmax, tau, prec="mixed")
+        graph = wall(g.launch, 3)
+        g.close()
+        ctx.set_spatial_sort(True, True)
+        dt0 = torch.as_tensor(1.5 * tau / 2.0 ** lv.astype(np.float64), device="cuda")
+        levels_seen = []
+        adaptive = wall(lambda: levels_seen.append(ctx.hhs_interval_adaptive(P, dt0, kmax, tau, 0.05, 0.05,
+                                                                                prec="mixed")), 2)
+        counts = np.bincount(lv, minlength=kmax + 1)
+        rec.update({"n": n, "kmax": kmax, "tau": tau, "particles_per_level": counts.tolist(),
+                    "interval_ms": {"eager": eager, "eager_unsorted": eager_unsorted, "graph": graph,
+                                    "adaptive": adaptive},
+                    "adaptive_deepest_level": levels_seen[-1][0], "adaptive_levels_visited": levels_seen[-1][1]})
     ctx.close()
     print(json.dumps(rec), flush=True)
 
@@ -222,7 +259,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 2 GiB device-to-device copy kernel first (HBM counter calibration)")
     ap.add_argument("--workload", default="king1m",
-                    choices=["king1m", "plummer1k-fsi", "plummer64k-level", "ensemble256", "bh-levels"],
+                    choices=["king1m", "plummer1k-fsi", "plummer64k-level", "ensemble256", "bh-levels", "bh-hhs"],
                     help="king1m (default): the headline sweep; the others measure the remaining "
                          "workloads and print their own JSON line")
     args = ap.parse_args()

@@ -226,8 +226,10 @@ BF_API int bf_level_partition(bf_ctx *ctx, const bf_set *set, int64_t n, const i
  *   HHS(F, tau/2); FSI(S, tau/2); kick tau/6.
  * An empty F ends the recursion with one FSI cycle of S over tau; an empty S gives two half
  * intervals of F.  Positions and velocities of S are updated in place (FP64).  The partition
- * synchronises once; everything else is stream-ordered.  prm->n_bh must be 0 (PN1.0 is not part
- * of this driver). */
+ * synchronises once; everything else is stream-ordered.  With prm->n_bh > 0 (PN1.0, Sec. 3.8,
+ * FP64) every FSI cycle is wrapped in PN half-kicks over its own pairs (as bf_fsi_step) and
+ * every level's cycle in PN half-kicks of tau/2 over its inter-level pairs with a listed
+ * particle; the paper does not place the PN terms in the hierarchy, this is a reading. */
 BF_API int bf_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, const int32_t *level,
                            int kmax, double tau, const bf_fsi_params *prm);
 
@@ -238,7 +240,7 @@ BF_API int bf_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, co
  * scratch buffers, so later calls on the context never invalidate it.  Inside the graph the
  * mixed passes run unsorted (the spatially sorted mode and kernel timing are off while
  * capturing); results equal an eager bf_hhs_interval with the sorted mode off.  Errors as
- * bf_hhs_interval; an empty set is BF_ERR_ARG. */
+ * bf_hhs_interval; an empty set is BF_ERR_ARG; prm->n_bh must be 0 (BF_ERR_UNSUPPORTED). */
 BF_API int bf_graph_capture_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, const int32_t *level,
                                          int kmax, double tau, const bf_fsi_params *prm, void **graph_exec);
 
@@ -252,7 +254,7 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx *ctx, const bf_state *S, const b
  * with time-step >= pivot are slow, the others fast; on level kmax all are slow.  The cycle on
  * each level is the one of bf_hhs_interval.  Synchronises once per visited level (the split
  * sizes); max_level / n_levels (host, may be NULL) receive the deepest level reached and the
- * number of levels visited.  prm->n_bh must be 0. */
+ * number of levels visited.  PN1.0 as in bf_hhs_interval. */
 BF_API int bf_hhs_interval_adaptive(bf_ctx *ctx, const bf_state *S, const bf_set *set, const double *dt0,
                                     int kmax, double tau, double eta_ff, double eta_fb,
                                     const bf_fsi_params *prm, int *max_level, int64_t *n_levels);
@@ -357,6 +359,7 @@ BF_API int bf_set_subsystems(bf_ctx *ctx, const int32_t *label, int64_t n);
 /* ---- tuning ------------------------------------------------------------------------- */
 
 typedef enum { BF_OP_FORCES = 0, BF_OP_GRADIENT = 1, BF_OP_DTMIN = 2 } bf_op;
+#define BF_SORT_ANY_SIZE 0x100  /* bf_set_spatial_sort: sort passes of any size */
 
 /* Synchronising.  Time every kernel variant (targets per lane, waves per workgroup,
  * source split) for operation `op` at precision `prec` on n_targets x n_sources synthetic
@@ -369,9 +372,11 @@ BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
 
 /* Spatially sorted mode of the mixed acceleration and gradient passes.  ops_mask selects the
  * passes that use it: bit (1 << BF_OP_FORCES) and/or bit (1 << BF_OP_GRADIENT); the default is
- * both.  When selected, and r_fb == 0, with at least 2048 sources and 512
- * targets, targets and sources are ordered along a Morton curve and the sources packed into
- * tiles; a tile whose gap to a workgroup's target box is at least kappa times its half-extent
+ * both.  When selected, and r_fb == 0, with at least 16384 targets and 16384 sources and
+ * 2^31 pairs (below that the sort costs more than it saves; bit BF_SORT_ANY_SIZE in ops_mask
+ * lifts these limits), without subsystem labels and outside graph capture, targets and sources
+ * are ordered along a Morton curve and the sources packed into tiles; a tile whose gap to a
+ * workgroup's target box is at least kappa times its half-extent
  * is summed from FP32 offsets to the tile centre (pair separation rounding error at most
  * u (1 + 2 sqrt(3) / kappa) relative), nearer tiles from FP64 differences.  kappa = 0 keeps the
  * current value (default 1); otherwise it must lie in [0.5, 64] (BF_ERR_ARG).  Outputs stay

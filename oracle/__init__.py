@@ -307,39 +307,57 @@ def _interlevel_acc(p: Particles, S: np.ndarray, F: np.ndarray, G: float, eps2: 
     return full
 
 
+def _interlevel_pn(p: Particles, S: np.ndarray, F: np.ndarray, bh, G: float, c: float):
+    """PN1.0 accelerations over inter-level pairs with a flagged particle: slow targets from
+    fast sources and fast targets from slow sources (particle-indexed, zero elsewhere)."""
+    full = np.zeros((p.n, 3))
+    full[S] = pn1(p, bh, S, F, G, c)
+    full[F] = pn1(p, bh, F, S, G, c)
+    return full
+
+
 def hhs_interval(p: Particles, levels: np.ndarray, tau: float, subset=None, level: int = 0,
-                 G: float = 1.0, eps2: float = 0.0) -> Particles:
+                 G: float = 1.0, eps2: float = 0.0, bh=None, c: float = 1e4) -> Particles:
     """One HHS-FSI interval of length tau over `subset`, with per-particle levels given
     (Sec. 2.2, Eq. hhsfsi-cycle).  Slow set S = particles at `level`, fast set F =
     particles at deeper levels.  Readings for cases the paper leaves open: with F
     empty the slow set takes one plain FSI cycle; with S empty the fast set takes two
-    half intervals at the next level."""
+    half intervals at the next level.  With `bh` given (PN1.0 for pairs with a flagged
+    particle, Sec. 3.8), every plain FSI cycle is wrapped in PN half-kicks over its own pairs
+    and every level's cycle in PN half-kicks over its inter-level pairs (a reading: the paper
+    does not place the PN terms in the hierarchy)."""
     idx = _idx(subset, p.n)
     lv = np.asarray(levels)[idx]
     S = idx[lv == level]
     F = idx[lv > level]
+    pn = bh is not None and len(bh) > 0
+    sub = dict(G=G, eps2=eps2, bh=bh, c=c)
     if F.size == 0:
         if S.size:
-            fsi_step(p, tau, S, G, eps2)
+            fsi_step(p, tau, S, G, eps2, bh=bh, c=c)
         return p
     if S.size == 0:
-        hhs_interval(p, levels, tau / 2, F, level + 1, G, eps2)
-        hhs_interval(p, levels, tau / 2, F, level + 1, G, eps2)
+        hhs_interval(p, levels, tau / 2, F, level + 1, **sub)
+        hhs_interval(p, levels, tau / 2, F, level + 1, **sub)
         return p
     both = np.concatenate([S, F])
+    if pn:
+        _kick(p, both, _interlevel_pn(p, S, F, bh, G, c)[both], tau / 2)
     a = _interlevel_acc(p, S, F, G, eps2)
     _kick(p, both, a[both], tau / 6)
-    fsi_step(p, tau / 2, S, G, eps2)
-    hhs_interval(p, levels, tau / 2, F, level + 1, G, eps2)
+    fsi_step(p, tau / 2, S, G, eps2, bh=bh, c=c)
+    hhs_interval(p, levels, tau / 2, F, level + 1, **sub)
     a = _interlevel_acc(p, S, F, G, eps2)
     g = np.zeros((p.n, 3))
     g[S] = gradient(p, a, S, F, G, eps2)
     g[F] = gradient(p, a, F, S, G, eps2)
     _kick(p, both, a[both] + (tau * tau / 24.0) * g[both], 2.0 * tau / 3.0)
-    hhs_interval(p, levels, tau / 2, F, level + 1, G, eps2)
-    fsi_step(p, tau / 2, S, G, eps2)
+    hhs_interval(p, levels, tau / 2, F, level + 1, **sub)
+    fsi_step(p, tau / 2, S, G, eps2, bh=bh, c=c)
     a = _interlevel_acc(p, S, F, G, eps2)
     _kick(p, both, a[both], tau / 6)
+    if pn:
+        _kick(p, both, _interlevel_pn(p, S, F, bh, G, c)[both], tau / 2)
     return p
 
 

@@ -24,6 +24,7 @@ BF_FLAG_COINCIDENT = 0x2
 BF_FLAG_BADINDEX = 0x4
 BF_A_VALID = 0x1
 BF_ERR_NOMEM = -5
+BF_SORT_ANY_SIZE = 0x100
 BF_OP_FORCES, BF_OP_GRADIENT, BF_OP_DTMIN = 0, 1, 2
 
 PRECISIONS = {"fp64": BF_PREC_FP64, "mixed": BF_PREC_MIXED}
@@ -344,20 +345,23 @@ class Context:
         return order[:s.count], [int(counts[k]) for k in range(kmax + 1)]
 
     def hhs_interval(self, P: Particles, level: torch.Tensor, kmax: int, tau: float, subset=None, G=1.0, eps2=0.0,
-                     prec="mixed", r_fb=0.0):
-        """One HHS-FSI interval with fixed levels, in place."""
+                     prec="mixed", r_fb=0.0, bh=None, c=1e4):
+        """One HHS-FSI interval with fixed levels, in place (PN1.0 half-kicks when bh is given)."""
         s = ParticleSet.of(subset, P.n)
         _need(level, torch.int32, P.n, "level")
-        prm = _FsiParams(float(G), float(eps2), PRECISIONS[prec], float(r_fb), None, 0, 1.0)
+        b = ParticleSet.of(bh, P.n) if bh is not None else ParticleSet(None, 0, 0)
+        prm = _FsiParams(float(G), float(eps2), PRECISIONS[prec], float(r_fb), _ptr(b.idx), int(b.count), float(c))
         _check("bf_hhs_interval", _lib.bf_hhs_interval(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()),
                                                        _ptr(level), int(kmax), float(tau), ctypes.byref(prm)))
 
     def capture_hhs_interval(self, P: Particles, level: torch.Tensor, kmax: int, tau: float, subset=None, G=1.0,
-                             eps2=0.0, prec="mixed", r_fb=0.0) -> "Graph":
-        """Capture one fixed-level HHS-FSI interval into a HIP graph (launch to advance P)."""
+                             eps2=0.0, prec="mixed", r_fb=0.0, bh=None, c=1e4) -> "Graph":
+        """Capture one fixed-level HHS-FSI interval into a HIP graph (launch to advance P).
+        PN1.0 is not captured: a non-empty bh is refused by the library."""
         s = ParticleSet.of(subset, P.n)
         _need(level, torch.int32, P.n, "level")
-        prm = _FsiParams(float(G), float(eps2), PRECISIONS[prec], float(r_fb), None, 0, 1.0)
+        b = ParticleSet.of(bh, P.n) if bh is not None else ParticleSet(None, 0, 0)
+        prm = _FsiParams(float(G), float(eps2), PRECISIONS[prec], float(r_fb), _ptr(b.idx), int(b.count), float(c))
         h = _vp()
         _check("bf_graph_capture_hhs_interval",
                _lib.bf_graph_capture_hhs_interval(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()), _ptr(level),
@@ -456,10 +460,12 @@ class Context:
                                                              ctypes.byref(nf)))
         return f.value, nn.value, nf.value
 
-    def set_spatial_sort(self, forces: bool = True, gradient: bool = True, kappa: float = 0.0):
+    def set_spatial_sort(self, forces: bool = True, gradient: bool = True, kappa: float = 0.0,
+                         any_size: bool = False):
         """Select the passes that use the spatially sorted mixed kernels (default: both); kappa = 0
-        keeps the near-tile threshold (default 1)."""
+        keeps the near-tile threshold (default 1); any_size lifts the minimum pass size."""
         mask = (int(bool(forces)) << BF_OP_FORCES) | (int(bool(gradient)) << BF_OP_GRADIENT)
+        mask |= BF_SORT_ANY_SIZE if any_size else 0
         _check("bf_set_spatial_sort", _lib.bf_set_spatial_sort(self._h, mask, float(kappa)))
 
     # ---- subsystems --------------------------------------------------------------------------

@@ -103,14 +103,18 @@ struct Plan {
 };
 
 // Spatially sorted mode: mixed acceleration / gradient passes on large enough sets.
-constexpr int64_t kSortMinSources = 2048, kSortMinTargets = 512;
+// Below these sizes the sort, the tile packs and their launches cost more than the far tiles
+// save (measured on a 262,144-body HHS interval, whose deep levels are small).
+constexpr int64_t kSortMinSources = 16384, kSortMinTargets = 16384, kSortMinPairs = (int64_t)1 << 31;
 constexpr double kKappaMin = 0.5, kKappaMax = 64.0;
 
 bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb) {
     return (ctx->sort_ops >> op & 1) && ctx->sub == nullptr && !ctx->capturing && prec == BF_PREC_MIXED &&
            (op == OP_ACC || op == OP_GRAD) &&
            r_fb == 0.0 &&
-           ns >= kSortMinSources && nt >= kSortMinTargets;
+           ((ctx->sort_ops & BF_SORT_ANY_SIZE) ||
+            (ns >= kSortMinSources && nt >= kSortMinTargets && nt * ns >= kSortMinPairs)) &&
+           ns >= 64 && nt >= 64;
 }
 
 int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool sorted = false) {
@@ -805,6 +809,21 @@ int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_
     const double* nul = nullptr;
     int rc;
     const bool go = !c->dry;
+    // PN1.0 (Sec. 3.8) in the hierarchy, a reading: every plain FSI cycle carries half-kicks
+    // over its own pairs (fsi_impl), and each level's cycle is wrapped in half-kicks over its
+    // inter-level pairs with a flagged particle
+    auto pn_interlevel_half_kick = [&]() -> int {
+        if (p->n_bh == 0) return BF_OK;
+        if (c->dry) return fail(BF_ERR_UNSUPPORTED, "PN1.0 kicks are not captured");
+        if (int r = pn1_impl(c, h.M, &Sset, &Fset, p->bh_idx, p->n_bh, p->G, p->c, h.gsf, h.gsf + n, h.gsf + 2 * n))
+            return r;
+        if (int r = pn1_impl(c, h.M, &Fset, &Sset, p->bh_idx, p->n_bh, p->G, p->c, h.gsf, h.gsf + n, h.gsf + 2 * n))
+            return r;
+        BF_HIP(launch_kick(*h.S, dB, 0.5 * tau, h.gsf, h.gsf + n, h.gsf + 2 * n, 0.0, nul, nul, nul, c->d_flags,
+                           c->stream));
+        return BF_OK;
+    };
+    if ((rc = pn_interlevel_half_kick())) return rc;
     if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
     if (go) BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
     if ((rc = fsi(0.5 * tau))) return rc;
@@ -825,7 +844,7 @@ int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_
     if ((rc = fsi(0.5 * tau))) return rc;
     if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
     if (go) BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
-    return BF_OK;
+    return pn_interlevel_half_kick();
 }
 }  // extern "C++"
 
@@ -882,7 +901,6 @@ static int hhs_setup(bf_ctx* c, const bf_state* S, const bf_set* set, const int3
     if (int rc = check_state(S)) return rc;
     if (int rc = check_set(set, S->n, "hhs")) return rc;
     if (int rc = check_fsi_params(prm)) return rc;
-    if (prm->n_bh != 0) return fail(BF_ERR_UNSUPPORTED, "the HHS driver runs without PN1.0 (n_bh must be 0)");
     if (!level) return fail(BF_ERR_ARG, "level NULL");
     if (kmax < 0 || kmax > 63) return fail(BF_ERR_ARG, "kmax must be in [0, 63]");
     if (!(isfinite(tau) && tau > 0)) return fail(BF_ERR_ARG, "tau must be finite and > 0");
@@ -923,6 +941,7 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_
     if (int rc = check_ctx(c)) return rc;
     if (!graph_exec) return fail(BF_ERR_ARG, "graph pointer NULL");
     *graph_exec = nullptr;
+    if (prm && prm->n_bh != 0) return fail(BF_ERR_UNSUPPORTED, "a captured interval runs without PN1.0 (n_bh must be 0)");
     // The graph gets buffers of its own: park the context's while the interval is sized and
     // captured, then hand the new ones to the graph and give the context its own back.
     void** slot[4] = {&c->scratch, &c->scratch2, &c->scratch7, &c->scratch8};
@@ -1003,7 +1022,6 @@ BF_API int bf_hhs_interval_adaptive(bf_ctx* c, const bf_state* S, const bf_set* 
     if (int rc = check_state(S)) return rc;
     if (int rc = check_set(set, S->n, "hhs")) return rc;
     if (int rc = check_fsi_params(prm)) return rc;
-    if (prm->n_bh != 0) return fail(BF_ERR_UNSUPPORTED, "the HHS driver runs without PN1.0 (n_bh must be 0)");
     if (!dt0) return fail(BF_ERR_ARG, "dt0 NULL");
     if (kmax < 0 || kmax > 63) return fail(BF_ERR_ARG, "kmax must be in [0, 63]");
     if (!(isfinite(tau) && tau > 0)) return fail(BF_ERR_ARG, "tau must be finite and > 0");
@@ -1060,7 +1078,8 @@ BF_API int bf_last_pass_stats(bf_ctx* c, int64_t* fixups, int64_t* near_tiles, i
 
 BF_API int bf_set_spatial_sort(bf_ctx* c, int ops_mask, double kappa) {
     if (int rc = check_ctx(c)) return rc;
-    if (ops_mask & ~((1 << OP_ACC) | (1 << OP_GRAD))) return fail(BF_ERR_ARG, "ops_mask: only the force and gradient passes");
+    if (ops_mask & ~((1 << OP_ACC) | (1 << OP_GRAD) | BF_SORT_ANY_SIZE))
+        return fail(BF_ERR_ARG, "ops_mask: only the force and gradient passes and BF_SORT_ANY_SIZE");
     if (kappa != 0.0 && !(kappa >= kKappaMin && kappa <= kKappaMax))
         return fail(BF_ERR_ARG, "kappa must be 0 (keep) or in [0.5, 64]");
     c->sort_ops = ops_mask;

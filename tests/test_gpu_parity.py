@@ -49,7 +49,7 @@ def _flags_clean(ctx):
 def sort_mode(ctx, request):
     """Run a test with the spatially sorted mixed kernels on (the default) and off."""
     on = request.param == "sorted"
-    ctx.set_spatial_sort(forces=on, gradient=on)
+    ctx.set_spatial_sort(forces=on, gradient=on, any_size=on)  # test sets are below the size limits
     yield request.param
     ctx.set_spatial_sort(forces=True, gradient=True, kappa=1.0)
 
@@ -167,7 +167,7 @@ def test_sorted_mode_king_cluster(ctx, op):
         acc = [torch.as_tensor(np.ascontiguousarray(af[:, k]), device="cuda") for k in range(3)]
     try:
         for mode, kappa in ((True, 3.0), (True, 0.5), (True, 1.0), (False, 1.0)):
-            ctx.set_spatial_sort(forces=mode, gradient=mode, kappa=kappa)
+            ctx.set_spatial_sort(forces=mode, gradient=mode, kappa=kappa, any_size=mode)
             for targets in (None, T):
                 if op == "forces":
                     out = ctx.forces(Pd, targets, None, prec="mixed", r_fb=0.0)
@@ -423,3 +423,60 @@ def test_autotune_table_round_trip(ctx, tmp_path):
     got = gather(ctx.forces(Pd, T, None, prec="mixed", r_fb=0.0), T)
     rms, mx = stats(rel_errors(got, oracle.forces(P, T, None)))
     assert rms <= RMS_TOL and mx <= MAX_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_degenerate_systems(ctx, prec):
+    """One particle: no source but itself, so zero acceleration and gradient and infinite
+    time-steps.  Two particles: the two-body closed form.  A massless test particle feels the
+    field and exerts none."""
+    one = {k: np.array([0.3]) for k in ("x", "y", "z", "vx", "vy", "vz")}
+    one["m"] = np.array([1.0])
+    P1 = _dev(one)
+    a = ctx.forces(P1, prec=prec)
+    g = ctx.force_gradient(P1, a, prec=prec)
+    ff, fb = ctx.dt_min(P1, prec=prec)
+    assert all(float(t[0]) == 0.0 for t in (*a, *g))
+    assert torch.isinf(ff[0]) and torch.isinf(fb[0])
+    two = {"x": np.array([0.0, 0.6]), "y": np.array([0.0, 0.8]), "z": np.zeros(2), "vx": np.zeros(2),
+           "vy": np.zeros(2), "vz": np.zeros(2), "m": np.array([0.25, 0.75])}
+    a = gather(ctx.forces(_dev(two), prec=prec), np.arange(2))
+    u = np.array([0.6, 0.8, 0.0])  # unit vector from body 0 to body 1 at distance 1
+    np.testing.assert_allclose(a[0], 0.75 * u, rtol=1e-6 if prec == "mixed" else 1e-14)
+    np.testing.assert_allclose(a[1], -0.25 * u, rtol=1e-6 if prec == "mixed" else 1e-14)
+    d = _cluster(2000, 41)
+    d["m"][7] = 0.0
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    got = gather(ctx.forces(Pd, prec=prec, r_fb=0.0), np.arange(2000))
+    ref = oracle.forces(P)
+    without = oracle.forces(P, None, np.delete(np.arange(2000), 7))
+    np.testing.assert_array_equal(ref, without)  # the oracle agrees the massless source adds nothing
+    if prec == "fp64":
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    else:
+        rms, mx = stats(rel_errors(got, ref))
+        assert rms <= RMS_TOL and mx <= MAX_TOL
+
+
+def test_size_limits_rejected(ctx):
+    """Sizes beyond the int32 index range, sets outside [0, n), negative softening and bad
+    precision are refused on the host before any launch."""
+    d = _cluster(100, 42)
+    Pd = _dev(d)
+    with pytest.raises(bf.BifrostError):
+        ctx.forces(Pd, bf.ParticleSet.range(90, 20), None)
+    with pytest.raises(bf.BifrostError):
+        ctx.forces(Pd, eps2=-1.0)
+    with pytest.raises((bf.BifrostError, KeyError)):
+        ctx.forces(Pd, prec="fp16")
+    # n = 2^31 through the C ABI: the arrays are never touched, the size check fails first
+    import ctypes
+    from paper_2210_02472_amd import _binding as B
+    big = Pd._c()
+    big.n = 1 << 31
+    rng = bf.ParticleSet.range(0, 10)._c()
+    out = [torch.zeros(100, dtype=torch.float64, device="cuda") for _ in range(3)]
+    rc = B._lib.bf_forces(ctx._h, ctypes.byref(big), ctypes.byref(rng), ctypes.byref(rng), 1.0, 0.0,
+                          B.BF_PREC_MIXED, 0.0, *[B._ptr(t) for t in out])
+    assert rc == -1  # BF_ERR_ARG
+    assert all(torch.all(t == 0) for t in out)

@@ -189,3 +189,26 @@ def test_hhs_interval_graph_replays_match_eager(ctx, prec):
     finally:
         ctx.set_spatial_sort(forces=True, gradient=True)
     assert ctx.read_flags() & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
+
+
+def test_hhs_interval_with_pn_parity(ctx):
+    """A fixed-level interval with black holes on the deepest level and PN1.0 (FP64, c = 30):
+    the device driver against the oracle recursion with the same placement of the PN kicks
+    (each FSI cycle over its own pairs, each level's cycle over its inter-level pairs)."""
+    n = 900
+    d = _cluster(n, 13)
+    bh = np.array([3, 100, 450], dtype=np.int32)
+    d["m"][bh] *= 50.0
+    rng = np.random.default_rng(15)
+    level = rng.choice([0, 1, 2], size=n, p=[0.6, 0.3, 0.1]).astype(np.int32)
+    level[bh] = 2
+    P, Pd = oracle.Particles.from_dict(d), bf.Particles.from_numpy(d)
+    tau = 2e-3
+    oracle.hhs_interval(P, level, tau, bh=bh, c=30.0)
+    ctx.hhs_interval(Pd, torch.as_tensor(level, device="cuda"), 2, tau, prec="fp64", bh=bh, c=30.0)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        ref = getattr(P, k)
+        got = getattr(Pd, k).cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
+    with pytest.raises(bf.BifrostError):  # PN kicks are not captured into graphs
+        ctx.capture_hhs_interval(Pd, torch.as_tensor(level, device="cuda"), 2, tau, prec="fp64", bh=bh)

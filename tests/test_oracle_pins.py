@@ -653,3 +653,44 @@ def test_exclusion_removes_intra_subsystem_pairs():
     f = (P.m[:, None] * a_ex).sum(axis=0)
     assert np.abs(f).max() < 1e-14 * (P.m[:, None] * np.abs(a_ex)).sum()
     assert not np.allclose(a_ex[[5, 17, 40, 60, 61]], af[[5, 17, 40, 60, 61]])
+
+
+def test_hhs_pn_single_level_is_fsi_with_pn():
+    P = Particles.from_dict(ics.plummer_cluster(ics.rng_for(61), 40, "equal"))
+    A, B = P.copy(), P.copy()
+    oracle.hhs_interval(A, np.zeros(P.n, dtype=int), 2e-3, bh=[0, 5], c=30.0)
+    oracle.fsi_step(B, 2e-3, bh=[0, 5], c=30.0)
+    for a, b in zip((A.x, A.vy, A.vz), (B.x, B.vy, B.vz)):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_hhs_pn_periapsis_advance_on_a_fast_level():
+    """A black-hole binary on the fast level of an HHS interval, with a light, distant third
+    body on the slow level: the binary's periapsis still advances by 6 pi G M / (c^2 a (1-e^2))
+    per orbit (Sec. 3.10, Eq. secular_omega) with the PN terms placed in the hierarchy."""
+    m1, m2, a0, e0, G, c = 0.5, 0.5, 1.0, 0.5, 1.0, 50.0
+    d = _kepler.binary_state(m1, m2, a0, e0)
+    d = {k: np.concatenate([v, [0.0]]) for k, v in d.items()}
+    d["x"][2] = 40.0; d["vy"][2] = math.sqrt(G * (m1 + m2) / 40.0); d["m"][2] = 1e-7
+    P = Particles.from_dict(d)
+    M = m1 + m2
+    period = 2 * math.pi * math.sqrt(a0 ** 3 / (G * M))
+    intervals_per_orbit = 300  # the binary takes two FSI cycles per interval
+    tau = period / intervals_per_orbit
+    lv = np.array([1, 1, 0])
+    angles, times = [], []
+    for s in range(4 * intervals_per_orbit + 1):
+        rel = np.array([P.x[1] - P.x[0], P.y[1] - P.y[0], P.z[1] - P.z[0]])
+        vrel = np.array([P.vx[1] - P.vx[0], P.vy[1] - P.vy[0], P.vz[1] - P.vz[0]])
+        h = np.cross(rel, vrel)
+        ev = np.cross(vrel, h) / (G * M) - rel / np.linalg.norm(rel)
+        if s == 0:
+            e1 = ev / np.linalg.norm(ev)
+            e2 = np.cross(h / np.linalg.norm(h), e1)
+        angles.append(math.atan2(ev @ e2, ev @ e1))
+        times.append(s * tau)
+        if s < 4 * intervals_per_orbit:
+            oracle.hhs_interval(P, lv, tau, G=G, bh=[0, 1], c=c)
+    rate = np.polyfit(np.array(times), np.unwrap(np.array(angles)), 1)[0]
+    expected = 6 * math.pi * G * M / (c * c * a0 * (1 - e0 * e0)) / period
+    assert abs(rate / expected - 1.0) < 0.03, (rate, expected)
