@@ -25,6 +25,7 @@ BF_FLAG_BADINDEX = 0x4
 BF_A_VALID = 0x1
 BF_ERR_NOMEM = -5
 BF_SORT_ANY_SIZE = 0x100
+BF_SORT_DIRECTED = 0x200
 BF_OP_FORCES, BF_OP_GRADIENT, BF_OP_DTMIN = 0, 1, 2
 
 PRECISIONS = {"fp64": BF_PREC_FP64, "mixed": BF_PREC_MIXED}
@@ -461,11 +462,13 @@ class Context:
         return f.value, nn.value, nf.value
 
     def set_spatial_sort(self, forces: bool = True, gradient: bool = True, kappa: float = 0.0,
-                         any_size: bool = False):
+                         any_size: bool = False, symmetric: bool = True):
         """Select the passes that use the spatially sorted mixed kernels (default: both); kappa = 0
-        keeps the near-tile threshold (default 1); any_size lifts the minimum pass size."""
+        keeps the near-tile threshold (default 1); any_size lifts the minimum pass size;
+        symmetric = False keeps the directed sweep where targets and sources are one set."""
         mask = (int(bool(forces)) << BF_OP_FORCES) | (int(bool(gradient)) << BF_OP_GRADIENT)
         mask |= BF_SORT_ANY_SIZE if any_size else 0
+        mask |= 0 if symmetric else BF_SORT_DIRECTED
         _check("bf_set_spatial_sort", _lib.bf_set_spatial_sort(self._h, mask, float(kappa)))
 
     # ---- subsystems --------------------------------------------------------------------------

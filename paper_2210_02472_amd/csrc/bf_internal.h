@@ -117,6 +117,35 @@ hipError_t launch_pairs_sorted(int op, const KernelConfig& cfg, const PairArgs& 
 bool sorted_variant_exists(int op, int k, int waves);
 int sorted_blocks_per_cu(int op, int k, int waves);
 
+// Pair-symmetric sorted sweep (symmetric.hip): targets and sources are one set, sorted and
+// packed in tiles of 64; a workgroup owns a block of kSymBlockTiles row tiles (W wavefronts of R
+// row tiles each, W R = kSymBlockTiles).
+constexpr int kSymBlockTiles = 16;
+struct SymArgs {
+    const void* near_pack;     // sorted particles, FP64 (the near stream of launch_pack_tiles)
+    const void* far_pack;      // sorted particles, FP32 offsets from their tile's centre
+    const double4* tile_meta;  // per tile: (centre, [half-extent, G tile mass]) [, (a centre, [a half-extent])]
+    int32_t n;                 // particles
+    int32_t n_tiles;           // ceil(n / 64)
+    int32_t n_blocks;          // ceil(n_tiles / kSymBlockTiles)
+    int32_t n_pad;             // 64 n_tiles: row stride of part and own
+    float eps2f, kappa;
+    int32_t n_chunks;          // the block distances 0..n_blocks/2 are split into n_chunks shares
+    int32_t chunk_len;         // of chunk_len distances (one workgroup per block and share)
+    float* part;               // [n_blocks / 2 + 1][4][n_pad] column-side partials, one row per block distance
+    double* own;               // [n_chunks][4][n_pad] row-side sums, one row per share
+    unsigned long long* tile_stats;  // [near, far] wavefront-tile visits (NULL: not counted)
+};
+// bytes of own (256-byte aligned) and of own + part for n particles and `chunks` shares
+size_t sym_own_bytes(int64_t n, int chunks);
+size_t sym_scratch_bytes(int64_t n, int chunks);
+// resident workgroups per CU of the symmetric kernel of op
+int sym_blocks_per_cu(int op);
+hipError_t launch_pairs_sym(int op, const SymArgs& g, hipStream_t st);
+// adds the row-side sums and the partials in a fixed order and writes the particle-indexed
+// outputs of a.tgt (the sorted list), queueing ill-conditioned targets for the fix-up
+hipError_t launch_sym_reduce(int op, const PairArgs& a, const SymArgs& g, hipStream_t st);
+
 // time-step assignment epilogue (timestep.hip)
 struct TimestepArgs {
     Masters P;
@@ -228,6 +257,8 @@ struct bf_ctx {
     size_t scratch7_bytes = 0;
     void* scratch8 = nullptr;         // FP64 fix-up partial sums
     size_t scratch8_bytes = 0;
+    void* scratch9 = nullptr;         // pair-symmetric sweep: row sums and column partials
+    size_t scratch9_bytes = 0;
     bool capturing = false;           // a graph capture is recording this context's work
     bool dry = false;                 // size scratch only, launch nothing (before a capture)
     unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass

@@ -107,6 +107,26 @@ struct Plan {
 // save (measured on a 262,144-body HHS interval, whose deep levels are small).
 constexpr int64_t kSortMinSources = 16384, kSortMinTargets = 16384, kSortMinPairs = (int64_t)1 << 31;
 constexpr double kKappaMin = 0.5, kKappaMax = 64.0;
+// Pair-symmetric sweep: its column partials take (n / 2048 + 1) * 16 bytes per particle
+// (8.6 GB at n = 2^20); above this size the directed sorted sweep runs instead.
+constexpr size_t kSymMaxScratch = (size_t)32 << 30;
+
+bool same_set(const bf_set* t, const bf_set* s) {
+    return t->idx == s->idx && t->count == s->count && (t->idx != nullptr || t->begin == s->begin);
+}
+
+// Shares of the block distances per row block: at least two rounds of resident workgroups.
+int sym_chunks(bf_ctx* ctx, int op, int64_t n) {
+    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
+    const int64_t want = 2 * (int64_t)ctx->num_cu * sym_blocks_per_cu(op);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb / 2 + 1, (want + nb - 1) / nb));
+}
+
+bool use_symmetric(bf_ctx* ctx, int op, bool sorted, const bf_set* tg, const bf_set* sr) {
+    return sorted && !(ctx->sort_ops & BF_SORT_DIRECTED) && same_set(tg, sr) &&
+           sym_scratch_bytes(tg->count, sym_chunks(ctx, op, tg->count)) <= kSymMaxScratch;
+}
 
 bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb) {
     return (ctx->sort_ops >> op & 1) && ctx->sub == nullptr && !ctx->capturing && prec == BF_PREC_MIXED &&
@@ -174,6 +194,8 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     if (rc) return rc;
     if (sorted && !sorted_variant_exists(op, p.cfg.k, p.cfg.waves))
         return fail(BF_ERR_UNSUPPORTED, "no sorted kernel variant for this configuration");
+    const bool sym = use_symmetric(ctx, op, sorted, tg, sr);
+    if (sym) p.split = 1;  // no source split: the symmetric sweep has its own partials
     PairArgs a{};
     a.P = M;
     a.tgt = devset(tg);
@@ -217,6 +239,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     if (fix) BF_HIP(launch_zero_count(a.fix_count, ctx->stream));
     BF_HIP(launch_zero_u64(ctx->d_stats, 3, ctx->stream));
     a.tile_stats = ctx->d_stats + 1;
+    SymArgs g{};
     if (sorted) {
         // order targets and sources along a Morton curve, then pack the sorted sources into tiles
         const int64_t nt = tg->count, ns = sr->count, nmax = std::max(nt, ns);
@@ -238,11 +261,12 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         sb.tmp_bytes = tmp;
         const DevSet ds = devset(sr), dt = devset(tg);
         BF_HIP(launch_sort_set(M, ds, ds, sb, src_sorted, ctx->d_flags, ctx->stream));
-        const bool same = tg->idx == sr->idx && tg->count == sr->count && tg->begin == sr->begin;
+        const bool same = same_set(tg, sr);
         if (!same) BF_HIP(launch_sort_set(M, dt, ds, sb, tgt_sorted, ctx->d_flags, ctx->stream));
         a.src = DevSet{src_sorted, (int32_t)ns, 0};
         a.tgt = DevSet{same ? src_sorted : tgt_sorted, (int32_t)nt, 0};
-        const int T = 64 * p.cfg.waves;
+        const int tile_waves = sym ? 1 : p.cfg.waves;  // the symmetric sweep packs tiles of 64
+        const int T = 64 * tile_waves;
         const int64_t ntiles = (ns + T - 1) / T;
         const int kmeta = op == OP_GRAD ? 2 : 1;
         rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)ns * pack_bytes(op, prec), ctx->stream);
@@ -255,8 +279,27 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         a.pack_far = ctx->scratch6;
         a.tile_meta = reinterpret_cast<const double4*>(static_cast<char*>(ctx->scratch6) + far_bytes);
         a.kappa = ctx->kappa;
-        BF_HIP(launch_pack_tiles(op, p.cfg.waves, a, ctx->scratch2, ctx->scratch6,
+        BF_HIP(launch_pack_tiles(op, tile_waves, a, ctx->scratch2, ctx->scratch6,
                                  reinterpret_cast<double4*>(static_cast<char*>(ctx->scratch6) + far_bytes), ctx->stream));
+        if (sym) {
+            const int chunks = sym_chunks(ctx, op, ns);
+            rc = ensure(&ctx->scratch9, &ctx->scratch9_bytes, sym_scratch_bytes(ns, chunks), ctx->stream);
+            if (rc) return rc;
+            g.near_pack = a.pack;
+            g.far_pack = a.pack_far;
+            g.tile_meta = a.tile_meta;
+            g.n = (int32_t)ns;
+            g.n_tiles = (int32_t)ntiles;
+            g.n_blocks = (int32_t)((ntiles + kSymBlockTiles - 1) / kSymBlockTiles);
+            g.n_pad = (int32_t)(64 * ntiles);
+            g.eps2f = a.eps2f;
+            g.kappa = a.kappa;
+            g.n_chunks = chunks;
+            g.chunk_len = (g.n_blocks / 2 + 1 + chunks - 1) / chunks;
+            g.own = static_cast<double*>(ctx->scratch9);
+            g.part = reinterpret_cast<float*>(static_cast<char*>(ctx->scratch9) + sym_own_bytes(ns, chunks));
+            g.tile_stats = a.tile_stats;
+        }
     } else if (sr->count > 0) {
         a.pack = ctx->scratch2;
         BF_HIP(launch_pack(op, prec, a, ctx->stream));
@@ -273,13 +316,15 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         }
         BF_HIP(hipEventRecord(ev.first, ctx->stream));
     }
-    if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
+    if (sym) BF_HIP(launch_pairs_sym(op, g, ctx->stream));
+    else if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
     else BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
     if (timed) {
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
     }
-    if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
+    if (sym) BF_HIP(launch_sym_reduce(op, a, g, ctx->stream));
+    else if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
     if (fix) BF_HIP(launch_fixup(op, a, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
     if (fix) BF_HIP(hipMemcpyAsync(ctx->d_stats, a.fix_count, sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
     return BF_OK;
@@ -401,6 +446,7 @@ BF_API int bf_destroy(bf_ctx* c) {
     if (c->scratch6) hipFree(c->scratch6);
     if (c->scratch7) hipFree(c->scratch7);
     if (c->scratch8) hipFree(c->scratch8);
+    if (c->scratch9) hipFree(c->scratch9);
     if (c->d_flags) hipFree(c->d_flags);
     if (c->d_stats) hipFree(c->d_stats);
     if (c->h_flags) hipHostFree(c->h_flags);
@@ -1078,8 +1124,8 @@ BF_API int bf_last_pass_stats(bf_ctx* c, int64_t* fixups, int64_t* near_tiles, i
 
 BF_API int bf_set_spatial_sort(bf_ctx* c, int ops_mask, double kappa) {
     if (int rc = check_ctx(c)) return rc;
-    if (ops_mask & ~((1 << OP_ACC) | (1 << OP_GRAD) | BF_SORT_ANY_SIZE))
-        return fail(BF_ERR_ARG, "ops_mask: only the force and gradient passes and BF_SORT_ANY_SIZE");
+    if (ops_mask & ~((1 << OP_ACC) | (1 << OP_GRAD) | BF_SORT_ANY_SIZE | BF_SORT_DIRECTED))
+        return fail(BF_ERR_ARG, "ops_mask: only the force and gradient passes, BF_SORT_ANY_SIZE and BF_SORT_DIRECTED");
     if (kappa != 0.0 && !(kappa >= kKappaMin && kappa <= kKappaMax))
         return fail(BF_ERR_ARG, "kappa must be 0 (keep) or in [0.5, 64]");
     c->sort_ops = ops_mask;

@@ -18,26 +18,6 @@
 
 namespace bf {
 
-// ---- output of one target ------------------------------------------------------------------
-
-template <class Op>
-__device__ __forceinline__ void write_result(const PairArgs& a, int slot, int pi, const double* v) {
-    if constexpr (Op::kMax) {
-        // dt = eta W^(-1/2); W = 0 (no valid source) gives +inf
-        const double dff = a.eta0 / sqrt(v[0]), dfb = a.eta1 / sqrt(v[1]);
-        if (__builtin_isnan(dff) || __builtin_isnan(dfb)) atomicOr(a.flags, BF_FLAG_NONFINITE);
-        a.o0[pi] = dff;
-        a.o1[pi] = dfb;
-    } else {
-        if (!__builtin_isfinite(v[0]) || !__builtin_isfinite(v[1]) || !__builtin_isfinite(v[2]))
-            atomicOr(a.flags, BF_FLAG_NONFINITE);
-        a.o0[pi] = v[0];
-        a.o1[pi] = v[1];
-        a.o2[pi] = v[2];
-        if constexpr (Op::kCond) cond_check(a, slot, v);
-    }
-}
-
 template <class Op>
 __device__ __forceinline__ void emit(const PairArgs& a, int c, int slot, int pi, const typename Op::A64& acc) {
     constexpr int NP = ncomp_of<Op>();

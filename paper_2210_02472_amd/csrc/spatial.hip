@@ -218,10 +218,10 @@ hipError_t launch_pack_tiles(int op, int waves, const PairArgs& a, void* near_pa
     float4* fp = static_cast<float4*>(far_pack);
 #define BF_PT(OPV, TV) hipLaunchKernelGGL((k_pack_tiles<OPV, TV>), g, dim3(TV), 0, st, a, np, fp, meta)
     if (op == OP_ACC) {
-        if (T == 128) BF_PT(OP_ACC, 128); else if (T == 256) BF_PT(OP_ACC, 256); else if (T == 512) BF_PT(OP_ACC, 512);
+        if (T == 64) BF_PT(OP_ACC, 64); else if (T == 128) BF_PT(OP_ACC, 128); else if (T == 256) BF_PT(OP_ACC, 256); else if (T == 512) BF_PT(OP_ACC, 512);
         else return hipErrorInvalidValue;
     } else {
-        if (T == 128) BF_PT(OP_GRAD, 128); else if (T == 256) BF_PT(OP_GRAD, 256); else if (T == 512) BF_PT(OP_GRAD, 512);
+        if (T == 64) BF_PT(OP_GRAD, 64); else if (T == 128) BF_PT(OP_GRAD, 128); else if (T == 256) BF_PT(OP_GRAD, 256); else if (T == 512) BF_PT(OP_GRAD, 512);
         else return hipErrorInvalidValue;
     }
 #undef BF_PT

@@ -1,0 +1,536 @@
+// Pair-symmetric sweep of the spatially sorted mixed acceleration and force-gradient passes, for
+// passes whose targets and sources are one set (every particle active: a plain FSI step, level
+// 0 of the hierarchy).
+//
+// The two terms of a pair differ only by the mass factor and the sign (Sec. 2.1, Eqs.
+// new-newton-acc and new-grad-acc; r = x_j - x_i, a_ji = a_j - a_i, s^2 = r^2 + eps^2):
+//   acceleration:   +G m_j r / s^3 on i,   -G m_i r / s^3 on j;
+//   force gradient: +G m_j U / s^3 on i,   -G m_i U / s^3 on j,  U = a_ji - 3 (a_ji . r) r / s^2
+// (swapping i and j flips both r and a_ji).  Each unordered pair is evaluated once and both
+// terms are kept: the shared part (differences, s^2, rsqrt, U) is paid once per pair.
+//
+// Decomposition.  Particles are in Morton order, in tiles of 64; a block is B = kSymBlockTiles
+// tiles.
+//  * Workgroup w owns block w as rows: its W wavefronts hold R row tiles each (W R = B), one
+//    particle of each row tile per lane.
+//  * It sweeps the column blocks w, w+1, ..., w + nb/2 (cyclically, nb blocks), so that every
+//    unordered pair of blocks is visited once; the pair at distance exactly nb/2 (nb even) is
+//    visited by the lower-numbered block only.  Inside its own block a row tile pairs with the
+//    column tiles after it and, in the diagonal tile, with the later particles only.
+//  * All wavefronts of the workgroup work on the same column tile at a time.  The tile is staged
+//    in LDS (FP32 offsets from the tile centre and FP64 values, each plane stored twice so that
+//    index lane + k never wraps), prefetched one tile ahead through registers.
+//  * Rotation: at step k = 0..63 lane l pairs its row particles with column particle (l + k) mod
+//    64.  Row terms accumulate in registers (FP32 over the tile, then merged into FP64).  The
+//    column particle's accumulator travels with it: every step moves the accumulators one lane
+//    down (DPP wave_rol:1, fused into the add), so that after step k lane l holds the accumulator
+//    of column (l + k) mod 64; the R row particles of a lane add their column terms before the
+//    move.  No cross-lane reduction is needed.
+//  * After a tile the W wavefronts' column sums go through LDS, are added in FP64 in wavefront
+//    order and stored as one FP32 partial per (column particle, block distance).  A second
+//    kernel adds, per particle, the row sum and the partials of all distances in a fixed order.
+//    No atomics touch the results, so they are bitwise repeatable.
+//
+// Precision follows the directed sorted sweep: a tile near the wavefront's rows (gap below
+// kappa times the tile half-extent, and the tiles of the workgroup's own block with a diagonal
+// or skipped row tile) uses FP64 differences rounded once to FP32; a far tile uses FP32 offsets
+// from the column tile's centre for both particles.  The magnitude estimates that drive the
+// FP64 fix-up: the force gradient carries w max|a_ji| per pair on both sides; the acceleration
+// carries w max|r| per pair on near tiles, and on far tiles the bound G m_tile / d^2 (d: the
+// particle's distance to the other tile's box) on both sides.
+#include "pair_ops.h"
+
+namespace bf {
+
+namespace {
+
+// x taken from lane (l + 1) mod 64, fused by the compiler into the consuming add
+__device__ __forceinline__ float rol1(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x134 /* wave_rol:1 */, 0xf,
+                                                              0xf, true));
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ float wave_sum_xor(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+struct P32 { float x, y, z, m; };
+struct P64 { double x, y, z, m; };
+__device__ __forceinline__ void fold(P64& o, const P32& i) {
+    o.x += (double)i.x; o.y += (double)i.y; o.z += (double)i.z; o.m += (double)i.m;
+}
+
+// Particles past the last one sit far away with zero mass and zero acceleration: every term
+// they take part in vanishes (their own pairs give 0 * finite).
+constexpr double kFarAway = 1e18;
+
+// LDS planes of one staged column tile: 16-byte elements, 128 per plane (two copies of the 64)
+constexpr int kPlaneLen = 128;
+
+// ---- the acceleration ----------------------------------------------------------------------
+// planes: 0 far (x - cx, y - cy, z - cz, G m) FP32; 1 near (x, y) FP64; 2 near (z, [G m]) FP64
+struct SymAcc {
+    static constexpr int kS = 1, kMeta = 1, kPlanes = 3, kRedNear = 4, kRedFar = 3;
+    static constexpr bool kAcc = true;
+    struct Row { double x, y, z; float gm; };
+    struct Rel { float x, y, z; };
+    __device__ static void load_row(const SymArgs& g, int s, bool live, Row& t) {
+        if (live) {
+            const double4 p = static_cast<const double4*>(g.near_pack)[s];
+            t.x = p.x; t.y = p.y; t.z = p.z; t.gm = unpack_gm(p.w);
+        } else {
+            t.x = t.y = t.z = kFarAway; t.gm = 0.f;
+        }
+    }
+    // 16-byte element `plane` of sorted particle s, or the far-away filler
+    __device__ static uint4 stage_elem(const SymArgs& g, int plane, int s, bool ok) {
+        if (ok) {
+            if (plane == 0) return static_cast<const uint4*>(g.far_pack)[s];
+            return static_cast<const uint4*>(g.near_pack)[2 * s + (plane - 1)];
+        }
+        if (plane == 0) return __builtin_bit_cast(uint4, make_float4(1e18f, 1e18f, 1e18f, 0.f));
+        if (plane == 1) return __builtin_bit_cast(uint4, make_double2(kFarAway, kFarAway));
+        return __builtin_bit_cast(uint4, make_double2(kFarAway, 0.0));
+    }
+    __device__ static void rel(Rel& t, const Row& r, const double4& c, const double4&) {
+        t.x = (float)(r.x - c.x); t.y = (float)(r.y - c.y); t.z = (float)(r.z - c.z);
+    }
+    template <bool MASK>
+    __device__ static void near(P32& r, float (&c)[4], const Row& t, const uint4* pl, int j, float eps2f, bool ok) {
+        const double2 xy = __builtin_bit_cast(double2, pl[kPlaneLen + j]);
+        const double2 zw = __builtin_bit_cast(double2, pl[2 * kPlaneLen + j]);
+        const float dx = dif32(xy.x, t.x), dy = dif32(xy.y, t.y), dz = dif32(zw.x, t.z);
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+        float ri = rsqrt32(r2);
+        if (MASK) ri = ok ? ri : 0.f;
+        const float ri3 = (ri * ri) * ri;
+        const float wj = unpack_gm(zw.y) * ri3, wi = t.gm * ri3;
+        const float mx = max3abs(dx, dy, dz);
+        r.x = __builtin_fmaf(wj, dx, r.x);
+        r.y = __builtin_fmaf(wj, dy, r.y);
+        r.z = __builtin_fmaf(wj, dz, r.z);
+        r.m = __builtin_fmaf(wj, mx, r.m);
+        c[0] = wi * dx; c[1] = wi * dy; c[2] = wi * dz; c[3] = wi * mx;
+    }
+    __device__ static void far(P32& r, float (&c)[4], const Rel& t, const uint4* pl, int j, float gmi, float eps2f) {
+        const float4 sp = __builtin_bit_cast(float4, pl[j]);
+        const float dx = sp.x - t.x, dy = sp.y - t.y, dz = sp.z - t.z;
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+        const float ri = rsqrt32(r2);
+        const float ri3 = (ri * ri) * ri;
+        const float wj = sp.w * ri3, wi = gmi * ri3;
+        r.x = __builtin_fmaf(wj, dx, r.x);
+        r.y = __builtin_fmaf(wj, dy, r.y);
+        r.z = __builtin_fmaf(wj, dz, r.z);
+        c[0] = wi * dx; c[1] = wi * dy; c[2] = wi * dz;
+    }
+};
+
+// ---- the force gradient --------------------------------------------------------------------
+// planes: 0 far position offsets + G m, 1 far acceleration offsets (FP32); 2 near (x, y),
+// 3 near (z, [G m]), 4 near (ax, ay), 5 near (az, 0) (FP64)
+struct SymGrad {
+    static constexpr int kS = 2, kMeta = 2, kPlanes = 6, kRedNear = 4, kRedFar = 4;
+    static constexpr bool kAcc = false;
+    struct Row { double x, y, z, ax, ay, az; float gm; };
+    struct Rel { float x, y, z, ax, ay, az; };
+    __device__ static void load_row(const SymArgs& g, int s, bool live, Row& t) {
+        if (live) {
+            const double4* pk = static_cast<const double4*>(g.near_pack);
+            const double4 p = pk[2 * s], a = pk[2 * s + 1];
+            t.x = p.x; t.y = p.y; t.z = p.z; t.gm = unpack_gm(p.w);
+            t.ax = a.x; t.ay = a.y; t.az = a.z;
+        } else {
+            t.x = t.y = t.z = kFarAway; t.gm = 0.f;
+            t.ax = t.ay = t.az = 0.0;
+        }
+    }
+    __device__ static uint4 stage_elem(const SymArgs& g, int plane, int s, bool ok) {
+        if (ok) {
+            if (plane < 2) return static_cast<const uint4*>(g.far_pack)[2 * s + plane];
+            return static_cast<const uint4*>(g.near_pack)[4 * s + (plane - 2)];
+        }
+        if (plane == 0) return __builtin_bit_cast(uint4, make_float4(1e18f, 1e18f, 1e18f, 0.f));
+        if (plane == 2) return __builtin_bit_cast(uint4, make_double2(kFarAway, kFarAway));
+        if (plane == 3) return __builtin_bit_cast(uint4, make_double2(kFarAway, 0.0));
+        return make_uint4(0u, 0u, 0u, 0u);
+    }
+    __device__ static void rel(Rel& t, const Row& r, const double4& c, const double4& ca) {
+        t.x = (float)(r.x - c.x); t.y = (float)(r.y - c.y); t.z = (float)(r.z - c.z);
+        t.ax = (float)(r.ax - ca.x); t.ay = (float)(r.ay - ca.y); t.az = (float)(r.az - ca.z);
+    }
+    // shared part of a pair from FP32 differences: U, 1/s^3, both terms
+    __device__ static void core(P32& r, float (&c)[4], float dx, float dy, float dz, float dax, float day, float daz,
+                                float ri, float gmj, float gmi) {
+        const float ri2 = ri * ri;
+        const float ri3 = ri2 * ri;
+        const float q = __builtin_fmaf(dax, dx, __builtin_fmaf(day, dy, daz * dz));
+        const float sq = (-3.f * q) * ri2;
+        const float ux = __builtin_fmaf(sq, dx, dax), uy = __builtin_fmaf(sq, dy, day), uz = __builtin_fmaf(sq, dz, daz);
+        const float wj = gmj * ri3, wi = gmi * ri3;
+        const float mx = max3abs(dax, day, daz);
+        r.x = __builtin_fmaf(wj, ux, r.x);
+        r.y = __builtin_fmaf(wj, uy, r.y);
+        r.z = __builtin_fmaf(wj, uz, r.z);
+        r.m = __builtin_fmaf(wj, mx, r.m);
+        c[0] = wi * ux; c[1] = wi * uy; c[2] = wi * uz; c[3] = wi * mx;
+    }
+    template <bool MASK>
+    __device__ static void near(P32& r, float (&c)[4], const Row& t, const uint4* pl, int j, float eps2f, bool ok) {
+        const double2 xy = __builtin_bit_cast(double2, pl[2 * kPlaneLen + j]);
+        const double2 zw = __builtin_bit_cast(double2, pl[3 * kPlaneLen + j]);
+        const double2 axy = __builtin_bit_cast(double2, pl[4 * kPlaneLen + j]);
+        const double2 az0 = __builtin_bit_cast(double2, pl[5 * kPlaneLen + j]);
+        const float dx = dif32(xy.x, t.x), dy = dif32(xy.y, t.y), dz = dif32(zw.x, t.z);
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+        float ri = rsqrt32(r2);
+        if (MASK) ri = ok ? ri : 0.f;
+        core(r, c, dx, dy, dz, dif32(axy.x, t.ax), dif32(axy.y, t.ay), dif32(az0.x, t.az), ri, unpack_gm(zw.y), t.gm);
+    }
+    __device__ static void far(P32& r, float (&c)[4], const Rel& t, const uint4* pl, int j, float gmi, float eps2f) {
+        const float4 sp = __builtin_bit_cast(float4, pl[j]);
+        const float4 sa = __builtin_bit_cast(float4, pl[kPlaneLen + j]);
+        const float dx = sp.x - t.x, dy = sp.y - t.y, dz = sp.z - t.z;
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+        core(r, c, dx, dy, dz, sa.x - t.ax, sa.y - t.ay, sa.z - t.az, rsqrt32(r2), sp.w, gmi);
+    }
+};
+
+// G m / d^2 with d the distance of point p to the box [lo, hi] (FP32, same frame)
+__device__ __forceinline__ float box_bound(const float p[3], const float lo[3], const float hi[3], float gm) {
+    float d2 = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float g = fmaxf(0.f, fmaxf(lo[d] - p[d], p[d] - hi[d]));
+        d2 = __builtin_fmaf(g, g, d2);
+    }
+    return gm / fmaxf(d2, 1e-30f);
+}
+
+// The column tiles a workgroup visits, in order: block distance d = 0..nb/2, tile t of block
+// (wg + d) mod nb.  Uniform over the workgroup.
+struct TileWalk {
+    int d = 0, t = 0, ct = -1;
+    int d_end = 0;  // first distance past this workgroup's share
+    __device__ void next(const SymArgs& g, int wg) {
+        const int nb = g.n_blocks, W = kSymBlockTiles;
+        if (ct >= 0) ++t;
+        for (;;) {
+            if (d >= d_end || 2 * d > nb || (d > 0 && 2 * d == nb && wg >= d)) { ct = -1; return; }
+            const int b = wg + d < nb ? wg + d : wg + d - nb;
+            if (t < W && b * W + t < g.n_tiles) { ct = b * W + t; return; }
+            ++d;
+            t = 0;
+        }
+    }
+};
+
+// Row modes of a (row tile, column tile) visit: the tile pair is skipped, it is the diagonal
+// tile (pairs whose column index within the tile exceeds the row index), or it is counted whole.
+enum { kSkip = 0, kDiag = 1, kFull = 2 };
+
+// pair (lane, column (lane + k) mod 64) counts for a row in `mode`
+__device__ __forceinline__ bool counts(int mode, int lane, int k) {
+    return mode == kFull || (mode == kDiag && k > 0 && lane + k < 64);
+}
+
+// One column tile for the R row particles of each lane: row terms into own[r]; the column sums
+// end in xs[q][slot], slot = the column each lane holds after the 64 steps.
+template <class S, int R>
+__device__ __forceinline__ void sym_tile(const SymArgs& g, int ct, const int (&mode)[R], bool masked,
+                                         const typename S::Row (&row)[R], const float (&lo)[3], const float (&hi)[3],
+                                         float gm_rows, P64 (&own)[R], const uint4* pl, float (*xs)[64],
+                                         unsigned& n_near, unsigned& n_far) {
+    const int lane = threadIdx.x & 63;
+    const double4 c = load_uniform4d(g.tile_meta, S::kMeta * ct);
+    const double4 ca = S::kMeta > 1 ? load_uniform4d(g.tile_meta, S::kMeta * ct + 1) : c;
+    const float2 hm = __builtin_bit_cast(float2, c.w);  // (half-extent, G * tile mass)
+    const float h = hm.x;
+    const float cc[3] = {(float)c.x, (float)c.y, (float)c.z};
+    float gap2 = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float gg = fmaxf(0.f, fmaxf(cc[d] - h - hi[d], lo[d] - (cc[d] + h)));
+        gap2 = __builtin_fmaf(gg, gg, gap2);
+    }
+    // tiles with a diagonal or skipped row (own block only) take the masked FP64-difference loop
+    const bool near = masked || gap2 < (g.kappa * h) * (g.kappa * h);
+    n_near += near ? 1u : 0u;
+    n_far += near ? 0u : 1u;
+    P32 part[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) part[r] = P32{0.f, 0.f, 0.f, 0.f};
+    float ja[4] = {0.f, 0.f, 0.f, 0.f};  // accumulator of column (lane + k) mod 64 after step k
+    if (near) {
+        if (masked) {
+            for (int k = 0; k < 64; ++k) {
+                float cs[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float cv[4];
+                    S::template near<true>(part[r], cv, row[r], pl, lane + k, g.eps2f, counts(mode[r], lane, k));
+#pragma unroll
+                    for (int q = 0; q < S::kRedNear; ++q) cs[q] += cv[q];
+                }
+#pragma unroll
+                for (int q = 0; q < S::kRedNear; ++q) ja[q] = rol1(ja[q]) + cs[q];
+            }
+        } else {
+#pragma unroll 2
+            for (int k = 0; k < 64; ++k) {
+                float cs[4];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float cv[4];
+                    S::template near<false>(part[r], cv, row[r], pl, lane + k, g.eps2f, true);
+#pragma unroll
+                    for (int q = 0; q < S::kRedNear; ++q) cs[q] = r == 0 ? cv[q] : cs[q] + cv[q];
+                }
+#pragma unroll
+                for (int q = 0; q < S::kRedNear; ++q) ja[q] = rol1(ja[q]) + cs[q];
+            }
+        }
+    } else {
+        typename S::Rel tr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) S::rel(tr[r], row[r], c, ca);
+#pragma unroll 2
+        for (int k = 0; k < 64; ++k) {
+            float cs[4];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float cv[4];
+                S::far(part[r], cv, tr[r], pl, lane + k, row[r].gm, g.eps2f);
+#pragma unroll
+                for (int q = 0; q < S::kRedFar; ++q) cs[q] = r == 0 ? cv[q] : cs[q] + cv[q];
+            }
+#pragma unroll
+            for (int q = 0; q < S::kRedFar; ++q) ja[q] = rol1(ja[q]) + cs[q];
+        }
+        if constexpr (S::kAcc) {
+            // row side: every source of the tile lies in the cube of half-extent h about c
+            const float clo[3] = {-h, -h, -h}, chi[3] = {h, h, h};
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float p[3] = {tr[r].x, tr[r].y, tr[r].z};
+                own[r].m += (double)box_bound(p, clo, chi, hm.y);
+            }
+            // column side: the column this lane holds, against the box of the wavefront's rows
+            // (a filler column gets a bound too; it is never stored)
+            const float4 f = __builtin_bit_cast(float4, pl[(lane + 63) & 63]);
+            const float ps[3] = {f.x, f.y, f.z};
+            const float rlo[3] = {lo[0] - cc[0], lo[1] - cc[1], lo[2] - cc[2]};
+            const float rhi[3] = {hi[0] - cc[0], hi[1] - cc[1], hi[2] - cc[2]};
+            ja[3] = box_bound(ps, rlo, rhi, gm_rows);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) fold(own[r], part[r]);
+    const int slot = (lane + 63) & 63;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xs[q][slot] = ja[q];
+}
+
+// Workgroup of W wavefronts; wavefront v holds row tiles B R W + R v + r (r < R) of block B.
+template <class S, int W, int R>
+__global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
+    static_assert(W * R == kSymBlockTiles, "a workgroup covers one block");
+    constexpr int NPL = S::kPlanes;
+    __shared__ uint4 colbuf[2][NPL * kPlaneLen];
+    __shared__ float xch[2][W][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // workgroup (chunk, block): block wg's rows against its share [d0, d1) of the distances
+    const int wg = blockIdx.x % g.n_blocks, chunk = blockIdx.x / g.n_blocks;
+    const int d0 = chunk * g.chunk_len, d1 = d0 + g.chunk_len;
+    const int rbase = wg * (W * R) + wave * R;
+    typename S::Row row[R];
+    bool tile_live[R];
+    int rs[R];
+    float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
+    float hi[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
+    float gm_lane = 0.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        tile_live[r] = rbase + r < g.n_tiles;
+        rs[r] = (rbase + r) * 64 + lane;
+        const bool live = tile_live[r] && rs[r] < g.n;
+        S::load_row(g, rs[r], live, row[r]);
+        if (live) {
+            const float p[3] = {(float)row[r].x, (float)row[r].y, (float)row[r].z};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) { lo[d] = fminf(lo[d], p[d]); hi[d] = fmaxf(hi[d], p[d]); }
+        }
+        gm_lane += row[r].gm;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { lo[d] = wave_min(lo[d]); hi[d] = wave_max(hi[d]); }
+    const float gm_rows = S::kAcc ? wave_sum_xor(gm_lane) * (1.0f + 1e-5f) : 0.f;
+    P64 own[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) own[r] = P64{0.0, 0.0, 0.0, 0.0};
+    unsigned n_near = 0, n_far = 0;
+
+    // staging: element k of plane p is copied (twice) by thread 64 p' + k, p = p' + W u
+    constexpr int SPT = (NPL + W - 1) / W;  // planes per staging thread
+    const int st_k = threadIdx.x & 63;
+    TileWalk cur, pre;
+    cur.d = d0;
+    cur.d_end = d1;
+    cur.next(g, wg);
+    pre = cur;
+    pre.next(g, wg);
+    uint4 held[SPT];
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+        const int pl = wave + W * u;
+        if (pl < NPL && cur.ct >= 0) {
+            const int s = cur.ct * 64 + st_k;
+            const uint4 e = S::stage_elem(g, pl, s, s < g.n);
+            colbuf[0][pl * kPlaneLen + st_k] = e;
+            colbuf[0][pl * kPlaneLen + st_k + 64] = e;
+        }
+        held[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (pl < NPL && pre.ct >= 0) {
+            const int s = pre.ct * 64 + st_k;
+            held[u] = S::stage_elem(g, pl, s, s < g.n);
+        }
+    }
+    __syncthreads();
+    for (int i = 0; cur.ct >= 0; ++i) {
+        const int buf = i & 1;
+        const int ct = cur.ct;
+        float (*xs)[64] = xch[buf][wave];
+        int mode[R];
+        bool any = false, masked = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int rt = rbase + r;
+            mode[r] = !tile_live[r] ? kSkip : (cur.d > 0 || ct > rt) ? kFull : ct == rt ? kDiag : kSkip;
+            any = any || mode[r] != kSkip;
+            masked = masked || mode[r] != kFull;
+        }
+        if (any) {
+            sym_tile<S, R>(g, ct, mode, masked, row, lo, hi, gm_rows, own, colbuf[buf], xs, n_near, n_far);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xs[q][lane] = 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int pl = wave + W * u;
+            if (pl < NPL && pre.ct >= 0) {
+                colbuf[buf ^ 1][pl * kPlaneLen + st_k] = held[u];
+                colbuf[buf ^ 1][pl * kPlaneLen + st_k + 64] = held[u];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 * 64) {
+            const int q = threadIdx.x >> 6, k = threadIdx.x & 63;
+            double s = 0.0;
+#pragma unroll
+            for (int v = 0; v < W; ++v) s += (double)xch[buf][v][q][k];
+            const int col = ct * 64 + k;
+            // the column term carries the opposite sign (the estimate M does not)
+            if (col < g.n) g.part[((size_t)cur.d * 4 + q) * g.n_pad + col] = (float)(q < 3 ? -s : s);
+        }
+        cur = pre;
+        pre.next(g, wg);
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int pl = wave + W * u;
+            if (pl < NPL && pre.ct >= 0) {
+                const int s = pre.ct * 64 + st_k;
+                held[u] = S::stage_elem(g, pl, s, s < g.n);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (tile_live[r] && rs[r] < g.n) {
+            double* o = g.own + (size_t)chunk * 4 * g.n_pad;  // every chunk writes its row sums
+            o[rs[r]] = own[r].x;
+            o[(size_t)g.n_pad + rs[r]] = own[r].y;
+            o[(size_t)2 * g.n_pad + rs[r]] = own[r].z;
+            o[(size_t)3 * g.n_pad + rs[r]] = own[r].m;
+        }
+    }
+    if (g.tile_stats && lane == 0) {
+        atomicAdd(&g.tile_stats[0], (unsigned long long)n_near);
+        atomicAdd(&g.tile_stats[1], (unsigned long long)n_far);
+    }
+}
+
+template <class Op>
+__global__ __launch_bounds__(256) void k_sym_reduce(const PairArgs a, const SymArgs g) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= g.n) return;
+    const int b = (s >> 6) / kSymBlockTiles;
+    const int nb = g.n_blocks, D = nb / 2;
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = 0.0;
+    for (int c = 0; c < g.n_chunks; ++c) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += g.own[((size_t)c * 4 + q) * g.n_pad + s];
+    }
+    for (int d = 0; d <= D; ++d) {
+        if (d > 0 && 2 * d == nb && b < d) continue;  // no partial: this block pair was swept from here
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += (double)g.part[((size_t)d * 4 + q) * g.n_pad + s];
+    }
+    write_result<Op>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), v);
+}
+
+}  // namespace
+
+size_t sym_own_bytes(int64_t n, int chunks) {
+    return ((size_t)chunks * 4 * 64 * ((n + 63) / 64) * sizeof(double) + 255) & ~size_t(255);
+}
+
+size_t sym_scratch_bytes(int64_t n, int chunks) {
+    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
+    return sym_own_bytes(n, chunks) + (size_t)(nb / 2 + 1) * 4 * 64 * n_tiles * sizeof(float);
+}
+
+int sym_blocks_per_cu(int op) {
+    const void* f = op == OP_ACC ? reinterpret_cast<const void*>(k_pairs_sym<SymAcc, 8, 2>)
+                                 : reinterpret_cast<const void*>(k_pairs_sym<SymGrad, 4, 4>);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, op == OP_ACC ? 64 * 8 : 64 * 4, 0) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_pairs_sym(int op, const SymArgs& g, hipStream_t st) {
+    if (g.n <= 0) return hipSuccess;
+    // measured at N = 2^20: 8 wavefronts of 2 row tiles for the acceleration, 4 of 4 for the
+    // gradient (more rows per lane share each column read and rotation; fewer fit the VGPRs)
+    const dim3 grid((unsigned)g.n_blocks * (unsigned)g.n_chunks);
+    if (op == OP_ACC) hipLaunchKernelGGL((k_pairs_sym<SymAcc, 8, 2>), grid, dim3(64 * 8), 0, st, g);
+    else if (op == OP_GRAD) hipLaunchKernelGGL((k_pairs_sym<SymGrad, 4, 4>), grid, dim3(64 * 4), 0, st, g);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_reduce(int op, const PairArgs& a, const SymArgs& g, hipStream_t st) {
+    if (g.n <= 0) return hipSuccess;
+    const dim3 grid((g.n + 255) / 256);
+    if (op == OP_ACC) hipLaunchKernelGGL(k_sym_reduce<AccMixed>, grid, dim3(256), 0, st, a, g);
+    else if (op == OP_GRAD) hipLaunchKernelGGL(k_sym_reduce<GradMixed>, grid, dim3(256), 0, st, a, g);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace bf

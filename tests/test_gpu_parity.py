@@ -45,11 +45,13 @@ def _flags_clean(ctx):
 # accelerations
 # --------------------------------------------------------------------------------------------
 
-@pytest.fixture(params=["sorted", "unsorted"])
+@pytest.fixture(params=["sorted", "directed", "unsorted"])
 def sort_mode(ctx, request):
-    """Run a test with the spatially sorted mixed kernels on (the default) and off."""
-    on = request.param == "sorted"
-    ctx.set_spatial_sort(forces=on, gradient=on, any_size=on)  # test sets are below the size limits
+    """Run a test with the spatially sorted mixed kernels on (the default: pair-symmetric where
+    targets and sources are one set), on but directed, and off."""
+    on = request.param != "unsorted"
+    # test sets are below the size limits
+    ctx.set_spatial_sort(forces=on, gradient=on, any_size=on, symmetric=request.param == "sorted")
     yield request.param
     ctx.set_spatial_sort(forces=True, gradient=True, kappa=1.0)
 

@@ -1,0 +1,143 @@
+"""GPU parity of the pair-symmetric sorted sweep (targets and sources one set) against the oracle.
+
+The symmetric sweep evaluates each unordered pair once and keeps both terms (Sec. 2.1: the
+acceleration and force-gradient terms of a pair are equal and opposite up to the mass factor).
+The block sizes below cover one block, two blocks (the half-ring distance), an odd and an even
+block count (the block pair at distance nb/2 visited from one side only) and ragged last tiles.
+Tolerances are those of the mixed pass: relative error RMS <= 1e-6 and max <= 1e-5 per target.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2210_02472_amd import ics
+from tests._parity import gather, rel_errors, stats
+
+bf = pytest.importorskip("paper_2210_02472_amd")
+
+pytestmark = pytest.mark.gpu
+
+RMS_TOL, MAX_TOL = 1e-6, 1e-5
+BLOCK_TILES = 16  # row tiles of 64 per workgroup of the symmetric sweep
+WALKS = {"forces": (8, 2), "gradient": (4, 4)}  # (wavefronts, row tiles per wavefront)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = bf.Context(0)
+    c.set_spatial_sort(forces=True, gradient=True, any_size=True)
+    yield c
+    c.close()
+
+
+def _king(n, seed):
+    return ics.king_cluster(ics.rng_for(200, seed), n, 6.0, 0.01)
+
+
+def _tile_pairs(n, op="forces"):
+    """Tile visits of the symmetric walk: every unordered pair of 64-particle tiles once; a
+    wavefront's visit of a column tile covers its row tiles together."""
+    WAVES, ROWS = WALKS[op]
+    t = (n + 63) // 64
+    bt = WAVES * ROWS
+    nb = -(-t // bt)
+    visits = 0
+    for w in range(nb):
+        for v in range(WAVES):
+            rows = [w * bt + v * ROWS + r for r in range(ROWS) if w * bt + v * ROWS + r < t]
+            if not rows:
+                continue
+            for d in range(nb // 2 + 1):
+                if d > 0 and 2 * d == nb and w >= d:
+                    break
+                b = (w + d) % nb
+                for ct in range(b * bt, min(b * bt + bt, t)):
+                    visits += 1 if d > 0 or ct >= rows[0] else 0
+    return visits
+
+
+@pytest.mark.parametrize("n", [1000, 1100, 17000, 20000])
+@pytest.mark.parametrize("op", ["forces", "gradient"])
+def test_symmetric_sweep_parity(ctx, n, op):
+    """All targets against the oracle; the sweep visits every unordered pair of 64-particle
+    tiles exactly once (the near + far visit count of the walk)."""
+    blocks = -(-((n + 63) // 64) // BLOCK_TILES)
+    print(f"n={n} blocks={blocks} op={op}", flush=True)
+    d = _king(n, n)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    if op == "forces":
+        ref = oracle.forces(P)
+        out = ctx.forces(Pd, prec="mixed", r_fb=0.0)
+    else:
+        a = oracle.forces(P)
+        ref = oracle.gradient(P, a)
+        acc = [torch.as_tensor(np.ascontiguousarray(a[:, k]), device="cuda") for k in range(3)]
+        out = ctx.force_gradient(Pd, acc, prec="mixed", r_fb=0.0)
+    fix, near, far = ctx.last_pass_stats()
+    assert near + far == _tile_pairs(n, op), (near, far, _tile_pairs(n, op))
+    got = gather(out, np.arange(n))
+    f = ctx.read_flags(clear=True)
+    assert f & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0, f"device flags {f:#x}"
+    rms, mx = stats(rel_errors(got, ref))
+    assert rms <= RMS_TOL and mx <= MAX_TOL, (rms, mx, fix)
+
+
+@pytest.mark.parametrize("op", ["forces", "gradient"])
+def test_symmetric_softened_and_repeatable(ctx, op):
+    """Softened pairs (eps^2 = 1e-6), bitwise repeatable results, and agreement with the directed
+    sorted sweep (both within the mixed tolerance of the oracle)."""
+    n = 9000
+    d = _king(n, 5)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    eps2 = 1e-6
+    a = oracle.forces(P, eps2=eps2)
+    acc = [torch.as_tensor(np.ascontiguousarray(a[:, k]), device="cuda") for k in range(3)]
+
+    def run():
+        if op == "forces":
+            return ctx.forces(Pd, eps2=eps2, prec="mixed", r_fb=0.0)
+        return ctx.force_gradient(Pd, acc, eps2=eps2, prec="mixed", r_fb=0.0)
+
+    ref = oracle.forces(P, eps2=eps2) if op == "forces" else oracle.gradient(P, a, eps2=eps2)
+    x, y = run(), run()
+    assert all(torch.equal(u, v) for u, v in zip(x, y))
+    try:
+        ctx.set_spatial_sort(forces=True, gradient=True, any_size=True, symmetric=False)
+        z = run()
+        _, near, far = ctx.last_pass_stats()
+        assert near + far != _tile_pairs(n, op)  # the directed sweep ran
+    finally:
+        ctx.set_spatial_sort(forces=True, gradient=True, any_size=True)
+    for out in (x, z):
+        rms, mx = stats(rel_errors(gather(out, np.arange(n)), ref))
+        assert rms <= RMS_TOL and mx <= MAX_TOL, (rms, mx)
+
+
+def test_symmetric_momentum_balance(ctx):
+    """Evaluating each pair once makes sum_i m_i a_i vanish up to the FP32 rounding of the terms."""
+    n = 12000
+    d = _king(n, 9)
+    Pd = _dev(d)
+    a = ctx.forces(Pd, prec="mixed", r_fb=0.0)
+    m = Pd.m
+    tot = torch.stack([(m * x).sum() for x in a]).abs()
+    scale = (m * torch.sqrt(a[0] ** 2 + a[1] ** 2 + a[2] ** 2)).sum()
+    assert torch.all(tot <= 1e-6 * scale), (tot, scale)
+
+
+def test_symmetric_subset_runs_directed(ctx):
+    """Target and source sets that differ (an index list against all) keep the directed sweep."""
+    n = 5000
+    d = _king(n, 3)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    T = np.sort(np.random.default_rng(4).choice(n, 3000, replace=False))
+    got = gather(ctx.forces(Pd, T, None, prec="mixed", r_fb=0.0), T)
+    _, near, far = ctx.last_pass_stats()
+    assert near + far != _tile_pairs(n)
+    rms, mx = stats(rel_errors(got, oracle.forces(P, T, None)))
+    assert rms <= RMS_TOL and mx <= MAX_TOL
+
+
+def _dev(d):
+    return bf.Particles.from_numpy(d)
