@@ -36,8 +36,23 @@ PEAK_FP64_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.64
 # HBM traffic of the dominant kernel, measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE)
 # and scaled by the same counters' reading for a copy kernel of known size.  The figure is used
 # only while the kernel sources hash to the value recorded with it.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_sorted_GradMixed_king1m_hbm_traffic.txt")
-KERNEL_SOURCES = ["pair_ops.h", "pairs.hip", "spatial.hip", "bf_internal.h", "capi.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_sym_SymGrad_king1m_hbm_traffic.txt")
+TRAFFIC_KIND = "symmetric"  # the pass kind whose kernel the counters were taken on
+KERNEL_SOURCES = ["pair_ops.h", "pairs.hip", "spatial.hip", "symmetric.hip", "bf_internal.h", "capi.hip"]
+
+# gradient kernel of each pass kind (the library's launch of that kind at this size)
+KERNEL_NAMES = {"unsorted": "k_pairs<GradMixed>", "sorted": "k_pairs_sorted<GradMixed>",
+                "symmetric": "k_pairs_sym<SymGrad>"}
+
+
+def pass_desc(cfg):
+    """Report of bf_last_pass_config: the sweep and its launch shape."""
+    kind, k, waves, split = cfg
+    if kind == "symmetric":
+        return {"sweep": "pair-symmetric, spatially sorted", "row_tiles_per_wave": k, "waves": waves,
+                "distance_shares": split}
+    return {"sweep": "directed, " + ("spatially sorted" if kind == "sorted" else "unsorted"),
+            "k_per_lane": k, "waves": waves, "split": split}
 
 
 def kernel_source_hash():
@@ -251,8 +266,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", type=int, default=256, help="targets sampled for the error check")
-    ap.add_argument("--spatial-sort", default="default", choices=["default", "off", "acc", "grad", "both"],
-                    help="passes that use the spatially sorted mixed kernels (default: the library's)")
+    ap.add_argument("--spatial-sort", default="default", choices=["default", "off", "acc", "grad", "both", "directed"],
+                    help="passes that use the spatially sorted mixed kernels (default: the library's; directed: sorted without the pair-symmetric sweep)")
     ap.add_argument("--kappa", type=float, default=0.0, help="near-tile threshold (0: the library's)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library autotuner for both passes before timing")
@@ -295,8 +310,9 @@ def main():
     ctx = bf.Context(0)
     if args.spatial_sort != "default" or args.kappa:
         mode = {"default": (True, True), "off": (False, False), "acc": (True, False), "grad": (False, True),
-                "both": (True, True)}[args.spatial_sort]
-        ctx.set_spatial_sort(forces=mode[0], gradient=mode[1], kappa=args.kappa)
+                "both": (True, True), "directed": (True, True)}[args.spatial_sort]
+        ctx.set_spatial_sort(forces=mode[0], gradient=mode[1], kappa=args.kappa,
+                             symmetric=args.spatial_sort != "directed")
     if args.autotune:
         t1 = time.time()
         for op in (bf.BF_OP_FORCES, bf.BF_OP_GRADIENT):
@@ -375,12 +391,11 @@ def main():
     e_g = np.linalg.norm(got_g - ref_g, axis=1) / np.linalg.norm(ref_g, axis=1)
     flags = ctx.read_flags()
 
-    cfg_a = ctx.query_config(bf.BF_OP_FORCES, "mixed", n, n)
-    cfg_g = ctx.query_config(bf.BF_OP_GRADIENT, "mixed", n, n)
-    sorted_g = stats_m[1] + stats_m[2] > 0
+    ctx.force_gradient(P, acc_m, None, None, prec="mixed", r_fb=args.r_fb, out=out_g)
+    cfg_g = ctx.last_pass_config()
     ctx.forces(P, None, None, prec="mixed", r_fb=args.r_fb, out=out_a)
     stats_a = ctx.last_pass_stats()
-    sorted_a = stats_a[1] + stats_a[2] > 0
+    cfg_a = ctx.last_pass_config()
     avg = lambda v: float(np.mean(v)) if v else float("nan")  # noqa: E731
     ka, kg = avg(ka_m), avg(kg_m)
     grad_tflops = pairs * FLOPS_GRAD / (kg * 1e-3) / 1e12
@@ -424,15 +439,16 @@ def main():
                                f"merge and cancellation fix-up)",
                    "n": n, "eps": 0.0, "r_fb": args.r_fb,
                    "fp64_differences": "all pairs (covers pairs at r < 1e-3)",
-                   "spatial_sort": {"forces": sorted_a, "gradient": sorted_g}, "autotuned": bool(args.autotune),
-                   "acc_kernel": {"k_per_lane": cfg_a[0], "waves": cfg_a[1], "split": cfg_a[2]},
-                   "grad_kernel": {"k_per_lane": cfg_g[0], "waves": cfg_g[1], "split": cfg_g[2]}},
+                   "autotuned": bool(args.autotune),
+                   "acc_pass": pass_desc(cfg_a), "grad_pass": pass_desc(cfg_g)},
         "roofline": {"bound": "alu",
-                     "kernel": ("k_pairs_sorted<GradMixed>" if sorted_g else "k_pairs<GradMixed>") +
-                               " (force-gradient pass)",
+                     "kernel": KERNEL_NAMES[cfg_g[0]] + " (force-gradient pass)",
                      "achieved": grad_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": grad_tflops / PEAK_FP32_TFLOPS, "traffic": measured_traffic(n) if sorted_g else None,
-                     "flops_per_pair": FLOPS_GRAD, "pairs_per_launch": pairs, "avg_kernel_ms": kg},
+                     "frac": grad_tflops / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(n) if cfg_g[0] == TRAFFIC_KIND else None,
+                     "flops_per_pair": FLOPS_GRAD, "pairs_per_launch": pairs,
+                     "pair_evaluations_per_launch": pairs // 2 if cfg_g[0] == "symmetric" else pairs,
+                     "avg_kernel_ms": kg},
         "acc_pass": {"avg_kernel_ms": ka, "tflops": acc_tflops, "frac": acc_tflops / PEAK_FP32_TFLOPS,
                      "pairs_per_s": pairs / (ka * 1e-3)},
         "fp64": {"ms_per_step": ms_fp64, "value": pairs / (wall_d / args.fp64_steps),

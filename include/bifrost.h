@@ -397,8 +397,20 @@ BF_API int bf_set_spatial_sort(bf_ctx *ctx, int ops_mask, double kappa);
  * took the near (FP64-difference) and far (FP32 tile-offset) paths. */
 BF_API int bf_last_pass_stats(bf_ctx *ctx, int64_t *fixups, int64_t *near_tiles, int64_t *far_tiles);
 
-/* Kernel configuration the context would use for a pass (for reporting):
- * targets per lane, waves per workgroup, source split. */
+/* Not synchronising.  How the most recent acceleration / gradient / time-step pass ran:
+ * kind BF_PASS_UNSORTED, BF_PASS_SORTED (spatially sorted, directed sweep) or BF_PASS_SYMMETRIC
+ * (spatially sorted, each unordered pair once); k_per_lane = targets per lane (row tiles per
+ * wavefront for BF_PASS_SYMMETRIC), waves = wavefronts per workgroup, split = source chunks
+ * (shares of the block distances for BF_PASS_SYMMETRIC).  Any pointer may be NULL.  Before the
+ * first pass all are 0. */
+#define BF_PASS_UNSORTED 0
+#define BF_PASS_SORTED 1
+#define BF_PASS_SYMMETRIC 2
+BF_API int bf_last_pass_config(bf_ctx *ctx, int *kind, int *k_per_lane, int *waves, int *split);
+
+/* Kernel configuration the context would use for a directed pass of these sizes (for
+ * reporting): targets per lane, waves per workgroup, source split.  A pass whose targets and
+ * sources are one set may run the pair-symmetric sweep instead; bf_last_pass_config tells. */
 BF_API int bf_query_config(bf_ctx *ctx, int op, int prec, int64_t n_targets, int64_t n_sources,
                            int *k_per_lane, int *waves, int *split);
 /* Force the kernel configuration for subsequent calls of op/prec (0 restores the default

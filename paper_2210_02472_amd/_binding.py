@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH):
         "bf_subsystems": [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i64)],
         "bf_set_subsystems": [_vp, _vp, _i64],
         "bf_last_pass_stats": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+        "bf_last_pass_config": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
+                                ctypes.POINTER(_int)],
         "bf_kernel_times": [_vp, _int, ctypes.POINTER(ctypes.c_float), _int, ctypes.POINTER(_int)],
     }
     for name, args in sig.items():
@@ -460,6 +462,13 @@ class Context:
         _check("bf_last_pass_stats", _lib.bf_last_pass_stats(self._h, ctypes.byref(f), ctypes.byref(nn),
                                                              ctypes.byref(nf)))
         return f.value, nn.value, nf.value
+
+    def last_pass_config(self):
+        """(kind, k_per_lane, waves, split) of the most recent pass; kind is "unsorted", "sorted"
+        (directed sweep) or "symmetric" (each unordered pair once)."""
+        v = [_int(0) for _ in range(4)]
+        _check("bf_last_pass_config", _lib.bf_last_pass_config(self._h, *(ctypes.byref(x) for x in v)))
+        return ("unsorted", "sorted", "symmetric")[v[0].value], v[1].value, v[2].value, v[3].value
 
     def set_spatial_sort(self, forces: bool = True, gradient: bool = True, kappa: float = 0.0,
                          any_size: bool = False, symmetric: bool = True):

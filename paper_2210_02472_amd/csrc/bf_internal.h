@@ -139,8 +139,11 @@ struct SymArgs {
 // bytes of own (256-byte aligned) and of own + part for n particles and `chunks` shares
 size_t sym_own_bytes(int64_t n, int chunks);
 size_t sym_scratch_bytes(int64_t n, int chunks);
-// resident workgroups per CU of the symmetric kernel of op
+// resident workgroups per CU, wavefronts per workgroup and row tiles per wavefront of the
+// symmetric kernel of op
 int sym_blocks_per_cu(int op);
+int sym_waves(int op);
+int sym_rows_per_wave(int op);
 hipError_t launch_pairs_sym(int op, const SymArgs& g, hipStream_t st);
 // adds the row-side sums and the partials in a fixed order and writes the particle-indexed
 // outputs of a.tgt (the sorted list), queueing ill-conditioned targets for the fix-up
@@ -262,6 +265,7 @@ struct bf_ctx {
     bool capturing = false;           // a graph capture is recording this context's work
     bool dry = false;                 // size scratch only, launch nothing (before a capture)
     unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass
+    int last_kind = 0, last_k = 0, last_waves = 0, last_split = 0;  // how the last pass ran
     // spatially sorted mixed passes: bit op set = use them for that operation when large enough
     int sort_ops = (1 << 0) | (1 << 1);  // acceleration and force-gradient passes
     const int32_t* sub = nullptr;     // subsystem labels applied to acc / grad / dt passes (NULL: none)

@@ -319,6 +319,10 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     if (sym) BF_HIP(launch_pairs_sym(op, g, ctx->stream));
     else if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
     else BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
+    ctx->last_kind = sym ? BF_PASS_SYMMETRIC : sorted ? BF_PASS_SORTED : BF_PASS_UNSORTED;
+    ctx->last_k = sym ? sym_rows_per_wave(op) : p.cfg.k;
+    ctx->last_waves = sym ? sym_waves(op) : p.cfg.waves;
+    ctx->last_split = sym ? g.n_chunks : p.split;
     if (timed) {
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
@@ -1119,6 +1123,15 @@ BF_API int bf_last_pass_stats(bf_ctx* c, int64_t* fixups, int64_t* near_tiles, i
     if (fixups) *fixups = (int64_t)(h[0] & 0xffffffffull);
     if (near_tiles) *near_tiles = (int64_t)h[1];
     if (far_tiles) *far_tiles = (int64_t)h[2];
+    return BF_OK;
+}
+
+BF_API int bf_last_pass_config(bf_ctx* c, int* kind, int* k, int* waves, int* split) {
+    if (int rc = check_ctx(c)) return rc;
+    if (kind) *kind = c->last_kind;
+    if (k) *k = c->last_k;
+    if (waves) *waves = c->last_waves;
+    if (split) *split = c->last_split;
     return BF_OK;
 }
 

@@ -505,21 +505,28 @@ size_t sym_scratch_bytes(int64_t n, int chunks) {
     return sym_own_bytes(n, chunks) + (size_t)(nb / 2 + 1) * 4 * 64 * n_tiles * sizeof(float);
 }
 
+// Launch shapes, measured at N = 2^20: 8 wavefronts of 2 row tiles for the acceleration, 4 of 4
+// for the gradient (more row tiles per lane share each column read and rotation; fewer fit the
+// VGPRs).
+constexpr int kAccWaves = 8, kAccRows = 2, kGradWaves = 4, kGradRows = 4;
+int sym_waves(int op) { return op == OP_ACC ? kAccWaves : kGradWaves; }
+int sym_rows_per_wave(int op) { return op == OP_ACC ? kAccRows : kGradRows; }
+
 int sym_blocks_per_cu(int op) {
-    const void* f = op == OP_ACC ? reinterpret_cast<const void*>(k_pairs_sym<SymAcc, 8, 2>)
-                                 : reinterpret_cast<const void*>(k_pairs_sym<SymGrad, 4, 4>);
+    const void* f = op == OP_ACC ? reinterpret_cast<const void*>(k_pairs_sym<SymAcc, kAccWaves, kAccRows>)
+                                 : reinterpret_cast<const void*>(k_pairs_sym<SymGrad, kGradWaves, kGradRows>);
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, op == OP_ACC ? 64 * 8 : 64 * 4, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * sym_waves(op), 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
 hipError_t launch_pairs_sym(int op, const SymArgs& g, hipStream_t st) {
     if (g.n <= 0) return hipSuccess;
-    // measured at N = 2^20: 8 wavefronts of 2 row tiles for the acceleration, 4 of 4 for the
-    // gradient (more rows per lane share each column read and rotation; fewer fit the VGPRs)
     const dim3 grid((unsigned)g.n_blocks * (unsigned)g.n_chunks);
-    if (op == OP_ACC) hipLaunchKernelGGL((k_pairs_sym<SymAcc, 8, 2>), grid, dim3(64 * 8), 0, st, g);
-    else if (op == OP_GRAD) hipLaunchKernelGGL((k_pairs_sym<SymGrad, 4, 4>), grid, dim3(64 * 4), 0, st, g);
+    if (op == OP_ACC)
+        hipLaunchKernelGGL((k_pairs_sym<SymAcc, kAccWaves, kAccRows>), grid, dim3(64 * kAccWaves), 0, st, g);
+    else if (op == OP_GRAD)
+        hipLaunchKernelGGL((k_pairs_sym<SymGrad, kGradWaves, kGradRows>), grid, dim3(64 * kGradWaves), 0, st, g);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -75,6 +75,8 @@ def test_symmetric_sweep_parity(ctx, n, op):
         acc = [torch.as_tensor(np.ascontiguousarray(a[:, k]), device="cuda") for k in range(3)]
         out = ctx.force_gradient(Pd, acc, prec="mixed", r_fb=0.0)
     fix, near, far = ctx.last_pass_stats()
+    kind, rows, waves, _ = ctx.last_pass_config()
+    assert (kind, waves, rows) == ("symmetric", *WALKS[op])
     assert near + far == _tile_pairs(n, op), (near, far, _tile_pairs(n, op))
     got = gather(out, np.arange(n))
     f = ctx.read_flags(clear=True)
@@ -105,8 +107,7 @@ def test_symmetric_softened_and_repeatable(ctx, op):
     try:
         ctx.set_spatial_sort(forces=True, gradient=True, any_size=True, symmetric=False)
         z = run()
-        _, near, far = ctx.last_pass_stats()
-        assert near + far != _tile_pairs(n, op)  # the directed sweep ran
+        assert ctx.last_pass_config()[0] == "sorted"  # the directed sweep ran
     finally:
         ctx.set_spatial_sort(forces=True, gradient=True, any_size=True)
     for out in (x, z):
@@ -133,8 +134,7 @@ def test_symmetric_subset_runs_directed(ctx):
     P, Pd = oracle.Particles.from_dict(d), _dev(d)
     T = np.sort(np.random.default_rng(4).choice(n, 3000, replace=False))
     got = gather(ctx.forces(Pd, T, None, prec="mixed", r_fb=0.0), T)
-    _, near, far = ctx.last_pass_stats()
-    assert near + far != _tile_pairs(n)
+    assert ctx.last_pass_config()[0] == "sorted"
     rms, mx = stats(rel_errors(got, oracle.forces(P, T, None)))
     assert rms <= RMS_TOL and mx <= MAX_TOL
 
