@@ -340,7 +340,7 @@ extern "C" {
 BF_API int bf_forces_batched(bf_ctx* c, const bf_particles* P, int32_t nclusters, const int64_t* coff,
                              const int32_t* aidx, const int64_t* aoff, int64_t max_active, int64_t max_cluster_n,
                              double G, double eps2, int prec, double r_fb, double* ax, double* ay, double* az) {
-    Batch b;
+    Batch b{};
     if (int rc = batch_setup(c, P, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, OP_ACC, b))
         return rc;
     if (!ax || !ay || !az) return bf_internal_fail(BF_ERR_ARG, "output pointer NULL");
@@ -354,7 +354,7 @@ BF_API int bf_force_gradient_batched(bf_ctx* c, const bf_particles* P, int32_t n
                                      int64_t max_cluster_n, const double* ax, const double* ay, const double* az,
                                      double G, double eps2, int prec, double r_fb, double* gx, double* gy,
                                      double* gz) {
-    Batch b;
+    Batch b{};
     if (int rc = batch_setup(c, P, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, OP_GRAD, b))
         return rc;
     if (!ax || !ay || !az || !gx || !gy || !gz) return bf_internal_fail(BF_ERR_ARG, "array pointer NULL");
@@ -417,7 +417,7 @@ BF_API int bf_fsi_step_batched(bf_ctx* c, const bf_state* S, int32_t nclusters, 
                                double G, double eps2, int prec, double r_fb, double dt, double* ax, double* ay,
                                double* az) {
     if (!c) return bf_internal_fail(BF_ERR_ARG, "NULL context");
-    Batch ba, bg;
+    Batch ba{}, bg{};
     if (int rc = batched_fsi_setup(c, S, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, dt,
                                    ax, ay, az, ba, bg))
         return rc;
@@ -434,7 +434,7 @@ BF_API int bf_graph_capture_batched_fsi(bf_ctx* c, const bf_state* S, int32_t nc
     void* saved[3] = {nullptr, nullptr, nullptr};
     size_t saved_bytes[3] = {0, 0, 0};
     bf_internal_swap_scratch(c, saved, saved_bytes);
-    Batch ba, bg;
+    Batch ba{}, bg{};
     if (int rc = batched_fsi_setup(c, S, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, dt,
                                    ax, ay, az, ba, bg)) {
         bf_internal_swap_scratch(c, saved, saved_bytes);  // context buffers back, graph ones out

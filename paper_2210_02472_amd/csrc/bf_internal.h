@@ -52,6 +52,7 @@ struct PairArgs {
     int32_t* fix_list;     // [tgt.count] target slots queued for the FP64 fix-up
     int32_t* fix_count;    // number of queued slots
     unsigned long long* tile_stats;  // sorted mode: [near tiles, far tiles] visited (NULL: not counted)
+    unsigned long long* pass_stats;  // [fix-ups, near, far] of the pass: the fix-up writes entry 0 (NULL: not)
     const int32_t* sub;    // particle-indexed subsystem labels (NULL: no exclusion)
     uint32_t* flags;
 };
@@ -81,6 +82,8 @@ hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_zero_count(int32_t* c, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st);
+// one kernel: zero the fix-up counter (if not NULL) and the three pass statistics
+hipError_t launch_pass_begin(int32_t* fix_count, unsigned long long* stats, hipStream_t st);
 // A captured graph and the scratch buffers it owns (freed with it).
 struct bf_graph {
     hipGraph_t graph = nullptr;

@@ -75,6 +75,7 @@ int ensure(void** buf, size_t* have, size_t need, hipStream_t st) {
     }
     if (hipMalloc(buf, want) != hipSuccess) {
         *buf = nullptr;
+        (void)hipGetLastError();  // not left for the next launch check to report
         return fail(BF_ERR_NOMEM, "scratch allocation of " + std::to_string(want) + " bytes failed");
     }
     *have = want;
@@ -194,7 +195,17 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     if (rc) return rc;
     if (sorted && !sorted_variant_exists(op, p.cfg.k, p.cfg.waves))
         return fail(BF_ERR_UNSUPPORTED, "no sorted kernel variant for this configuration");
-    const bool sym = use_symmetric(ctx, op, sorted, tg, sr);
+    bool sym = use_symmetric(ctx, op, sorted, tg, sr);
+    int sym_shares = 0;
+    if (sym && !ctx->dry) {
+        // the column partials are large (8.6 GB at n = 2^20): without the memory, the directed
+        // sweep runs instead
+        sym_shares = sym_chunks(ctx, op, sr->count);
+        if (ensure(&ctx->scratch9, &ctx->scratch9_bytes, sym_scratch_bytes(sr->count, sym_shares), ctx->stream)) {
+            g_err.clear();
+            sym = false;
+        }
+    }
     if (sym) p.split = 1;  // no source split: the symmetric sweep has its own partials
     PairArgs a{};
     a.P = M;
@@ -236,9 +247,9 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     a.fix_count = static_cast<int32_t*>(ctx->scratch);
     a.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + 256);
     if (p.split > 1) a.part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + head);
-    if (fix) BF_HIP(launch_zero_count(a.fix_count, ctx->stream));
-    BF_HIP(launch_zero_u64(ctx->d_stats, 3, ctx->stream));
+    BF_HIP(launch_pass_begin(fix ? a.fix_count : nullptr, ctx->d_stats, ctx->stream));
     a.tile_stats = ctx->d_stats + 1;
+    a.pass_stats = ctx->d_stats;
     SymArgs g{};
     if (sorted) {
         // order targets and sources along a Morton curve, then pack the sorted sources into tiles
@@ -282,9 +293,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         BF_HIP(launch_pack_tiles(op, tile_waves, a, ctx->scratch2, ctx->scratch6,
                                  reinterpret_cast<double4*>(static_cast<char*>(ctx->scratch6) + far_bytes), ctx->stream));
         if (sym) {
-            const int chunks = sym_chunks(ctx, op, ns);
-            rc = ensure(&ctx->scratch9, &ctx->scratch9_bytes, sym_scratch_bytes(ns, chunks), ctx->stream);
-            if (rc) return rc;
+            const int chunks = sym_shares;
             g.near_pack = a.pack;
             g.far_pack = a.pack_far;
             g.tile_meta = a.tile_meta;
@@ -330,7 +339,6 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     if (sym) BF_HIP(launch_sym_reduce(op, a, g, ctx->stream));
     else if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
     if (fix) BF_HIP(launch_fixup(op, a, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
-    if (fix) BF_HIP(hipMemcpyAsync(ctx->d_stats, a.fix_count, sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
     return BF_OK;
 }
 

@@ -101,6 +101,11 @@ __global__ void k_zero_count(int32_t* c) { *c = 0; }
 __global__ void k_zero_u64(unsigned long long* c, int n) {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
+// start of a pass: the fix-up queue counter (if any) and the three pass statistics
+__global__ void k_pass_begin(int32_t* fix_count, unsigned long long* stats) {
+    if (threadIdx.x < 3) stats[threadIdx.x] = 0;
+    if (threadIdx.x == 3 && fix_count) *fix_count = 0;
+}
 
 // The queue is worked in rounds of up to kFixTiled targets.  In a round a workgroup takes 256
 // queued targets (one per thread) against one source chunk staged through LDS and writes FP64
@@ -175,6 +180,8 @@ __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* p
 }
 
 __global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part, int base) {
+    if (base == 0 && a.pass_stats && blockIdx.x == 0 && threadIdx.x == 0)
+        a.pass_stats[0] = (unsigned long long)min(*a.fix_count, a.tgt.count);
     const int count = fix_round_count(a, base);
     if (count <= 0) return;
     const int nch = fix_chunks(count);
@@ -302,6 +309,11 @@ hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st) {
 
 hipError_t launch_zero_count(int32_t* c, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_begin(int32_t* fix_count, unsigned long long* stats, hipStream_t st) {
+    hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, st, fix_count, stats);
     return hipGetLastError();
 }
 
