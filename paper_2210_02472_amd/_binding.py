@@ -256,9 +256,11 @@ class Context:
             _need(t, torch.float64, P.n, "output")
         return list(out)
 
-    def forces(self, P: Particles, targets=None, sources=None, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3,
+    def forces(self, P: Particles, targets=None, sources=None, G=1.0, eps2=0.0, prec="mixed", r_fb=0.0,
                out: Optional[Sequence[torch.Tensor]] = None):
-        """Accelerations (particle-indexed ax, ay, az; only target entries written)."""
+        """Accelerations (particle-indexed ax, ay, az; only target entries written).  r_fb > 0 re-evaluates
+        in FP64 the 64-source slices holding a pair closer than r_fb; the default 0 relies on the mixed
+        path's FP64 pair differences alone (and allows the spatially sorted sweeps)."""
         t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
         o = self._outs(P, out, 3)
         _check("bf_forces", _lib.bf_forces(self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()),
@@ -266,7 +268,7 @@ class Context:
         return o
 
     def force_gradient(self, P: Particles, acc: Sequence[torch.Tensor], targets=None, sources=None, G=1.0, eps2=0.0,
-                       prec="mixed", r_fb=1e-3, out: Optional[Sequence[torch.Tensor]] = None):
+                       prec="mixed", r_fb=0.0, out: Optional[Sequence[torch.Tensor]] = None):
         """Force-gradient sums Gsum (particle-indexed gx, gy, gz)."""
         t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
         for a in acc:
@@ -304,7 +306,7 @@ class Context:
                                            ctypes.byref(k), ctypes.byref(u)))
         return k.value, u.value
 
-    def fsi_step(self, P: Particles, dt: float, subset=None, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3, bh=None,
+    def fsi_step(self, P: Particles, dt: float, subset=None, G=1.0, eps2=0.0, prec="mixed", r_fb=0.0, bh=None,
                  c=1e4, acc: Optional[Sequence[torch.Tensor]] = None, acc_valid: bool = False):
         """One FSI cycle in place over `subset`; returns the accelerations of the final state."""
         s = ParticleSet.of(subset, P.n)
@@ -399,7 +401,7 @@ class Context:
 
     def forces_batched(self, P: Particles, cluster_off: torch.Tensor, active_idx: torch.Tensor,
                        active_off: torch.Tensor, max_active_total: int, max_cluster_n: int, G=1.0, eps2=0.0,
-                       prec="mixed", r_fb=1e-3, out=None):
+                       prec="mixed", r_fb=0.0, out=None):
         _need(cluster_off, torch.int64, None, "cluster_off")
         _need(active_off, torch.int64, None, "active_off")
         _need(active_idx, torch.int32, None, "active_idx")
@@ -412,7 +414,7 @@ class Context:
         return o
 
     def force_gradient_batched(self, P: Particles, cluster_off, active_idx, active_off, max_active_total: int,
-                               max_cluster_n: int, acc, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3, out=None):
+                               max_cluster_n: int, acc, G=1.0, eps2=0.0, prec="mixed", r_fb=0.0, out=None):
         o = self._outs(P, out, 3)
         nc = int(cluster_off.numel()) - 1
         _check("bf_force_gradient_batched", _lib.bf_force_gradient_batched(
@@ -422,7 +424,7 @@ class Context:
         return o
 
     def fsi_step_batched(self, P: Particles, cluster_off, active_idx, active_off, max_active_total, max_cluster_n,
-                         dt, acc, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3):
+                         dt, acc, G=1.0, eps2=0.0, prec="mixed", r_fb=0.0):
         """One FSI cycle of every cluster's active particles (see bf_fsi_step_batched)."""
         nc = int(cluster_off.numel()) - 1
         _check("bf_fsi_step_batched", _lib.bf_fsi_step_batched(
@@ -431,7 +433,7 @@ class Context:
             float(dt), *map(_ptr, acc)))
 
     def capture_batched_fsi(self, P: Particles, cluster_off, active_idx, active_off, max_active_total,
-                            max_cluster_n, dt, acc, G=1.0, eps2=0.0, prec="mixed", r_fb=1e-3):
+                            max_cluster_n, dt, acc, G=1.0, eps2=0.0, prec="mixed", r_fb=0.0):
         """Capture one batched FSI cycle into a HIP graph (see bf_graph_capture_batched_fsi)."""
         g = _vp()
         nc = int(cluster_off.numel()) - 1

@@ -141,3 +141,38 @@ def test_symmetric_subset_runs_directed(ctx):
 
 def _dev(d):
     return bf.Particles.from_numpy(d)
+
+
+def test_symmetric_fsi_steps_parity(ctx):
+    """Three FSI cycles (Sec. 2.1) of a King cluster whose acceleration and gradient passes take
+    the symmetric sweep: the change of the state within 1e-5 of the oracle's change."""
+    n = 4000
+    d = _king(n, 21)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    P0 = P.copy()
+    acc = None
+    for s in range(3):
+        oracle.fsi_step(P, 2e-4)
+        acc = ctx.fsi_step(Pd, 2e-4, prec="mixed", acc=acc, acc_valid=s > 0)
+    assert ctx.last_pass_config()[0] == "symmetric"
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        change = np.abs(getattr(P, k) - getattr(P0, k)).max()
+        assert np.abs(getattr(Pd, k).cpu().numpy() - getattr(P, k)).max() <= MAX_TOL * change, k
+
+
+def test_symmetric_hhs_interval_parity(ctx):
+    """One HHS-FSI interval (Sec. 2.2) with four populated levels: each level's own FSI passes take
+    the symmetric sweep and the inter-level passes the directed one; the change of the state
+    within 1e-5 of the oracle's change."""
+    n = 3000
+    d = _king(n, 23)
+    level = np.random.default_rng(6).choice([0, 1, 2, 4], size=n, p=[0.5, 0.25, 0.15, 0.10]).astype(np.int32)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    P0 = P.copy()
+    tau = 4e-4
+    oracle.hhs_interval(P, level, tau)
+    ctx.hhs_interval(Pd, torch.as_tensor(level, device="cuda"), 4, tau, prec="mixed")
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        change = np.abs(getattr(P, k) - getattr(P0, k)).max()
+        assert np.abs(getattr(Pd, k).cpu().numpy() - getattr(P, k)).max() <= MAX_TOL * change, k
+    assert ctx.read_flags() & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
