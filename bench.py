@@ -42,7 +42,7 @@ KERNEL_SOURCES = ["pair_ops.h", "pairs.hip", "spatial.hip", "symmetric.hip", "bf
 
 # gradient kernel of each pass kind (the library's launch of that kind at this size)
 KERNEL_NAMES = {"unsorted": "k_pairs<GradMixed>", "sorted": "k_pairs_sorted<GradMixed>",
-                "symmetric": "k_pairs_sym<SymGrad>"}
+                "symmetric": "k_pairs_sym<SymGrad>", "between": "k_pairs_sym<SymGrad> (two sets)"}
 
 
 def pass_desc(cfg):

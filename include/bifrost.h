@@ -134,6 +134,24 @@ BF_API int bf_force_gradient(bf_ctx *ctx, const bf_particles *P, const bf_set *t
                              const double *az, double G, double eps2, int prec, double r_fb,
                              double *gx, double *gy, double *gz);
 
+/* Both inter-set sums at once (Sec. 2.2: the inter-level terms of the hierarchy, S <- F and
+ * F <- S, are the same pairs seen from either side).  For every particle i of set a it writes
+ * ax/ay/az[i] = the acceleration of i due to the particles of b, and for every particle j of b
+ * the acceleration of j due to a; entries outside a and b are not written.  a and b must be
+ * disjoint: overlapping ranges and a shared index array fail with BF_ERR_ARG; for other index
+ * lists disjointness is the caller's promise (a particle in both gets one of its two sums).
+ * Mixed precision with r_fb = 0 and both directions large enough for the spatially sorted mode
+ * (bf_set_spatial_sort) evaluates every pair once (two-set symmetric sweep, scratch
+ * (n_a / 1024 + 1) * 16 bytes per particle of b plus O(n_a)); otherwise it runs as the two
+ * passes bf_forces(a <- b) and bf_forces(b <- a).  Results, errors and flags as bf_forces. */
+BF_API int bf_forces_between(bf_ctx *ctx, const bf_particles *P, const bf_set *a, const bf_set *b, double G,
+                             double eps2, int prec, double r_fb, double *ax, double *ay, double *az);
+/* The force-gradient sums between two disjoint sets, as bf_forces_between: a's particles get
+ * Gsum over b, b's over a, with a_ji from the given accelerations (particle-indexed). */
+BF_API int bf_force_gradient_between(bf_ctx *ctx, const bf_particles *P, const bf_set *a, const bf_set *b,
+                                     const double *ax, const double *ay, const double *az, double G, double eps2,
+                                     int prec, double r_fb, double *gx, double *gy, double *gz);
+
 /* Pairwise time-steps (Sec. 3.5.3, Eqs. dt-freefall and dt-flyby), unsoftened:
  *     dt_ff,i = eta_ff min_j (|r_ij|^3 / (G (m_i + m_j)))^(1/2)
  *     dt_fb,i = eta_fb min_j |r_ij| / |v_ij|
@@ -398,14 +416,16 @@ BF_API int bf_set_spatial_sort(bf_ctx *ctx, int ops_mask, double kappa);
 BF_API int bf_last_pass_stats(bf_ctx *ctx, int64_t *fixups, int64_t *near_tiles, int64_t *far_tiles);
 
 /* Not synchronising.  How the most recent acceleration / gradient / time-step pass ran:
- * kind BF_PASS_UNSORTED, BF_PASS_SORTED (spatially sorted, directed sweep) or BF_PASS_SYMMETRIC
- * (spatially sorted, each unordered pair once); k_per_lane = targets per lane (row tiles per
- * wavefront for BF_PASS_SYMMETRIC), waves = wavefronts per workgroup, split = source chunks
- * (shares of the block distances for BF_PASS_SYMMETRIC).  Any pointer may be NULL.  Before the
+ * kind BF_PASS_UNSORTED, BF_PASS_SORTED (spatially sorted, directed sweep), BF_PASS_SYMMETRIC
+ * (spatially sorted, each unordered pair once) or BF_PASS_BETWEEN (the two-set symmetric sweep
+ * of bf_forces_between / bf_force_gradient_between); k_per_lane = targets per lane (row tiles per
+ * wavefront for the symmetric sweeps), waves = wavefronts per workgroup, split = source chunks
+ * (shares of the column range for the symmetric sweeps).  Any pointer may be NULL.  Before the
  * first pass all are 0. */
 #define BF_PASS_UNSORTED 0
 #define BF_PASS_SORTED 1
 #define BF_PASS_SYMMETRIC 2
+#define BF_PASS_BETWEEN 3
 BF_API int bf_last_pass_config(bf_ctx *ctx, int *kind, int *k_per_lane, int *waves, int *split);
 
 /* Kernel configuration the context would use for a directed pass of these sizes (for

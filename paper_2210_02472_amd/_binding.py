@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH):
         "bf_subsystems": [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i64)],
         "bf_set_subsystems": [_vp, _vp, _i64],
         "bf_last_pass_stats": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+        "bf_forces_between": [_vp, P, S, S, _d, _d, _int, _d, _vp, _vp, _vp],
+        "bf_force_gradient_between": [_vp, P, S, S, _vp, _vp, _vp, _d, _d, _int, _d, _vp, _vp, _vp],
         "bf_last_pass_config": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
                                 ctypes.POINTER(_int)],
         "bf_kernel_times": [_vp, _int, ctypes.POINTER(ctypes.c_float), _int, ctypes.POINTER(_int)],
@@ -276,6 +278,28 @@ class Context:
         o = self._outs(P, out, 3)
         _check("bf_force_gradient", _lib.bf_force_gradient(
             self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()), *map(_ptr, acc), float(G),
+            float(eps2), PRECISIONS[prec], float(r_fb), *map(_ptr, o)))
+        return o
+
+    def forces_between(self, P: Particles, a, b, G=1.0, eps2=0.0, prec="mixed", r_fb=0.0,
+                       out: Optional[Sequence[torch.Tensor]] = None):
+        """Accelerations of a's particles due to b and of b's due to a (disjoint sets), one output."""
+        sa, sb = ParticleSet.of(a, P.n), ParticleSet.of(b, P.n)
+        o = self._outs(P, out, 3)
+        _check("bf_forces_between", _lib.bf_forces_between(self._h, ctypes.byref(P._c()), ctypes.byref(sa._c()),
+                                                           ctypes.byref(sb._c()), float(G), float(eps2),
+                                                           PRECISIONS[prec], float(r_fb), *map(_ptr, o)))
+        return o
+
+    def force_gradient_between(self, P: Particles, acc: Sequence[torch.Tensor], a, b, G=1.0, eps2=0.0, prec="mixed",
+                               r_fb=0.0, out: Optional[Sequence[torch.Tensor]] = None):
+        """Force-gradient sums of a's particles over b and of b's over a (disjoint sets)."""
+        sa, sb = ParticleSet.of(a, P.n), ParticleSet.of(b, P.n)
+        for x in acc:
+            _need(x, torch.float64, P.n, "acceleration")
+        o = self._outs(P, out, 3)
+        _check("bf_force_gradient_between", _lib.bf_force_gradient_between(
+            self._h, ctypes.byref(P._c()), ctypes.byref(sa._c()), ctypes.byref(sb._c()), *map(_ptr, acc), float(G),
             float(eps2), PRECISIONS[prec], float(r_fb), *map(_ptr, o)))
         return o
 
@@ -467,10 +491,10 @@ class Context:
 
     def last_pass_config(self):
         """(kind, k_per_lane, waves, split) of the most recent pass; kind is "unsorted", "sorted"
-        (directed sweep) or "symmetric" (each unordered pair once)."""
+        (directed sweep), "symmetric" (each unordered pair once) or "between" (the two-set sweep)."""
         v = [_int(0) for _ in range(4)]
         _check("bf_last_pass_config", _lib.bf_last_pass_config(self._h, *(ctypes.byref(x) for x in v)))
-        return ("unsorted", "sorted", "symmetric")[v[0].value], v[1].value, v[2].value, v[3].value
+        return ("unsorted", "sorted", "symmetric", "between")[v[0].value], v[1].value, v[2].value, v[3].value
 
     def set_spatial_sort(self, forces: bool = True, gradient: bool = True, kappa: float = 0.0,
                          any_size: bool = False, symmetric: bool = True):

@@ -124,24 +124,37 @@ int sorted_blocks_per_cu(int op, int k, int waves);
 // packed in tiles of 64; a workgroup owns a block of kSymBlockTiles row tiles (W wavefronts of R
 // row tiles each, W R = kSymBlockTiles).
 constexpr int kSymBlockTiles = 16;
+// Two modes:
+//  * one set (between == 0): rows and columns are the same sorted set; each unordered pair once;
+//  * two sets (between == 1): rows are set A, columns set B (disjoint); every pair (a, b) once.
 struct SymArgs {
-    const void* near_pack;     // sorted particles, FP64 (the near stream of launch_pack_tiles)
-    const void* far_pack;      // sorted particles, FP32 offsets from their tile's centre
-    const double4* tile_meta;  // per tile: (centre, [half-extent, G tile mass]) [, (a centre, [a half-extent])]
-    int32_t n;                 // particles
+    const void* near_pack;     // sorted columns, FP64 (the near stream of launch_pack_tiles)
+    const void* far_pack;      // sorted columns, FP32 offsets from their tile's centre
+    const double4* tile_meta;  // per column tile: (centre, [half-extent, G tile mass]) [, (a centre, [a half-extent])]
+    const void* row_pack;      // sorted rows, FP64, same layout as near_pack (one set: near_pack)
+    int32_t n;                 // columns
     int32_t n_tiles;           // ceil(n / 64)
-    int32_t n_blocks;          // ceil(n_tiles / kSymBlockTiles)
-    int32_t n_pad;             // 64 n_tiles: row stride of part and own
+    int32_t n_pad;             // 64 n_tiles: stride of part
+    int32_t n_rows, n_row_tiles, n_row_pad;  // rows: count, ceil(count / 64), 64 n_row_tiles (stride of own)
+    int32_t n_blocks;          // row blocks: ceil(n_row_tiles / kSymBlockTiles)
+    int32_t between;           // 0: one set, 1: two sets
     float eps2f, kappa;
-    int32_t n_chunks;          // the block distances 0..n_blocks/2 are split into n_chunks shares
-    int32_t chunk_len;         // of chunk_len distances (one workgroup per block and share)
-    float* part;               // [n_blocks / 2 + 1][4][n_pad] column-side partials, one row per block distance
-    double* own;               // [n_chunks][4][n_pad] row-side sums, one row per share
+    int32_t n_chunks;          // the column range of a row block is split into n_chunks shares of
+    int32_t chunk_len;         // chunk_len block distances (one set) or column tiles (two sets)
+    float* part;               // one set: [n_blocks / 2 + 1][4][n_pad] column partials per block distance;
+                               // two sets: [n_blocks][4][n_pad] column partials per row block
+    double* own;               // [n_chunks][4][n_row_pad] row sums, one row per share
     unsigned long long* tile_stats;  // [near, far] wavefront-tile visits (NULL: not counted)
 };
-// bytes of own (256-byte aligned) and of own + part for n particles and `chunks` shares
+// bytes of own (256-byte aligned) and of own + part for n particles and `chunks` shares (one set)
 size_t sym_own_bytes(int64_t n, int chunks);
 size_t sym_scratch_bytes(int64_t n, int chunks);
+// the same for rows of n_rows particles against columns of n_cols (two sets)
+size_t between_scratch_bytes(int64_t n_rows, int64_t n_cols, int chunks);
+// adds the row sums (rows: a_rows.tgt, sorted) and the column partials (columns: a_cols.tgt) in a
+// fixed order, writes both sets' particle-indexed outputs and queues ill-conditioned targets
+hipError_t launch_between_reduce(int op, const PairArgs& a_rows, const PairArgs& a_cols, const SymArgs& g,
+                                 hipStream_t st);
 // resident workgroups per CU, wavefronts per workgroup and row tiles per wavefront of the
 // symmetric kernel of op
 int sym_blocks_per_cu(int op);
@@ -265,6 +278,8 @@ struct bf_ctx {
     size_t scratch8_bytes = 0;
     void* scratch9 = nullptr;         // pair-symmetric sweep: row sums and column partials
     size_t scratch9_bytes = 0;
+    void* scratch10 = nullptr;        // two-set symmetric sweep: FP64 stream of the row set
+    size_t scratch10_bytes = 0;
     bool capturing = false;           // a graph capture is recording this context's work
     bool dry = false;                 // size scratch only, launch nothing (before a capture)
     unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass

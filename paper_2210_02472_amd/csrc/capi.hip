@@ -297,10 +297,12 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
             g.near_pack = a.pack;
             g.far_pack = a.pack_far;
             g.tile_meta = a.tile_meta;
-            g.n = (int32_t)ns;
-            g.n_tiles = (int32_t)ntiles;
+            g.row_pack = a.pack;
+            g.n = g.n_rows = (int32_t)ns;
+            g.n_tiles = g.n_row_tiles = (int32_t)ntiles;
             g.n_blocks = (int32_t)((ntiles + kSymBlockTiles - 1) / kSymBlockTiles);
-            g.n_pad = (int32_t)(64 * ntiles);
+            g.n_pad = g.n_row_pad = (int32_t)(64 * ntiles);
+            g.between = 0;
             g.eps2f = a.eps2f;
             g.kappa = a.kappa;
             g.n_chunks = chunks;
@@ -339,6 +341,147 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     if (sym) BF_HIP(launch_sym_reduce(op, a, g, ctx->stream));
     else if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
     if (fix) BF_HIP(launch_fixup(op, a, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
+    return BF_OK;
+}
+
+// Both inter-set passes A <- B and B <- A (Sec. 2.2: the inter-level sums of the hierarchy are
+// the same pairs seen from either side), written into the same particle-indexed outputs.  When
+// the spatially sorted mode applies to both and the sets are disjoint (the caller's guarantee),
+// one two-set symmetric sweep evaluates every pair (a, b) once; otherwise two passes run.
+int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* A, const bf_set* B, double G,
+                      double eps2, double r_fb, double* o0, double* o1, double* o2) {
+    auto two_passes = [&]() -> int {
+        if (int rc = run_pairs(ctx, op, prec, M, A, B, G, eps2, r_fb, 0, 0, o0, o1, o2)) return rc;
+        return run_pairs(ctx, op, prec, M, B, A, G, eps2, r_fb, 0, 0, o0, o1, o2);
+    };
+    const int64_t na = A->count, nb = B->count;
+    if (na == 0 || nb == 0 || ctx->dry || (ctx->sort_ops & BF_SORT_DIRECTED) ||
+        !use_sorted(ctx, op, prec, na, nb, r_fb) || !use_sorted(ctx, op, prec, nb, na, r_fb))
+        return two_passes();
+    // shares of each row block's column tiles: at least two rounds of resident workgroups
+    const int64_t a_tiles = (na + 63) / 64, b_tiles = (nb + 63) / 64;
+    const int64_t rblocks = (a_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
+    const int64_t want = 2 * (int64_t)ctx->num_cu * sym_blocks_per_cu(op);
+    const int shares = (int)std::max<int64_t>(1, std::min<int64_t>(b_tiles, (want + rblocks - 1) / rblocks));
+    if (between_scratch_bytes(na, nb, shares) > kSymMaxScratch ||
+        ensure(&ctx->scratch9, &ctx->scratch9_bytes, between_scratch_bytes(na, nb, shares), ctx->stream)) {
+        g_err.clear();
+        return two_passes();
+    }
+    // scratch: two fix-up queues [counter | list] for A and B
+    const size_t qa = 256 + (((size_t)na * sizeof(int32_t) + 255) & ~size_t(255));
+    const size_t qb = 256 + (((size_t)nb * sizeof(int32_t) + 255) & ~size_t(255));
+    if (int rc = ensure(&ctx->scratch, &ctx->scratch_bytes, qa + qb, ctx->stream)) return rc;
+    if (int rc = ensure(&ctx->scratch8, &ctx->scratch8_bytes, (size_t)kFixChunks * 3 * kFixTiled * sizeof(double),
+                        ctx->stream))
+        return rc;
+    // sort both sets, pack B as column tiles of 64 and A as the FP64 row stream
+    const int64_t nmax = std::max(na, nb);
+    const size_t tmp = sort_tmp_bytes((int)nmax);
+    const size_t list_bytes = ((size_t)nmax * 4 + 255) & ~size_t(255);
+    if (int rc = ensure(&ctx->scratch5, &ctx->scratch5_bytes, 256 + 6 * list_bytes + ((tmp + 255) & ~size_t(255)),
+                        ctx->stream))
+        return rc;
+    char* b5 = static_cast<char*>(ctx->scratch5);
+    SortBuffers sb;
+    sb.bbox = reinterpret_cast<uint32_t*>(b5);
+    sb.keys_in = reinterpret_cast<uint32_t*>(b5 + 256);
+    sb.keys_out = reinterpret_cast<uint32_t*>(b5 + 256 + list_bytes);
+    sb.vals_in = reinterpret_cast<int32_t*>(b5 + 256 + 2 * list_bytes);
+    sb.vals_out = reinterpret_cast<int32_t*>(b5 + 256 + 3 * list_bytes);
+    int32_t* b_sorted = reinterpret_cast<int32_t*>(b5 + 256 + 4 * list_bytes);
+    int32_t* a_sorted = reinterpret_cast<int32_t*>(b5 + 256 + 5 * list_bytes);
+    sb.tmp = b5 + 256 + 6 * list_bytes;
+    sb.tmp_bytes = tmp;
+    const int pb = pack_bytes(op, prec);
+    const size_t far_bytes = (((size_t)nb * (op == OP_GRAD ? 32 : 16)) + 255) & ~size_t(255);
+    const int kmeta = op == OP_GRAD ? 2 : 1;
+    if (int rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)nb * pb, ctx->stream)) return rc;
+    if (int rc = ensure(&ctx->scratch6, &ctx->scratch6_bytes, far_bytes + (size_t)b_tiles * kmeta * sizeof(double4),
+                        ctx->stream))
+        return rc;
+    if (int rc = ensure(&ctx->scratch10, &ctx->scratch10_bytes, (size_t)na * pb, ctx->stream)) return rc;
+
+    PairArgs ab{};  // A targets, B sources
+    ab.P = M;
+    ab.G = G;
+    ab.eps2 = eps2;
+    ab.eps2f = (float)eps2 + 1e-20f;
+    ab.rfb2f = 0.0f;
+    ab.split = 1;
+    ab.o0 = o0; ab.o1 = o1; ab.o2 = o2;
+    ab.flags = ctx->d_flags;
+    ab.cond_max = cond_max_for(op);
+    ab.kappa = ctx->kappa;
+    PairArgs ba = ab;  // B targets, A sources
+    ab.fix_count = static_cast<int32_t*>(ctx->scratch);
+    ab.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + 256);
+    ba.fix_count = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + qa);
+    ba.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + qa + 256);
+    BF_HIP(launch_pass_begin(ab.fix_count, ctx->d_stats, ctx->stream));
+    BF_HIP(launch_zero_count(ba.fix_count, ctx->stream));
+    ab.tile_stats = ctx->d_stats + 1;
+    ab.pass_stats = ctx->d_stats;  // the count of A's queue is reported
+    const DevSet dA = devset(A), dB = devset(B);
+    BF_HIP(launch_sort_set(M, dB, dB, sb, b_sorted, ctx->d_flags, ctx->stream));
+    BF_HIP(launch_sort_set(M, dA, dA, sb, a_sorted, ctx->d_flags, ctx->stream));
+    ab.tgt = ba.src = DevSet{a_sorted, (int32_t)na, 0};
+    ab.src = ba.tgt = DevSet{b_sorted, (int32_t)nb, 0};
+    double4* meta = reinterpret_cast<double4*>(static_cast<char*>(ctx->scratch6) + far_bytes);
+    ab.pack = ctx->scratch2;
+    ab.pack_far = ctx->scratch6;
+    ab.tile_meta = meta;
+    BF_HIP(launch_pack_tiles(op, 1, ab, ctx->scratch2, ctx->scratch6, meta, ctx->stream));
+    PairArgs pa = ab;  // the rows' FP64 stream: the mixed pack of the sorted A list
+    pa.src = ab.tgt;
+    pa.pack = ctx->scratch10;
+    BF_HIP(launch_pack(op, BF_PREC_MIXED, pa, ctx->stream));
+
+    SymArgs g{};
+    g.near_pack = ctx->scratch2;
+    g.far_pack = ctx->scratch6;
+    g.tile_meta = meta;
+    g.row_pack = ctx->scratch10;
+    g.n = (int32_t)nb;
+    g.n_tiles = (int32_t)b_tiles;
+    g.n_pad = (int32_t)(64 * b_tiles);
+    g.n_rows = (int32_t)na;
+    g.n_row_tiles = (int32_t)a_tiles;
+    g.n_row_pad = (int32_t)(64 * a_tiles);
+    g.n_blocks = (int32_t)rblocks;
+    g.between = 1;
+    g.eps2f = ab.eps2f;
+    g.kappa = ctx->kappa;
+    g.n_chunks = shares;
+    g.chunk_len = (int32_t)((b_tiles + shares - 1) / shares);
+    g.own = static_cast<double*>(ctx->scratch9);
+    g.part = reinterpret_cast<float*>(static_cast<char*>(ctx->scratch9) + sym_own_bytes(na, shares));
+    g.tile_stats = ab.tile_stats;
+
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    const bool timed = ctx->timing && !ctx->capturing;
+    if (timed) {
+        if (!ctx->tpool.empty()) {
+            ev = ctx->tpool.back();
+            ctx->tpool.pop_back();
+        } else {
+            BF_HIP(hipEventCreate(&ev.first));
+            BF_HIP(hipEventCreate(&ev.second));
+        }
+        BF_HIP(hipEventRecord(ev.first, ctx->stream));
+    }
+    BF_HIP(launch_pairs_sym(op, g, ctx->stream));
+    if (timed) {
+        BF_HIP(hipEventRecord(ev.second, ctx->stream));
+        ctx->tev[op].push_back(ev);
+    }
+    ctx->last_kind = BF_PASS_BETWEEN;
+    ctx->last_k = sym_rows_per_wave(op);
+    ctx->last_waves = sym_waves(op);
+    ctx->last_split = shares;
+    BF_HIP(launch_between_reduce(op, ab, ba, g, ctx->stream));
+    BF_HIP(launch_fixup(op, ab, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
+    BF_HIP(launch_fixup(op, ba, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
     return BF_OK;
 }
 
@@ -459,6 +602,7 @@ BF_API int bf_destroy(bf_ctx* c) {
     if (c->scratch7) hipFree(c->scratch7);
     if (c->scratch8) hipFree(c->scratch8);
     if (c->scratch9) hipFree(c->scratch9);
+    if (c->scratch10) hipFree(c->scratch10);
     if (c->d_flags) hipFree(c->d_flags);
     if (c->d_stats) hipFree(c->d_stats);
     if (c->h_flags) hipHostFree(c->h_flags);
@@ -557,6 +701,52 @@ BF_API int bf_force_gradient(bf_ctx* c, const bf_particles* P, const bf_set* t, 
     Masters M = masters_of(P);
     M.ax = ax; M.ay = ay; M.az = az;
     return run_pairs(c, OP_GRAD, prec, M, t, s, G, eps2, r_fb, 0, 0, gx, gy, gz);
+}
+
+// ranges can be checked for overlap on the host; index lists are the caller's promise
+static int check_disjoint(const bf_set* a, const bf_set* b) {
+    if (a->idx == nullptr && b->idx == nullptr && a->count > 0 && b->count > 0 &&
+        a->begin < b->begin + b->count && b->begin < a->begin + a->count)
+        return fail(BF_ERR_ARG, "the two sets overlap");
+    if (a->idx != nullptr && a->idx == b->idx && a->count > 0 && b->count > 0)
+        return fail(BF_ERR_ARG, "the two sets share their index list");
+    return BF_OK;
+}
+
+BF_API int bf_forces_between(bf_ctx* c, const bf_particles* P, const bf_set* a, const bf_set* b, double G,
+                             double eps2, int prec, double r_fb, double* ax, double* ay, double* az) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, false)) return rc;
+    if (int rc = check_set(a, P->n, "first")) return rc;
+    if (int rc = check_set(b, P->n, "second")) return rc;
+    if (int rc = check_disjoint(a, b)) return rc;
+    if (int rc = check_prec(prec)) return rc;
+    if (!isfinite(G)) return fail(BF_ERR_ARG, "G not finite");
+    if (!finite_nonneg(eps2)) return fail(BF_ERR_ARG, "eps2 must be finite and >= 0");
+    if (!finite_nonneg(r_fb)) return fail(BF_ERR_ARG, "r_fb must be finite and >= 0");
+    if (!ax || !ay || !az) return fail(BF_ERR_ARG, "output pointer NULL");
+    return run_pairs_between(c, OP_ACC, prec, masters_of(P), a, b, G, eps2, r_fb, ax, ay, az);
+}
+
+BF_API int bf_force_gradient_between(bf_ctx* c, const bf_particles* P, const bf_set* a, const bf_set* b,
+                                     const double* ax, const double* ay, const double* az, double G, double eps2,
+                                     int prec, double r_fb, double* gx, double* gy, double* gz) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, false)) return rc;
+    if (int rc = check_set(a, P->n, "first")) return rc;
+    if (int rc = check_set(b, P->n, "second")) return rc;
+    if (int rc = check_disjoint(a, b)) return rc;
+    if (int rc = check_prec(prec)) return rc;
+    if (!isfinite(G)) return fail(BF_ERR_ARG, "G not finite");
+    if (!finite_nonneg(eps2)) return fail(BF_ERR_ARG, "eps2 must be finite and >= 0");
+    if (!finite_nonneg(r_fb)) return fail(BF_ERR_ARG, "r_fb must be finite and >= 0");
+    if (!ax || !ay || !az) return fail(BF_ERR_ARG, "acceleration pointer NULL");
+    if (!gx || !gy || !gz) return fail(BF_ERR_ARG, "output pointer NULL");
+    Masters M = masters_of(P);
+    M.ax = ax; M.ay = ay; M.az = az;
+    return run_pairs_between(c, OP_GRAD, prec, M, a, b, G, eps2, r_fb, gx, gy, gz);
 }
 
 BF_API int bf_dt_min(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf_set* s, double G, double eta_ff,
@@ -840,11 +1030,8 @@ bf_set segment(const HhsCtx& h, int64_t b, int64_t e) { return bf_set{h.order + 
 int interlevel_acc(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset) {
     const int64_t n = h.S->n;
     const bf_fsi_params* p = h.prm;
-    if (int rc = run_pairs(h.c, OP_ACC, p->prec, h.M, &Sset, &Fset, p->G, p->eps2, p->r_fb, 0, 0, h.asf, h.asf + n,
-                           h.asf + 2 * n))
-        return rc;
-    return run_pairs(h.c, OP_ACC, p->prec, h.M, &Fset, &Sset, p->G, p->eps2, p->r_fb, 0, 0, h.asf, h.asf + n,
-                     h.asf + 2 * n);
+    return run_pairs_between(h.c, OP_ACC, p->prec, h.M, &Sset, &Fset, p->G, p->eps2, p->r_fb, h.asf, h.asf + n,
+                             h.asf + 2 * n);
 }
 
 // One level of the HHS-FSI cycle (Sec. 2.2, Eq. hhsfsi-cycle) for slow set Sset and fast set
@@ -889,11 +1076,8 @@ int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_
     if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
     Masters Mg = h.M;
     Mg.ax = h.asf; Mg.ay = h.asf + n; Mg.az = h.asf + 2 * n;
-    if ((rc = run_pairs(c, OP_GRAD, p->prec, Mg, &Sset, &Fset, p->G, p->eps2, p->r_fb, 0, 0, h.gsf, h.gsf + n,
-                        h.gsf + 2 * n)))
-        return rc;
-    if ((rc = run_pairs(c, OP_GRAD, p->prec, Mg, &Fset, &Sset, p->G, p->eps2, p->r_fb, 0, 0, h.gsf, h.gsf + n,
-                        h.gsf + 2 * n)))
+    if ((rc = run_pairs_between(c, OP_GRAD, p->prec, Mg, &Sset, &Fset, p->G, p->eps2, p->r_fb, h.gsf, h.gsf + n,
+                                h.gsf + 2 * n)))
         return rc;
     if (go)
         BF_HIP(launch_kick(*h.S, dB, 2.0 * tau / 3.0, h.asf, h.asf + n, h.asf + 2 * n, tau * tau / 24.0, h.gsf,

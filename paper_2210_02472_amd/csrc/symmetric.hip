@@ -88,7 +88,7 @@ struct SymAcc {
     struct Rel { float x, y, z; };
     __device__ static void load_row(const SymArgs& g, int s, bool live, Row& t) {
         if (live) {
-            const double4 p = static_cast<const double4*>(g.near_pack)[s];
+            const double4 p = static_cast<const double4*>(g.row_pack)[s];
             t.x = p.x; t.y = p.y; t.z = p.z; t.gm = unpack_gm(p.w);
         } else {
             t.x = t.y = t.z = kFarAway; t.gm = 0.f;
@@ -148,7 +148,7 @@ struct SymGrad {
     struct Rel { float x, y, z, ax, ay, az; };
     __device__ static void load_row(const SymArgs& g, int s, bool live, Row& t) {
         if (live) {
-            const double4* pk = static_cast<const double4*>(g.near_pack);
+            const double4* pk = static_cast<const double4*>(g.row_pack);
             const double4 p = pk[2 * s], a = pk[2 * s + 1];
             t.x = p.x; t.y = p.y; t.z = p.z; t.gm = unpack_gm(p.w);
             t.ax = a.x; t.ay = a.y; t.az = a.z;
@@ -219,13 +219,20 @@ __device__ __forceinline__ float box_bound(const float p[3], const float lo[3], 
     return gm / fmaxf(d2, 1e-30f);
 }
 
-// The column tiles a workgroup visits, in order: block distance d = 0..nb/2, tile t of block
-// (wg + d) mod nb.  Uniform over the workgroup.
+// The column tiles a workgroup visits, in order (uniform over the workgroup).  One set: block
+// distance d = 0..nb/2, tile t of block (wg + d) mod nb.
+// Two sets: the column tiles [t, d_end) of the workgroup's share in order, d = the row block (the
+// partial row).
 struct TileWalk {
     int d = 0, t = 0, ct = -1;
-    int d_end = 0;  // first distance past this workgroup's share
+    int d_end = 0;  // first distance (one set) or column tile (two sets) past this workgroup's share
     __device__ void next(const SymArgs& g, int wg) {
         const int nb = g.n_blocks, W = kSymBlockTiles;
+        if (g.between) {
+            ct = ct < 0 ? t : ct + 1;
+            if (ct >= d_end) ct = -1;
+            return;
+        }
         if (ct >= 0) ++t;
         for (;;) {
             if (d >= d_end || 2 * d > nb || (d > 0 && 2 * d == nb && wg >= d)) { ct = -1; return; }
@@ -351,7 +358,8 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
     __shared__ uint4 colbuf[2][NPL * kPlaneLen];
     __shared__ float xch[2][W][4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // workgroup (chunk, block): block wg's rows against its share [d0, d1) of the distances
+    // workgroup (chunk, block): block wg's rows against its share [d0, d1) of the distances (one
+    // set) or of the column tiles (two sets)
     const int wg = blockIdx.x % g.n_blocks, chunk = blockIdx.x / g.n_blocks;
     const int d0 = chunk * g.chunk_len, d1 = d0 + g.chunk_len;
     const int rbase = wg * (W * R) + wave * R;
@@ -363,9 +371,9 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
     float gm_lane = 0.f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        tile_live[r] = rbase + r < g.n_tiles;
+        tile_live[r] = rbase + r < g.n_row_tiles;
         rs[r] = (rbase + r) * 64 + lane;
-        const bool live = tile_live[r] && rs[r] < g.n;
+        const bool live = tile_live[r] && rs[r] < g.n_rows;
         S::load_row(g, rs[r], live, row[r]);
         if (live) {
             const float p[3] = {(float)row[r].x, (float)row[r].y, (float)row[r].z};
@@ -386,8 +394,14 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
     constexpr int SPT = (NPL + W - 1) / W;  // planes per staging thread
     const int st_k = threadIdx.x & 63;
     TileWalk cur, pre;
-    cur.d = d0;
-    cur.d_end = d1;
+    if (g.between) {
+        cur.d = wg;
+        cur.t = d0;
+        cur.d_end = min(d1, g.n_tiles);
+    } else {
+        cur.d = d0;
+        cur.d_end = d1;
+    }
     cur.next(g, wg);
     pre = cur;
     pre.next(g, wg);
@@ -417,7 +431,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int rt = rbase + r;
-            mode[r] = !tile_live[r] ? kSkip : (cur.d > 0 || ct > rt) ? kFull : ct == rt ? kDiag : kSkip;
+            mode[r] = !tile_live[r] ? kSkip : (g.between || cur.d > 0 || ct > rt) ? kFull : ct == rt ? kDiag : kSkip;
             any = any || mode[r] != kSkip;
             masked = masked || mode[r] != kFull;
         }
@@ -458,12 +472,12 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (tile_live[r] && rs[r] < g.n) {
-            double* o = g.own + (size_t)chunk * 4 * g.n_pad;  // every chunk writes its row sums
+        if (tile_live[r] && rs[r] < g.n_rows) {
+            double* o = g.own + (size_t)chunk * 4 * g.n_row_pad;  // every chunk writes its row sums
             o[rs[r]] = own[r].x;
-            o[(size_t)g.n_pad + rs[r]] = own[r].y;
-            o[(size_t)2 * g.n_pad + rs[r]] = own[r].z;
-            o[(size_t)3 * g.n_pad + rs[r]] = own[r].m;
+            o[(size_t)g.n_row_pad + rs[r]] = own[r].y;
+            o[(size_t)2 * g.n_row_pad + rs[r]] = own[r].z;
+            o[(size_t)3 * g.n_row_pad + rs[r]] = own[r].m;
         }
     }
     if (g.tile_stats && lane == 0) {
@@ -483,7 +497,7 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const PairArgs a, const SymA
     for (int q = 0; q < 4; ++q) v[q] = 0.0;
     for (int c = 0; c < g.n_chunks; ++c) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += g.own[((size_t)c * 4 + q) * g.n_pad + s];
+        for (int q = 0; q < 4; ++q) v[q] += g.own[((size_t)c * 4 + q) * g.n_row_pad + s];
     }
     for (int d = 0; d <= D; ++d) {
         if (d > 0 && 2 * d == nb && b < d) continue;  // no partial: this block pair was swept from here
@@ -493,7 +507,45 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const PairArgs a, const SymA
     write_result<Op>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), v);
 }
 
+// Two sets: threads [0, n_rows) finish the rows (sums over the shares), threads [n_rows,
+// n_rows + n) the columns (sums over the row blocks, with the opposite sign for the terms).
+template <class Op>
+__global__ __launch_bounds__(256) void k_between_reduce(const PairArgs ar, const PairArgs ac, const SymArgs g) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (t < g.n_rows) {
+        for (int c = 0; c < g.n_chunks; ++c) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] += g.own[((size_t)c * 4 + q) * g.n_row_pad + t];
+        }
+        write_result<Op>(ar, t, particle_of(ar.tgt, t, ar.P.n, ar.flags), v);
+    } else if (t < g.n_rows + g.n) {
+        const int s = t - g.n_rows;
+        for (int w = 0; w < g.n_blocks; ++w) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] += (double)g.part[((size_t)w * 4 + q) * g.n_pad + s];
+        }
+        write_result<Op>(ac, s, particle_of(ac.tgt, s, ac.P.n, ac.flags), v);
+    }
+}
+
 }  // namespace
+
+size_t between_scratch_bytes(int64_t n_rows, int64_t n_cols, int chunks) {
+    const int64_t row_tiles = (n_rows + 63) / 64, col_tiles = (n_cols + 63) / 64;
+    const int64_t nb = (row_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
+    return sym_own_bytes(n_rows, chunks) + (size_t)nb * 4 * 64 * col_tiles * sizeof(float);
+}
+
+hipError_t launch_between_reduce(int op, const PairArgs& ar, const PairArgs& ac, const SymArgs& g, hipStream_t st) {
+    const int64_t n = (int64_t)g.n_rows + g.n;
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (op == OP_ACC) hipLaunchKernelGGL(k_between_reduce<AccMixed>, grid, dim3(256), 0, st, ar, ac, g);
+    else if (op == OP_GRAD) hipLaunchKernelGGL(k_between_reduce<GradMixed>, grid, dim3(256), 0, st, ar, ac, g);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 size_t sym_own_bytes(int64_t n, int chunks) {
     return ((size_t)chunks * 4 * 64 * ((n + 63) / 64) * sizeof(double) + 255) & ~size_t(255);

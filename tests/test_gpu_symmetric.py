@@ -176,3 +176,62 @@ def test_symmetric_hhs_interval_parity(ctx):
         change = np.abs(getattr(P, k) - getattr(P0, k)).max()
         assert np.abs(getattr(Pd, k).cpu().numpy() - getattr(P, k)).max() <= MAX_TOL * change, k
     assert ctx.read_flags() & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
+
+
+@pytest.mark.parametrize("kind", ["list", "range"])
+@pytest.mark.parametrize("op", ["forces", "gradient"])
+def test_between_parity(ctx, kind, op):
+    """bf_forces_between / bf_force_gradient_between: the sums of set a over set b and of b over a
+    (Sec. 2.2, the inter-level terms) from one two-set symmetric sweep, against the oracle's two
+    directed sums, on every particle of both sets."""
+    n = 12000
+    d = _king(n, 31)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    if kind == "list":
+        rng = np.random.default_rng(32)
+        A = np.sort(rng.choice(n, 7001, replace=False))
+        B = np.setdiff1d(np.arange(n), A)
+        Ag, Bg = A, B
+    else:
+        A, B = np.arange(0, 5003), np.arange(5003, n)
+        Ag, Bg = bf.ParticleSet.range(0, 5003), bf.ParticleSet.range(5003, n - 5003)
+    if op == "forces":
+        out = ctx.forces_between(Pd, Ag, Bg, prec="mixed")
+        ref_a, ref_b = oracle.forces(P, A, B), oracle.forces(P, B, A)
+    else:
+        a = oracle.forces(P)
+        acc = [torch.as_tensor(np.ascontiguousarray(a[:, k]), device="cuda") for k in range(3)]
+        out = ctx.force_gradient_between(Pd, acc, Ag, Bg, prec="mixed")
+        ref_a, ref_b = oracle.gradient(P, a, A, B), oracle.gradient(P, a, B, A)
+    assert ctx.last_pass_config()[0] == "between"
+    f = ctx.read_flags(clear=True)
+    assert f & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0, f"device flags {f:#x}"
+    for idx, ref in ((A, ref_a), (B, ref_b)):
+        rms, mx = stats(rel_errors(gather(out, idx), ref))
+        assert rms <= RMS_TOL and mx <= MAX_TOL, (rms, mx)
+
+
+def test_between_fallbacks_and_checks(ctx):
+    """The two-set entry with the directed sweep forced, and with sets too small for the sorted
+    mode (two directed passes either way), gives the same sums; overlapping ranges are refused."""
+    n = 3000
+    d = _king(n, 33)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    A, B = np.arange(0, 40), np.arange(40, n)
+    out = ctx.forces_between(Pd, bf.ParticleSet.range(0, 40), bf.ParticleSet.range(40, n - 40), prec="mixed")
+    assert ctx.last_pass_config()[0] != "between"
+    for idx, ref in ((A, oracle.forces(P, A, B)), (B, oracle.forces(P, B, A))):
+        rms, mx = stats(rel_errors(gather(out, idx), ref))
+        assert rms <= RMS_TOL and mx <= MAX_TOL, (rms, mx)
+    try:
+        ctx.set_spatial_sort(forces=True, gradient=True, any_size=True, symmetric=False)
+        A, B = np.arange(0, 1500), np.arange(1500, n)
+        out = ctx.forces_between(Pd, bf.ParticleSet.range(0, 1500), bf.ParticleSet.range(1500, 1500), prec="mixed")
+        assert ctx.last_pass_config()[0] == "sorted"
+        for idx, ref in ((A, oracle.forces(P, A, B)), (B, oracle.forces(P, B, A))):
+            rms, mx = stats(rel_errors(gather(out, idx), ref))
+            assert rms <= RMS_TOL and mx <= MAX_TOL, (rms, mx)
+    finally:
+        ctx.set_spatial_sort(forces=True, gradient=True, any_size=True)
+    with pytest.raises(bf.BifrostError):
+        ctx.forces_between(Pd, bf.ParticleSet.range(0, 100), bf.ParticleSet.range(50, 100))
