@@ -179,6 +179,25 @@ __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* p
     }
 }
 
+// Small source sets: one workgroup per queued target (its 256 threads split the sources, a
+// fixed-order reduction in LDS), results written directly: one launch, no partials.
+template <int OP>
+__global__ __launch_bounds__(256) void k_fixup_each(const PairArgs a) {
+    const int count = min(*a.fix_count, a.tgt.count);
+    if (a.pass_stats && blockIdx.x == 0 && threadIdx.x == 0) a.pass_stats[0] = (unsigned long long)count;
+    for (int e = blockIdx.x; e < count; e += gridDim.x) {  // uniform over the workgroup
+        const int pi = particle_of(a.tgt, a.fix_list[e], a.P.n, a.flags);
+        double v[3];
+        fix_one<OP>(a.P, a.src, a.sub, pi, a.G, a.eps2, a.flags, v);
+        if (threadIdx.x == 0) {
+            a.o0[pi] = v[0];
+            a.o1[pi] = v[1];
+            a.o2[pi] = v[2];
+        }
+        __syncthreads();  // fix_one's LDS is reused by the next target
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part, int base) {
     if (base == 0 && a.pass_stats && blockIdx.x == 0 && threadIdx.x == 0)
         a.pass_stats[0] = (unsigned long long)min(*a.fix_count, a.tgt.count);
@@ -326,6 +345,12 @@ hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hip
     const int nt = a.tgt.count;
     if (nt <= 0) return hipSuccess;
     if (op != OP_ACC && op != OP_GRAD) return hipErrorInvalidValue;
+    if (a.src.count <= kFixEachSources) {
+        const int g = std::min(nt, 8 * num_cu);
+        if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_each<OP_ACC>, dim3(g), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(k_fixup_each<OP_GRAD>, dim3(g), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     for (int base = 0; base < nt; base += kFixTiled) {  // rounds past the queue's end exit at once
         const int len = std::min(nt - base, kFixTiled);
         const int g1 = std::min((len + 255) / 256 * kFixChunks, 8 * num_cu);
