@@ -90,6 +90,11 @@ typedef struct bf_ctx bf_ctx;
 BF_API int bf_create(bf_ctx **ctx, int device, void *hip_stream);
 /* Destroy a context (synchronising) and free its scratch.  NULL is accepted. */
 BF_API int bf_destroy(bf_ctx *ctx);
+/* Synchronising.  Free the context's scratch buffers (they grow to the largest pass run; the
+ * pair-symmetric sweep's partials take 8.6 GB at n = 2^20) and report the bytes freed in
+ * *freed (may be NULL).  Later calls allocate again as needed.  Captured graphs keep their own
+ * buffers. */
+BF_API int bf_release_scratch(bf_ctx *ctx, size_t *freed);
 /* Rebind the context to another stream of the same device. */
 BF_API int bf_set_stream(bf_ctx *ctx, void *hip_stream);
 /* Static string for a bf_status value. */

@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH):
         "bf_last_pass_stats": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
         "bf_forces_between": [_vp, P, S, S, _d, _d, _int, _d, _vp, _vp, _vp],
         "bf_force_gradient_between": [_vp, P, S, S, _vp, _vp, _vp, _d, _d, _int, _d, _vp, _vp, _vp],
+        "bf_release_scratch": [_vp, ctypes.POINTER(ctypes.c_size_t)],
         "bf_last_pass_config": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
                                 ctypes.POINTER(_int)],
         "bf_kernel_times": [_vp, _int, ctypes.POINTER(ctypes.c_float), _int, ctypes.POINTER(_int)],
@@ -488,6 +489,12 @@ class Context:
         _check("bf_last_pass_stats", _lib.bf_last_pass_stats(self._h, ctypes.byref(f), ctypes.byref(nn),
                                                              ctypes.byref(nf)))
         return f.value, nn.value, nf.value
+
+    def release_scratch(self) -> int:
+        """Free the context's scratch buffers; returns the bytes freed."""
+        freed = ctypes.c_size_t(0)
+        _check("bf_release_scratch", _lib.bf_release_scratch(self._h, ctypes.byref(freed)))
+        return freed.value
 
     def last_pass_config(self):
         """(kind, k_per_lane, waves, split) of the most recent pass; kind is "unsorted", "sorted"

@@ -156,6 +156,14 @@ size_t between_scratch_bytes(int64_t n_rows, int64_t n_cols, int chunks);
 // fixed order, writes both sets' particle-indexed outputs and queues ill-conditioned targets
 hipError_t launch_between_reduce(int op, const PairArgs& a_rows, const PairArgs& a_cols, const SymArgs& g,
                                  hipStream_t st);
+// FP64 one-set sweep: the set in its own order, FP64 pack (launch_pack, FP64) as columns and
+// rows, FP64 row sums [chunks][3][n_pad] and partials [n_blocks/2 + 1][3][n_pad] (part holds
+// doubles), no fix-up
+size_t sym64_scratch_bytes(int64_t n, int chunks);
+size_t sym64_own_bytes(int64_t n, int chunks);
+int sym64_blocks_per_cu(int op);
+hipError_t launch_pairs_sym64(int op, const SymArgs& g, double eps2t, hipStream_t st);
+hipError_t launch_sym_reduce64(int op, const PairArgs& a, const SymArgs& g, hipStream_t st);
 // resident workgroups per CU, wavefronts per workgroup and row tiles per wavefront of the
 // symmetric kernel of op
 int sym_blocks_per_cu(int op);

@@ -124,6 +124,22 @@ int sym_chunks(bf_ctx* ctx, int op, int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb / 2 + 1, (want + nb - 1) / nb));
 }
 
+// FP64 passes over one set: the symmetric sweep in the set's own order (no sort needed)
+bool use_symmetric64(bf_ctx* ctx, int op, int prec, const bf_set* tg, const bf_set* sr) {
+    const int64_t n = sr->count;
+    return prec == BF_PREC_FP64 && (op == OP_ACC || op == OP_GRAD) && (ctx->sort_ops >> op & 1) &&
+           !(ctx->sort_ops & BF_SORT_DIRECTED) && same_set(tg, sr) && ctx->sub == nullptr && !ctx->capturing &&
+           !ctx->dry && n >= 64 &&
+           ((ctx->sort_ops & BF_SORT_ANY_SIZE) || (n >= kSortMinSources && n * n >= kSortMinPairs));
+}
+
+int sym64_chunks(bf_ctx* ctx, int op, int64_t n) {
+    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
+    const int64_t want = 2 * (int64_t)ctx->num_cu * sym64_blocks_per_cu(op);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb / 2 + 1, (want + nb - 1) / nb));
+}
+
 bool use_symmetric(bf_ctx* ctx, int op, bool sorted, const bf_set* tg, const bf_set* sr) {
     return sorted && !(ctx->sort_ops & BF_SORT_DIRECTED) && same_set(tg, sr) &&
            sym_scratch_bytes(tg->count, sym_chunks(ctx, op, tg->count)) <= kSymMaxScratch;
@@ -206,7 +222,17 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
             sym = false;
         }
     }
-    if (sym) p.split = 1;  // no source split: the symmetric sweep has its own partials
+    bool sym64 = use_symmetric64(ctx, op, prec, tg, sr);
+    int sym64_shares = 0;
+    if (sym64) {
+        sym64_shares = sym64_chunks(ctx, op, sr->count);
+        const size_t need = sym64_scratch_bytes(sr->count, sym64_shares);
+        if (need > kSymMaxScratch || ensure(&ctx->scratch9, &ctx->scratch9_bytes, need, ctx->stream)) {
+            g_err.clear();
+            sym64 = false;
+        }
+    }
+    if (sym || sym64) p.split = 1;  // no source split: the symmetric sweeps have their own partials
     PairArgs a{};
     a.P = M;
     a.tgt = devset(tg);
@@ -314,6 +340,19 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     } else if (sr->count > 0) {
         a.pack = ctx->scratch2;
         BF_HIP(launch_pack(op, prec, a, ctx->stream));
+        if (sym64) {  // rows and columns: the FP64 pack in the set's order
+            const int64_t ns = sr->count, ntiles = (ns + 63) / 64;
+            g.near_pack = g.row_pack = a.pack;
+            g.n = g.n_rows = (int32_t)ns;
+            g.n_tiles = g.n_row_tiles = (int32_t)ntiles;
+            g.n_blocks = (int32_t)((ntiles + kSymBlockTiles - 1) / kSymBlockTiles);
+            g.n_pad = g.n_row_pad = (int32_t)(64 * ntiles);
+            g.between = 0;
+            g.n_chunks = sym64_shares;
+            g.chunk_len = (g.n_blocks / 2 + 1 + sym64_shares - 1) / sym64_shares;
+            g.own = static_cast<double*>(ctx->scratch9);
+            g.part = reinterpret_cast<float*>(static_cast<char*>(ctx->scratch9) + sym64_own_bytes(ns, sym64_shares));
+        }
     }
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     const bool timed = ctx->timing && !ctx->capturing;
@@ -328,17 +367,19 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         BF_HIP(hipEventRecord(ev.first, ctx->stream));
     }
     if (sym) BF_HIP(launch_pairs_sym(op, g, ctx->stream));
+    else if (sym64) BF_HIP(launch_pairs_sym64(op, g, eps2 + 1e-150 /* the FP64 kernels' tiny */, ctx->stream));
     else if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
     else BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
-    ctx->last_kind = sym ? BF_PASS_SYMMETRIC : sorted ? BF_PASS_SORTED : BF_PASS_UNSORTED;
-    ctx->last_k = sym ? sym_rows_per_wave(op) : p.cfg.k;
-    ctx->last_waves = sym ? sym_waves(op) : p.cfg.waves;
-    ctx->last_split = sym ? g.n_chunks : p.split;
+    ctx->last_kind = sym || sym64 ? BF_PASS_SYMMETRIC : sorted ? BF_PASS_SORTED : BF_PASS_UNSORTED;
+    ctx->last_k = sym ? sym_rows_per_wave(op) : sym64 ? 4 : p.cfg.k;
+    ctx->last_waves = sym ? sym_waves(op) : sym64 ? 4 : p.cfg.waves;
+    ctx->last_split = sym || sym64 ? g.n_chunks : p.split;
     if (timed) {
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
     }
     if (sym) BF_HIP(launch_sym_reduce(op, a, g, ctx->stream));
+    else if (sym64) BF_HIP(launch_sym_reduce64(op, a, g, ctx->stream));
     else if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
     if (fix) BF_HIP(launch_fixup(op, a, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
     return BF_OK;
@@ -607,6 +648,25 @@ BF_API int bf_destroy(bf_ctx* c) {
     if (c->d_stats) hipFree(c->d_stats);
     if (c->h_flags) hipHostFree(c->h_flags);
     delete c;
+    return BF_OK;
+}
+
+BF_API int bf_release_scratch(bf_ctx* c, size_t* freed) {
+    if (int rc = check_ctx(c)) return rc;
+    BF_HIP(hipStreamSynchronize(c->stream));
+    size_t total = 0;
+    void** bufs[] = {&c->scratch, &c->scratch2, &c->scratch3, &c->scratch4, &c->scratch5,
+                     &c->scratch6, &c->scratch7, &c->scratch8, &c->scratch9, &c->scratch10};
+    size_t* sizes[] = {&c->scratch_bytes, &c->scratch2_bytes, &c->scratch3_bytes, &c->scratch4_bytes,
+                       &c->scratch5_bytes, &c->scratch6_bytes, &c->scratch7_bytes, &c->scratch8_bytes,
+                       &c->scratch9_bytes, &c->scratch10_bytes};
+    for (int i = 0; i < 10; ++i) {
+        if (*bufs[i]) BF_HIP(hipFree(*bufs[i]));
+        *bufs[i] = nullptr;
+        total += *sizes[i];
+        *sizes[i] = 0;
+    }
+    if (freed) *freed = total;
     return BF_OK;
 }
 

@@ -507,6 +507,247 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const PairArgs a, const SymA
     write_result<Op>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), v);
 }
 
+// ---- FP64 -----------------------------------------------------------------------------------
+// The same walk with every pair in FP64: the set in its own order (no near / far split, so no
+// sort), the columns staged from the FP64 pack (double4 (x, y, z, G m) [+ (ax, ay, az, 0)]),
+// FP64 row sums, FP64 column accumulators moved by two DPP moves each, FP64 partials (3
+// components, no magnitude estimate: the FP64 pass has no fix-up).
+
+__device__ __forceinline__ double rol1d(double x) {
+    const int2 v = __builtin_bit_cast(int2, x);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_mov_dpp(v.x, 0x134, 0xf, 0xf, true),
+                                                __builtin_amdgcn_mov_dpp(v.y, 0x134, 0xf, 0xf, true)));
+}
+
+struct Sym64Acc {
+    static constexpr int kPlanes = 2;  // (x, y), (z, G m)
+    struct Row { double x, y, z, gm; };
+    __device__ static void load_row(const SymArgs& g, int s, bool live, Row& t) {
+        if (live) {
+            const double4 p = static_cast<const double4*>(g.row_pack)[s];
+            t.x = p.x; t.y = p.y; t.z = p.z; t.gm = p.w;
+        } else {
+            t.x = t.y = t.z = kFarAway; t.gm = 0.0;
+        }
+    }
+    __device__ static uint4 stage_elem(const SymArgs& g, int plane, int s, bool ok) {
+        if (ok) return static_cast<const uint4*>(g.near_pack)[2 * s + plane];
+        return __builtin_bit_cast(uint4, plane == 0 ? make_double2(kFarAway, kFarAway) : make_double2(kFarAway, 0.0));
+    }
+    template <bool MASK>
+    __device__ static void pair(double (&r)[3], double (&c)[3], const Row& t, const uint4* pl, int j, double eps2t,
+                                bool ok) {
+        const double2 xy = __builtin_bit_cast(double2, pl[j]);
+        const double2 zw = __builtin_bit_cast(double2, pl[kPlaneLen + j]);
+        const double dx = xy.x - t.x, dy = xy.y - t.y, dz = zw.x - t.z;
+        const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2t)));
+        double ri = rsqrt64(r2);
+        if (MASK) ri = ok ? ri : 0.0;
+        const double ri3 = (ri * ri) * ri;
+        const double wj = zw.y * ri3, wi = t.gm * ri3;
+        r[0] = __builtin_fma(wj, dx, r[0]);
+        r[1] = __builtin_fma(wj, dy, r[1]);
+        r[2] = __builtin_fma(wj, dz, r[2]);
+        c[0] = wi * dx; c[1] = wi * dy; c[2] = wi * dz;
+    }
+};
+
+struct Sym64Grad {
+    static constexpr int kPlanes = 4;  // (x, y), (z, G m), (ax, ay), (az, 0)
+    struct Row { double x, y, z, gm, ax, ay, az; };
+    __device__ static void load_row(const SymArgs& g, int s, bool live, Row& t) {
+        if (live) {
+            const double4* pk = static_cast<const double4*>(g.row_pack);
+            const double4 p = pk[2 * s], a = pk[2 * s + 1];
+            t.x = p.x; t.y = p.y; t.z = p.z; t.gm = p.w;
+            t.ax = a.x; t.ay = a.y; t.az = a.z;
+        } else {
+            t.x = t.y = t.z = kFarAway; t.gm = 0.0;
+            t.ax = t.ay = t.az = 0.0;
+        }
+    }
+    __device__ static uint4 stage_elem(const SymArgs& g, int plane, int s, bool ok) {
+        if (ok) return static_cast<const uint4*>(g.near_pack)[4 * s + plane];
+        if (plane == 0) return __builtin_bit_cast(uint4, make_double2(kFarAway, kFarAway));
+        if (plane == 1) return __builtin_bit_cast(uint4, make_double2(kFarAway, 0.0));
+        return make_uint4(0u, 0u, 0u, 0u);
+    }
+    template <bool MASK>
+    __device__ static void pair(double (&r)[3], double (&c)[3], const Row& t, const uint4* pl, int j, double eps2t,
+                                bool ok) {
+        const double2 xy = __builtin_bit_cast(double2, pl[j]);
+        const double2 zw = __builtin_bit_cast(double2, pl[kPlaneLen + j]);
+        const double2 axy = __builtin_bit_cast(double2, pl[2 * kPlaneLen + j]);
+        const double2 az0 = __builtin_bit_cast(double2, pl[3 * kPlaneLen + j]);
+        const double dx = xy.x - t.x, dy = xy.y - t.y, dz = zw.x - t.z;
+        const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2t)));
+        double ri = rsqrt64(r2);
+        if (MASK) ri = ok ? ri : 0.0;
+        const double ri2 = ri * ri;
+        const double ri3 = ri2 * ri;
+        const double dax = axy.x - t.ax, day = axy.y - t.ay, daz = az0.x - t.az;
+        const double q = __builtin_fma(dax, dx, __builtin_fma(day, dy, daz * dz));
+        const double sq = (-3.0 * q) * ri2;
+        const double ux = __builtin_fma(sq, dx, dax), uy = __builtin_fma(sq, dy, day), uz = __builtin_fma(sq, dz, daz);
+        const double wj = zw.y * ri3, wi = t.gm * ri3;
+        r[0] = __builtin_fma(wj, ux, r[0]);
+        r[1] = __builtin_fma(wj, uy, r[1]);
+        r[2] = __builtin_fma(wj, uz, r[2]);
+        c[0] = wi * ux; c[1] = wi * uy; c[2] = wi * uz;
+    }
+};
+
+template <class S, int W, int R>
+__global__ __launch_bounds__(64 * W) void k_pairs_sym64(const SymArgs g, double eps2t) {
+    static_assert(W * R == kSymBlockTiles, "a workgroup covers one block");
+    constexpr int NPL = S::kPlanes;
+    __shared__ uint4 colbuf[2][NPL * kPlaneLen];
+    __shared__ double xch[2][W][3][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wg = blockIdx.x % g.n_blocks, chunk = blockIdx.x / g.n_blocks;
+    const int d0 = chunk * g.chunk_len, d1 = d0 + g.chunk_len;
+    const int rbase = wg * (W * R) + wave * R;
+    typename S::Row row[R];
+    bool tile_live[R];
+    int rs[R];
+    double own[R][3];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        tile_live[r] = rbase + r < g.n_row_tiles;
+        rs[r] = (rbase + r) * 64 + lane;
+        S::load_row(g, rs[r], tile_live[r] && rs[r] < g.n_rows, row[r]);
+        own[r][0] = own[r][1] = own[r][2] = 0.0;
+    }
+    constexpr int SPT = (NPL + W - 1) / W;
+    const int st_k = threadIdx.x & 63;
+    TileWalk cur, pre;
+    cur.d = d0;
+    cur.d_end = d1;
+    cur.next(g, wg);
+    pre = cur;
+    pre.next(g, wg);
+    uint4 held[SPT];
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+        const int pl = wave + W * u;
+        if (pl < NPL && cur.ct >= 0) {
+            const int s = cur.ct * 64 + st_k;
+            const uint4 e = S::stage_elem(g, pl, s, s < g.n);
+            colbuf[0][pl * kPlaneLen + st_k] = e;
+            colbuf[0][pl * kPlaneLen + st_k + 64] = e;
+        }
+        held[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (pl < NPL && pre.ct >= 0) {
+            const int s = pre.ct * 64 + st_k;
+            held[u] = S::stage_elem(g, pl, s, s < g.n);
+        }
+    }
+    __syncthreads();
+    for (int i = 0; cur.ct >= 0; ++i) {
+        const int buf = i & 1;
+        const int ct = cur.ct;
+        const uint4* pls = colbuf[buf];
+        int mode[R];
+        bool any = false, masked = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int rt = rbase + r;
+            mode[r] = !tile_live[r] ? kSkip : (cur.d > 0 || ct > rt) ? kFull : ct == rt ? kDiag : kSkip;
+            any = any || mode[r] != kSkip;
+            masked = masked || mode[r] != kFull;
+        }
+        double ja[3] = {0.0, 0.0, 0.0};  // accumulator of column (lane + k) mod 64 after step k
+        if (any) {
+            if (masked) {
+                for (int k = 0; k < 64; ++k) {
+                    double cs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        double cv[3];
+                        S::template pair<true>(own[r], cv, row[r], pls, lane + k, eps2t, counts(mode[r], lane, k));
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) cs[q] += cv[q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) ja[q] = rol1d(ja[q]) + cs[q];
+                }
+            } else {
+#pragma unroll 2
+                for (int k = 0; k < 64; ++k) {
+                    double cs[3];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        double cv[3];
+                        S::template pair<false>(own[r], cv, row[r], pls, lane + k, eps2t, true);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) cs[q] = r == 0 ? cv[q] : cs[q] + cv[q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) ja[q] = rol1d(ja[q]) + cs[q];
+                }
+            }
+        }
+        const int slot = any ? (lane + 63) & 63 : lane;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) xch[buf][wave][q][slot] = ja[q];
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int pl = wave + W * u;
+            if (pl < NPL && pre.ct >= 0) {
+                colbuf[buf ^ 1][pl * kPlaneLen + st_k] = held[u];
+                colbuf[buf ^ 1][pl * kPlaneLen + st_k + 64] = held[u];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 3 * 64) {
+            const int q = threadIdx.x >> 6, k = threadIdx.x & 63;
+            double s = 0.0;
+#pragma unroll
+            for (int v = 0; v < W; ++v) s += xch[buf][v][q][k];
+            const int col = ct * 64 + k;
+            if (col < g.n) reinterpret_cast<double*>(g.part)[((size_t)cur.d * 3 + q) * g.n_pad + col] = -s;
+        }
+        cur = pre;
+        pre.next(g, wg);
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int pl = wave + W * u;
+            if (pl < NPL && pre.ct >= 0) {
+                const int s = pre.ct * 64 + st_k;
+                held[u] = S::stage_elem(g, pl, s, s < g.n);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (tile_live[r] && rs[r] < g.n_rows) {
+            double* o = g.own + (size_t)chunk * 3 * g.n_row_pad;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) o[(size_t)q * g.n_row_pad + rs[r]] = own[r][q];
+        }
+    }
+}
+
+template <class Op>
+__global__ __launch_bounds__(256) void k_sym_reduce64(const PairArgs a, const SymArgs g) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= g.n) return;
+    const int b = (s >> 6) / kSymBlockTiles;
+    const int nb = g.n_blocks, D = nb / 2;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < g.n_chunks; ++c) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] += g.own[((size_t)c * 3 + q) * g.n_row_pad + s];
+    }
+    const double* part = reinterpret_cast<const double*>(g.part);
+    for (int d = 0; d <= D; ++d) {
+        if (d > 0 && 2 * d == nb && b < d) continue;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] += part[((size_t)d * 3 + q) * g.n_pad + s];
+    }
+    write_result<Op>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), v);
+}
+
 // Two sets: threads [0, n_rows) finish the rows (sums over the shares), threads [n_rows,
 // n_rows + n) the columns (sums over the row blocks, with the opposite sign for the terms).
 template <class Op>
@@ -579,6 +820,46 @@ hipError_t launch_pairs_sym(int op, const SymArgs& g, hipStream_t st) {
         hipLaunchKernelGGL((k_pairs_sym<SymAcc, kAccWaves, kAccRows>), grid, dim3(64 * kAccWaves), 0, st, g);
     else if (op == OP_GRAD)
         hipLaunchKernelGGL((k_pairs_sym<SymGrad, kGradWaves, kGradRows>), grid, dim3(64 * kGradWaves), 0, st, g);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// FP64: 4 wavefronts of 4 row tiles for both passes
+constexpr int kSym64Waves = 4, kSym64Rows = 4;
+
+size_t sym64_scratch_bytes(int64_t n, int chunks) {
+    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
+    const size_t own = ((size_t)chunks * 3 * 64 * n_tiles * sizeof(double) + 255) & ~size_t(255);
+    return own + (size_t)(nb / 2 + 1) * 3 * 64 * n_tiles * sizeof(double);
+}
+size_t sym64_own_bytes(int64_t n, int chunks) {
+    return ((size_t)chunks * 3 * 64 * ((n + 63) / 64) * sizeof(double) + 255) & ~size_t(255);
+}
+int sym64_blocks_per_cu(int op) {
+    const void* f = op == OP_ACC ? reinterpret_cast<const void*>(k_pairs_sym64<Sym64Acc, kSym64Waves, kSym64Rows>)
+                                 : reinterpret_cast<const void*>(k_pairs_sym64<Sym64Grad, kSym64Waves, kSym64Rows>);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * kSym64Waves, 0) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_pairs_sym64(int op, const SymArgs& g, double eps2t, hipStream_t st) {
+    if (g.n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)g.n_blocks * (unsigned)g.n_chunks);
+    if (op == OP_ACC)
+        hipLaunchKernelGGL((k_pairs_sym64<Sym64Acc, kSym64Waves, kSym64Rows>), grid, dim3(64 * kSym64Waves), 0, st, g, eps2t);
+    else if (op == OP_GRAD)
+        hipLaunchKernelGGL((k_pairs_sym64<Sym64Grad, kSym64Waves, kSym64Rows>), grid, dim3(64 * kSym64Waves), 0, st, g, eps2t);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_reduce64(int op, const PairArgs& a, const SymArgs& g, hipStream_t st) {
+    if (g.n <= 0) return hipSuccess;
+    const dim3 grid((g.n + 255) / 256);
+    if (op == OP_ACC) hipLaunchKernelGGL(k_sym_reduce64<Acc64>, grid, dim3(256), 0, st, a, g);
+    else if (op == OP_GRAD) hipLaunchKernelGGL(k_sym_reduce64<Grad64>, grid, dim3(256), 0, st, a, g);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

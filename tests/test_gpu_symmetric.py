@@ -235,3 +235,42 @@ def test_between_fallbacks_and_checks(ctx):
         ctx.set_spatial_sort(forces=True, gradient=True, any_size=True)
     with pytest.raises(bf.BifrostError):
         ctx.forces_between(Pd, bf.ParticleSet.range(0, 100), bf.ParticleSet.range(50, 100))
+
+
+def test_release_scratch(ctx):
+    """The symmetric sweep's scratch is freed on request and allocated again by the next pass,
+    with the same results."""
+    n = 6000
+    d = _king(n, 41)
+    Pd = _dev(d)
+    a = ctx.forces(Pd, prec="mixed")
+    assert ctx.release_scratch() > 0
+    assert ctx.release_scratch() == 0
+    b = ctx.forces(Pd, prec="mixed")
+    assert ctx.last_pass_config()[0] == "symmetric"
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("n", [1100, 17000, 20000])
+@pytest.mark.parametrize("op", ["forces", "gradient"])
+@pytest.mark.parametrize("eps2", [0.0, 1e-6])
+def test_symmetric_fp64_parity(ctx, n, op, eps2):
+    """FP64 passes over one set take the symmetric sweep in the set's own order: every target
+    within 1e-12 of the oracle's magnitude sum (the FP64 tolerance), bitwise repeatable."""
+    d = _king(n, 50 + n % 7)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    if op == "forces":
+        ref, mag, _ = oracle.forces(P, eps2=eps2, return_mag=True)
+        run = lambda: ctx.forces(Pd, eps2=eps2, prec="fp64")  # noqa: E731
+    else:
+        a = oracle.forces(P, eps2=eps2)
+        ref, mag, _ = oracle.gradient(P, a, eps2=eps2, return_mag=True)
+        acc = [torch.as_tensor(np.ascontiguousarray(a[:, k]), device="cuda") for k in range(3)]
+        run = lambda: ctx.force_gradient(Pd, acc, eps2=eps2, prec="fp64")  # noqa: E731
+    out = run()
+    assert ctx.last_pass_config()[0] == "symmetric"
+    again = run()
+    assert all(torch.equal(x, y) for x, y in zip(out, again))
+    got = gather(out, np.arange(n))
+    assert np.all(np.linalg.norm(got - ref, axis=1) <= 1e-12 * mag)
+    assert ctx.read_flags(clear=True) & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
