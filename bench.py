@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--rfb-variant", type=float, default=1e-3,
                     help="also time the sweep with this re-evaluation radius (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-single-seconds", type=float, default=5.0,
+                    help="target time of a one-thread oracle sample (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", type=int, default=256, help="targets sampled for the error check")
     ap.add_argument("--spatial-sort", default="default", choices=["default", "off", "acc", "grad", "both", "directed"],
@@ -419,6 +421,23 @@ def main():
         cpu = {"value": k * (n - 1) / tc, "unit": "pair interactions/s", "cores": nthreads, "kind": "oracle",
                "sample": f"{k} random targets x all {n} sources, acceleration + force-gradient passes, FP64, "
                          f"{tc:.1f} s"}
+        if args.cpu_single_seconds > 0 and nthreads > 1:
+            # the same passes on one thread, in smaller batches, for a per-core figure
+            log("cpu oracle sample: batches of 64 targets on 1 thread ...")
+            oracle.set_num_threads(1)
+            try:
+                k1, t1c = 0, 0.0
+                while t1c < args.cpu_single_seconds and k1 < 4096:
+                    Ts = np.sort(rng.choice(n, 64, replace=False))
+                    t1 = time.perf_counter()
+                    oracle.forces(Po, Ts, None)
+                    oracle.gradient(Po, af, Ts, None)
+                    t1c += time.perf_counter() - t1
+                    k1 += Ts.size
+            finally:
+                oracle.set_num_threads(nthreads)
+            cpu["single_core"] = {"value": k1 * (n - 1) / t1c, "cores": 1,
+                                  "sample": f"{k1} random targets x all {n} sources, {t1c:.1f} s"}
 
     rec = {
         "metric": "pair interactions/s (acc+force-gradient) at N=2^20, mixed vs FP64; rel. err",

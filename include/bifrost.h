@@ -252,7 +252,11 @@ BF_API int bf_level_partition(bf_ctx *ctx, const bf_set *set, int64_t n, const i
  * synchronises once; everything else is stream-ordered.  With prm->n_bh > 0 (PN1.0, Sec. 3.8,
  * FP64) every FSI cycle is wrapped in PN half-kicks over its own pairs (as bf_fsi_step) and
  * every level's cycle in PN half-kicks of tau/2 over its inter-level pairs with a listed
- * particle; the paper does not place the PN terms in the hierarchy, this is a reading. */
+ * particle; the paper does not place the PN terms in the hierarchy, this is a reading.
+ * Between two visits of a level no particle of that level or deeper moves, so the driver keeps
+ * the level's own accelerations after each FSI cycle and its inter-level accelerations after
+ * each visit, and the next visit starts from them instead of recomputing them (the result is
+ * the same bit for bit; the context holds 3n doubles per level that has both S and F). */
 BF_API int bf_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, const int32_t *level,
                            int kmax, double tau, const bf_fsi_params *prm);
 

@@ -289,6 +289,8 @@ struct bf_ctx {
     size_t scratch9_bytes = 0;
     void* scratch10 = nullptr;        // two-set symmetric sweep: FP64 stream of the row set
     size_t scratch10_bytes = 0;
+    void* scratch11 = nullptr;        // HHS driver: inter-level accelerations kept per level
+    size_t scratch11_bytes = 0;
     bool capturing = false;           // a graph capture is recording this context's work
     bool dry = false;                 // size scratch only, launch nothing (before a capture)
     unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass

@@ -644,6 +644,7 @@ BF_API int bf_destroy(bf_ctx* c) {
     if (c->scratch8) hipFree(c->scratch8);
     if (c->scratch9) hipFree(c->scratch9);
     if (c->scratch10) hipFree(c->scratch10);
+    if (c->scratch11) hipFree(c->scratch11);
     if (c->d_flags) hipFree(c->d_flags);
     if (c->d_stats) hipFree(c->d_stats);
     if (c->h_flags) hipHostFree(c->h_flags);
@@ -656,11 +657,11 @@ BF_API int bf_release_scratch(bf_ctx* c, size_t* freed) {
     BF_HIP(hipStreamSynchronize(c->stream));
     size_t total = 0;
     void** bufs[] = {&c->scratch, &c->scratch2, &c->scratch3, &c->scratch4, &c->scratch5,
-                     &c->scratch6, &c->scratch7, &c->scratch8, &c->scratch9, &c->scratch10};
+                     &c->scratch6, &c->scratch7, &c->scratch8, &c->scratch9, &c->scratch10, &c->scratch11};
     size_t* sizes[] = {&c->scratch_bytes, &c->scratch2_bytes, &c->scratch3_bytes, &c->scratch4_bytes,
                        &c->scratch5_bytes, &c->scratch6_bytes, &c->scratch7_bytes, &c->scratch8_bytes,
-                       &c->scratch9_bytes, &c->scratch10_bytes};
-    for (int i = 0; i < 10; ++i) {
+                       &c->scratch9_bytes, &c->scratch10_bytes, &c->scratch11_bytes};
+    for (int i = 0; i < 11; ++i) {
         if (*bufs[i]) BF_HIP(hipFree(*bufs[i]));
         *bufs[i] = nullptr;
         total += *sizes[i];
@@ -1082,28 +1083,51 @@ struct HhsCtx {
     int64_t begin[65];  // begin[k] = first position of level k in `order`; begin[kmax+1] = total
     int kmax;
     double *asf, *gsf, *afsi, *gfsi;  // each 3n
+    // Fixed levels: results a later visit of the same level may take instead of recomputing.
+    // A particle drifts only in the FSI cycles of its own level, and those run only inside
+    // visits of its level, so between two visits of level k no particle of level >= k moves:
+    //  - afsi holds level k's own accelerations at its final positions after each of its FSI
+    //    cycles (the sets of the levels are disjoint), valid for the next one (a_ok[k]);
+    //  - asf_lv[k] (3n, particle-indexed) holds level k's inter-level accelerations; the last
+    //    ones of a visit equal the first ones of the next visit (il_ok[k]).
+    // Kernels are deterministic, so an interval with reuse equals one without, bit for bit.
+    double* asf_lv[64];
+    mutable bool a_ok[64], il_ok[64];
+    bool reuse = false;
 };
 
 bf_set segment(const HhsCtx& h, int64_t b, int64_t e) { return bf_set{h.order + b, (int32_t)(e - b), 0}; }
 
-// inter-level accelerations (Sec. 2.2): S <- F and F <- S into asf
-int interlevel_acc(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset) {
+// inter-level accelerations (Sec. 2.2): S <- F and F <- S into as (3n, particle-indexed)
+int interlevel_acc(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, double* as) {
     const int64_t n = h.S->n;
     const bf_fsi_params* p = h.prm;
-    return run_pairs_between(h.c, OP_ACC, p->prec, h.M, &Sset, &Fset, p->G, p->eps2, p->r_fb, h.asf, h.asf + n,
-                             h.asf + 2 * n);
+    return run_pairs_between(h.c, OP_ACC, p->prec, h.M, &Sset, &Fset, p->G, p->eps2, p->r_fb, as, as + n, as + 2 * n);
 }
 
 // One level of the HHS-FSI cycle (Sec. 2.2, Eq. hhsfsi-cycle) for slow set Sset and fast set
-// Fset (Bset = both, contiguous); `fast` advances F by tau/2 (the next level).
+// Fset (Bset = both, contiguous); `fast` advances F by tau/2 (the next level).  k is the fixed
+// level (results reused between its visits) or -1 (nothing reused).
 extern "C++" {
 template <class Fast>
-int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_set& Bset, double tau, Fast&& fast) {
+int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_set& Bset, double tau, int k,
+              Fast&& fast) {
     const int64_t n = h.S->n;
     bf_ctx* c = h.c;
     const bf_fsi_params* p = h.prm;
+    const bool keep = h.reuse && k >= 0;
+    double* const as = keep && h.asf_lv[k] ? h.asf_lv[k] : h.asf;
     auto fsi = [&](double dt) {
-        return fsi_impl(c, h.S, &Sset, dt, p, h.afsi, h.afsi + n, h.afsi + 2 * n, 0, h.gfsi, h.gfsi + n, h.gfsi + 2 * n);
+        const int fl = keep && h.a_ok[k] ? BF_A_VALID : 0;
+        const int r = fsi_impl(c, h.S, &Sset, dt, p, h.afsi, h.afsi + n, h.afsi + 2 * n, fl, h.gfsi, h.gfsi + n,
+                               h.gfsi + 2 * n);
+        if (keep) h.a_ok[k] = r == BF_OK;
+        return r;
+    };
+    auto inter = [&]() {
+        const int r = interlevel_acc(h, Sset, Fset, as);
+        if (keep) h.il_ok[k] = r == BF_OK && as != h.asf;
+        return r;
     };
     if (Fset.count == 0) return Sset.count ? fsi(tau) : BF_OK;  // no split at the last level
     if (Sset.count == 0) {
@@ -1129,23 +1153,24 @@ int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_
         return BF_OK;
     };
     if ((rc = pn_interlevel_half_kick())) return rc;
-    if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
-    if (go) BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
+    if (!(keep && h.il_ok[k]))
+        if ((rc = inter())) return rc;
+    if (go) BF_HIP(launch_kick(*h.S, dB, tau / 6.0, as, as + n, as + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
     if ((rc = fsi(0.5 * tau))) return rc;
     if ((rc = fast())) return rc;
-    if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
+    if ((rc = inter())) return rc;
     Masters Mg = h.M;
-    Mg.ax = h.asf; Mg.ay = h.asf + n; Mg.az = h.asf + 2 * n;
+    Mg.ax = as; Mg.ay = as + n; Mg.az = as + 2 * n;
     if ((rc = run_pairs_between(c, OP_GRAD, p->prec, Mg, &Sset, &Fset, p->G, p->eps2, p->r_fb, h.gsf, h.gsf + n,
                                 h.gsf + 2 * n)))
         return rc;
     if (go)
-        BF_HIP(launch_kick(*h.S, dB, 2.0 * tau / 3.0, h.asf, h.asf + n, h.asf + 2 * n, tau * tau / 24.0, h.gsf,
-                           h.gsf + n, h.gsf + 2 * n, c->d_flags, c->stream));
+        BF_HIP(launch_kick(*h.S, dB, 2.0 * tau / 3.0, as, as + n, as + 2 * n, tau * tau / 24.0, h.gsf, h.gsf + n,
+                           h.gsf + 2 * n, c->d_flags, c->stream));
     if ((rc = fast())) return rc;
     if ((rc = fsi(0.5 * tau))) return rc;
-    if ((rc = interlevel_acc(h, Sset, Fset))) return rc;
-    if (go) BF_HIP(launch_kick(*h.S, dB, tau / 6.0, h.asf, h.asf + n, h.asf + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
+    if ((rc = inter())) return rc;
+    if (go) BF_HIP(launch_kick(*h.S, dB, tau / 6.0, as, as + n, as + 2 * n, 0.0, nul, nul, nul, c->d_flags, c->stream));
     return pn_interlevel_half_kick();
 }
 }  // extern "C++"
@@ -1155,7 +1180,13 @@ int hhs_rec(const HhsCtx& h, int k, double tau) {
     const int64_t total = h.begin[h.kmax + 1];
     const int64_t sb = h.begin[k], fb = k < h.kmax ? h.begin[k + 1] : total;
     const bf_set Sset = segment(h, sb, fb), Fset = segment(h, fb, total), Bset = segment(h, sb, total);
-    return hhs_cycle(h, Sset, Fset, Bset, tau, [&]() { return hhs_rec(h, k + 1, 0.5 * tau); });
+    return hhs_cycle(h, Sset, Fset, Bset, tau, k, [&]() { return hhs_rec(h, k + 1, 0.5 * tau); });
+}
+
+// one fixed-level interval: nothing is valid at its start
+int hhs_run(const HhsCtx& h, double tau) {
+    for (int k = 0; k < 64; ++k) h.a_ok[k] = h.il_ok[k] = false;
+    return hhs_rec(h, 0, tau);
 }
 
 // adaptive levels: every level assigns time-steps to its particles P and splits them at the
@@ -1192,7 +1223,7 @@ int hhs_adapt(const HhsCtx& h, HhsAdapt& A, const bf_set& P, int k, double tau) 
     ++A.nodes;
     const bf_set Sset{mine, (int32_t)cnt[0], 0}, Fset{mine + cnt[0], (int32_t)cnt[1], 0};
     const bf_set Bset{mine, (int32_t)(cnt[0] + cnt[1]), 0};
-    return hhs_cycle(h, Sset, Fset, Bset, tau, [&]() { return hhs_adapt(h, A, Fset, k + 1, 0.5 * tau); });
+    return hhs_cycle(h, Sset, Fset, Bset, tau, -1, [&]() { return hhs_adapt(h, A, Fset, k + 1, 0.5 * tau); });
 }
 
 }  // namespace
@@ -1225,6 +1256,18 @@ static int hhs_setup(bf_ctx* c, const bf_state* S, const bf_set* set, const int3
         if (int rc = partition_impl(c, set, n, level, kmax, order, counts)) return rc;
     h.begin[0] = 0;
     for (int k = 0; k <= kmax; ++k) h.begin[k + 1] = h.begin[k] + counts[k];
+    // inter-level accelerations kept per level: one 3n array for each level with S and F
+    const int64_t total = h.begin[kmax + 1];
+    int nl = 0;
+    for (int k = 0; k < kmax; ++k) nl += counts[k] > 0 && h.begin[k + 1] < total;
+    if (nl > 0)
+        if (int rc = ensure(&c->scratch11, &c->scratch11_bytes, (size_t)nl * 3 * n * sizeof(double), c->stream))
+            return rc;
+    for (int k = 0, i = 0; k < 64; ++k) {
+        const bool split = k < kmax && counts[k] > 0 && h.begin[k + 1] < total;
+        h.asf_lv[k] = split ? static_cast<double*>(c->scratch11) + (size_t)(i++) * 3 * n : nullptr;
+    }
+    h.reuse = true;
     return BF_OK;
 }
 
@@ -1234,7 +1277,7 @@ BF_API int bf_hhs_interval(bf_ctx* c, const bf_state* S, const bf_set* set, cons
     HhsCtx h;
     if (int rc = hhs_setup(c, S, set, level, kmax, tau, prm, h)) return rc;
     if (set->count == 0) return BF_OK;
-    return hhs_rec(h, 0, tau);
+    return hhs_run(h, tau);
 }
 
 BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_set* set, const int32_t* level,
@@ -1246,18 +1289,20 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_
     if (prm && prm->n_bh != 0) return fail(BF_ERR_UNSUPPORTED, "a captured interval runs without PN1.0 (n_bh must be 0)");
     // The graph gets buffers of its own: park the context's while the interval is sized and
     // captured, then hand the new ones to the graph and give the context its own back.
-    void** slot[4] = {&c->scratch, &c->scratch2, &c->scratch7, &c->scratch8};
-    size_t* slot_bytes[4] = {&c->scratch_bytes, &c->scratch2_bytes, &c->scratch7_bytes, &c->scratch8_bytes};
-    void* parked[4];
-    size_t parked_bytes[4];
-    for (int i = 0; i < 4; ++i) {
+    constexpr int kSlots = 5;
+    void** slot[kSlots] = {&c->scratch, &c->scratch2, &c->scratch7, &c->scratch8, &c->scratch11};
+    size_t* slot_bytes[kSlots] = {&c->scratch_bytes, &c->scratch2_bytes, &c->scratch7_bytes, &c->scratch8_bytes,
+                                  &c->scratch11_bytes};
+    void* parked[kSlots];
+    size_t parked_bytes[kSlots];
+    for (int i = 0; i < kSlots; ++i) {
         parked[i] = *slot[i];
         parked_bytes[i] = *slot_bytes[i];
         *slot[i] = nullptr;
         *slot_bytes[i] = 0;
     }
     auto unpark = [&](bool free_new) {
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kSlots; ++i) {
             if (free_new && *slot[i]) hipFree(*slot[i]);
             *slot[i] = parked[i];
             *slot_bytes[i] = parked_bytes[i];
@@ -1273,7 +1318,7 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_
     }
     c->capturing = true;  // no sorted passes, no timing events inside the graph
     c->dry = true;
-    rc = hhs_rec(h, 0, tau);
+    rc = hhs_run(h, tau);
     c->dry = false;
     hipStream_t user = c->stream, cap = nullptr;
     hipGraph_t g = nullptr;
@@ -1286,7 +1331,7 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_
             rc = fail(BF_ERR_HIP, hipGetErrorString(e));
         } else {
             c->stream = cap;
-            rc = hhs_rec(h, 0, tau);
+            rc = hhs_run(h, tau);
             c->stream = user;
             e = hipStreamEndCapture(cap, &g);
             if (!rc && e != hipSuccess) rc = fail(BF_ERR_HIP, hipGetErrorString(e));
@@ -1310,7 +1355,7 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_
         unpark(true);
         return rc;
     }
-    for (int i = 0; i < 4; ++i) gr->owned[i] = *slot[i];
+    for (int i = 0; i < kSlots; ++i) gr->owned[i] = *slot[i];
     unpark(false);
     *graph_exec = gr;
     return BF_OK;

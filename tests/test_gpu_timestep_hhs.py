@@ -106,6 +106,66 @@ def test_hhs_interval_parity(ctx, prec):
     assert ctx.read_flags() & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
 
 
+def _hhs_composed(ctx, P, level, kmax, tau, prec):
+    """The fixed-level interval (the cycle documented for bf_hhs_interval) composed from the
+    public passes, every acceleration recomputed where the cycle needs it."""
+    n = P.n
+    order, counts = ctx.level_partition(None, n, level, kmax)
+    begin = np.concatenate([[0], np.cumsum(counts)]).astype(int)
+    total = int(begin[-1])
+    z3 = lambda: [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    asf, gsf, afsi = z3(), z3(), z3()
+
+    def rec(k, t):
+        sb, fb = int(begin[k]), int(begin[k + 1]) if k < kmax else total
+        S, F, B = order[sb:fb], order[fb:total], order[sb:total]
+        if F.numel() == 0:
+            if S.numel():
+                ctx.fsi_step(P, t, S, prec=prec, acc=afsi)
+            return
+        if S.numel() == 0:
+            rec(k + 1, 0.5 * t)
+            rec(k + 1, 0.5 * t)
+            return
+        ctx.forces_between(P, S, F, prec=prec, out=asf)
+        ctx.kick(P, B, t / 6.0, asf)
+        ctx.fsi_step(P, 0.5 * t, S, prec=prec, acc=afsi)
+        rec(k + 1, 0.5 * t)
+        ctx.forces_between(P, S, F, prec=prec, out=asf)
+        ctx.force_gradient_between(P, asf, S, F, prec=prec, out=gsf)
+        ctx.kick(P, B, 2.0 * t / 3.0, asf, h2=t * t / 24.0, grad=gsf)
+        rec(k + 1, 0.5 * t)
+        ctx.fsi_step(P, 0.5 * t, S, prec=prec, acc=afsi)
+        ctx.forces_between(P, S, F, prec=prec, out=asf)
+        ctx.kick(P, B, t / 6.0, asf)
+
+    rec(0, tau)
+
+
+@pytest.mark.parametrize("prec,mode", [("fp64", "default"), ("mixed", "default"), ("mixed", "sorted-any-size")])
+def test_hhs_interval_reuse_matches_composed_passes(ctx, prec, mode):
+    """The driver keeps each level's own and inter-level accelerations between its visits
+    instead of recomputing them; the interval must equal, bit for bit, the same cycle composed
+    from the public passes with every acceleration recomputed (mixed with the sorted mode at
+    every size: pair-symmetric and two-set sweeps on every level)."""
+    n, kmax, tau = 1500, 5, 1e-3
+    d = _cluster(n, 16)
+    level = np.random.default_rng(17).choice([0, 1, 2, 3, 5], size=n, p=[0.4, 0.25, 0.15, 0.1, 0.1])
+    lv = torch.as_tensor(level.astype(np.int32), device="cuda")
+    A, B = bf.Particles.from_numpy(d), bf.Particles.from_numpy(d)
+    try:
+        if mode == "sorted-any-size":
+            ctx.set_spatial_sort(forces=True, gradient=True, any_size=True)
+        for _ in range(2):
+            ctx.hhs_interval(A, lv, kmax, tau, prec=prec)
+            _hhs_composed(ctx, B, lv, kmax, tau, prec)
+            for k in ("x", "y", "z", "vx", "vy", "vz"):
+                assert torch.equal(getattr(A, k), getattr(B, k)), k
+    finally:
+        ctx.set_spatial_sort(forces=True, gradient=True)
+    assert ctx.read_flags() & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
+
+
 def test_hhs_single_level_matches_fsi(ctx):
     d = _cluster(700, 6)
     A, B = bf.Particles.from_numpy(d), bf.Particles.from_numpy(d)
