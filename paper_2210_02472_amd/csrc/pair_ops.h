@@ -694,14 +694,14 @@ __device__ __forceinline__ void write_result(const PairArgs& a, int slot, int pi
     }
 }
 
-// FP64 sum of all sources of `src` for target particle pi, one workgroup of 256 threads;
-// returns the result in thread 0.
+// FP64 sum over the sources q0 <= q < q1 of `src` for target particle pi, one workgroup of 256
+// threads (each takes every 256th source, then a fixed tree in LDS); the result in thread 0.
 template <int OP>
-__device__ __forceinline__ void fix_one(const Masters& P, const DevSet& src, const int32_t* sub, int pi, double G,
-                                        double eps2, uint32_t* flags, double* out3) {
+__device__ __forceinline__ void fix_range(const Masters& P, const DevSet& src, const int32_t* sub, int pi, double G,
+                                          double eps2, uint32_t* flags, int q0, int q1, double* out3) {
     __shared__ double red[3][256];
     double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
-    for (int q = threadIdx.x; q < src.count; q += 256) {
+    for (int q = q0 + (int)threadIdx.x; q < q1; q += 256) {
         const int pj = particle_of(src, q, P.n, flags);
         if (pj == pi || same_sub(sub, pi, pj)) continue;
         if constexpr (OP == OP_ACC) acc_pair64(P, pi, pj, G, eps2, sx, sy, sz, sm, flags);
@@ -719,6 +719,12 @@ __device__ __forceinline__ void fix_one(const Masters& P, const DevSet& src, con
         __syncthreads();
     }
     if (threadIdx.x == 0) { out3[0] = red[0][0]; out3[1] = red[1][0]; out3[2] = red[2][0]; }
+}
+
+template <int OP>
+__device__ __forceinline__ void fix_one(const Masters& P, const DevSet& src, const int32_t* sub, int pi, double G,
+                                        double eps2, uint32_t* flags, double* out3) {
+    fix_range<OP>(P, src, sub, pi, G, eps2, flags, 0, src.count, out3);
 }
 
 }  // namespace bf

@@ -107,14 +107,36 @@ __global__ void k_pass_begin(int32_t* fix_count, unsigned long long* stats) {
     if (threadIdx.x == 3 && fix_count) *fix_count = 0;
 }
 
-// The queue is worked in rounds of up to kFixTiled targets.  In a round a workgroup takes 256
-// queued targets (one per thread) against one source chunk staged through LDS and writes FP64
-// partial sums; k_fixup_reduce adds the chunks in order.  The number of chunks follows the
-// round's length (at most kFixChunks), so that short queues still fill the chip.  Rounds past
-// the queue's end exit at once.
-__device__ __forceinline__ int fix_chunks(int count) {
-    const int slabs = (count + 255) / 256;
-    return max(8, min(kFixChunks, 2048 / max(slabs, 1)));
+// The queue is worked in rounds of up to kFixTiled targets, each round split into source chunks
+// so that the grid (wgs workgroups) fills: a round of at least kFixWide targets gives each
+// thread one target and stages every source chunk through LDS for 256 targets at once; a shorter
+// round gives each workgroup one (target, chunk) item, its threads splitting the chunk.  Both
+// write FP64 partial sums per chunk, which k_fixup_reduce adds in chunk order.  The plan depends
+// only on the round's length, the source count and wgs, so the two kernels agree on it and the
+// sums are repeatable.  Rounds past the queue's end exit at once.
+constexpr int kFixWide = 64;
+
+struct FixPlan {
+    bool wide;   // thread per target (else workgroup per (target, chunk))
+    int nch;     // source chunks
+    int chunk;   // sources per chunk
+    int stride;  // partial-sum stride between chunk components
+};
+
+__device__ __forceinline__ FixPlan fix_plan(int count, int ns, int wgs) {
+    FixPlan f;
+    f.wide = count >= kFixWide;
+    if (f.wide) {
+        const int slabs = (count + 255) / 256;
+        f.stride = slabs * 256;
+        f.nch = max(1, min(wgs / slabs, (ns + 255) / 256));  // chunks of at least 256 sources
+    } else {
+        f.stride = kFixWide;
+        f.nch = max(1, min((wgs + count - 1) / count, (ns + 1023) / 1024));  // at least 1024
+    }
+    f.nch = min(f.nch, kFixChunks * kFixTiled / f.stride);  // the partial-sum buffer
+    f.chunk = (ns + f.nch - 1) / f.nch;
+    return f;
 }
 
 __device__ __forceinline__ int fix_round_count(const PairArgs& a, int base) {
@@ -122,13 +144,28 @@ __device__ __forceinline__ int fix_round_count(const PairArgs& a, int base) {
 }
 
 template <int OP>
-__global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* part, int base) {
+__global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* part, int base, int wgs) {
     const int count = fix_round_count(a, base);
     if (count <= 0) return;
-    const int nch = fix_chunks(count);
-    const int items = (count + 255) / 256 * nch;
     const int ns = a.src.count;
-    const int chunk = (ns + nch - 1) / nch;
+    const FixPlan f = fix_plan(count, ns, wgs);
+    if (!f.wide) {
+        for (int it = blockIdx.x; it < count * f.nch; it += gridDim.x) {  // uniform over the workgroup
+            const int e = it / f.nch, c = it % f.nch;
+            const int pi = particle_of(a.tgt, a.fix_list[base + e], a.P.n, a.flags);
+            const int q0 = c * f.chunk, q1 = min(ns, q0 + f.chunk);
+            double v[3];
+            fix_range<OP>(a.P, a.src, a.sub, pi, a.G, a.eps2, a.flags, q0, q1, v);
+            if (threadIdx.x == 0) {
+                part[((size_t)c * 3 + 0) * f.stride + e] = v[0];
+                part[((size_t)c * 3 + 1) * f.stride + e] = v[1];
+                part[((size_t)c * 3 + 2) * f.stride + e] = v[2];
+            }
+            __syncthreads();  // fix_range's LDS is reused by the next item
+        }
+        return;
+    }
+    const int nch = f.nch, items = (count + 255) / 256 * nch, chunk = f.chunk;
     __shared__ double4 sp[256];  // (x, y, z, G m)
     __shared__ double4 sa[256];  // (ax, ay, az, particle index)
     for (int it = blockIdx.x; it < items; it += gridDim.x) {
@@ -172,9 +209,9 @@ __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* p
             }
         }
         if (act) {
-            part[((size_t)c * 3 + 0) * kFixTiled + e] = sx;
-            part[((size_t)c * 3 + 1) * kFixTiled + e] = sy;
-            part[((size_t)c * 3 + 2) * kFixTiled + e] = sz;
+            part[((size_t)c * 3 + 0) * f.stride + e] = sx;
+            part[((size_t)c * 3 + 1) * f.stride + e] = sy;
+            part[((size_t)c * 3 + 2) * f.stride + e] = sz;
         }
     }
 }
@@ -198,20 +235,27 @@ __global__ __launch_bounds__(256) void k_fixup_each(const PairArgs a) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part, int base) {
+// one wavefront per queued target: lane l adds chunks l, l + 64, ... in order, then a fixed
+// butterfly over the lanes
+__global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part, int base, int wgs) {
     if (base == 0 && a.pass_stats && blockIdx.x == 0 && threadIdx.x == 0)
         a.pass_stats[0] = (unsigned long long)min(*a.fix_count, a.tgt.count);
     const int count = fix_round_count(a, base);
     if (count <= 0) return;
-    const int nch = fix_chunks(count);
-    for (int e = blockIdx.x * 256 + (int)threadIdx.x; e < count; e += gridDim.x * 256) {
+    const FixPlan f = fix_plan(count, a.src.count, wgs);
+    const int lane = threadIdx.x & 63;
+    for (int e = blockIdx.x * 4 + (int)(threadIdx.x >> 6); e < count; e += gridDim.x * 4) {  // uniform per wave
         double v[3] = {0.0, 0.0, 0.0};
-        for (int c = 0; c < nch; ++c)
-            for (int k = 0; k < 3; ++k) v[k] += part[((size_t)c * 3 + k) * kFixTiled + e];
-        const int pi = particle_of(a.tgt, a.fix_list[base + e], a.P.n, a.flags);
-        a.o0[pi] = v[0];
-        a.o1[pi] = v[1];
-        a.o2[pi] = v[2];
+        for (int c = lane; c < f.nch; c += 64)
+            for (int k = 0; k < 3; ++k) v[k] += part[((size_t)c * 3 + k) * f.stride + e];
+        for (int m = 32; m > 0; m >>= 1)
+            for (int k = 0; k < 3; ++k) v[k] += __shfl_xor(v[k], m, 64);
+        if (lane == 0) {
+            const int pi = particle_of(a.tgt, a.fix_list[base + e], a.P.n, a.flags);
+            a.o0[pi] = v[0];
+            a.o1[pi] = v[1];
+            a.o2[pi] = v[2];
+        }
     }
 }
 
@@ -351,13 +395,17 @@ hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hip
         else hipLaunchKernelGGL(k_fixup_each<OP_GRAD>, dim3(g), dim3(256), 0, st, a);
         return hipGetLastError();
     }
+    const int64_t ns = a.src.count;
     for (int base = 0; base < nt; base += kFixTiled) {  // rounds past the queue's end exit at once
         const int len = std::min(nt - base, kFixTiled);
-        const int g1 = std::min((len + 255) / 256 * kFixChunks, 8 * num_cu);
-        const int g2 = std::min((len + 255) / 256, 4 * num_cu);
-        if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_tiled<OP_ACC>, dim3(g1), dim3(256), 0, st, a, part, base);
-        else hipLaunchKernelGGL(k_fixup_tiled<OP_GRAD>, dim3(g1), dim3(256), 0, st, a, part, base);
-        hipLaunchKernelGGL(k_fixup_reduce, dim3(g2), dim3(256), 0, st, a, (const double*)part, base);
+        // enough workgroups for the longest possible round of either kind, at most 8 per CU
+        const int64_t most = std::max<int64_t>((int64_t)std::min(len, kFixWide - 1) * ((ns + 1023) / 1024),
+                                               (int64_t)((len + 255) / 256) * ((ns + 255) / 256));
+        const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>(most, 8 * num_cu));
+        const int g2 = std::min((len + 3) / 4, 8 * num_cu);
+        if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_tiled<OP_ACC>, dim3(g1), dim3(256), 0, st, a, part, base, g1);
+        else hipLaunchKernelGGL(k_fixup_tiled<OP_GRAD>, dim3(g1), dim3(256), 0, st, a, part, base, g1);
+        hipLaunchKernelGGL(k_fixup_reduce, dim3(g2), dim3(256), 0, st, a, (const double*)part, base, g1);
     }
     return hipGetLastError();
 }

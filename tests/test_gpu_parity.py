@@ -404,6 +404,38 @@ def test_fixups_are_rare(ctx, sort_mode, op):
     assert fixups <= (0.01 if op == "forces" else 0.05) * n, fixups
 
 
+@pytest.mark.parametrize("n_cancel", [10, 300])
+@pytest.mark.parametrize("op", ["forces", "gradient"])
+def test_fixup_of_cancelling_targets(ctx, n_cancel, op):
+    """Targets near the centre of a mirror-symmetric source cloud (20,000 sources: each point
+    and its reflection through the origin) feel sums that cancel to about 1e-3 of their
+    magnitude estimate, so every one is re-evaluated in FP64.  10 queued targets take the
+    fix-up's workgroup-per-target split, 300 its thread-per-target tiles; both must give the
+    oracle's FP64 sums to 1e-12 of the magnitude estimate."""
+    rng = np.random.default_rng(60 + n_cancel)
+    half = 10000
+    p = rng.normal(size=(half, 3))
+    pos = np.concatenate([p, -p, 1e-3 * rng.normal(size=(n_cancel, 3))])
+    n = pos.shape[0]
+    m = np.concatenate([np.full(2 * half, 1.0 / (2 * half)), np.full(n_cancel, 1e-12)])
+    vel = 0.1 * rng.normal(size=(n, 3))
+    d = {"x": pos[:, 0], "y": pos[:, 1], "z": pos[:, 2], "vx": vel[:, 0], "vy": vel[:, 1], "vz": vel[:, 2], "m": m}
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    tg = np.arange(2 * half, n)
+    if op == "forces":
+        ref, mag, _ = oracle.forces(P, tg, return_mag=True)
+        got = gather(ctx.forces(Pd, tg, prec="mixed"), tg)
+    else:
+        af = oracle.forces(P)
+        ref, mag, _ = oracle.gradient(P, af, tg, return_mag=True)
+        ad = [torch.as_tensor(af[:, k].copy(), device="cuda") for k in range(3)]
+        got = gather(ctx.force_gradient(Pd, ad, tg, prec="mixed"), tg)
+    fixups = ctx.last_pass_stats()[0]
+    assert fixups >= 0.9 * n_cancel, fixups
+    err = np.linalg.norm(got - ref, axis=1)
+    assert np.all(err <= 1e-12 * mag), (err / mag).max()
+
+
 def test_autotune_table_round_trip(ctx, tmp_path):
     """The autotuner times the kernel variants for one size bucket, stores the fastest in the
     context and in a JSON cache; a fresh context loading the cache plans the same variant, and
