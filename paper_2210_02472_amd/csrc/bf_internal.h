@@ -91,9 +91,10 @@ struct bf_graph {
     void* owned[8] = {};
 };
 
-// FP64 fix-up of queued targets; part: kFixChunks * 3 * kFixTiled doubles of scratch.  Up to
-// kFixEachSources sources one workgroup per target does it in a single launch.
-constexpr int kFixTiled = 32768, kFixChunks = 64, kFixEachSources = 8192;
+// FP64 fix-up of queued targets; part: kFixChunks * 3 * kFixTiled doubles of scratch.
+constexpr int kFixTiled = 32768, kFixChunks = 64;
+// source-chunk partials: more chunks than this are added by one wavefront per target
+constexpr int kReduceWaveSplit = 16;
 hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hipStream_t st);
 
 // Spatially sorted mixed acc/grad (spatial.hip).

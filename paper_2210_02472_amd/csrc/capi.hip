@@ -169,10 +169,14 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool so
     }
     if (!variant_exists(op, prec, c.k, c.waves, excl))
         return fail(BF_ERR_UNSUPPORTED, "no kernel variant for k=" + std::to_string(c.k) + " waves=" + std::to_string(c.waves));
+    // Source chunks are whole groups of G sources: the LDS tile (T) in sorted mode, which walks
+    // tiles; 64 in unsorted mode, whose sweep takes any chunk, so that passes over few sources
+    // still split into enough workgroups.
     const int T = 64 * c.waves;
+    const int G = sorted ? T : 64;
     const int64_t slab = (int64_t)64 * c.k * c.waves;
     const int64_t nslabs = std::max<int64_t>(1, (nt + slab - 1) / slab);
-    const int64_t ntiles = std::max<int64_t>(1, (ns + T - 1) / T);
+    const int64_t ntiles = std::max<int64_t>(1, (ns + G - 1) / G);
     int64_t split = c.split;
     if (split <= 0) {
         int bpc = sorted ? sorted_blocks_per_cu(op, c.k, c.waves) : variant_blocks_per_cu(op, prec, c.k, c.waves, excl);
@@ -187,12 +191,12 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool so
     }
     split = std::min<int64_t>(split, ntiles);
     split = std::max<int64_t>(split, 1);
-    // sources per chunk: whole tiles
+    // sources per chunk: whole groups
     const int64_t tiles_per_chunk = (ntiles + split - 1) / split;
     split = (ntiles + tiles_per_chunk - 1) / tiles_per_chunk;
     p.cfg = c;
     p.split = (int)split;
-    p.chunk = (int)(tiles_per_chunk * T);
+    p.chunk = (int)(tiles_per_chunk * G);
     if (nslabs * split > INT32_MAX) return fail(BF_ERR_UNSUPPORTED, "grid too large");
     p.nblocks = (int)(nslabs * split);
     return BF_OK;

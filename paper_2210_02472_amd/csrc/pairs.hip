@@ -95,6 +95,35 @@ __global__ __launch_bounds__(256) void k_reduce(const PairArgs a) {
     write_result<Op>(a, k, particle_of(a.tgt, k, a.P.n, a.flags), v);
 }
 
+// many chunks: one wavefront per target, lane l combining chunks l, l + 64, ... in order, then
+// a fixed butterfly over the lanes
+template <class Op>
+__global__ __launch_bounds__(256) void k_reduce_wave(const PairArgs a) {
+    constexpr int NP = ncomp_of<Op>();
+    const int k = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int nt = a.tgt.count;
+    if (k >= nt) return;  // uniform over the wavefront
+    double v[NP];
+#pragma unroll
+    for (int comp = 0; comp < NP; ++comp) v[comp] = 0.0;
+    for (int c = lane; c < a.split; c += 64) {
+#pragma unroll
+        for (int comp = 0; comp < NP; ++comp) {
+            const double x = a.part[((size_t)c * NP + comp) * nt + k];
+            v[comp] = Op::kMax ? fmax(v[comp], x) : v[comp] + x;
+        }
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+#pragma unroll
+        for (int comp = 0; comp < NP; ++comp) {
+            const double x = __shfl_xor(v[comp], m, 64);
+            v[comp] = Op::kMax ? fmax(v[comp], x) : v[comp] + x;
+        }
+    }
+    if (lane == 0) write_result<Op>(a, k, particle_of(a.tgt, k, a.P.n, a.flags), v);
+}
+
 // ---- FP64 fix-up of ill-conditioned targets ------------------------------------------------
 
 __global__ void k_zero_count(int32_t* c) { *c = 0; }
@@ -108,13 +137,15 @@ __global__ void k_pass_begin(int32_t* fix_count, unsigned long long* stats) {
 }
 
 // The queue is worked in rounds of up to kFixTiled targets, each round split into source chunks
-// so that the grid (wgs workgroups) fills: a round of at least kFixWide targets gives each
-// thread one target and stages every source chunk through LDS for 256 targets at once; a shorter
-// round gives each workgroup one (target, chunk) item, its threads splitting the chunk.  Both
-// write FP64 partial sums per chunk, which k_fixup_reduce adds in chunk order.  The plan depends
-// only on the round's length, the source count and wgs, so the two kernels agree on it and the
-// sums are repeatable.  Rounds past the queue's end exit at once.
+// so that the grid (wgs workgroups) fills.  Where a round has at least kFixWide targets and
+// kFixWidePairs target-source pairs, each thread takes one target and every source chunk is
+// staged through LDS for 256 targets at once; otherwise each workgroup takes one (target,
+// chunk) item, its threads splitting the chunk.  Both write FP64 partial sums per chunk, which
+// k_fixup_reduce adds in chunk order.  The plan depends only on the round's length, the source
+// count and wgs, so the two kernels agree on it and the sums are repeatable.  Rounds past the
+// queue's end exit at once.
 constexpr int kFixWide = 64;
+constexpr int64_t kFixWidePairs = 1 << 22;
 
 struct FixPlan {
     bool wide;   // thread per target (else workgroup per (target, chunk))
@@ -125,14 +156,14 @@ struct FixPlan {
 
 __device__ __forceinline__ FixPlan fix_plan(int count, int ns, int wgs) {
     FixPlan f;
-    f.wide = count >= kFixWide;
+    f.wide = count >= kFixWide && (int64_t)count * ns >= kFixWidePairs;
     if (f.wide) {
         const int slabs = (count + 255) / 256;
         f.stride = slabs * 256;
         f.nch = max(1, min(wgs / slabs, (ns + 255) / 256));  // chunks of at least 256 sources
     } else {
-        f.stride = kFixWide;
-        f.nch = max(1, min((wgs + count - 1) / count, (ns + 1023) / 1024));  // at least 1024
+        f.stride = (count + 63) / 64 * 64;
+        f.nch = max(1, min((wgs + count - 1) / count, (ns + 255) / 256));
     }
     f.nch = min(f.nch, kFixChunks * kFixTiled / f.stride);  // the partial-sum buffer
     f.chunk = (ns + f.nch - 1) / f.nch;
@@ -213,25 +244,6 @@ __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* p
             part[((size_t)c * 3 + 1) * f.stride + e] = sy;
             part[((size_t)c * 3 + 2) * f.stride + e] = sz;
         }
-    }
-}
-
-// Small source sets: one workgroup per queued target (its 256 threads split the sources, a
-// fixed-order reduction in LDS), results written directly: one launch, no partials.
-template <int OP>
-__global__ __launch_bounds__(256) void k_fixup_each(const PairArgs a) {
-    const int count = min(*a.fix_count, a.tgt.count);
-    if (a.pass_stats && blockIdx.x == 0 && threadIdx.x == 0) a.pass_stats[0] = (unsigned long long)count;
-    for (int e = blockIdx.x; e < count; e += gridDim.x) {  // uniform over the workgroup
-        const int pi = particle_of(a.tgt, a.fix_list[e], a.P.n, a.flags);
-        double v[3];
-        fix_one<OP>(a.P, a.src, a.sub, pi, a.G, a.eps2, a.flags, v);
-        if (threadIdx.x == 0) {
-            a.o0[pi] = v[0];
-            a.o1[pi] = v[1];
-            a.o2[pi] = v[2];
-        }
-        __syncthreads();  // fix_one's LDS is reused by the next target
     }
 }
 
@@ -358,7 +370,8 @@ hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st) {
 template <class Op>
 static void reduce_one(const PairArgs& a, hipStream_t st) {
     const int n = a.tgt.count;
-    hipLaunchKernelGGL(k_reduce<Op>, dim3((n + 255) / 256), dim3(256), 0, st, a);
+    if (a.split > kReduceWaveSplit) hipLaunchKernelGGL(k_reduce_wave<Op>, dim3((n + 3) / 4), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_reduce<Op>, dim3((n + 255) / 256), dim3(256), 0, st, a);
 }
 
 hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st) {
@@ -389,18 +402,11 @@ hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hip
     const int nt = a.tgt.count;
     if (nt <= 0) return hipSuccess;
     if (op != OP_ACC && op != OP_GRAD) return hipErrorInvalidValue;
-    if (a.src.count <= kFixEachSources) {
-        const int g = std::min(nt, 8 * num_cu);
-        if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_each<OP_ACC>, dim3(g), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL(k_fixup_each<OP_GRAD>, dim3(g), dim3(256), 0, st, a);
-        return hipGetLastError();
-    }
     const int64_t ns = a.src.count;
     for (int base = 0; base < nt; base += kFixTiled) {  // rounds past the queue's end exit at once
         const int len = std::min(nt - base, kFixTiled);
-        // enough workgroups for the longest possible round of either kind, at most 8 per CU
-        const int64_t most = std::max<int64_t>((int64_t)std::min(len, kFixWide - 1) * ((ns + 1023) / 1024),
-                                               (int64_t)((len + 255) / 256) * ((ns + 255) / 256));
+        // enough workgroups for the longest possible round, at most 8 per CU
+        const int64_t most = (int64_t)len * ((ns + 255) / 256);
         const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>(most, 8 * num_cu));
         const int g2 = std::min((len + 3) / 4, 8 * num_cu);
         if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_tiled<OP_ACC>, dim3(g1), dim3(256), 0, st, a, part, base, g1);
