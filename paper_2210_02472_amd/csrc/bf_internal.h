@@ -78,7 +78,8 @@ int pack_bytes(int op, int prec);
 // Stored components per target (results, plus the magnitude estimate of the mixed acc/grad).
 int stored_components(int op, int prec);
 
-hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st);
+// begin: 0, or start the pass as well (1: clear a.pass_stats; 2: and *a.fix_count)
+hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st, int begin = 0);
 hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st);
 hipError_t launch_zero_count(int32_t* c, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st);

@@ -107,6 +107,7 @@ struct Plan {
 // Below these sizes the sort, the tile packs and their launches cost more than the far tiles
 // save (measured on a 262,144-body HHS interval, whose deep levels are small).
 constexpr int64_t kSortMinSources = 16384, kSortMinTargets = 16384, kSortMinPairs = (int64_t)1 << 31;
+constexpr int64_t kMaxAutoSplit = 32;
 constexpr double kKappaMin = 0.5, kKappaMax = 64.0;
 // Pair-symmetric sweep: its column partials take (n / 2048 + 1) * 16 bytes per particle
 // (8.6 GB at n = 2^20); above this size the directed sorted sweep runs instead.
@@ -188,6 +189,9 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool so
         const int64_t want = 4 * resident;
         split = (want + nslabs - 1) / nslabs;
         split = std::max<int64_t>(8, (split + 7) / 8 * 8);
+        // unsorted passes over few targets: beyond 32 chunks the partial sums cost more than
+        // the extra workgroups gain (measured on the levels of a 262,144-body HHS interval)
+        if (!sorted) split = std::min<int64_t>(split, kMaxAutoSplit);
     }
     split = std::min<int64_t>(split, ntiles);
     split = std::max<int64_t>(split, 1);
@@ -277,9 +281,10 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     a.fix_count = static_cast<int32_t*>(ctx->scratch);
     a.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + 256);
     if (p.split > 1) a.part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + head);
-    BF_HIP(launch_pass_begin(fix ? a.fix_count : nullptr, ctx->d_stats, ctx->stream));
     a.tile_stats = ctx->d_stats + 1;
     a.pass_stats = ctx->d_stats;
+    const bool pack_begins = !sorted && sr->count > 0;  // the pack kernel starts the pass
+    if (!pack_begins) BF_HIP(launch_pass_begin(fix ? a.fix_count : nullptr, ctx->d_stats, ctx->stream));
     SymArgs g{};
     if (sorted) {
         // order targets and sources along a Morton curve, then pack the sorted sources into tiles
@@ -343,7 +348,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         }
     } else if (sr->count > 0) {
         a.pack = ctx->scratch2;
-        BF_HIP(launch_pack(op, prec, a, ctx->stream));
+        BF_HIP(launch_pack(op, prec, a, ctx->stream, fix ? 2 : 1));
         if (sym64) {  // rows and columns: the FP64 pack in the set's order
             const int64_t ns = sr->count, ntiles = (ns + 63) / 64;
             g.near_pack = g.row_pack = a.pack;

@@ -54,8 +54,14 @@ __global__ __launch_bounds__(64 * W) void k_pairs(const PairArgs a) {
 
 // ---- packing the source stream -------------------------------------------------------------
 
+// begin > 0: this launch also starts the pass (the three pass statistics; begin == 2: and the
+// fix-up queue counter), which saves a launch
 template <int OP, bool MIXED>
-__global__ __launch_bounds__(256) void k_pack(const PairArgs a) {
+__global__ __launch_bounds__(256) void k_pack(const PairArgs a, int begin) {
+    if (begin > 0 && blockIdx.x == 0) {
+        if (threadIdx.x < 3) a.pass_stats[threadIdx.x] = 0;
+        if (threadIdx.x == 3 && begin == 2) *a.fix_count = 0;
+    }
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.src.count) return;
     const int p = particle_of(a.src, q, a.P.n, a.flags);
@@ -353,17 +359,17 @@ int stored_components(int op, int prec) {
 }
 
 template <int OP, bool MIXED>
-static void pack_one(const PairArgs& a, hipStream_t st) {
+static void pack_one(const PairArgs& a, int begin, hipStream_t st) {
     const int n = a.src.count;
-    hipLaunchKernelGGL((k_pack<OP, MIXED>), dim3((n + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_pack<OP, MIXED>), dim3((n + 255) / 256), dim3(256), 0, st, a, begin);
 }
 
-hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st) {
+hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st, int begin) {
     if (a.src.count <= 0) return hipSuccess;
     const bool mixed = prec == BF_PREC_MIXED;
-    if (op == OP_ACC) mixed ? pack_one<OP_ACC, true>(a, st) : pack_one<OP_ACC, false>(a, st);
-    else if (op == OP_GRAD) mixed ? pack_one<OP_GRAD, true>(a, st) : pack_one<OP_GRAD, false>(a, st);
-    else mixed ? pack_one<OP_DT, true>(a, st) : pack_one<OP_DT, false>(a, st);
+    if (op == OP_ACC) mixed ? pack_one<OP_ACC, true>(a, begin, st) : pack_one<OP_ACC, false>(a, begin, st);
+    else if (op == OP_GRAD) mixed ? pack_one<OP_GRAD, true>(a, begin, st) : pack_one<OP_GRAD, false>(a, begin, st);
+    else mixed ? pack_one<OP_DT, true>(a, begin, st) : pack_one<OP_DT, false>(a, begin, st);
     return hipGetLastError();
 }
 
