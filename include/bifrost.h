@@ -145,8 +145,9 @@ BF_API int bf_force_gradient(bf_ctx *ctx, const bf_particles *P, const bf_set *t
  * the acceleration of j due to a; entries outside a and b are not written.  a and b must be
  * disjoint: overlapping ranges and a shared index array fail with BF_ERR_ARG; for other index
  * lists disjointness is the caller's promise (a particle in both gets one of its two sums).
- * Mixed precision with r_fb = 0 and both directions large enough for the spatially sorted mode
- * (bf_set_spatial_sort) evaluates every pair once (two-set symmetric sweep, scratch
+ * Mixed precision with r_fb = 0 and both sets large enough for the spatially sorted mode
+ * (bf_set_spatial_sort; here from 2^29 pairs, since the sweep replaces two passes) evaluates
+ * every pair once (two-set symmetric sweep, scratch
  * (n_a / 1024 + 1) * 16 bytes per particle of b plus O(n_a)); otherwise it runs as the two
  * passes bf_forces(a <- b) and bf_forces(b <- a).  Results, errors and flags as bf_forces. */
 BF_API int bf_forces_between(bf_ctx *ctx, const bf_particles *P, const bf_set *a, const bf_set *b, double G,

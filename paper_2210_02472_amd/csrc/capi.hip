@@ -107,6 +107,8 @@ struct Plan {
 // Below these sizes the sort, the tile packs and their launches cost more than the far tiles
 // save (measured on a 262,144-body HHS interval, whose deep levels are small).
 constexpr int64_t kSortMinSources = 16384, kSortMinTargets = 16384, kSortMinPairs = (int64_t)1 << 31;
+// The two-set sweep replaces two directed passes and pays off from a quarter of that size.
+constexpr int64_t kSortMinPairsBetween = kSortMinPairs / 4;
 constexpr int64_t kMaxAutoSplit = 32;
 constexpr double kKappaMin = 0.5, kKappaMax = 64.0;
 // Pair-symmetric sweep: its column partials take (n / 2048 + 1) * 16 bytes per particle
@@ -146,12 +148,13 @@ bool use_symmetric(bf_ctx* ctx, int op, bool sorted, const bf_set* tg, const bf_
            sym_scratch_bytes(tg->count, sym_chunks(ctx, op, tg->count)) <= kSymMaxScratch;
 }
 
-bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb) {
+bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb,
+                int64_t min_pairs = kSortMinPairs) {
     return (ctx->sort_ops >> op & 1) && ctx->sub == nullptr && !ctx->capturing && prec == BF_PREC_MIXED &&
            (op == OP_ACC || op == OP_GRAD) &&
            r_fb == 0.0 &&
            ((ctx->sort_ops & BF_SORT_ANY_SIZE) ||
-            (ns >= kSortMinSources && nt >= kSortMinTargets && nt * ns >= kSortMinPairs)) &&
+            (ns >= kSortMinSources && nt >= kSortMinTargets && nt * ns >= min_pairs)) &&
            ns >= 64 && nt >= 64;
 }
 
@@ -406,7 +409,8 @@ int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_
     };
     const int64_t na = A->count, nb = B->count;
     if (na == 0 || nb == 0 || ctx->dry || (ctx->sort_ops & BF_SORT_DIRECTED) ||
-        !use_sorted(ctx, op, prec, na, nb, r_fb) || !use_sorted(ctx, op, prec, nb, na, r_fb))
+        !use_sorted(ctx, op, prec, na, nb, r_fb, kSortMinPairsBetween) ||
+        !use_sorted(ctx, op, prec, nb, na, r_fb, kSortMinPairsBetween))
         return two_passes();
     // shares of each row block's column tiles: at least two rounds of resident workgroups
     const int64_t a_tiles = (na + 63) / 64, b_tiles = (nb + 63) / 64;
