@@ -109,7 +109,7 @@ struct Plan {
 constexpr int64_t kSortMinSources = 16384, kSortMinTargets = 16384, kSortMinPairs = (int64_t)1 << 31;
 // The two-set sweep replaces two directed passes and pays off from a quarter of that size.
 constexpr int64_t kSortMinPairsBetween = kSortMinPairs / 4;
-constexpr int64_t kMaxAutoSplit = 32;
+constexpr int64_t kAutoSplitCap = 32, kAutoChunkMin = 512;
 constexpr double kKappaMin = 0.5, kKappaMax = 64.0;
 // Pair-symmetric sweep: its column partials take (n / 2048 + 1) * 16 bytes per particle
 // (8.6 GB at n = 2^20); above this size the directed sorted sweep runs instead.
@@ -192,9 +192,10 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool so
         const int64_t want = 4 * resident;
         split = (want + nslabs - 1) / nslabs;
         split = std::max<int64_t>(8, (split + 7) / 8 * 8);
-        // unsorted passes over few targets: beyond 32 chunks the partial sums cost more than
-        // the extra workgroups gain (measured on the levels of a 262,144-body HHS interval)
-        if (!sorted) split = std::min<int64_t>(split, kMaxAutoSplit);
+        // unsorted passes over few targets: beyond max(32, ns / 512) chunks the partial sums
+        // cost more than the extra workgroups gain (measured on the levels of a 262,144-body
+        // HHS interval, 2,083 to 32,701 bodies, and on 6,554 targets x 65,536 sources)
+        if (!sorted) split = std::min<int64_t>(split, std::max<int64_t>(kAutoSplitCap, ns / kAutoChunkMin));
     }
     split = std::min<int64_t>(split, ntiles);
     split = std::max<int64_t>(split, 1);
