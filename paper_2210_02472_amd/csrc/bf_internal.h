@@ -81,6 +81,9 @@ int stored_components(int op, int prec);
 // begin: 0, or start the pass as well (1: clear a.pass_stats; 2: and *a.fix_count)
 hipError_t launch_pack(int op, int prec, const PairArgs& a, hipStream_t st, int begin = 0);
 hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st);
+// Mixed acceleration / gradient pass over few targets and sources in one launch (no source
+// split in memory): results and the fix-up queue written directly.
+hipError_t launch_pairs_small(int op, const PairArgs& a, hipStream_t st);
 hipError_t launch_zero_count(int32_t* c, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st);
 // one kernel: zero the fix-up counter (if not NULL) and the three pass statistics

@@ -52,6 +52,80 @@ __global__ __launch_bounds__(64 * W) void k_pairs(const PairArgs a) {
         if (slot[k] < a.tgt.count) emit<Op>(a, c, slot[k], pidx[k], acc[k]);
 }
 
+// ---- small passes: one launch, no partials in memory ----------------------------------------
+// A workgroup of kSmallWaves wavefronts takes kSmallT targets.  Wavefront w sweeps the w-th
+// slice of the sources in tiles of 64 staged in its own LDS region; within a wavefront lane
+// (t, g) = (lane % kSmallT, lane / kSmallT) pairs target t with entries [16 g, 16 g + 16) of
+// each tile (so an FP32 partial spans 16 sources, folded into FP64 after every tile).  At the
+// end the workgroup adds the 16 x 4 FP64 sums of each target in a fixed order (wavefront,
+// then lane group) and writes the result with the cancellation check, as the split kernels'
+// reduction does.  All wavefronts take the same number of tile steps, so the barriers are
+// uniform.
+constexpr int kSmallWaves = 16, kSmallG = 4, kSmallT = 64 / kSmallG;
+
+template <class Op>
+__global__ __launch_bounds__(64 * kSmallWaves) void k_pairs_small(const PairArgs a) {
+    constexpr int NP = ncomp_of<Op>();
+    constexpr int kTileBytes = kSmallWaves * 64 * (int)sizeof(typename Op::Src);
+    constexpr int kRedBytes = kSmallWaves * kSmallG * NP * kSmallT * (int)sizeof(double);
+    __shared__ __align__(16) unsigned char lds[kTileBytes > kRedBytes ? kTileBytes : kRedBytes];
+    typename Op::Src* tile = reinterpret_cast<typename Op::Src*>(lds) + (threadIdx.x >> 6) * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = lane % kSmallT, grp = lane / kSmallT;
+    const int nt = a.tgt.count, ns = a.src.count;
+    const int slot = blockIdx.x * kSmallT + t;
+    const int pi = particle_of(a.tgt, slot < nt ? slot : nt - 1, a.P.n, a.flags);
+    typename Op::Tgt tg;
+    Op::target(a, pi, tg);
+    typename Op::A64 acc;
+    Op::zero(acc);
+    const int per = (ns + kSmallWaves - 1) / kSmallWaves;  // sources per wavefront
+    const int j0 = wave * per, j1 = min(ns, j0 + per);
+    const int steps = (per + 63) / 64;  // the same for every wavefront
+    for (int st = 0; st < steps; ++st) {
+        const int jt = j0 + st * 64;
+        const int len = min(64, j1 - jt);  // <= 0 past this wavefront's slice
+        __syncthreads();
+        if (lane < len) tile[lane] = Op::load(a, jt + lane);
+        __syncthreads();
+        const int e0 = grp * (64 / kSmallG), e1 = min(len, e0 + 64 / kSmallG);
+        if (e0 < e1) {
+            typename Op::A32 part;
+            Op::zero(part);
+#pragma unroll 2
+            for (int e = e0; e < e1; ++e) Op::pair(part, tg, tile[e], a.eps2f);
+            Op::fold(acc, part);
+        }
+    }
+    double v[NP];
+    Op::comps(acc, v);
+    __syncthreads();  // the tiles are done with: the LDS now holds the sums
+    double* red = reinterpret_cast<double*>(lds);  // [wave][group][comp][target]
+#pragma unroll
+    for (int c = 0; c < NP; ++c) red[((wave * kSmallG + grp) * NP + c) * kSmallT + t] = v[c];
+    __syncthreads();
+    if ((int)threadIdx.x < kSmallT && slot < nt) {
+        double r[NP];
+#pragma unroll
+        for (int c = 0; c < NP; ++c) r[c] = 0.0;
+#pragma unroll 4
+        for (int q = 0; q < kSmallWaves * kSmallG; ++q)
+#pragma unroll
+            for (int c = 0; c < NP; ++c) r[c] += red[(q * NP + c) * kSmallT + t];
+        write_result<Op>(a, slot, pi, r);
+    }
+}
+
+hipError_t launch_pairs_small(int op, const PairArgs& a, hipStream_t st) {
+    const int nt = a.tgt.count;
+    if (nt <= 0) return hipSuccess;
+    const dim3 grid((nt + kSmallT - 1) / kSmallT), block(64 * kSmallWaves);
+    if (op == OP_ACC) hipLaunchKernelGGL(k_pairs_small<AccMixed>, grid, block, 0, st, a);
+    else if (op == OP_GRAD) hipLaunchKernelGGL(k_pairs_small<GradMixed>, grid, block, 0, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 // ---- packing the source stream -------------------------------------------------------------
 
 // begin > 0: this launch also starts the pass (the three pass statistics; begin == 2: and the

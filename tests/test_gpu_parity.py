@@ -436,6 +436,41 @@ def test_fixup_of_cancelling_targets(ctx, n_cancel, op):
     assert np.all(err <= 1e-12 * mag), (err / mag).max()
 
 
+@pytest.mark.parametrize("op", ["forces", "gradient"])
+def test_small_pass_kernel_parity(ctx, op):
+    """Mixed passes of up to 6,144 targets and sources run as one launch of the small kernel
+    (16 wavefronts and 4 lane groups splitting the sources of 16 targets, the sums added in
+    the workgroup): ragged and tiny shapes against the oracle, bitwise repeatable, and equal
+    within tolerance to the split kernels that a forced configuration selects; larger passes
+    keep the split kernels."""
+    d = _cluster(20000, 71)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    rng = np.random.default_rng(72)
+    af = oracle.forces(P)
+    ad = [torch.as_tensor(af[:, k].copy(), device="cuda") for k in range(3)]
+    opc = bf.BF_OP_FORCES if op == "forces" else bf.BF_OP_GRADIENT
+    for nt, ns in ((1, 5), (17, 1000), (333, 4097), (6144, 6144), (6145, 100), (2000, 20000)):
+        tg = np.sort(rng.choice(20000, nt, replace=False))
+        sr = np.sort(rng.choice(20000, ns, replace=False))
+        run = (lambda: ctx.forces(Pd, tg, sr, prec="mixed")) if op == "forces" else \
+            (lambda: ctx.force_gradient(Pd, ad, tg, sr, prec="mixed"))
+        a, b = run(), run()
+        assert all(torch.equal(x, y) for x, y in zip(a, b))
+        kind, k, waves, split = ctx.last_pass_config()
+        assert kind == "unsorted" and (waves == 16) == (nt <= 6144 and ns <= 6144), (nt, ns, waves)
+        ref = oracle.forces(P, tg, sr) if op == "forces" else oracle.gradient(P, af, tg, sr)
+        got = gather(a, tg)
+        rms, mx = stats(rel_errors(got, ref))
+        assert rms <= RMS_TOL and mx <= MAX_TOL, (nt, ns, rms, mx)
+        try:
+            ctx.set_config(opc, "mixed", 1, 4, 0)
+            c = run()
+        finally:
+            ctx.set_config(opc, "mixed", 0)
+        rms, mx = stats(rel_errors(gather(c, tg), got))
+        assert rms <= RMS_TOL and mx <= MAX_TOL, (nt, ns, rms, mx)
+
+
 def test_autotune_table_round_trip(ctx, tmp_path):
     """The autotuner times the kernel variants for one size bucket, stores the fastest in the
     context and in a JSON cache; a fresh context loading the cache plans the same variant, and
