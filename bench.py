@@ -232,6 +232,11 @@ def run_workload(name, args):
             return (time.perf_counter() - t) / reps * 1e3
 
         eager = wall(lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed"), 3)
+        if args.hhs_eager_only:  # for a kernel trace of the eager interval alone
+            rec.update({"n": n, "kmax": kmax, "tau": tau, "interval_ms": {"eager": eager}})
+            ctx.close()
+            print(json.dumps(rec), flush=True)
+            return
         ctx.set_spatial_sort(False, False)  # what the graph records: the unsorted passes
         eager_unsorted = wall(lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed"), 3)
         g = ctx.capture_hhs_interval(P, level, kmax, tau, prec="mixed")
@@ -267,6 +272,8 @@ def main():
     ap.add_argument("--cpu-single-seconds", type=float, default=5.0,
                     help="target time of a one-thread oracle sample (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hhs-eager-only", action="store_true",
+                    help="bh-hhs workload: time only the eager interval (for kernel traces)")
     ap.add_argument("--sample", type=int, default=256, help="targets sampled for the error check")
     ap.add_argument("--spatial-sort", default="default", choices=["default", "off", "acc", "grad", "both", "directed"],
                     help="passes that use the spatially sorted mixed kernels (default: the library's; directed: sorted without the pair-symmetric sweep)")
