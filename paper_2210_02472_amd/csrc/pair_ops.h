@@ -72,10 +72,21 @@ constexpr float kTiny32 = 1e-20f;   // added to s^2 in FP32: keeps the self pair
 constexpr double kTiny64 = 1e-150;  // same in FP64
 
 // FP64 contributions of one pair, straight from the masters (re-evaluation and fix-up paths).
-// r = x_j - x_i, s2 = |r|^2 + eps2 > 0.
-__device__ __forceinline__ void acc_pair64(const Masters& P, int pi, int pj, double G, double eps2, double& sx,
+// r = x_j - x_i, s2 = |r|^2 + eps2 > 0.  The target's values come in registers (T64), so a
+// loop over sources loads them once.
+struct T64 {
+    double x, y, z, ax, ay, az;
+};
+template <bool GRAD>
+__device__ __forceinline__ T64 target64(const Masters& P, int pi) {
+    T64 t{P.x[pi], P.y[pi], P.z[pi], 0.0, 0.0, 0.0};
+    if constexpr (GRAD) { t.ax = P.ax[pi]; t.ay = P.ay[pi]; t.az = P.az[pi]; }
+    return t;
+}
+
+__device__ __forceinline__ void acc_pair64(const Masters& P, const T64& t, int pj, double G, double eps2, double& sx,
                                            double& sy, double& sz, double& sm, uint32_t* flags) {
-    const double dx = P.x[pj] - P.x[pi], dy = P.y[pj] - P.y[pi], dz = P.z[pj] - P.z[pi];
+    const double dx = P.x[pj] - t.x, dy = P.y[pj] - t.y, dz = P.z[pj] - t.z;
     const double r2 = dx * dx + dy * dy + dz * dz + eps2;
     if (r2 == 0.0) { atomicOr(flags, BF_FLAG_COINCIDENT); return; }
     const double ri = rsqrt64(r2);
@@ -84,12 +95,12 @@ __device__ __forceinline__ void acc_pair64(const Masters& P, int pi, int pj, dou
     sm += w * fmax(fabs(dx), fmax(fabs(dy), fabs(dz)));
 }
 
-__device__ __forceinline__ void grad_pair64(const Masters& P, int pi, int pj, double G, double eps2, double& sx,
+__device__ __forceinline__ void grad_pair64(const Masters& P, const T64& t, int pj, double G, double eps2, double& sx,
                                             double& sy, double& sz, double& sm, uint32_t* flags) {
-    const double dx = P.x[pj] - P.x[pi], dy = P.y[pj] - P.y[pi], dz = P.z[pj] - P.z[pi];
+    const double dx = P.x[pj] - t.x, dy = P.y[pj] - t.y, dz = P.z[pj] - t.z;
     const double r2 = dx * dx + dy * dy + dz * dz + eps2;
     if (r2 == 0.0) { atomicOr(flags, BF_FLAG_COINCIDENT); return; }
-    const double dax = P.ax[pj] - P.ax[pi], day = P.ay[pj] - P.ay[pi], daz = P.az[pj] - P.az[pi];
+    const double dax = P.ax[pj] - t.ax, day = P.ay[pj] - t.ay, daz = P.az[pj] - t.az;
     const double ri = rsqrt64(r2);
     const double ri2 = ri * ri;
     const double w = G * P.m[pj] * ri * ri2;
@@ -134,9 +145,10 @@ struct AccMixed {
     }
     __device__ static void redo(A64& o, const PairArgs& a, int pi, int q0, int len) {
         double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
+        const T64 t = target64<false>(a.P, pi);
         for (int q = q0; q < q0 + len; ++q) {
             const int pj = particle_of(a.src, q, a.P.n, a.flags);
-            if (pj != pi && !same_sub(a.sub, pi, pj)) acc_pair64(a.P, pi, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
+            if (pj != pi && !same_sub(a.sub, pi, pj)) acc_pair64(a.P, t, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
         }
         o.x += sx; o.y += sy; o.z += sz; o.m += sm;
     }
@@ -192,9 +204,10 @@ struct GradMixed {
     }
     __device__ static void redo(A64& o, const PairArgs& a, int pi, int q0, int len) {
         double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
+        const T64 t = target64<true>(a.P, pi);
         for (int q = q0; q < q0 + len; ++q) {
             const int pj = particle_of(a.src, q, a.P.n, a.flags);
-            if (pj != pi && !same_sub(a.sub, pi, pj)) grad_pair64(a.P, pi, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
+            if (pj != pi && !same_sub(a.sub, pi, pj)) grad_pair64(a.P, t, pj, a.G, a.eps2, sx, sy, sz, sm, a.flags);
         }
         o.x += sx; o.y += sy; o.z += sz; o.m += sm;
     }
@@ -701,11 +714,13 @@ __device__ __forceinline__ void fix_range(const Masters& P, const DevSet& src, c
                                           double eps2, uint32_t* flags, int q0, int q1, double* out3) {
     __shared__ double red[3][256];
     double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
+    const T64 t = target64<OP == OP_GRAD>(P, pi);
+#pragma unroll 2
     for (int q = q0 + (int)threadIdx.x; q < q1; q += 256) {
         const int pj = particle_of(src, q, P.n, flags);
         if (pj == pi || same_sub(sub, pi, pj)) continue;
-        if constexpr (OP == OP_ACC) acc_pair64(P, pi, pj, G, eps2, sx, sy, sz, sm, flags);
-        else grad_pair64(P, pi, pj, G, eps2, sx, sy, sz, sm, flags);
+        if constexpr (OP == OP_ACC) acc_pair64(P, t, pj, G, eps2, sx, sy, sz, sm, flags);
+        else grad_pair64(P, t, pj, G, eps2, sx, sy, sz, sm, flags);
     }
     __syncthreads();
     red[0][threadIdx.x] = sx; red[1][threadIdx.x] = sy; red[2][threadIdx.x] = sz;
