@@ -300,6 +300,33 @@ __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* p
             }
             __syncthreads();
             if (!act) continue;
+            // Without subsystem labels the loop has no branch: a skipped pair (the target
+            // itself, or a coincident pair, which raises the flag once per tile) adds w = 0.
+            if (a.sub == nullptr) {
+                bool coincident = false;
+#pragma unroll 4
+                for (int j = 0; j < len; ++j) {
+                    const double4 q = sp[j];
+                    const double4 qa = sa[j];
+                    const double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+                    const double r2 = dx * dx + dy * dy + dz * dz + a.eps2;
+                    const bool self = (int)qa.w == pi, zero = r2 == 0.0;
+                    coincident = coincident || (zero && !self);
+                    const bool off = self || zero;
+                    const double ri = rsqrt64(off ? 1.0 : r2);
+                    const double ri2 = ri * ri;
+                    const double w = off ? 0.0 : q.w * ri * ri2;
+                    if constexpr (OP == OP_ACC) {
+                        sx += w * dx; sy += w * dy; sz += w * dz;
+                    } else {
+                        const double dax = qa.x - axi, day = qa.y - ayi, daz = qa.z - azi;
+                        const double q3 = 3.0 * (dax * dx + day * dy + daz * dz) * ri2;
+                        sx += w * (dax - q3 * dx); sy += w * (day - q3 * dy); sz += w * (daz - q3 * dz);
+                    }
+                }
+                if (coincident) atomicOr(a.flags, BF_FLAG_COINCIDENT);
+                continue;
+            }
             for (int j = 0; j < len; ++j) {
                 const int pj = (int)sa[j].w;
                 if (pj == pi || same_sub(a.sub, pi, pj)) continue;
