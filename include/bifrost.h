@@ -430,8 +430,11 @@ BF_API int bf_last_pass_stats(bf_ctx *ctx, int64_t *fixups, int64_t *near_tiles,
  * (spatially sorted, each unordered pair once) or BF_PASS_BETWEEN (the two-set symmetric sweep
  * of bf_forces_between / bf_force_gradient_between); k_per_lane = targets per lane (row tiles per
  * wavefront for the symmetric sweeps), waves = wavefronts per workgroup, split = source chunks
- * (shares of the column range for the symmetric sweeps).  Any pointer may be NULL.  Before the
- * first pass all are 0. */
+ * (shares of the column range for the symmetric sweeps).  A mixed unsorted acceleration or
+ * gradient pass of at most 6,144 targets and sources, with no subsystem labels, r_fb = 0 and no
+ * forced or tuned configuration, runs as one launch of the small kernel (16 wavefronts splitting
+ * the sources of 16 targets per workgroup) and reports k_per_lane 1, waves 16, split 1.  Any
+ * pointer may be NULL.  Before the first pass all are 0. */
 #define BF_PASS_UNSORTED 0
 #define BF_PASS_SORTED 1
 #define BF_PASS_SYMMETRIC 2
@@ -440,7 +443,8 @@ BF_API int bf_last_pass_config(bf_ctx *ctx, int *kind, int *k_per_lane, int *wav
 
 /* Kernel configuration the context would use for a directed pass of these sizes (for
  * reporting): targets per lane, waves per workgroup, source split.  A pass whose targets and
- * sources are one set may run the pair-symmetric sweep instead; bf_last_pass_config tells. */
+ * sources are one set may run the pair-symmetric sweep instead, and a small mixed pass the
+ * one-launch small kernel; bf_last_pass_config tells. */
 BF_API int bf_query_config(bf_ctx *ctx, int op, int prec, int64_t n_targets, int64_t n_sources,
                            int *k_per_lane, int *waves, int *split);
 /* Force the kernel configuration for subsequent calls of op/prec (0 restores the default
