@@ -265,9 +265,11 @@ BF_API int bf_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, co
  * HIP graph: *graph_exec receives a handle for bf_graph_launch / bf_graph_destroy.  Each launch
  * advances the state in S by one interval with the level structure given here (the partition
  * is taken once, at capture; recapture when levels change).  Synchronising; the graph owns its
- * scratch buffers, so later calls on the context never invalidate it.  Inside the graph the
- * mixed passes run unsorted (the spatially sorted mode and kernel timing are off while
- * capturing); results equal an eager bf_hhs_interval with the sorted mode off.  Errors as
+ * scratch buffers, so later calls on the context never invalidate it.  The passes inside the
+ * graph are the eager ones, the spatially sorted mode included; there its Morton order comes
+ * from a merge sort, which launches kernels only (the eager radix sort clears its counters with
+ * memset operations, which a graph must not hold): both sorts are stable, so a replay equals an
+ * eager bf_hhs_interval bit for bit.  Kernel timing is off while capturing.  Errors as
  * bf_hhs_interval; an empty set is BF_ERR_ARG; prm->n_bh must be 0 (BF_ERR_UNSUPPORTED). */
 BF_API int bf_graph_capture_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, const int32_t *level,
                                          int kmax, double tau, const bf_fsi_params *prm, void **graph_exec);
@@ -403,7 +405,7 @@ BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
  * passes that use it: bit (1 << BF_OP_FORCES) and/or bit (1 << BF_OP_GRADIENT); the default is
  * both.  When selected, and r_fb == 0, with at least 16384 targets and 16384 sources and
  * 2^31 pairs (below that the sort costs more than it saves; bit BF_SORT_ANY_SIZE in ops_mask
- * lifts these limits), without subsystem labels and outside graph capture, targets and sources
+ * lifts these limits), and without subsystem labels, targets and sources
  * are ordered along a Morton curve and the sources packed into tiles; a tile whose gap to a
  * workgroup's target box is at least kappa times its half-extent
  * is summed from FP32 offsets to the tile centre (pair separation rounding error at most

@@ -92,7 +92,7 @@ hipError_t launch_pass_begin(int32_t* fix_count, unsigned long long* stats, hipS
 struct bf_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void* owned[8] = {};
+    void* owned[12] = {};
 };
 
 // FP64 fix-up of queued targets; part: kFixChunks * 3 * kFixTiled doubles of scratch.
@@ -108,15 +108,16 @@ struct SortBuffers {
     uint32_t* keys_out;  // [n]
     int32_t* vals_in;    // [n]
     int32_t* vals_out;   // [n]
-    void* tmp;           // radix-sort temporary storage
+    void* tmp;           // sort temporary storage
     size_t tmp_bytes;
 };
-// bytes of radix-sort temporary storage for n keys
+// bytes of sort temporary storage for n keys
 size_t sort_tmp_bytes(int n);
 // sort the particles of `set` along a Morton curve over the box of `box_set`; writes the sorted
-// particle list to out[0..set.count)
+// particle list to out[0..set.count).  graph_safe: a sort made of kernel launches only (for
+// graph capture); the same order.
 hipError_t launch_sort_set(const Masters& P, const DevSet& set, const DevSet& box_set, const SortBuffers& sb,
-                           int32_t* out, uint32_t* flags, hipStream_t st);
+                           int32_t* out, uint32_t* flags, hipStream_t st, bool graph_safe = false);
 // pack sorted sources into tiles of 64*waves: near (FP64) stream, far (FP32 tile-relative)
 // stream and tile metadata
 hipError_t launch_pack_tiles(int op, int waves, const PairArgs& a, void* near_pack, void* far_pack,

@@ -134,8 +134,7 @@ int sym_chunks(bf_ctx* ctx, int op, int64_t n) {
 bool use_symmetric64(bf_ctx* ctx, int op, int prec, const bf_set* tg, const bf_set* sr) {
     const int64_t n = sr->count;
     return prec == BF_PREC_FP64 && (op == OP_ACC || op == OP_GRAD) && (ctx->sort_ops >> op & 1) &&
-           !(ctx->sort_ops & BF_SORT_DIRECTED) && same_set(tg, sr) && ctx->sub == nullptr && !ctx->capturing &&
-           !ctx->dry && n >= 64 &&
+           !(ctx->sort_ops & BF_SORT_DIRECTED) && same_set(tg, sr) && ctx->sub == nullptr && n >= 64 &&
            ((ctx->sort_ops & BF_SORT_ANY_SIZE) || (n >= kSortMinSources && n * n >= kSortMinPairs));
 }
 
@@ -153,7 +152,7 @@ bool use_symmetric(bf_ctx* ctx, int op, bool sorted, const bf_set* tg, const bf_
 
 bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb,
                 int64_t min_pairs = kSortMinPairs) {
-    return (ctx->sort_ops >> op & 1) && ctx->sub == nullptr && !ctx->capturing && prec == BF_PREC_MIXED &&
+    return (ctx->sort_ops >> op & 1) && ctx->sub == nullptr && prec == BF_PREC_MIXED &&
            (op == OP_ACC || op == OP_GRAD) &&
            r_fb == 0.0 &&
            ((ctx->sort_ops & BF_SORT_ANY_SIZE) ||
@@ -228,7 +227,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         return fail(BF_ERR_UNSUPPORTED, "no sorted kernel variant for this configuration");
     bool sym = use_symmetric(ctx, op, sorted, tg, sr);
     int sym_shares = 0;
-    if (sym && !ctx->dry) {
+    if (sym) {
         // the column partials are large (8.6 GB at n = 2^20): without the memory, the directed
         // sweep runs instead
         sym_shares = sym_chunks(ctx, op, sr->count);
@@ -288,10 +287,25 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)sr->count * pack_bytes(op, prec), ctx->stream);
         if (rc) return rc;
     }
-    if (ctx->dry) {  // sizing before a capture: every buffer of this pass now exists
-        if (sorted) return fail(BF_ERR_UNSUPPORTED, "sorted passes are not captured");
-        return BF_OK;
+    // sorted mode: sort lists and temporaries, near and far streams, tile metadata
+    const int64_t s_nt = tg->count, s_ns = sr->count, s_nmax = std::max(s_nt, s_ns);
+    const size_t s_tmp = sorted ? sort_tmp_bytes((int)s_nmax) : 0;
+    const size_t s_list = ((size_t)s_nmax * 4 + 255) & ~size_t(255);
+    const int s_waves = sym ? 1 : p.cfg.waves;  // the symmetric sweep packs tiles of 64
+    const int64_t s_ntiles = (s_ns + 64 * s_waves - 1) / (64 * s_waves);
+    const int s_kmeta = op == OP_GRAD ? 2 : 1;
+    const size_t s_far = (((size_t)s_ns * (op == OP_GRAD ? 32 : 16)) + 255) & ~size_t(255);
+    if (sorted) {
+        rc = ensure(&ctx->scratch5, &ctx->scratch5_bytes, 256 + 6 * s_list + ((s_tmp + 255) & ~size_t(255)),
+                    ctx->stream);
+        if (rc) return rc;
+        rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)s_ns * pack_bytes(op, prec), ctx->stream);
+        if (rc) return rc;
+        rc = ensure(&ctx->scratch6, &ctx->scratch6_bytes, s_far + (size_t)s_ntiles * s_kmeta * sizeof(double4),
+                    ctx->stream);
+        if (rc) return rc;
     }
+    if (ctx->dry) return BF_OK;  // sizing before a capture: every buffer of this pass now exists
     a.fix_count = static_cast<int32_t*>(ctx->scratch);
     a.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + 256);
     if (p.split > 1) a.part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + head);
@@ -302,12 +316,8 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     SymArgs g{};
     if (sorted) {
         // order targets and sources along a Morton curve, then pack the sorted sources into tiles
-        const int64_t nt = tg->count, ns = sr->count, nmax = std::max(nt, ns);
-        const size_t tmp = sort_tmp_bytes((int)nmax);
-        const size_t list_bytes = ((size_t)nmax * 4 + 255) & ~size_t(255);
-        const size_t need5 = 256 + 4 * list_bytes + 2 * list_bytes + ((tmp + 255) & ~size_t(255));
-        rc = ensure(&ctx->scratch5, &ctx->scratch5_bytes, need5, ctx->stream);
-        if (rc) return rc;
+        const int64_t nt = s_nt, ns = s_ns;
+        const size_t tmp = s_tmp, list_bytes = s_list;
         char* b5 = static_cast<char*>(ctx->scratch5);
         SortBuffers sb;
         sb.bbox = reinterpret_cast<uint32_t*>(b5);
@@ -320,21 +330,14 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         sb.tmp = b5 + 256 + 6 * list_bytes;
         sb.tmp_bytes = tmp;
         const DevSet ds = devset(sr), dt = devset(tg);
-        BF_HIP(launch_sort_set(M, ds, ds, sb, src_sorted, ctx->d_flags, ctx->stream));
+        BF_HIP(launch_sort_set(M, ds, ds, sb, src_sorted, ctx->d_flags, ctx->stream, ctx->capturing));
         const bool same = same_set(tg, sr);
-        if (!same) BF_HIP(launch_sort_set(M, dt, ds, sb, tgt_sorted, ctx->d_flags, ctx->stream));
+        if (!same) BF_HIP(launch_sort_set(M, dt, ds, sb, tgt_sorted, ctx->d_flags, ctx->stream, ctx->capturing));
         a.src = DevSet{src_sorted, (int32_t)ns, 0};
         a.tgt = DevSet{same ? src_sorted : tgt_sorted, (int32_t)nt, 0};
-        const int tile_waves = sym ? 1 : p.cfg.waves;  // the symmetric sweep packs tiles of 64
-        const int T = 64 * tile_waves;
-        const int64_t ntiles = (ns + T - 1) / T;
-        const int kmeta = op == OP_GRAD ? 2 : 1;
-        rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)ns * pack_bytes(op, prec), ctx->stream);
-        if (rc) return rc;
-        const size_t far_bytes = (((size_t)ns * (op == OP_GRAD ? 32 : 16)) + 255) & ~size_t(255);
-        rc = ensure(&ctx->scratch6, &ctx->scratch6_bytes, far_bytes + (size_t)ntiles * kmeta * sizeof(double4),
-                    ctx->stream);
-        if (rc) return rc;
+        const int tile_waves = s_waves;
+        const int64_t ntiles = s_ntiles;
+        const size_t far_bytes = s_far;
         a.pack = ctx->scratch2;
         a.pack_far = ctx->scratch6;
         a.tile_meta = reinterpret_cast<const double4*>(static_cast<char*>(ctx->scratch6) + far_bytes);
@@ -420,7 +423,7 @@ int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_
         return run_pairs(ctx, op, prec, M, B, A, G, eps2, r_fb, 0, 0, o0, o1, o2);
     };
     const int64_t na = A->count, nb = B->count;
-    if (na == 0 || nb == 0 || ctx->dry || (ctx->sort_ops & BF_SORT_DIRECTED) ||
+    if (na == 0 || nb == 0 || (ctx->sort_ops & BF_SORT_DIRECTED) ||
         !use_sorted(ctx, op, prec, na, nb, r_fb, kSortMinPairsBetween) ||
         !use_sorted(ctx, op, prec, nb, na, r_fb, kSortMinPairsBetween))
         return two_passes();
@@ -467,6 +470,7 @@ int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_
                         ctx->stream))
         return rc;
     if (int rc = ensure(&ctx->scratch10, &ctx->scratch10_bytes, (size_t)na * pb, ctx->stream)) return rc;
+    if (ctx->dry) return BF_OK;  // sizing before a capture: every buffer of this sweep now exists
 
     PairArgs ab{};  // A targets, B sources
     ab.P = M;
@@ -489,8 +493,8 @@ int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_
     ab.tile_stats = ctx->d_stats + 1;
     ab.pass_stats = ctx->d_stats;  // the count of A's queue is reported
     const DevSet dA = devset(A), dB = devset(B);
-    BF_HIP(launch_sort_set(M, dB, dB, sb, b_sorted, ctx->d_flags, ctx->stream));
-    BF_HIP(launch_sort_set(M, dA, dA, sb, a_sorted, ctx->d_flags, ctx->stream));
+    BF_HIP(launch_sort_set(M, dB, dB, sb, b_sorted, ctx->d_flags, ctx->stream, ctx->capturing));
+    BF_HIP(launch_sort_set(M, dA, dA, sb, a_sorted, ctx->d_flags, ctx->stream, ctx->capturing));
     ab.tgt = ba.src = DevSet{a_sorted, (int32_t)na, 0};
     ab.src = ba.tgt = DevSet{b_sorted, (int32_t)nb, 0};
     double4* meta = reinterpret_cast<double4*>(static_cast<char*>(ctx->scratch6) + far_bytes);
@@ -1314,10 +1318,12 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_
     if (prm && prm->n_bh != 0) return fail(BF_ERR_UNSUPPORTED, "a captured interval runs without PN1.0 (n_bh must be 0)");
     // The graph gets buffers of its own: park the context's while the interval is sized and
     // captured, then hand the new ones to the graph and give the context its own back.
-    constexpr int kSlots = 5;
-    void** slot[kSlots] = {&c->scratch, &c->scratch2, &c->scratch7, &c->scratch8, &c->scratch11};
-    size_t* slot_bytes[kSlots] = {&c->scratch_bytes, &c->scratch2_bytes, &c->scratch7_bytes, &c->scratch8_bytes,
-                                  &c->scratch11_bytes};
+    constexpr int kSlots = 9;
+    void** slot[kSlots] = {&c->scratch,  &c->scratch2, &c->scratch5,  &c->scratch6, &c->scratch7,
+                           &c->scratch8, &c->scratch9, &c->scratch10, &c->scratch11};
+    size_t* slot_bytes[kSlots] = {&c->scratch_bytes,  &c->scratch2_bytes, &c->scratch5_bytes,
+                                  &c->scratch6_bytes, &c->scratch7_bytes, &c->scratch8_bytes,
+                                  &c->scratch9_bytes, &c->scratch10_bytes, &c->scratch11_bytes};
     void* parked[kSlots];
     size_t parked_bytes[kSlots];
     for (int i = 0; i < kSlots; ++i) {
@@ -1341,7 +1347,7 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_
         unpark(true);
         return rc;
     }
-    c->capturing = true;  // no sorted passes, no timing events inside the graph
+    c->capturing = true;  // no timing events inside the graph; graph-safe sorts
     c->dry = true;
     rc = hhs_run(h, tau);
     c->dry = false;

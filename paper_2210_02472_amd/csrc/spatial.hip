@@ -6,6 +6,9 @@
 // near a workgroup's targets, and as FP32 offsets from the tile centre for all other tiles; the
 // sorted sweep (pair_ops.h) picks per tile.  Outputs stay particle-indexed, so the ordering is
 // invisible to the caller.
+#include <algorithm>
+
+#include <rocprim/device/device_merge_sort.hpp>
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "pair_ops.h"
@@ -96,15 +99,21 @@ __global__ __launch_bounds__(256) void k_sorted_list(DevSet set, const int32_t* 
     out[s] = particle_of(set, k, n, flags);
 }
 
+// Temporary storage of either sort below (the larger of the two).
 size_t sort_tmp_bytes(int n) {
-    size_t bytes = 0;
-    rocprim::radix_sort_pairs(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr, (const int32_t*)nullptr,
+    size_t radix = 0, merge = 0;
+    rocprim::radix_sort_pairs(nullptr, radix, (const uint32_t*)nullptr, (uint32_t*)nullptr, (const int32_t*)nullptr,
                               (int32_t*)nullptr, (unsigned)n, 0, 30, (hipStream_t)0);
-    return bytes;
+    rocprim::merge_sort(nullptr, merge, (const uint32_t*)nullptr, (uint32_t*)nullptr, (const int32_t*)nullptr,
+                        (int32_t*)nullptr, (size_t)n, rocprim::less<uint32_t>(), (hipStream_t)0);
+    return std::max(radix, merge);
 }
 
+// The Morton order of a set.  Both sorts are stable, so they give the same order; the radix sort
+// is the faster, but it clears its counters with memset operations, which a captured graph must
+// not hold (graph_safe: the merge sort, which launches kernels only).
 hipError_t launch_sort_set(const Masters& P, const DevSet& set, const DevSet& box_set, const SortBuffers& sb,
-                           int32_t* out, uint32_t* flags, hipStream_t st) {
+                           int32_t* out, uint32_t* flags, hipStream_t st, bool graph_safe) {
     const int n = set.count;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_box_init, dim3(1), dim3(64), 0, st, sb.bbox);
@@ -113,8 +122,10 @@ hipError_t launch_sort_set(const Masters& P, const DevSet& set, const DevSet& bo
     hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, st, P, set, (const uint32_t*)sb.bbox, sb.keys_in,
                        sb.vals_in, flags);
     size_t bytes = sb.tmp_bytes;
-    hipError_t e = rocprim::radix_sort_pairs(sb.tmp, bytes, sb.keys_in, sb.keys_out, sb.vals_in, sb.vals_out,
-                                             (unsigned)n, 0, 30, st);
+    hipError_t e = graph_safe ? rocprim::merge_sort(sb.tmp, bytes, sb.keys_in, sb.keys_out, sb.vals_in, sb.vals_out,
+                                                    (size_t)n, rocprim::less<uint32_t>(), st)
+                              : rocprim::radix_sort_pairs(sb.tmp, bytes, sb.keys_in, sb.keys_out, sb.vals_in,
+                                                          sb.vals_out, (unsigned)n, 0, 30, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sorted_list, dim3((n + 255) / 256), dim3(256), 0, st, set, (const int32_t*)sb.vals_out, out,
                        P.n, flags);

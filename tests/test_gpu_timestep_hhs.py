@@ -224,19 +224,25 @@ def test_hhs_adaptive_fixed_level_equivalence(ctx):
         assert (a - b).abs().max().item() <= 1e-13 * b.abs().max().item(), k
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_hhs_interval_graph_replays_match_eager(ctx, prec):
+@pytest.mark.parametrize("prec,mode", [("fp64", "unsorted"), ("mixed", "unsorted"), ("fp64", "any-size"),
+                                       ("mixed", "any-size")])
+def test_hhs_interval_graph_replays_match_eager(ctx, prec, mode):
     """One fixed-level interval captured into a HIP graph and replayed three times, with eager
     work and synchronisation between the replays, against three eager intervals on a copy of the
-    state (sorted mode off on both sides, as inside the graph): equal bit for bit after every
-    replay."""
+    state: equal bit for bit after every replay.  "unsorted": the sorted mode off on both sides;
+    "any-size": the sorted mode at every size, so that the graph holds Morton sorts (a merge sort
+    inside the graph, the radix sort eager), pair-symmetric sweeps (mixed and FP64) and two-set
+    sweeps."""
     n, kmax, tau = 3000, 4, 1e-3
     d = _cluster(n, 11)
     level = np.random.default_rng(14).choice([0, 1, 2, 4], size=n, p=[0.4, 0.3, 0.2, 0.1]).astype(np.int32)
     lv = torch.as_tensor(level, device="cuda")
     A, B = bf.Particles.from_numpy(d), bf.Particles.from_numpy(d)
     try:
-        ctx.set_spatial_sort(forces=False, gradient=False)
+        if mode == "unsorted":
+            ctx.set_spatial_sort(forces=False, gradient=False)
+        else:
+            ctx.set_spatial_sort(forces=True, gradient=True, any_size=True)
         g = ctx.capture_hhs_interval(A, lv, kmax, tau, prec=prec)
         for _ in range(3):
             g.launch()
