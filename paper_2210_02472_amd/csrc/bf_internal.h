@@ -216,6 +216,10 @@ hipError_t launch_label_round(const int32_t* edges, int64_t m, int64_t n, int32_
 hipError_t launch_label_count(const int32_t* label, int64_t n, int32_t* mark, int32_t* count, hipStream_t st);
 
 size_t level_sort_tmp_bytes(int n);
+// Compare the split cur[0..n) (slow part counts[0], on the device) with the previous split
+// prev[0..n_prev) (slow part n0_prev): diff[0] = slow parts differ, diff[1] = lists differ.
+hipError_t launch_split_diff(const int32_t* cur, int n, const int32_t* counts, const int32_t* prev, int n_prev,
+                             int n0_prev, int32_t* diff, hipStream_t st);
 hipError_t launch_pivot_flags(const DevSet& set, int64_t n, const double* dt0, const double* ff, const double* fb,
                               double tau, bool all_slow, int32_t* flag, uint32_t* flags, hipStream_t st);
 hipError_t launch_level_partition(const DevSet& set, int64_t n, const int32_t* level, int kmax, uint32_t* keys_in,

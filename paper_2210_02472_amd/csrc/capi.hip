@@ -1070,8 +1070,12 @@ BF_API int bf_timestep_assign(bf_ctx* c, const bf_particles* P, const bf_set* se
 }
 
 // stable partition of a set by level into `order`; level counts copied to the host (synchronising)
+// Stable partition of `set` by level; counts to the host (synchronising).  With prev, also
+// whether the new order equals the previous one (prev[0..n_prev), n0_prev of them at level 0):
+// same_host[0] = same level-0 part, same_host[1] = same list (diff_dev: two device ints).
 static int partition_impl(bf_ctx* c, const bf_set* set, int64_t n, const int32_t* level, int kmax, int32_t* order,
-                          int64_t* counts_host) {
+                          int64_t* counts_host, const int32_t* prev = nullptr, int n_prev = 0, int n0_prev = 0,
+                          int32_t* diff_dev = nullptr, bool* same_host = nullptr) {
     const int cnt = set->count;
     const size_t lb = ((size_t)std::max(cnt, 1) * 4 + 255) & ~size_t(255);
     const size_t tmp = level_sort_tmp_bytes(std::max(cnt, 1));
@@ -1083,10 +1087,18 @@ static int partition_impl(bf_ctx* c, const bf_set* set, int64_t n, const int32_t
     int32_t* vin = reinterpret_cast<int32_t*>(b + 256 + 2 * lb);
     BF_HIP(launch_level_partition(devset(set), n, level, kmax, kin, kout, vin, order, counts, b + 256 + 3 * lb, tmp,
                                   c->d_flags, c->stream));
-    int32_t h[64];
+    int32_t h[64], d[2] = {1, 1};
+    if (prev) {
+        BF_HIP(launch_split_diff(order, cnt, counts, prev, n_prev, n0_prev, diff_dev, c->stream));
+        BF_HIP(hipMemcpyAsync(d, diff_dev, sizeof(d), hipMemcpyDeviceToHost, c->stream));
+    }
     BF_HIP(hipMemcpyAsync(h, counts, sizeof(int32_t) * (kmax + 1), hipMemcpyDeviceToHost, c->stream));
     BF_HIP(hipStreamSynchronize(c->stream));
     for (int k = 0; k <= kmax; ++k) counts_host[k] = h[k];
+    if (same_host) {
+        same_host[0] = prev && d[0] == 0;
+        same_host[1] = prev && d[1] == 0;
+    }
     return BF_OK;
 }
 
@@ -1112,9 +1124,10 @@ struct HhsCtx {
     int64_t begin[65];  // begin[k] = first position of level k in `order`; begin[kmax+1] = total
     int kmax;
     double *asf, *gsf, *afsi, *gfsi;  // each 3n
-    // Fixed levels: results a later visit of the same level may take instead of recomputing.
-    // A particle drifts only in the FSI cycles of its own level, and those run only inside
-    // visits of its level, so between two visits of level k no particle of level >= k moves:
+    // Results a later visit of the same level may take instead of recomputing.  A particle
+    // drifts only in the FSI cycles of its own level, and those run only inside visits of its
+    // level, so between two visits of level k no particle of level >= k moves (with levels
+    // reassigned per visit the driver also checks that the level's sets are unchanged):
     //  - afsi holds level k's own accelerations at its final positions after each of its FSI
     //    cycles (the sets of the levels are disjoint), valid for the next one (a_ok[k]);
     //  - asf_lv[k] (3n, particle-indexed) holds level k's inter-level accelerations; the last
@@ -1135,8 +1148,8 @@ int interlevel_acc(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, doub
 }
 
 // One level of the HHS-FSI cycle (Sec. 2.2, Eq. hhsfsi-cycle) for slow set Sset and fast set
-// Fset (Bset = both, contiguous); `fast` advances F by tau/2 (the next level).  k is the fixed
-// level (results reused between its visits) or -1 (nothing reused).
+// Fset (Bset = both, contiguous); `fast` advances F by tau/2 (the next level).  k is the level
+// (results reused between its visits while h.a_ok / h.il_ok say so) or -1 (nothing reused).
 extern "C++" {
 template <class Fast>
 int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_set& Bset, double tau, int k,
@@ -1226,7 +1239,11 @@ struct HhsAdapt {
     double eta_ff, eta_fb;
     double *dtff, *dtfb;  // particle-indexed
     int32_t* flag;        // particle-indexed: 0 slow, 1 fast
-    int32_t* lists;       // (kmax + 1) buffers of `cap` entries: the split of the level-k set
+    int32_t* lists;       // 2 (kmax + 1) buffers of `cap` entries: the splits of the level-k set,
+                          // this visit's and the previous visit's
+    int32_t* diff;        // two device ints: does this split differ from the previous one
+    int which[64];        // buffer of level k's latest split
+    int64_t prev_n[64], prev_n0[64];  // its size and slow count (-1: none yet)
     int64_t cap;
     int max_level;
     int64_t nodes;
@@ -1245,14 +1262,30 @@ int hhs_adapt(const HhsCtx& h, HhsAdapt& A, const bf_set& P, int k, double tau) 
     }
     BF_HIP(launch_pivot_flags(devset(&P), n, A.dt0, top ? nullptr : A.dtff, top ? nullptr : A.dtfb, tau,
                               k >= h.kmax, A.flag, c->d_flags, c->stream));
-    int32_t* mine = A.lists + (size_t)k * A.cap;
+    // Level k's split goes to the buffer its previous split is not in, and is compared with it:
+    // the positions of level k's particles and deeper do not change between two visits of level
+    // k (a particle that drifted in between sits on a shallower level at the next visit, so the
+    // lists differ), so equal lists keep level k's own accelerations (same slow set) and its
+    // inter-level accelerations (same slow and fast sets) valid, as for fixed levels.
+    const bool had = A.prev_n[k] >= 0;
+    const int cur = had ? 1 - A.which[k] : 0;
+    int32_t* mine = A.lists + ((size_t)k * 2 + cur) * A.cap;
+    const int32_t* prev = had ? A.lists + ((size_t)k * 2 + (1 - cur)) * A.cap : nullptr;
     int64_t cnt[2];
-    if (int rc = partition_impl(c, &P, n, A.flag, 1, mine, cnt)) return rc;
+    bool same[2] = {false, false};
+    if (int rc = partition_impl(c, &P, n, A.flag, 1, mine, cnt, prev, had ? (int)A.prev_n[k] : 0,
+                                had ? (int)A.prev_n0[k] : 0, A.diff, same))
+        return rc;
+    A.which[k] = cur;
+    A.prev_n[k] = P.count;
+    A.prev_n0[k] = cnt[0];
+    if (!same[0]) h.a_ok[k] = false;
+    if (!same[1]) h.il_ok[k] = false;
     A.max_level = std::max(A.max_level, k);
     ++A.nodes;
     const bf_set Sset{mine, (int32_t)cnt[0], 0}, Fset{mine + cnt[0], (int32_t)cnt[1], 0};
     const bf_set Bset{mine, (int32_t)(cnt[0] + cnt[1]), 0};
-    return hhs_cycle(h, Sset, Fset, Bset, tau, -1, [&]() { return hhs_adapt(h, A, Fset, k + 1, 0.5 * tau); });
+    return hhs_cycle(h, Sset, Fset, Bset, tau, k, [&]() { return hhs_adapt(h, A, Fset, k + 1, 0.5 * tau); });
 }
 
 }  // namespace
@@ -1409,9 +1442,12 @@ BF_API int bf_hhs_interval_adaptive(bf_ctx* c, const bf_state* S, const bf_set* 
     if (n_levels) *n_levels = 0;
     if (set->count == 0) return BF_OK;
     const int64_t n = S->n, cap = set->count;
-    const size_t lb = ((size_t)(kmax + 1) * cap * 4 + 255) & ~size_t(255);
-    const size_t fb = ((size_t)n * 4 + 255) & ~size_t(255);
+    const size_t lb = ((size_t)2 * (kmax + 1) * cap * 4 + 255) & ~size_t(255);
+    const size_t fb = (((size_t)n * 4 + 255) & ~size_t(255)) + 256;  // the flags, then the split diff
     if (int rc = ensure(&c->scratch7, &c->scratch7_bytes, lb + fb + (size_t)14 * n * sizeof(double), c->stream))
+        return rc;
+    // every level may split: an inter-level acceleration array (3n) for each
+    if (int rc = ensure(&c->scratch11, &c->scratch11_bytes, (size_t)(kmax + 1) * 3 * n * sizeof(double), c->stream))
         return rc;
     HhsCtx h;
     h.c = c;
@@ -1431,10 +1467,18 @@ BF_API int bf_hhs_interval_adaptive(bf_ctx* c, const bf_state* S, const bf_set* 
     A.dtff = d + 12 * n;
     A.dtfb = d + 13 * n;
     A.flag = reinterpret_cast<int32_t*>(base + lb);
+    A.diff = reinterpret_cast<int32_t*>(base + lb + fb - 256);
     A.lists = reinterpret_cast<int32_t*>(base);
     A.cap = cap;
     A.max_level = -1;
     A.nodes = 0;
+    for (int k = 0; k < 64; ++k) {
+        A.which[k] = 0;
+        A.prev_n[k] = A.prev_n0[k] = -1;
+        h.a_ok[k] = h.il_ok[k] = false;
+        h.asf_lv[k] = k <= kmax ? static_cast<double*>(c->scratch11) + (size_t)k * 3 * n : nullptr;
+    }
+    h.reuse = true;
     const int rc = hhs_adapt(h, A, *set, 0, tau);
     if (max_level) *max_level = A.max_level;
     if (n_levels) *n_levels = A.nodes;

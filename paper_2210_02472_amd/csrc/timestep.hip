@@ -92,6 +92,32 @@ __global__ void k_clear_i32(int32_t* v, int n) {
     if (k < n) v[k] = 0;
 }
 
+// Is a new split of a set the same as the previous one?  cur and prev hold n and n_prev
+// entries, the first counts[0] (device) and n0_prev (host) of them slow.  diff[0] = 1 if the slow
+// parts differ, diff[1] = 1 if the whole lists differ (diff must be cleared before).
+__global__ void k_split_diff(const int32_t* cur, int n, const int32_t* counts, const int32_t* prev, int n_prev,
+                             int n0_prev, int32_t* diff) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n0 = counts[0];
+    if (k == 0) {
+        if (n0 != n0_prev) diff[0] = 1;
+        if (n0 != n0_prev || n != n_prev) diff[1] = 1;
+    }
+    if (k < n && k < n_prev && cur[k] != prev[k]) {
+        if (k < n0) diff[0] = 1;
+        diff[1] = 1;
+    }
+}
+
+hipError_t launch_split_diff(const int32_t* cur, int n, const int32_t* counts, const int32_t* prev, int n_prev,
+                             int n0_prev, int32_t* diff, hipStream_t st) {
+    hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, st, diff, 2);
+    const int m = std::max(1, std::min(n, n_prev));
+    hipLaunchKernelGGL(k_split_diff, dim3((m + 255) / 256), dim3(256), 0, st, cur, n, counts, prev, n_prev, n0_prev,
+                       diff);
+    return hipGetLastError();
+}
+
 size_t level_sort_tmp_bytes(int n) {
     size_t bytes = 0;
     rocprim::radix_sort_pairs(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr, (const int32_t*)nullptr,
