@@ -284,7 +284,10 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx *ctx, const bf_state *S, const b
  * with time-step >= pivot are slow, the others fast; on level kmax all are slow.  The cycle on
  * each level is the one of bf_hhs_interval.  Synchronises once per visited level (the split
  * sizes); max_level / n_levels (host, may be NULL) receive the deepest level reached and the
- * number of levels visited.  PN1.0 as in bf_hhs_interval. */
+ * number of levels visited.  PN1.0 as in bf_hhs_interval.  A visit whose slow set (and fast
+ * set) equals the previous visit's of the same level starts from that visit's own (and
+ * inter-level) accelerations, as bf_hhs_interval does; the context holds 3n doubles per level
+ * for that. */
 BF_API int bf_hhs_interval_adaptive(bf_ctx *ctx, const bf_state *S, const bf_set *set, const double *dt0,
                                     int kmax, double tau, double eta_ff, double eta_fb,
                                     const bf_fsi_params *prm, int *max_level, int64_t *n_levels);
