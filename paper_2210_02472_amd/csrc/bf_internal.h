@@ -266,6 +266,10 @@ hipError_t launch_energy(const EnergyArgs& a, hipStream_t st);
 hipError_t launch_kick(const bf_state& S, const DevSet& set, double h, const double* ax, const double* ay,
                        const double* az, double h2, const double* gx, const double* gy, const double* gz,
                        uint32_t* flags, hipStream_t st);
+// launch_kick followed by x += hd v over the same set, in one launch
+hipError_t launch_kick_drift(const bf_state& S, const DevSet& set, double h, const double* ax, const double* ay,
+                             const double* az, double h2, const double* gx, const double* gy, const double* gz,
+                             double hd, uint32_t* flags, hipStream_t st);
 hipError_t launch_drift(const bf_state& S, const DevSet& set, double h, uint32_t* flags, hipStream_t st);
 hipError_t launch_validate(const DevSet& set, int64_t n, uint32_t* flags, hipStream_t st);
 

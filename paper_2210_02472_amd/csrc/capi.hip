@@ -991,14 +991,16 @@ static int fsi_impl(bf_ctx* c, const bf_state* S, const bf_set* set, double dt, 
     if (!(flags & BF_A_VALID))
         if ((rc = acc())) return rc;
     const bool go = !c->dry;  // a sizing pass before a capture launches nothing
-    if (go) BF_HIP(launch_kick(*S, ds, dt / 6.0, ax, ay, az, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
-    if (go) BF_HIP(launch_drift(*S, ds, 0.5 * dt, c->d_flags, c->stream));
+    if (go)
+        BF_HIP(launch_kick_drift(*S, ds, dt / 6.0, ax, ay, az, 0.0, nullptr, nullptr, nullptr, 0.5 * dt, c->d_flags,
+                                 c->stream));
     if ((rc = acc())) return rc;
     Masters Mg = M;
     Mg.ax = ax; Mg.ay = ay; Mg.az = az;
     if ((rc = run_pairs(c, OP_GRAD, prec, Mg, set, set, G, e2, rfb, 0, 0, gx, gy, gz))) return rc;
-    if (go) BF_HIP(launch_kick(*S, ds, 2.0 * dt / 3.0, ax, ay, az, dt * dt / 24.0, gx, gy, gz, c->d_flags, c->stream));
-    if (go) BF_HIP(launch_drift(*S, ds, 0.5 * dt, c->d_flags, c->stream));
+    if (go)
+        BF_HIP(launch_kick_drift(*S, ds, 2.0 * dt / 3.0, ax, ay, az, dt * dt / 24.0, gx, gy, gz, 0.5 * dt, c->d_flags,
+                                 c->stream));
     if ((rc = acc())) return rc;
     if (go) BF_HIP(launch_kick(*S, ds, dt / 6.0, ax, ay, az, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
     if ((rc = pn_half_kick())) return rc;

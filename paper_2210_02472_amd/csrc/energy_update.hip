@@ -95,11 +95,12 @@ hipError_t launch_energy(const EnergyArgs& e, hipStream_t st) {
     return hipGetLastError();
 }
 
-// v_i += h (a_i + h2 g_i)
+// v_i += h (a_i + h2 g_i); with drift, then x_i += hd v_i (the kick and the drift that follows it
+// in the FSI cycle, one launch)
 __global__ __launch_bounds__(256) void k_kick(bf_state S, DevSet set, double h, const double* __restrict__ ax,
                                               const double* __restrict__ ay, const double* __restrict__ az, double h2,
                                               const double* __restrict__ gx, const double* __restrict__ gy,
-                                              const double* __restrict__ gz, uint32_t* flags) {
+                                              const double* __restrict__ gz, bool drift, double hd, uint32_t* flags) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= set.count) return;
     const int p = upd_particle(set, k, S.n, flags);
@@ -110,9 +111,16 @@ __global__ __launch_bounds__(256) void k_kick(bf_state S, DevSet set, double h, 
         ky = __builtin_fma(h2, gy[p], ky);
         kz = __builtin_fma(h2, gz[p], kz);
     }
-    S.vx[p] = __builtin_fma(h, kx, S.vx[p]);
-    S.vy[p] = __builtin_fma(h, ky, S.vy[p]);
-    S.vz[p] = __builtin_fma(h, kz, S.vz[p]);
+    const double vx = __builtin_fma(h, kx, S.vx[p]), vy = __builtin_fma(h, ky, S.vy[p]),
+                 vz = __builtin_fma(h, kz, S.vz[p]);
+    S.vx[p] = vx;
+    S.vy[p] = vy;
+    S.vz[p] = vz;
+    if (drift) {
+        S.x[p] = __builtin_fma(hd, vx, S.x[p]);
+        S.y[p] = __builtin_fma(hd, vy, S.y[p]);
+        S.z[p] = __builtin_fma(hd, vz, S.z[p]);
+    }
 }
 
 // x_i += h v_i
@@ -138,7 +146,16 @@ hipError_t launch_kick(const bf_state& S, const DevSet& set, double h, const dou
                        uint32_t* flags, hipStream_t st) {
     if (set.count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_kick, dim3((set.count + 255) / 256), dim3(256), 0, st, S, set, h, ax, ay, az, h2, gx, gy,
-                       gz, flags);
+                       gz, false, 0.0, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(const bf_state& S, const DevSet& set, double h, const double* ax, const double* ay,
+                             const double* az, double h2, const double* gx, const double* gy, const double* gz,
+                             double hd, uint32_t* flags, hipStream_t st) {
+    if (set.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kick, dim3((set.count + 255) / 256), dim3(256), 0, st, S, set, h, ax, ay, az, h2, gx, gy,
+                       gz, true, hd, flags);
     return hipGetLastError();
 }
 
