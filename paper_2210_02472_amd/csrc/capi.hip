@@ -262,7 +262,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     a.eps2 = eps2;
     a.eps2f = (float)eps2 + 1e-20f;
     float rfb2 = (float)(r_fb * r_fb);
-    if (op == OP_DT) rfb2 = std::max(rfb2, 1e-30f);  // the self pair of the FP32 time-step pass
+    if (op == OP_DT) rfb2 = std::max(rfb2, 1e-30f);  // coincident pairs of the FP32 time-step pass
     a.rfb2f = prec == BF_PREC_MIXED ? rfb2 : -1.0f;
     a.split = p.split;
     a.chunk = p.chunk;

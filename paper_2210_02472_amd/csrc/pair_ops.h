@@ -221,8 +221,8 @@ struct GradMixed {
 struct DtMixed {
     static constexpr int NC = 2;
     static constexpr bool kMixed = true, kMax = true, kCond = false;
-    struct Src { double4 p, v; };
-    struct Tgt { double x, y, z, vx, vy, vz; float gm; };
+    struct Src { double4 p, v; };  // v.w: the source's particle index
+    struct Tgt { double x, y, z, vx, vy, vz; float gm; int pi; };
     struct A32 { float ff, fb; };
     struct A64 { double ff, fb; };
     __device__ static Src load(const PairArgs& a, int q) {
@@ -233,21 +233,26 @@ struct DtMixed {
         t.x = a.P.x[p]; t.y = a.P.y[p]; t.z = a.P.z[p];
         t.vx = a.P.vx[p]; t.vy = a.P.vy[p]; t.vz = a.P.vz[p];
         t.gm = (float)(a.G * a.P.m[p]);
+        t.pi = p;
     }
     __device__ static void zero(A32& r) { r.ff = r.fb = 0.f; }
     __device__ static void zero(A64& r) { r.ff = r.fb = 0.0; }
     // moved out of reach: s^2 overflows to +inf in FP32, so both maxima get zero
     __device__ static void exclude(Src& s) { s.p.x = 1e150; }
+    // The target itself (matched by index) adds nothing and reports an infinite separation, so
+    // the close-pair re-evaluation (a threshold of 1e-30 on s^2, which a coincident distinct
+    // pair meets) does not fire on it.
     __device__ static float pair(A32& r, const Tgt& t, const Src& s, float /*eps2f*/) {
+        const bool self = (int)s.v.w == t.pi;
         const float dx = dif32(s.p.x, t.x), dy = dif32(s.p.y, t.y), dz = dif32(s.p.z, t.z);
         const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
         const float ux = dif32(s.v.x, t.vx), uy = dif32(s.v.y, t.vy), uz = dif32(s.v.z, t.vz);
         const float u2 = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
         const float ri = rsqrt32(r2);
         const float ri2 = ri * ri;
-        r.fb = fmaxf(r.fb, u2 * ri2);
-        r.ff = fmaxf(r.ff, ((unpack_gm(s.p.w) + t.gm) * ri2) * ri);
-        return r2;
+        r.fb = fmaxf(r.fb, self ? 0.f : u2 * ri2);
+        r.ff = fmaxf(r.ff, self ? 0.f : ((unpack_gm(s.p.w) + t.gm) * ri2) * ri);
+        return self ? __builtin_huge_valf() : r2;
     }
     __device__ static void fold(A64& o, const A32& i) { o.ff = fmax(o.ff, (double)i.ff); o.fb = fmax(o.fb, (double)i.fb); }
     __device__ static void redo(A64& o, const PairArgs& a, int pi, int q0, int len) {
