@@ -404,16 +404,19 @@ def test_fixups_are_rare(ctx, sort_mode, op):
     assert fixups <= (0.01 if op == "forces" else 0.05) * n, fixups
 
 
-@pytest.mark.parametrize("n_cancel", [10, 300])
-@pytest.mark.parametrize("op", ["forces", "gradient"])
-def test_fixup_of_cancelling_targets(ctx, n_cancel, op):
-    """Targets near the centre of a mirror-symmetric source cloud (20,000 sources: each point
-    and its reflection through the origin) feel sums that cancel to about 1e-3 of their
-    magnitude estimate, so every one is re-evaluated in FP64.  10 queued targets take the
-    fix-up's workgroup-per-target split, 300 its thread-per-target tiles; both must give the
-    oracle's FP64 sums to 1e-12 of the magnitude estimate."""
+@pytest.mark.parametrize("op,n_cancel,half", [("forces", 10, 10000), ("forces", 300, 10000), ("forces", 16, 3000),
+                                              ("forces", 100, 3000), ("gradient", 10, 10000),
+                                              ("gradient", 300, 10000)])
+def test_fixup_of_cancelling_targets(ctx, n_cancel, half, op):
+    """Targets near the centre of a mirror-symmetric source cloud (each point and its
+    reflection through the origin) feel sums that cancel to about 1e-3 of their magnitude
+    estimate, so every one is re-evaluated in FP64.  With 20,000 sources, 10 queued targets
+    take the fix-up's workgroup-per-target split, 300 its thread-per-target tiles.  With 6,000
+    sources the forces pass runs in the one-launch small kernel, whose failing targets (16:
+    one full workgroup, and 100) go to the same fix-up queue.  (Gradients of that smaller cloud
+    do not all cancel below the check's threshold.)  All must give the oracle's FP64 sums to
+    1e-12 of the magnitude estimate."""
     rng = np.random.default_rng(60 + n_cancel)
-    half = 10000
     p = rng.normal(size=(half, 3))
     pos = np.concatenate([p, -p, 1e-3 * rng.normal(size=(n_cancel, 3))])
     n = pos.shape[0]
@@ -432,6 +435,7 @@ def test_fixup_of_cancelling_targets(ctx, n_cancel, op):
         got = gather(ctx.force_gradient(Pd, ad, tg, prec="mixed"), tg)
     fixups = ctx.last_pass_stats()[0]
     assert fixups >= 0.9 * n_cancel, fixups
+    assert (ctx.last_pass_config()[2] == 16) == (n <= 6144)
     err = np.linalg.norm(got - ref, axis=1)
     assert np.all(err <= 1e-12 * mag), (err / mag).max()
 
