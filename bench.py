@@ -253,6 +253,48 @@ def run_workload(name, args):
                     "interval_ms": {"eager": eager, "eager_unsorted": eager_unsorted, "graph": graph,
                                     "adaptive": adaptive},
                     "adaptive_deepest_level": levels_seen[-1][0], "adaptive_levels_visited": levels_seen[-1][1]})
+    elif name == "bh-aux":
+        # The same 262,144-body cluster, every particle a target and a source: the passes around
+        # the force sweeps, each timed on its own (wall clock, synchronised, mean of 3 after one
+        # untimed call). Time-step assignment: pairwise free-fall and fly-by time-steps, jerk,
+        # criteria and levels, stable level partition; subsystems: neighbour search, labels, and
+        # an acceleration pass with intra-subsystem pairs excluded; the FP64 energy.
+        d, _, _ = ics.config5_bh_cluster()
+        n = len(d["m"])
+        kmax, tau = 7, 1.0 / 4096
+        P = bf.Particles.from_numpy(d)
+
+        def wall(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / reps * 1e3
+
+        out = {}
+        out["forces_ms"] = wall(lambda: ctx.forces(P, prec="mixed"))
+        a = ctx.forces(P, prec="mixed")
+        g = ctx.force_gradient(P, a, prec="mixed")
+        out["dt_min_ms"] = wall(lambda: ctx.dt_min(P, prec="mixed"))
+        out["jerk_ms"] = wall(lambda: ctx.jerk(P, prec="mixed"))
+        dff, dfb = ctx.dt_min(P, prec="mixed")
+        j = ctx.jerk(P, prec="mixed")
+        out["timestep_assign_ms"] = wall(lambda: ctx.timestep_assign(P, None, dff, dfb, a, g, j, tau=tau, kmax=kmax))
+        _, lv = ctx.timestep_assign(P, None, dff, dfb, a, g, j, tau=tau, kmax=kmax)
+        out["level_partition_ms"] = wall(lambda: ctx.level_partition(None, n, lv, kmax))
+        _, counts = ctx.level_partition(None, n, lv, kmax)
+        out["neighbours_ms"] = wall(lambda: ctx.neighbours(P, tau=tau))
+        edges = ctx.neighbours(P, tau=tau)
+        out["subsystems_ms"] = wall(lambda: ctx.subsystems(n, edges))
+        label, nsub = ctx.subsystems(n, edges)
+        ctx.set_subsystems(label)
+        out["forces_excluded_ms"] = wall(lambda: ctx.forces(P, prec="mixed"))
+        ctx.set_subsystems(None)
+        out["energy_ms"] = wall(lambda: ctx.energy(P))
+        rec.update({"n": n, "pairs_per_pass": float(n) * n, "level_counts": [int(c) for c in counts],
+                    "neighbour_pairs": int(edges.shape[0]), "subsystems": int(nsub), "ms": out})
     ctx.close()
     print(json.dumps(rec), flush=True)
 
@@ -284,7 +326,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 2 GiB device-to-device copy kernel first (HBM counter calibration)")
     ap.add_argument("--workload", default="king1m",
-                    choices=["king1m", "plummer1k-fsi", "plummer64k-level", "ensemble256", "bh-levels", "bh-hhs"],
+                    choices=["king1m", "plummer1k-fsi", "plummer64k-level", "ensemble256", "bh-levels", "bh-hhs",
+                             "bh-aux"],
                     help="king1m (default): the headline sweep; the others measure the remaining "
                          "workloads and print their own JSON line")
     args = ap.parse_args()
