@@ -232,6 +232,16 @@ def run_workload(name, args):
             torch.cuda.synchronize()
             return (time.perf_counter() - t) / reps * 1e3
 
+        dt0 = torch.as_tensor(1.5 * tau / 2.0 ** lv.astype(np.float64), device="cuda")
+        if args.hhs_adaptive_only:  # for a kernel trace of the reassigned interval alone
+            seen = []
+            adaptive = wall(lambda: seen.append(ctx.hhs_interval_adaptive(P, dt0, kmax, tau, 0.05, 0.05,
+                                                                            prec="mixed")), 2)
+            rec.update({"n": n, "kmax": kmax, "tau": tau, "interval_ms": {"adaptive": adaptive},
+                        "adaptive_levels_visited": seen[-1][1]})
+            ctx.close()
+            print(json.dumps(rec), flush=True)
+            return
         eager = wall(lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed"), 3)
         if args.hhs_eager_only:  # for a kernel trace of the eager interval alone
             rec.update({"n": n, "kmax": kmax, "tau": tau, "interval_ms": {"eager": eager}})
@@ -244,7 +254,6 @@ def run_workload(name, args):
         ctx.set_spatial_sort(False, False)  # reference: every pass unsorted
         eager_unsorted = wall(lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed"), 3)
         ctx.set_spatial_sort(True, True)
-        dt0 = torch.as_tensor(1.5 * tau / 2.0 ** lv.astype(np.float64), device="cuda")
         levels_seen = []
         adaptive = wall(lambda: levels_seen.append(ctx.hhs_interval_adaptive(P, dt0, kmax, tau, 0.05, 0.05,
                                                                                 prec="mixed")), 2)
@@ -317,6 +326,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hhs-eager-only", action="store_true",
                     help="bh-hhs workload: time only the eager interval (for kernel traces)")
+    ap.add_argument("--hhs-adaptive-only", action="store_true",
+                    help="bh-hhs workload: time only the interval with reassigned time-steps (for kernel traces)")
     ap.add_argument("--sample", type=int, default=256, help="targets sampled for the error check")
     ap.add_argument("--spatial-sort", default="default", choices=["default", "off", "acc", "grad", "both", "directed"],
                     help="passes that use the spatially sorted mixed kernels (default: the library's; directed: sorted without the pair-symmetric sweep)")
