@@ -79,6 +79,15 @@ def test_level_partition_is_stable_sort(ctx):
     assert counts == [int(np.sum(level[sub] == k)) for k in range(kmax + 1)]
     order, counts = ctx.level_partition(None, n, lv, kmax)
     assert np.array_equal(order.cpu().numpy(), np.argsort(level, kind="stable"))
+    # many workgroups and a ragged tail, every level up to the largest kmax, most particles on
+    # level 0 (the counts are gathered per workgroup, then added once per level)
+    n, kmax = 300001, 63
+    level = np.minimum(rng.geometric(0.7, n) - 1, kmax).astype(np.int32)
+    level[rng.choice(n, kmax + 1, replace=False)] = np.arange(kmax + 1, dtype=np.int32)
+    lv = torch.as_tensor(level, device="cuda")
+    order, counts = ctx.level_partition(None, n, lv, kmax)
+    assert counts == np.bincount(level, minlength=kmax + 1).tolist()
+    assert np.array_equal(order.cpu().numpy(), np.argsort(level, kind="stable"))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
