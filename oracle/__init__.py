@@ -361,23 +361,48 @@ def hhs_interval(p: Particles, levels: np.ndarray, tau: float, subset=None, leve
     return p
 
 
+def level_timesteps(p: Particles, idx, G: float = 1.0, eps2: float = 0.0, eta_ff: float = 0.2,
+                    eta_fb: float = 0.2, eta_grad: float = 0.1, eta_jerk: float = 0.1):
+    """Time-steps of the particles `idx` from the particles of `idx` alone, as a level of the
+    hierarchy assigns them (Sec. 2.2): the pairwise free-fall and fly-by criteria (Sec. 3.5.3)
+    and the per-particle gradient (Sec. 3.5.4, Eqs. dt-nabla1, dt-nabla2) and jerk (Sec. 3.5.5)
+    criteria, with the acceleration, its gradient sum and the jerk all summed over the level's
+    particles (softened with eps2; the pairwise criteria are unsoftened).  A criterion with
+    eta <= 0 is left out.  Returns one time-step per entry of idx."""
+    idx = np.asarray(idx)
+    ff, fb = dt_min(p, idx, idx, G, max(eta_ff, 0.0), max(eta_fb, 0.0))
+    if eta_ff <= 0:
+        ff = np.full(idx.size, np.inf)
+    if eta_fb <= 0:
+        fb = np.full(idx.size, np.inf)
+    a = forces(p, idx, idx, G, eps2)
+    full = np.zeros((p.n, 3))
+    full[idx] = a
+    gs = gradient(p, full, idx, idx, G, eps2) if eta_grad > 0 else None
+    jr = jerk(p, idx, idx, G, eps2) if eta_jerk > 0 else None
+    return timestep_criteria(p, idx, ff, fb, a, gs, jr, eta_grad, eta_jerk)
+
+
 def hhs_interval_adaptive(p: Particles, dt0: np.ndarray, tau: float, kmax: int, eta_ff: float = 0.2,
-                          eta_fb: float = 0.2, subset=None, level: int = 0, G: float = 1.0,
-                          eps2: float = 0.0, trace=None) -> Particles:
+                          eta_fb: float = 0.2, eta_grad: float = 0.1, eta_jerk: float = 0.1,
+                          subset=None, level: int = 0, G: float = 1.0, eps2: float = 0.0,
+                          trace=None) -> Particles:
     """One HHS-FSI interval of length tau over `subset` in which every hierarchy level begins by
-    assigning time-steps and dividing its particles into slow (dt >= pivot) and fast (dt < pivot)
-    sets (Sec. 2.2).  `dt0` (particle-indexed) holds the time-steps assigned at the start of the
-    interval from all particles; on deeper levels a particle's time-step is the pairwise
-    free-fall / fly-by time-step over the particles of that level, capped by its dt0 so that it
-    cannot grow within the interval (Sec. 3.5.1, the level-0 minimum).  Particles on level kmax
-    are all slow.  `trace`, if a list, receives (level, pivot, slow count, fast count, smallest
-    distance of a time-step to the pivot relative to the pivot) per visited level."""
+    assigning time-steps to its particles and dividing them into slow (dt >= pivot) and fast
+    (dt < pivot) sets (Sec. 2.2).  `dt0` (particle-indexed) holds the time-steps assigned at the
+    start of the interval from all particles; they are level 0's.  On a deeper level every
+    criterion is evaluated again over the particles of that level alone (`level_timesteps`:
+    free-fall, fly-by, both gradient criteria and the jerk criterion) and the result is capped
+    by dt0, so that a time-step cannot grow within the interval (Sec. 3.5.1, the level-0
+    minimum).  Particles on level kmax are all slow.  `trace`, if a list, receives (level,
+    pivot, slow count, fast count, smallest distance of a time-step to the pivot relative to
+    the pivot) per visited level."""
     idx = _idx(subset, p.n)
     if level == 0:
         dt = np.asarray(dt0, float)[idx]
     else:
-        ff, fb = dt_min(p, idx, idx, G, eta_ff, eta_fb)
-        dt = np.minimum(np.minimum(ff, fb), np.asarray(dt0, float)[idx])
+        dt = level_timesteps(p, idx, G, eps2, eta_ff, eta_fb, eta_grad, eta_jerk)
+        dt = np.minimum(dt, np.asarray(dt0, float)[idx])
     if level >= kmax:
         slow = np.ones(idx.size, dtype=bool)
     else:
@@ -386,7 +411,8 @@ def hhs_interval_adaptive(p: Particles, dt0: np.ndarray, tau: float, kmax: int, 
     if trace is not None:
         gap = float(np.min(np.abs(dt / tau - 1.0))) if idx.size else np.inf
         trace.append((level, tau, S.size, F.size, gap))
-    sub = dict(eta_ff=eta_ff, eta_fb=eta_fb, G=G, eps2=eps2, trace=trace)
+    sub = dict(eta_ff=eta_ff, eta_fb=eta_fb, eta_grad=eta_grad, eta_jerk=eta_jerk, G=G, eps2=eps2,
+               trace=trace)
     if F.size == 0:
         if S.size:
             fsi_step(p, tau, S, G, eps2)
@@ -410,7 +436,6 @@ def hhs_interval_adaptive(p: Particles, dt0: np.ndarray, tau: float, kmax: int, 
     a = _interlevel_acc(p, S, F, G, eps2)
     _kick(p, both, a[both], tau / 6)
     return p
-
 
 
 # ---------------------------------------------------------------------------------------------

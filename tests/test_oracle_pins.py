@@ -482,7 +482,8 @@ def test_hhs_adaptive_reduces_to_fixed_levels():
     dt0 = 1.5 * tau / 2.0 ** lv
     A, B = P0.copy(), P0.copy()
     trace = []
-    oracle.hhs_interval_adaptive(A, dt0, tau, kmax, eta_ff=1e9, eta_fb=1e9, trace=trace)
+    oracle.hhs_interval_adaptive(A, dt0, tau, kmax, eta_ff=1e9, eta_fb=1e9, eta_grad=1e9, eta_jerk=1e9,
+                                 trace=trace)
     oracle.hhs_interval(B, lv, tau)
     for k in ("x", "y", "z", "vx", "vy", "vz"):
         np.testing.assert_array_equal(getattr(A, k), getattr(B, k))
@@ -505,14 +506,15 @@ def test_hhs_adaptive_level_zero_cap():
     dt0 = np.full(P0.n, 1.0)
     dt0[3] = 0.3e-3  # fast at pivots 1e-3 and 0.5e-3, slow at 0.25e-3
     trace = []
-    oracle.hhs_interval_adaptive(P0.copy(), dt0, 1e-3, 6, eta_ff=1e9, eta_fb=1e9, trace=trace)
+    oracle.hhs_interval_adaptive(P0.copy(), dt0, 1e-3, 6, eta_ff=1e9, eta_fb=1e9, eta_grad=1e9, eta_jerk=1e9,
+                                 trace=trace)
     assert [(t[0], t[2], t[3]) for t in trace] == [(0, 29, 1), (1, 0, 1), (2, 1, 0), (2, 1, 0),
                                                    (1, 0, 1), (2, 1, 0), (2, 1, 0)]
 
 
 def test_hhs_adaptive_energy_error_scales_as_eta_to_the_fourth():
-    """Time-steps proportional to eta on every level: the energy error of the fourth-order
-    HHS-FSI falls as eta^4 (Sec. 5.1, Eq. fourthorder).  Softened 64-body Plummer sphere,
+    """Time-steps proportional to eta on every level (every criterion scaled by the same eta):
+    the energy error of the fourth-order HHS-FSI falls as eta^4 (Sec. 5.1, Eq. fourthorder).  Softened 64-body Plummer sphere,
     eight intervals; log-log slope of the largest relative energy error against eta."""
     d = ics.plummer_cluster(ics.rng_for(301, 0), 64, "equal")
     eps2, tau, kmax = 1e-2, 1.0 / 8, 12
@@ -524,14 +526,85 @@ def test_hhs_adaptive_energy_error_scales_as_eta_to_the_fourth():
         p0 = (P.m[:, None] * P.vel()).sum(axis=0)
         emax = 0.0
         for _ in range(8):
-            ff, fb = oracle.dt_min(P, eta_ff=eta, eta_fb=eta)
-            oracle.hhs_interval_adaptive(P, np.minimum(ff, fb), tau, kmax, eta, eta, eps2=eps2)
+            dt0 = oracle.level_timesteps(P, np.arange(P.n), eps2=eps2, eta_ff=eta, eta_fb=eta, eta_grad=eta,
+                                         eta_jerk=eta)
+            oracle.hhs_interval_adaptive(P, dt0, tau, kmax, eta, eta, eta, eta, eps2=eps2)
             emax = max(emax, abs(sum(oracle.energy(P, eps2=eps2)) / E0 - 1))
         errs.append(emax)
         momenta.append(np.abs((P.m[:, None] * P.vel()).sum(axis=0) - p0).max())
     slope = np.polyfit(np.log(etas), np.log(errs), 1)[0]
     assert 3.3 < slope < 4.8, (slope, errs)
     assert max(momenta) < 1e-15
+
+
+def _moving_pair(r, vrel, vbulk, m1, m2):
+    """Two particles on the x axis, separation r, relative velocity vrel (second minus first),
+    both moving with the bulk velocity vbulk as well."""
+    M = m1 + m2
+    vb = np.asarray(vbulk, float)
+    v1 = vb - m2 / M * np.asarray(vrel, float)
+    v2 = vb + m1 / M * np.asarray(vrel, float)
+    return Particles.from_dict({"x": np.array([-m2 / M * r, m1 / M * r]), "y": np.zeros(2), "z": np.zeros(2),
+                                "vx": np.array([v1[0], v2[0]]), "vy": np.array([v1[1], v2[1]]),
+                                "vz": np.array([v1[2], v2[2]]), "m": np.array([m1, m2])})
+
+
+def test_hhs_adaptive_jerk_criterion_splits_a_level():
+    """The jerk criterion of Sec. 3.5.5 is evaluated on the deeper level itself (Sec. 2.2: each
+    level begins by assigning time-steps).  Two bodies falling straight at each other: the jerk
+    of either is 2 G m_other |v| / r^3 (the tidal tensor of one point mass applied to a radial
+    relative velocity doubles it), so eta_j |a|/|j| = eta_j r / (2 |v|), half the fly-by
+    time-step eta_fb r/|v| for eta_j = eta_fb.  With r = 0.01, |v| = 2.5 and eta = 0.2 that is
+    4e-4 against a fly-by 8e-4, a free-fall 0.2 (r^3/GM)^(1/2) = 3.65e-3 and gradient
+    criteria above 6e-3: the jerk alone moves both below the level-1 pivot 5e-4, and they come
+    to rest on level 2 (pivot 2.5e-4).  Without the jerk criterion both stay slow on level 1."""
+    m1, m2, r, v, tau = 1e-3, 2e-3, 0.01, 2.5, 1e-3
+    M = m1 + m2
+    jerk_dt = 0.2 * r / (2 * v)
+    assert abs(jerk_dt - 4e-4) < 1e-15
+    assert 0.2 * math.sqrt(r ** 3 / M) > tau / 2 and 0.2 * r / v > tau / 2
+    dt0 = np.full(2, 0.9 * tau)  # both fast on level 0, slow at any deeper pivot by the cap
+    tr_on, tr_off = [], []
+    oracle.hhs_interval_adaptive(_moving_pair(r, [-v, 0, 0], [0, 0, 0], m1, m2), dt0, tau, 6, eta_ff=0.2,
+                                 eta_fb=0.2, eta_grad=0.1, eta_jerk=0.2, trace=tr_on)
+    oracle.hhs_interval_adaptive(_moving_pair(r, [-v, 0, 0], [0, 0, 0], m1, m2), dt0, tau, 6, eta_ff=0.2,
+                                 eta_fb=0.2, eta_grad=0.1, eta_jerk=0.0, trace=tr_off)
+    assert [(t[0], t[2], t[3]) for t in tr_off] == [(0, 0, 2), (1, 2, 0), (1, 2, 0)]
+    assert [(t[0], t[2], t[3]) for t in tr_on] == [(0, 0, 2), (1, 0, 2), (2, 2, 0), (2, 2, 0),
+                                                   (1, 0, 2), (2, 2, 0), (2, 2, 0)]
+    # first level-1 visit: the state is the initial one, so its closest time-step to the
+    # pivot is the jerk time-step 4e-4 (fly-by 8e-4 is farther from 5e-4)
+    assert abs(tr_on[1][4] - abs(jerk_dt / (tau / 2) - 1)) < 1e-9
+
+
+def test_hhs_adaptive_gradient_criterion_splits_a_level():
+    """The gradient criteria (Sec. 3.5.4, Eqs. dt-nabla1, dt-nabla2) evaluated on the deeper
+    level.  Two bodies at rest relative to each other (no fly-by or jerk bound), moving
+    together with |v| = 1.  For two bodies |Gsum_i| = 2 G^2 m_j M / r^5, so with g' = Gsum/24
+    the criterion of Eq. dt-nabla1 is eta (12 |v| r^5 / (G^2 m_j M))^(1/3) and that of Eq.
+    dt-nabla2 is eta (12 r^3 / (G M))^(1/2).  With r^3 = GM 1e-6 and eta_grad = 0.1 these are
+    2.32e-4 (lighter body, j the heavier one), 2.92e-4 (heavier body) and 3.46e-4 (both),
+    against a free-fall time-step of 1e-3 at eta_ff = 1: level 1 (pivot 5e-4) passes both on,
+    level 2 (pivot 2.5e-4) keeps the heavier body slow and the lighter one fast."""
+    m1, m2, tau = 1e-3, 2e-3, 1e-3
+    M = m1 + m2
+    r = (M * 1e-6) ** (1.0 / 3.0)
+    nab1 = [0.1 * (12 * 1.0 * r ** 5 / (mj * M)) ** (1 / 3) for mj in (m2, m1)]
+    nab2 = 0.1 * math.sqrt(12 * r ** 3 / M)
+    dt_hand = [min(nab1[0], nab2, 1e-3), min(nab1[1], nab2, 1e-3)]
+    assert tau / 4 < dt_hand[1] < tau / 2 and tau / 8 < dt_hand[0] < tau / 4
+    dt0 = np.full(2, 0.9 * tau)
+    tr_on, tr_off = [], []
+    oracle.hhs_interval_adaptive(_moving_pair(r, [0, 0, 0], [0, 1.0, 0], m1, m2), dt0, tau, 6, eta_ff=1.0,
+                                 eta_fb=0.2, eta_grad=0.1, eta_jerk=0.1, trace=tr_on)
+    oracle.hhs_interval_adaptive(_moving_pair(r, [0, 0, 0], [0, 1.0, 0], m1, m2), dt0, tau, 6, eta_ff=1.0,
+                                 eta_fb=0.2, eta_grad=0.0, eta_jerk=0.1, trace=tr_off)
+    # level 1, then level 2 with the state still the initial one (S empty on levels 0 and 1)
+    assert [(t[0], t[2], t[3]) for t in tr_on[:3]] == [(0, 0, 2), (1, 0, 2), (2, 1, 1)]
+    assert [(t[0], t[2], t[3]) for t in tr_off[:2]] == [(0, 0, 2), (1, 2, 0)]
+    # the level-2 trace's closest time-step to the pivot 2.5e-4 is one of the two hand values
+    gap = min(abs(d / (tau / 4) - 1) for d in dt_hand)
+    assert abs(tr_on[2][4] - gap) < 1e-9
 
 
 # --------------------------------------------------------------------------------------------
