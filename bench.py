@@ -214,8 +214,8 @@ def run_workload(name, args):
         # One HHS-FSI interval over the same cluster and levels (Newtonian part, mixed precision):
         # eager device driver, the same interval replayed from a HIP graph, the eager interval with
         # every pass unsorted, and the interval with time-steps reassigned on every level (the
-        # initial time-steps put each particle on its level; pairwise time-steps over each level's
-        # particles may move it deeper)
+        # initial time-steps put each particle on its level; the free-fall, fly-by, gradient and
+        # jerk time-steps over each level's particles may move it deeper)
         d, bh, lv = ics.config5_bh_cluster()
         n = len(d["m"])
         kmax = int(lv.max())
@@ -235,7 +235,7 @@ def run_workload(name, args):
         dt0 = torch.as_tensor(1.5 * tau / 2.0 ** lv.astype(np.float64), device="cuda")
         if args.hhs_adaptive_only:  # for a kernel trace of the reassigned interval alone
             seen = []
-            adaptive = wall(lambda: seen.append(ctx.hhs_interval_adaptive(P, dt0, kmax, tau, 0.05, 0.05,
+            adaptive = wall(lambda: seen.append(ctx.hhs_interval_adaptive(P, dt0, kmax, tau, 0.05, 0.05, 0.05, 0.05,
                                                                             prec="mixed")), 2)
             rec.update({"n": n, "kmax": kmax, "tau": tau, "interval_ms": {"adaptive": adaptive},
                         "adaptive_levels_visited": seen[-1][1]})
@@ -255,8 +255,8 @@ def run_workload(name, args):
         eager_unsorted = wall(lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed"), 3)
         ctx.set_spatial_sort(True, True)
         levels_seen = []
-        adaptive = wall(lambda: levels_seen.append(ctx.hhs_interval_adaptive(P, dt0, kmax, tau, 0.05, 0.05,
-                                                                                prec="mixed")), 2)
+        adaptive = wall(lambda: levels_seen.append(ctx.hhs_interval_adaptive(P, dt0, kmax, tau, 0.05, 0.05, 0.05,
+                                                                                0.05, prec="mixed")), 2)
         counts = np.bincount(lv, minlength=kmax + 1)
         rec.update({"n": n, "kmax": kmax, "tau": tau, "particles_per_level": counts.tolist(),
                     "interval_ms": {"eager": eager, "eager_unsorted": eager_unsorted, "graph": graph,

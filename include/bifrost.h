@@ -279,18 +279,33 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx *ctx, const bf_state *S, const b
  * pivot; Sec. 3.5.1: a time-step cannot grow within the interval).  dt0 (device FP64,
  * particle-indexed) holds the time-steps assigned at the start of the interval from all
  * particles (e.g. bf_timestep_assign); it splits level 0.  On a deeper level k with particle set
- * P and pivot tau / 2^k, a particle's time-step is min(dt0, dt_ff, dt_fb) with the pairwise
- * free-fall / fly-by time-steps over P (eta_ff, eta_fb > 0, precision prm->prec); particles
- * with time-step >= pivot are slow, the others fast; on level kmax all are slow.  The cycle on
- * each level is the one of bf_hhs_interval.  Synchronises once per visited level (the split
- * sizes); max_level / n_levels (host, may be NULL) receive the deepest level reached and the
- * number of levels visited.  PN1.0 as in bf_hhs_interval.  A visit whose slow set (and fast
- * set) equals the previous visit's of the same level starts from that visit's own (and
- * inter-level) accelerations, as bf_hhs_interval does; the context holds 3n doubles per level
- * for that. */
+ * P and pivot tau / 2^k, every criterion is evaluated again over P alone: the pairwise free-fall
+ * and fly-by time-steps (Sec. 3.5.3; eta_ff, eta_fb > 0; unsoftened), both gradient criteria
+ * (Sec. 3.5.4, Eqs. dt-nabla1, dt-nabla2; eta_grad, with the acceleration and the gradient sum
+ * over P) and the jerk criterion (Sec. 3.5.5; eta_jerk, the jerk over P), as bf_timestep_assign
+ * combines them; eta_grad = 0 or eta_jerk = 0 leaves that criterion out.  A particle's time-step
+ * is the minimum of these and dt0; particles with time-step >= pivot are slow, the others fast;
+ * on level kmax all are slow.  The passes run in precision prm->prec, softened with prm->eps2
+ * except the pairwise criteria.  The cycle on each level is the one of bf_hhs_interval.
+ * Synchronises once per visited level (the split sizes); max_level / n_levels (host, may be NULL)
+ * receive the deepest level reached and the number of levels visited.  PN1.0 as in
+ * bf_hhs_interval.  A visit whose slow set (and fast set) equals the previous visit's of the same
+ * level starts from that visit's own (and inter-level) accelerations, as bf_hhs_interval does,
+ * unless a shallower level changed its split or ran with an empty fast set since (then its
+ * particles may have drifted); the context holds 3n doubles per level for that.  Errors:
+ * BF_ERR_ARG for a NULL dt0, kmax outside [0, 63], tau not finite and > 0, eta_ff or eta_fb not
+ * finite and > 0, eta_grad or eta_jerk negative or not finite; otherwise as bf_hhs_interval. */
 BF_API int bf_hhs_interval_adaptive(bf_ctx *ctx, const bf_state *S, const bf_set *set, const double *dt0,
-                                    int kmax, double tau, double eta_ff, double eta_fb,
-                                    const bf_fsi_params *prm, int *max_level, int64_t *n_levels);
+                                    int kmax, double tau, double eta_ff, double eta_fb, double eta_grad,
+                                    double eta_jerk, const bf_fsi_params *prm, int *max_level,
+                                    int64_t *n_levels);
+
+/* Whether the HHS drivers (bf_hhs_interval, bf_hhs_interval_adaptive, captured intervals) keep a
+ * level's own and inter-level accelerations between its visits (on = 1, the default) or
+ * recompute every one of them (on = 0).  Kernels are deterministic, so both give the same
+ * result bit for bit; the switch exists to check exactly that.  Errors: BF_ERR_ARG for a NULL
+ * context. */
+BF_API int bf_set_hhs_reuse(bf_ctx *ctx, int on);
 
 /* Elementwise kicks and drifts used by integrator drivers (FP64, over the set):
  *   bf_kick:  v_i += h (a_i + h2 g_i)   (g may be NULL, then h2 is ignored)

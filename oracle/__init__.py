@@ -396,7 +396,7 @@ def hhs_interval_adaptive(p: Particles, dt0: np.ndarray, tau: float, kmax: int, 
     by dt0, so that a time-step cannot grow within the interval (Sec. 3.5.1, the level-0
     minimum).  Particles on level kmax are all slow.  `trace`, if a list, receives (level,
     pivot, slow count, fast count, smallest distance of a time-step to the pivot relative to
-    the pivot) per visited level."""
+    the pivot, slow particles, fast particles) per visited level, in visiting order."""
     idx = _idx(subset, p.n)
     if level == 0:
         dt = np.asarray(dt0, float)[idx]
@@ -410,7 +410,7 @@ def hhs_interval_adaptive(p: Particles, dt0: np.ndarray, tau: float, kmax: int, 
     S, F = idx[slow], idx[~slow]
     if trace is not None:
         gap = float(np.min(np.abs(dt / tau - 1.0))) if idx.size else np.inf
-        trace.append((level, tau, S.size, F.size, gap))
+        trace.append((level, tau, S.size, F.size, gap, S.copy(), F.copy()))
     sub = dict(eta_ff=eta_ff, eta_fb=eta_fb, eta_grad=eta_grad, eta_jerk=eta_jerk, G=G, eps2=eps2,
                trace=trace)
     if F.size == 0:

@@ -90,7 +90,7 @@ def load_library(path: str = LIB_PATH):
         "bf_level_partition": [_vp, S, _i64, _vp, _int, _vp, ctypes.POINTER(_i64)],
         "bf_hhs_interval": [_vp, ST, S, _vp, _int, _d, FP],
         "bf_graph_capture_hhs_interval": [_vp, ST, S, _vp, _int, _d, FP, ctypes.POINTER(_vp)],
-        "bf_hhs_interval_adaptive": [_vp, ST, S, _vp, _int, _d, _d, _d, FP, ctypes.POINTER(_int),
+        "bf_hhs_interval_adaptive": [_vp, ST, S, _vp, _int, _d, _d, _d, _d, _d, FP, ctypes.POINTER(_int),
                                      ctypes.POINTER(_i64)],
         "bf_drift": [_vp, ST, S, _d],
         "bf_forces_batched": [_vp, P, _i32, _vp, _vp, _vp, _i64, _i64, _d, _d, _int, _d, _vp, _vp, _vp],
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "bf_set_config": [_vp, _int, _int, _int, _int, _int],
         "bf_enable_timing": [_vp, _int],
         "bf_set_spatial_sort": [_vp, _int, ctypes.c_double],
+        "bf_set_hhs_reuse": [_vp, _int],
         "bf_neighbours": [_vp, P, S, S, _d, _d, _d, _d, _d, _vp, _i64, ctypes.POINTER(_i64)],
         "bf_subsystems": [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i64)],
         "bf_set_subsystems": [_vp, _vp, _i64],
@@ -399,18 +400,23 @@ class Context:
         return Graph(self, h, keep=(P, level, s))
 
     def hhs_interval_adaptive(self, P: Particles, dt0: torch.Tensor, kmax: int, tau: float, eta_ff=0.2, eta_fb=0.2,
-                              subset=None, G=1.0, eps2=0.0, prec="fp64", r_fb=0.0):
-        """One HHS-FSI interval with time-steps assigned on every level (capped by dt0), in
-        place.  Returns (deepest level reached, number of levels visited)."""
+                              eta_grad=0.1, eta_jerk=0.1, subset=None, G=1.0, eps2=0.0, prec="fp64", r_fb=0.0):
+        """One HHS-FSI interval with time-steps assigned on every level from all criteria over
+        the level's particles (capped by dt0), in place.  Returns (deepest level reached, number
+        of levels visited)."""
         s = ParticleSet.of(subset, P.n)
         _need(dt0, torch.float64, P.n, "dt0")
         prm = _FsiParams(float(G), float(eps2), PRECISIONS[prec], float(r_fb), None, 0, 1.0)
         ml, nl = _int(0), _i64(0)
         _check("bf_hhs_interval_adaptive",
                _lib.bf_hhs_interval_adaptive(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()), _ptr(dt0),
-                                             int(kmax), float(tau), float(eta_ff), float(eta_fb), ctypes.byref(prm),
-                                             ctypes.byref(ml), ctypes.byref(nl)))
+                                             int(kmax), float(tau), float(eta_ff), float(eta_fb), float(eta_grad),
+                                             float(eta_jerk), ctypes.byref(prm), ctypes.byref(ml), ctypes.byref(nl)))
         return ml.value, nl.value
+
+    def set_hhs_reuse(self, on: bool = True) -> None:
+        """Keep (True, the default) or recompute every acceleration between visits of an HHS level."""
+        _check("bf_set_hhs_reuse", _lib.bf_set_hhs_reuse(self._h, 1 if on else 0))
 
     def kick(self, P: Particles, subset, h, acc, h2=0.0, grad=None):
         s = ParticleSet.of(subset, P.n)

@@ -220,8 +220,10 @@ size_t level_sort_tmp_bytes(int n);
 // prev[0..n_prev) (slow part n0_prev): diff[0] = slow parts differ, diff[1] = lists differ.
 hipError_t launch_split_diff(const int32_t* cur, int n, const int32_t* counts, const int32_t* prev, int n_prev,
                              int n0_prev, int32_t* diff, hipStream_t st);
-hipError_t launch_pivot_flags(const DevSet& set, int64_t n, const double* dt0, const double* ff, const double* fb,
-                              double tau, bool all_slow, int32_t* flag, uint32_t* flags, hipStream_t st);
+// slow (0) / fast (1) flag per particle of a level: time-step min(dt0, dtl) (dtl may be NULL)
+// against the pivot tau; all_slow: every particle slow (the deepest level)
+hipError_t launch_pivot_flags(const DevSet& set, int64_t n, const double* dt0, const double* dtl, double tau,
+                              bool all_slow, int32_t* flag, uint32_t* flags, hipStream_t st);
 hipError_t launch_level_partition(const DevSet& set, int64_t n, const int32_t* level, int kmax, uint32_t* keys_in,
                                   uint32_t* keys_out, int32_t* vals_in, int32_t* out_order, int32_t* counts,
                                   void* tmp, size_t tmp_bytes, uint32_t* flags, hipStream_t st);
@@ -314,6 +316,7 @@ struct bf_ctx {
     const int32_t* sub = nullptr;     // subsystem labels applied to acc / grad / dt passes (NULL: none)
     int64_t sub_n = 0;
     float kappa = 1.0f;               // a tile is near a workgroup when their gap < kappa * tile half-extent
+    bool hhs_reuse = true;            // HHS drivers keep accelerations between visits of a level
     // kernel timing: event pairs around pair-kernel launches, per op
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[bf::OP_COUNT];

@@ -1237,41 +1237,86 @@ int hhs_run(const HhsCtx& h, double tau) {
 }
 
 // adaptive levels: every level assigns time-steps to its particles P and splits them at the
-// pivot tau (Sec. 2.2); below the top level a time-step is the pairwise free-fall / fly-by
-// time-step over P capped by the interval's initial one (Sec. 3.5.1, the level-0 minimum).
+// pivot tau (Sec. 2.2).  Below the top level every criterion is evaluated again over P alone:
+// the pairwise free-fall / fly-by time-steps (Sec. 3.5.3), both gradient criteria (Sec. 3.5.4,
+// Eqs. dt-nabla1, dt-nabla2, with the acceleration and gradient sum over P) and the jerk
+// criterion (Sec. 3.5.5, the jerk over P); the result is capped by the interval's initial
+// time-step (Sec. 3.5.1, the level-0 minimum).
 struct HhsAdapt {
     const double* dt0;
-    double eta_ff, eta_fb;
-    double *dtff, *dtfb;  // particle-indexed
-    int32_t* flag;        // particle-indexed: 0 slow, 1 fast
-    int32_t* lists;       // 2 (kmax + 1) buffers of `cap` entries: the splits of the level-k set,
-                          // this visit's and the previous visit's
-    int32_t* diff;        // two device ints: does this split differ from the previous one
-    int which[64];        // buffer of level k's latest split
-    int64_t prev_n[64], prev_n0[64];  // its size and slow count (-1: none yet)
+    double eta_ff, eta_fb, eta_grad, eta_jerk;
+    double *dtff, *dtfb, *dtl;  // particle-indexed: pairwise criteria, the level's time-step
+    double *alv, *glv, *jlv;    // 3n each: acceleration, gradient sum and jerk over the level's set
+    int32_t* flag;              // particle-indexed: 0 slow, 1 fast
+    int32_t* lists;             // 2 (kmax + 1) buffers of `cap` entries: the splits of the level-k set,
+                                // this visit's and the previous visit's
+    int32_t* diff;              // two device ints: does this split differ from the previous one
+    int which[64];              // buffer of level k's latest split
+    int64_t prev_n[64], prev_n0[64];  // its size and slow count (-1: none, nothing kept)
     int64_t cap;
     int max_level;
     int64_t nodes;
 };
 
+// time-steps of the particles of P from P alone (all criteria), into A.dtl
+int level_timesteps(const HhsCtx& h, HhsAdapt& A, const bf_set& P) {
+    bf_ctx* c = h.c;
+    const int64_t n = h.S->n;
+    const bf_fsi_params* p = h.prm;
+    if (int rc = run_pairs(c, OP_DT, p->prec, h.M, &P, &P, p->G, 0.0, 0.0, A.eta_ff, A.eta_fb, A.dtff, A.dtfb,
+                           nullptr))
+        return rc;
+    if (int rc = run_pairs(c, OP_ACC, p->prec, h.M, &P, &P, p->G, p->eps2, p->r_fb, 0, 0, A.alv, A.alv + n,
+                           A.alv + 2 * n))
+        return rc;
+    const bool grad = A.eta_grad > 0.0, jerk = A.eta_jerk > 0.0;
+    if (grad) {
+        Masters Mg = h.M;
+        Mg.ax = A.alv; Mg.ay = A.alv + n; Mg.az = A.alv + 2 * n;
+        if (int rc = run_pairs(c, OP_GRAD, p->prec, Mg, &P, &P, p->G, p->eps2, p->r_fb, 0, 0, A.glv, A.glv + n,
+                               A.glv + 2 * n))
+            return rc;
+    }
+    if (jerk) {
+        // the jerk is the tidal contraction with the velocities in place of the accelerations
+        Masters Mj = h.M;
+        Mj.ax = h.S->vx; Mj.ay = h.S->vy; Mj.az = h.S->vz;
+        if (int rc = run_pairs(c, OP_GRAD, p->prec, Mj, &P, &P, p->G, p->eps2, 0.0, 0, 0, A.jlv, A.jlv + n,
+                               A.jlv + 2 * n))
+            return rc;
+    }
+    if (c->dry) return BF_OK;
+    TimestepArgs t{};
+    t.P = h.M;
+    t.set = devset(&P);
+    t.dt_ff = A.dtff; t.dt_fb = A.dtfb;
+    t.ax = A.alv; t.ay = A.alv + n; t.az = A.alv + 2 * n;
+    if (grad) { t.gx = A.glv; t.gy = A.glv + n; t.gz = A.glv + 2 * n; }
+    if (jerk) { t.jx = A.jlv; t.jy = A.jlv + n; t.jz = A.jlv + 2 * n; }
+    t.eta_grad = A.eta_grad; t.eta_jerk = A.eta_jerk; t.tau = 1.0; t.kmax = 0;
+    t.dt = A.dtl; t.level = nullptr;
+    t.flags = c->d_flags;
+    BF_HIP(launch_timestep(t, c->stream));
+    return BF_OK;
+}
+
 int hhs_adapt(const HhsCtx& h, HhsAdapt& A, const bf_set& P, int k, double tau) {
     if (P.count == 0) return BF_OK;
     bf_ctx* c = h.c;
     const int64_t n = h.S->n;
-    const bf_fsi_params* p = h.prm;
     const bool top = k == 0;
-    if (!top) {
-        if (int rc = run_pairs(c, OP_DT, p->prec, h.M, &P, &P, p->G, 0.0, 0.0, A.eta_ff, A.eta_fb, A.dtff, A.dtfb,
-                               nullptr))
-            return rc;
-    }
-    BF_HIP(launch_pivot_flags(devset(&P), n, A.dt0, top ? nullptr : A.dtff, top ? nullptr : A.dtfb, tau,
-                              k >= h.kmax, A.flag, c->d_flags, c->stream));
-    // Level k's split goes to the buffer its previous split is not in, and is compared with it:
-    // the positions of level k's particles and deeper do not change between two visits of level
-    // k (a particle that drifted in between sits on a shallower level at the next visit, so the
-    // lists differ), so equal lists keep level k's own accelerations (same slow set) and its
-    // inter-level accelerations (same slow and fast sets) valid, as for fixed levels.
+    if (!top)
+        if (int rc = level_timesteps(h, A, P)) return rc;
+    BF_HIP(launch_pivot_flags(devset(&P), n, A.dt0, top ? nullptr : A.dtl, tau, k >= h.kmax, A.flag, c->d_flags,
+                              c->stream));
+    // Level k's split goes to the buffer its previous split is not in, and is compared with it.
+    // Between two visits of level k only FSI cycles of shallower levels drift particles, each
+    // over its own slow set (or its whole set when its fast set is empty).  While every
+    // shallower level keeps its split and its fast set, the particles of level k and deeper
+    // therefore stay where they were, and equal lists keep level k's own accelerations (same
+    // slow set) and its inter-level accelerations (same slow and fast sets) valid, as for fixed
+    // levels.  A level whose split changes, or whose fast set is empty, drops what every deeper
+    // level kept: the next visit of a deeper level starts afresh.
     const bool had = A.prev_n[k] >= 0;
     const int cur = had ? 1 - A.which[k] : 0;
     int32_t* mine = A.lists + ((size_t)k * 2 + cur) * A.cap;
@@ -1286,6 +1331,11 @@ int hhs_adapt(const HhsCtx& h, HhsAdapt& A, const bf_set& P, int k, double tau) 
     A.prev_n0[k] = cnt[0];
     if (!same[0]) h.a_ok[k] = false;
     if (!same[1]) h.il_ok[k] = false;
+    if (!same[1] || cnt[1] == 0)
+        for (int d = k + 1; d < 64; ++d) {
+            A.prev_n[d] = -1;
+            h.a_ok[d] = h.il_ok[d] = false;
+        }
     A.max_level = std::max(A.max_level, k);
     ++A.nodes;
     const bf_set Sset{mine, (int32_t)cnt[0], 0}, Fset{mine + cnt[0], (int32_t)cnt[1], 0};
@@ -1334,7 +1384,7 @@ static int hhs_setup(bf_ctx* c, const bf_state* S, const bf_set* set, const int3
         const bool split = k < kmax && counts[k] > 0 && h.begin[k + 1] < total;
         h.asf_lv[k] = split ? static_cast<double*>(c->scratch11) + (size_t)(i++) * 3 * n : nullptr;
     }
-    h.reuse = true;
+    h.reuse = c->hhs_reuse;
     return BF_OK;
 }
 
@@ -1431,8 +1481,8 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_
 }
 
 BF_API int bf_hhs_interval_adaptive(bf_ctx* c, const bf_state* S, const bf_set* set, const double* dt0, int kmax,
-                                    double tau, double eta_ff, double eta_fb, const bf_fsi_params* prm,
-                                    int* max_level, int64_t* n_levels) {
+                                    double tau, double eta_ff, double eta_fb, double eta_grad, double eta_jerk,
+                                    const bf_fsi_params* prm, int* max_level, int64_t* n_levels) {
     g_err.clear();
     if (int rc = check_ctx(c)) return rc;
     if (int rc = check_state(S)) return rc;
@@ -1442,14 +1492,16 @@ BF_API int bf_hhs_interval_adaptive(bf_ctx* c, const bf_state* S, const bf_set* 
     if (kmax < 0 || kmax > 63) return fail(BF_ERR_ARG, "kmax must be in [0, 63]");
     if (!(isfinite(tau) && tau > 0)) return fail(BF_ERR_ARG, "tau must be finite and > 0");
     if (!(isfinite(eta_ff) && eta_ff > 0) || !(isfinite(eta_fb) && eta_fb > 0))
-        return fail(BF_ERR_ARG, "eta must be finite and > 0");
+        return fail(BF_ERR_ARG, "eta_ff and eta_fb must be finite and > 0");
+    if (!finite_nonneg(eta_grad) || !finite_nonneg(eta_jerk))
+        return fail(BF_ERR_ARG, "eta_grad and eta_jerk must be finite and >= 0");
     if (max_level) *max_level = -1;
     if (n_levels) *n_levels = 0;
     if (set->count == 0) return BF_OK;
     const int64_t n = S->n, cap = set->count;
     const size_t lb = ((size_t)2 * (kmax + 1) * cap * 4 + 255) & ~size_t(255);
     const size_t fb = (((size_t)n * 4 + 255) & ~size_t(255)) + 256;  // the flags, then the split diff
-    if (int rc = ensure(&c->scratch7, &c->scratch7_bytes, lb + fb + (size_t)14 * n * sizeof(double), c->stream))
+    if (int rc = ensure(&c->scratch7, &c->scratch7_bytes, lb + fb + (size_t)24 * n * sizeof(double), c->stream))
         return rc;
     // every level may split: an inter-level acceleration array (3n) for each
     if (int rc = ensure(&c->scratch11, &c->scratch11_bytes, (size_t)(kmax + 1) * 3 * n * sizeof(double), c->stream))
@@ -1469,8 +1521,14 @@ BF_API int bf_hhs_interval_adaptive(bf_ctx* c, const bf_state* S, const bf_set* 
     A.dt0 = dt0;
     A.eta_ff = eta_ff;
     A.eta_fb = eta_fb;
+    A.eta_grad = eta_grad;
+    A.eta_jerk = eta_jerk;
     A.dtff = d + 12 * n;
     A.dtfb = d + 13 * n;
+    A.dtl = d + 14 * n;
+    A.alv = d + 15 * n;
+    A.glv = d + 18 * n;
+    A.jlv = d + 21 * n;
     A.flag = reinterpret_cast<int32_t*>(base + lb);
     A.diff = reinterpret_cast<int32_t*>(base + lb + fb - 256);
     A.lists = reinterpret_cast<int32_t*>(base);
@@ -1483,7 +1541,7 @@ BF_API int bf_hhs_interval_adaptive(bf_ctx* c, const bf_state* S, const bf_set* 
         h.a_ok[k] = h.il_ok[k] = false;
         h.asf_lv[k] = k <= kmax ? static_cast<double*>(c->scratch11) + (size_t)k * 3 * n : nullptr;
     }
-    h.reuse = true;
+    h.reuse = c->hhs_reuse;
     const int rc = hhs_adapt(h, A, *set, 0, tau);
     if (max_level) *max_level = A.max_level;
     if (n_levels) *n_levels = A.nodes;
@@ -1520,6 +1578,12 @@ BF_API int bf_set_spatial_sort(bf_ctx* c, int ops_mask, double kappa) {
         return fail(BF_ERR_ARG, "kappa must be 0 (keep) or in [0.5, 64]");
     c->sort_ops = ops_mask;
     if (kappa != 0.0) c->kappa = (float)kappa;
+    return BF_OK;
+}
+
+BF_API int bf_set_hhs_reuse(bf_ctx* c, int on) {
+    if (int rc = check_ctx(c)) return rc;
+    c->hhs_reuse = on != 0;
     return BF_OK;
 }
 

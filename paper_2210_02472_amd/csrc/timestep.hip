@@ -47,25 +47,24 @@ hipError_t launch_timestep(const TimestepArgs& t, hipStream_t st) {
 
 // ---- pivot split of one hierarchy level (adaptive HHS) ------------------------------------------
 // flag[p] = 0 (slow) when the particle's time-step reaches the pivot tau, else 1 (fast).  The
-// time-step is dt0[p], capped by min(dt_ff[p], dt_fb[p]) when those are given; all_slow keeps
-// every particle on this level (the deepest level).
+// time-step is dt0[p], capped by dtl[p] (the time-step the level assigned from its own
+// particles) when that is given; all_slow keeps every particle on this level (the deepest level).
 
-__global__ __launch_bounds__(256) void k_pivot_flags(const DevSet set, int64_t n, const double* dt0, const double* ff,
-                                                     const double* fb, double tau, int all_slow, int32_t* flag,
-                                                     uint32_t* flags) {
+__global__ __launch_bounds__(256) void k_pivot_flags(const DevSet set, int64_t n, const double* dt0, const double* dtl,
+                                                     double tau, int all_slow, int32_t* flag, uint32_t* flags) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= set.count) return;
     const int p = particle_of(set, k, n, flags);
     double dt = dt0[p];
-    if (ff) dt = fmin(dt, fmin(ff[p], fb[p]));
+    if (dtl) dt = fmin(dt, dtl[p]);
     if (__builtin_isnan(dt)) atomicOr(flags, BF_FLAG_NONFINITE);
     flag[p] = (all_slow || dt >= tau) ? 0 : 1;
 }
 
-hipError_t launch_pivot_flags(const DevSet& set, int64_t n, const double* dt0, const double* ff, const double* fb,
-                              double tau, bool all_slow, int32_t* flag, uint32_t* flags, hipStream_t st) {
+hipError_t launch_pivot_flags(const DevSet& set, int64_t n, const double* dt0, const double* dtl, double tau,
+                              bool all_slow, int32_t* flag, uint32_t* flags, hipStream_t st) {
     if (set.count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pivot_flags, dim3((set.count + 255) / 256), dim3(256), 0, st, set, n, dt0, ff, fb, tau,
+    hipLaunchKernelGGL(k_pivot_flags, dim3((set.count + 255) / 256), dim3(256), 0, st, set, n, dt0, dtl, tau,
                        all_slow ? 1 : 0, flag, flags);
     return hipGetLastError();
 }
