@@ -127,6 +127,24 @@ BF_API int bf_forces(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, 
                      double G, double eps2, int prec, double r_fb,
                      double *ax, double *ay, double *az);
 
+/* The accelerations of bf_forces (same arguments, same meaning, same results to the mixed or
+ * FP64 tolerance), for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine): the pass takes the unsorted directed
+ * sweep (no spatial sort, no pair-symmetric sweep) and carves its packed sources, source-chunk
+ * partials, fix-up queue and fix-up partials from a static device array of 64 MiB that each
+ * device holds until the process ends; it lowers the source split until the partials fit, and
+ * records no timing events.  Limit: 256 + 4 n_t (rounded up to 256) + pack + fix-up bytes must
+ * fit in 64 MiB, where pack = 32 n_s bytes (rounded up to 256) and fix-up = 3 MiB in mixed
+ * precision (0 in FP64): n_t + 8 n_s up to about 15.9 million in mixed precision and 16.7
+ * million in FP64.  Larger sets return
+ * BF_ERR_ARG before any launch; other errors as bf_forces, and BF_ERR_HIP if the array's device
+ * address could not be resolved when the context was created.  Every call on one device uses
+ * the same array, which keeps the last call's contents (each pass clears what must start at
+ * zero): calls that overlap on one device, from several streams or contexts, race. */
+BF_API int bf_forces_noalloc(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, const bf_set *sources,
+                             double G, double eps2, int prec, double r_fb, double *ax, double *ay, double *az);
+
 /* Force-gradient sum (Sec. 2.1, Eq. new-grad-acc; inter-level form Sec. 2.2):
  *     Gsum_i = sum_{j in sources, j != i} G m_j / s^5 (s^2 a_ji - 3 (a_ji . r_ji) r_ji),
  *     a_ji = a_j - a_i,

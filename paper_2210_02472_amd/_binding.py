@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
         "bf_read_flags": [_vp, ctypes.POINTER(ctypes.c_uint32), _int],
         "bf_validate_set": [_vp, S, _i64],
         "bf_forces": [_vp, P, S, S, _d, _d, _int, _d, _vp, _vp, _vp],
+        "bf_forces_noalloc": [_vp, P, S, S, _d, _d, _int, _d, _vp, _vp, _vp],
         "bf_force_gradient": [_vp, P, S, S, _vp, _vp, _vp, _d, _d, _int, _d, _vp, _vp, _vp],
         "bf_dt_min": [_vp, P, S, S, _d, _d, _d, _int, _d, _vp, _vp],
         "bf_pn1_bh": [_vp, P, S, S, _vp, _i32, _d, _d, _vp, _vp, _vp],
@@ -269,6 +270,17 @@ class Context:
         o = self._outs(P, out, 3)
         _check("bf_forces", _lib.bf_forces(self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()),
                                            float(G), float(eps2), PRECISIONS[prec], float(r_fb), *map(_ptr, o)))
+        return o
+
+    def forces_noalloc(self, P: Particles, targets=None, sources=None, G=1.0, eps2=0.0, prec="mixed", r_fb=0.0,
+                       out: Optional[Sequence[torch.Tensor]] = None):
+        """The accelerations of `forces` through bf_forces_noalloc: the library allocates nothing
+        (its pass runs in a static 64 MiB device array).  Pass `out` to allocate nothing here either."""
+        t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
+        o = self._outs(P, out, 3)
+        _check("bf_forces_noalloc", _lib.bf_forces_noalloc(
+            self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()), float(G), float(eps2),
+            PRECISIONS[prec], float(r_fb), *map(_ptr, o)))
         return o
 
     def force_gradient(self, P: Particles, acc: Sequence[torch.Tensor], targets=None, sources=None, G=1.0, eps2=0.0,

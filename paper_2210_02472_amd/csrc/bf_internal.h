@@ -95,11 +95,12 @@ struct bf_graph {
     void* owned[12] = {};
 };
 
-// FP64 fix-up of queued targets; part: kFixChunks * 3 * kFixTiled doubles of scratch.
+// FP64 fix-up of queued targets; part: 3 * cap doubles of scratch (cap >= kFixTiled; the
+// context's buffer holds cap = kFixChunks * kFixTiled).
 constexpr int kFixTiled = 32768, kFixChunks = 64;
 // source-chunk partials: more chunks than this are added by one wavefront per target
 constexpr int kReduceWaveSplit = 16;
-hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hipStream_t st);
+hipError_t launch_fixup(int op, const PairArgs& a, double* part, int cap, int num_cu, hipStream_t st);
 
 // Spatially sorted mixed acc/grad (spatial.hip).
 struct SortBuffers {

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -15,6 +16,14 @@
 #include "bf_internal.h"
 
 using namespace bf;
+
+// ---- scratch of the allocation-free entry point (bf_forces_noalloc) -------------------------
+// Every buffer of that entry point's pass is carved from this array; each device holds its own
+// copy until the process ends.  On the host the name stands in for the array and is not a
+// device address: bf_create resolves the address once per device, with that device current,
+// and only that address is handed to kernels.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -62,6 +71,39 @@ Masters masters_of(const bf_particles* P) {
 }
 
 DevSet devset(const bf_set* s) { return DevSet{s->idx, s->count, s->begin}; }
+
+// the static scratch's device address per device (resolved once, by bf_create)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+void static_scratch_init(int device) {  // the device is current
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();  // not left for the next launch check to report
+    g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_err[device] = e;
+    g_scratch_done[device] = true;
+}
+
+void* static_scratch_of(int device, std::string* why) {
+    if (device < 0 || device >= kMaxDevices) {
+        *why = "device index beyond the static scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        *why = "static scratch not set up on this device";
+        return nullptr;
+    }
+    if (!g_scratch_ptr[device]) *why = std::string("hipGetSymbolAddress failed: ") + hipGetErrorString(g_scratch_err[device]);
+    return g_scratch_ptr[device];
+}
 
 int ensure(void** buf, size_t* have, size_t need, hipStream_t st) {
     if (need <= *have) return BF_OK;
@@ -215,20 +257,43 @@ int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool so
     return BF_OK;
 }
 
-// Run one pair pass (acc, grad or dt) end to end on the context stream.
+// A fixed block of device memory that a pass takes all of its scratch from, instead of the
+// context's buffers (which grow by allocation).
+struct Arena {
+    char* base;
+    size_t bytes;
+};
+// fix-up partials of a pass run in an arena: 3 * kArenaFixCap doubles
+constexpr int kArenaFixCap = 4 * kFixTiled;
+
+// Lower a plan's source split to at most `most` chunks of whole 64-source groups (unsorted).
+void cap_split(Plan& p, int64_t ns, int64_t most) {
+    if (p.split <= most) return;
+    const int64_t nslabs = p.nblocks / p.split;
+    const int64_t ngroups = std::max<int64_t>(1, (ns + 63) / 64);
+    const int64_t per = (ngroups + most - 1) / most;
+    p.split = (int)((ngroups + per - 1) / per);
+    p.chunk = (int)(per * 64);
+    p.nblocks = (int)(nslabs * p.split);
+}
+
+// Run one pair pass (acc, grad or dt) end to end on the context stream.  With an arena the pass
+// allocates nothing: it takes the unsorted directed sweep, carves every buffer from the arena
+// (lowering the source split until the partials fit) and records no timing events.
 int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg, const bf_set* sr, double G, double eps2,
-              double r_fb, double eta0, double eta1, double* o0, double* o1, double* o2) {
+              double r_fb, double eta0, double eta1, double* o0, double* o1, double* o2,
+              const Arena* arena = nullptr) {
     if (tg->count == 0) return BF_OK;
     if (ctx->sub && ctx->sub_n != M.n)
         return fail(BF_ERR_ARG, "subsystem labels were set for n=" + std::to_string(ctx->sub_n) +
                                     " particles, this pass has n=" + std::to_string(M.n));
-    const bool sorted = use_sorted(ctx, op, prec, tg->count, sr->count, r_fb);
+    const bool sorted = !arena && use_sorted(ctx, op, prec, tg->count, sr->count, r_fb);
     Plan p;
     int rc = plan(ctx, op, prec, tg->count, sr->count, p, sorted);
     if (rc) return rc;
     if (sorted && !sorted_variant_exists(op, p.cfg.k, p.cfg.waves))
         return fail(BF_ERR_UNSUPPORTED, "no sorted kernel variant for this configuration");
-    bool sym = use_symmetric(ctx, op, sorted, tg, sr);
+    bool sym = !arena && use_symmetric(ctx, op, sorted, tg, sr);
     int sym_shares = 0;
     if (sym) {
         // the column partials are large (8.6 GB at n = 2^20): without the memory, the directed
@@ -239,7 +304,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
             sym = false;
         }
     }
-    bool sym64 = use_symmetric64(ctx, op, prec, tg, sr);
+    bool sym64 = !arena && use_symmetric64(ctx, op, prec, tg, sr);
     int sym64_shares = 0;
     if (sym64) {
         sym64_shares = sym64_chunks(ctx, op, sr->count);
@@ -257,6 +322,44 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
                        ctx->tuned.find(std::make_tuple(op, prec, ilog2_bucket(tg->count), ilog2_bucket(sr->count))) ==
                            ctx->tuned.end();
     if (sym || sym64 || small) p.split = 1;  // no source split in memory
+    // scratch: [fix counter | fix list (one slot per target)], the split partials, the packed
+    // sources (unsorted) and the fix-up partials: from the context's buffers, or the arena
+    const bool fix = prec == BF_PREC_MIXED && op != OP_DT;
+    const size_t head = 256 + (((size_t)tg->count * sizeof(int32_t) + 255) & ~size_t(255));
+    const size_t chunk_bytes = (size_t)stored_components(op, prec) * tg->count * sizeof(double);
+    char* head_buf = nullptr;
+    double* part_buf = nullptr;
+    void* pack_buf = nullptr;
+    double* fix_buf = nullptr;
+    int fix_cap = kFixChunks * kFixTiled;
+    if (arena) {
+        // [head | packed sources | fix-up partials | split partials], each 256-byte aligned
+        const size_t pack = (((size_t)sr->count * pack_bytes(op, prec)) + 255) & ~size_t(255);
+        const size_t fixb = fix ? (size_t)3 * kArenaFixCap * sizeof(double) : 0;
+        const size_t fixed = head + pack + fixb;
+        if (fixed > arena->bytes)
+            return fail(BF_ERR_ARG, "the pass needs " + std::to_string(fixed) + " bytes of scratch; the static buffer holds " +
+                                        std::to_string(arena->bytes));
+        if (p.split > 1) cap_split(p, sr->count, (int64_t)std::max<size_t>(1, (arena->bytes - fixed) / chunk_bytes));
+        head_buf = arena->base;
+        pack_buf = arena->base + head;
+        fix_buf = reinterpret_cast<double*>(arena->base + head + pack);
+        fix_cap = kArenaFixCap;
+        part_buf = reinterpret_cast<double*>(arena->base + fixed);
+    } else {
+        const size_t part_bytes = p.split > 1 ? (size_t)p.split * chunk_bytes : 0;
+        rc = ensure(&ctx->scratch, &ctx->scratch_bytes, head + part_bytes, ctx->stream);
+        if (rc) return rc;
+        if (fix) {
+            rc = ensure(&ctx->scratch8, &ctx->scratch8_bytes, (size_t)kFixChunks * 3 * kFixTiled * sizeof(double),
+                        ctx->stream);
+            if (rc) return rc;
+        }
+        if (!sorted && sr->count > 0) {
+            rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)sr->count * pack_bytes(op, prec), ctx->stream);
+            if (rc) return rc;
+        }
+    }
     PairArgs a{};
     a.P = M;
     a.tgt = devset(tg);
@@ -275,21 +378,6 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     a.flags = ctx->d_flags;
     a.cond_max = cond_max_for(op);
     a.sub = ctx->sub;
-    // scratch: [fix counter | fix list (one slot per target) | split partials]
-    const bool fix = prec == BF_PREC_MIXED && op != OP_DT;
-    const size_t head = 256 + (((size_t)tg->count * sizeof(int32_t) + 255) & ~size_t(255));
-    const size_t part_bytes = p.split > 1 ? (size_t)p.split * stored_components(op, prec) * tg->count * sizeof(double) : 0;
-    rc = ensure(&ctx->scratch, &ctx->scratch_bytes, head + part_bytes, ctx->stream);
-    if (rc) return rc;
-    if (fix) {
-        rc = ensure(&ctx->scratch8, &ctx->scratch8_bytes, (size_t)kFixChunks * 3 * kFixTiled * sizeof(double),
-                    ctx->stream);
-        if (rc) return rc;
-    }
-    if (!sorted && sr->count > 0) {
-        rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)sr->count * pack_bytes(op, prec), ctx->stream);
-        if (rc) return rc;
-    }
     // sorted mode: sort lists and temporaries, near and far streams, tile metadata
     const int64_t s_nt = tg->count, s_ns = sr->count, s_nmax = std::max(s_nt, s_ns);
     const size_t s_tmp = sorted ? sort_tmp_bytes((int)s_nmax) : 0;
@@ -309,9 +397,15 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         if (rc) return rc;
     }
     if (ctx->dry) return BF_OK;  // sizing before a capture: every buffer of this pass now exists
-    a.fix_count = static_cast<int32_t*>(ctx->scratch);
-    a.fix_list = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->scratch) + 256);
-    if (p.split > 1) a.part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + head);
+    if (!arena) {
+        head_buf = static_cast<char*>(ctx->scratch);
+        part_buf = reinterpret_cast<double*>(head_buf + head);
+        pack_buf = ctx->scratch2;
+        fix_buf = static_cast<double*>(ctx->scratch8);
+    }
+    a.fix_count = reinterpret_cast<int32_t*>(head_buf);
+    a.fix_list = reinterpret_cast<int32_t*>(head_buf + 256);
+    if (p.split > 1) a.part = part_buf;
     a.tile_stats = ctx->d_stats + 1;
     a.pass_stats = ctx->d_stats;
     const bool pack_begins = !sorted && sr->count > 0;  // the pack kernel starts the pass
@@ -367,7 +461,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
             g.tile_stats = a.tile_stats;
         }
     } else if (sr->count > 0) {
-        a.pack = ctx->scratch2;
+        a.pack = pack_buf;
         BF_HIP(launch_pack(op, prec, a, ctx->stream, fix ? 2 : 1));
         if (sym64) {  // rows and columns: the FP64 pack in the set's order
             const int64_t ns = sr->count, ntiles = (ns + 63) / 64;
@@ -384,7 +478,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         }
     }
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    const bool timed = ctx->timing && !ctx->capturing;
+    const bool timed = ctx->timing && !ctx->capturing && !arena;
     if (timed) {
         if (!ctx->tpool.empty()) {
             ev = ctx->tpool.back();
@@ -411,7 +505,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     if (sym) BF_HIP(launch_sym_reduce(op, a, g, ctx->stream));
     else if (sym64) BF_HIP(launch_sym_reduce64(op, a, g, ctx->stream));
     else if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
-    if (fix) BF_HIP(launch_fixup(op, a, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
+    if (fix) BF_HIP(launch_fixup(op, a, fix_buf, fix_cap, ctx->num_cu, ctx->stream));
     return BF_OK;
 }
 
@@ -553,8 +647,8 @@ int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_
     ctx->last_waves = sym_waves(op);
     ctx->last_split = shares;
     BF_HIP(launch_between_reduce(op, ab, ba, g, ctx->stream));
-    BF_HIP(launch_fixup(op, ab, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
-    BF_HIP(launch_fixup(op, ba, static_cast<double*>(ctx->scratch8), ctx->num_cu, ctx->stream));
+    BF_HIP(launch_fixup(op, ab, static_cast<double*>(ctx->scratch8), kFixChunks * kFixTiled, ctx->num_cu, ctx->stream));
+    BF_HIP(launch_fixup(op, ba, static_cast<double*>(ctx->scratch8), kFixChunks * kFixTiled, ctx->num_cu, ctx->stream));
     return BF_OK;
 }
 
@@ -627,6 +721,7 @@ BF_API int bf_create(bf_ctx** out, int device, void* stream) {
     BF_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(BF_ERR_ARG, "device out of range");
     BF_HIP(hipSetDevice(device));
+    static_scratch_init(device);
     hipDeviceProp_t prop;
     BF_HIP(hipGetDeviceProperties(&prop, device));
     bf_ctx* c = new bf_ctx();
@@ -775,6 +870,25 @@ BF_API int bf_forces(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf
     if (!finite_nonneg(r_fb)) return fail(BF_ERR_ARG, "r_fb must be finite and >= 0");
     if (!ax || !ay || !az) return fail(BF_ERR_ARG, "output pointer NULL");
     return run_pairs(c, OP_ACC, prec, masters_of(P), t, s, G, eps2, r_fb, 0, 0, ax, ay, az);
+}
+
+BF_API int bf_forces_noalloc(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf_set* s, double G,
+                             double eps2, int prec, double r_fb, double* ax, double* ay, double* az) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = check_particles(P, false)) return rc;
+    if (int rc = check_set(t, P->n, "target")) return rc;
+    if (int rc = check_set(s, P->n, "source")) return rc;
+    if (int rc = check_prec(prec)) return rc;
+    if (!isfinite(G)) return fail(BF_ERR_ARG, "G not finite");
+    if (!finite_nonneg(eps2)) return fail(BF_ERR_ARG, "eps2 must be finite and >= 0");
+    if (!finite_nonneg(r_fb)) return fail(BF_ERR_ARG, "r_fb must be finite and >= 0");
+    if (!ax || !ay || !az) return fail(BF_ERR_ARG, "output pointer NULL");
+    std::string why;
+    void* base = static_scratch_of(c->device, &why);
+    if (!base) return fail(BF_ERR_HIP, why);
+    const Arena arena{static_cast<char*>(base), kStaticScratchBytes};
+    return run_pairs(c, OP_ACC, prec, masters_of(P), t, s, G, eps2, r_fb, 0, 0, ax, ay, az, &arena);
 }
 
 BF_API int bf_force_gradient(bf_ctx* c, const bf_particles* P, const bf_set* t, const bf_set* s, const double* ax,

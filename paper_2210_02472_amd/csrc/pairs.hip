@@ -222,7 +222,8 @@ __global__ void k_pass_begin(int32_t* fix_count, unsigned long long* stats) {
 // staged through LDS for 256 targets at once; otherwise each workgroup takes one (target,
 // chunk) item, its threads splitting the chunk.  Both write FP64 partial sums per chunk, which
 // k_fixup_reduce adds in chunk order.  The plan depends only on the round's length, the source
-// count and wgs, so the two kernels agree on it and the sums are repeatable.  Rounds past the
+// count, wgs and the partial buffer's capacity `cap` (doubles per component, at least
+// kFixTiled), so the two kernels agree on it and the sums are repeatable.  Rounds past the
 // queue's end exit at once.
 constexpr int kFixWide = 64;
 constexpr int64_t kFixWidePairs = 1 << 22;
@@ -234,7 +235,7 @@ struct FixPlan {
     int stride;  // partial-sum stride between chunk components
 };
 
-__device__ __forceinline__ FixPlan fix_plan(int count, int ns, int wgs) {
+__device__ __forceinline__ FixPlan fix_plan(int count, int ns, int wgs, int cap) {
     FixPlan f;
     f.wide = count >= kFixWide && (int64_t)count * ns >= kFixWidePairs;
     if (f.wide) {
@@ -245,7 +246,7 @@ __device__ __forceinline__ FixPlan fix_plan(int count, int ns, int wgs) {
         f.stride = (count + 63) / 64 * 64;
         f.nch = max(1, min((wgs + count - 1) / count, (ns + 255) / 256));
     }
-    f.nch = min(f.nch, kFixChunks * kFixTiled / f.stride);  // the partial-sum buffer
+    f.nch = max(1, min(f.nch, cap / f.stride));  // the partial-sum buffer (stride <= kFixTiled <= cap)
     f.chunk = (ns + f.nch - 1) / f.nch;
     return f;
 }
@@ -255,11 +256,11 @@ __device__ __forceinline__ int fix_round_count(const PairArgs& a, int base) {
 }
 
 template <int OP>
-__global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* part, int base, int wgs) {
+__global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* part, int base, int wgs, int cap) {
     const int count = fix_round_count(a, base);
     if (count <= 0) return;
     const int ns = a.src.count;
-    const FixPlan f = fix_plan(count, ns, wgs);
+    const FixPlan f = fix_plan(count, ns, wgs, cap);
     if (!f.wide) {
         for (int it = blockIdx.x; it < count * f.nch; it += gridDim.x) {  // uniform over the workgroup
             const int e = it / f.nch, c = it % f.nch;
@@ -356,12 +357,13 @@ __global__ __launch_bounds__(256) void k_fixup_tiled(const PairArgs a, double* p
 
 // one wavefront per queued target: lane l adds chunks l, l + 64, ... in order, then a fixed
 // butterfly over the lanes
-__global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part, int base, int wgs) {
+__global__ __launch_bounds__(256) void k_fixup_reduce(const PairArgs a, const double* part, int base, int wgs,
+                                                      int cap) {
     if (base == 0 && a.pass_stats && blockIdx.x == 0 && threadIdx.x == 0)
         a.pass_stats[0] = (unsigned long long)min(*a.fix_count, a.tgt.count);
     const int count = fix_round_count(a, base);
     if (count <= 0) return;
-    const FixPlan f = fix_plan(count, a.src.count, wgs);
+    const FixPlan f = fix_plan(count, a.src.count, wgs, cap);
     const int lane = threadIdx.x & 63;
     for (int e = blockIdx.x * 4 + (int)(threadIdx.x >> 6); e < count; e += gridDim.x * 4) {  // uniform per wave
         double v[3] = {0.0, 0.0, 0.0};
@@ -505,10 +507,10 @@ hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hipStream_t st) {
+hipError_t launch_fixup(int op, const PairArgs& a, double* part, int cap, int num_cu, hipStream_t st) {
     const int nt = a.tgt.count;
     if (nt <= 0) return hipSuccess;
-    if (op != OP_ACC && op != OP_GRAD) return hipErrorInvalidValue;
+    if ((op != OP_ACC && op != OP_GRAD) || cap < kFixTiled) return hipErrorInvalidValue;
     const int64_t ns = a.src.count;
     for (int base = 0; base < nt; base += kFixTiled) {  // rounds past the queue's end exit at once
         const int len = std::min(nt - base, kFixTiled);
@@ -516,9 +518,9 @@ hipError_t launch_fixup(int op, const PairArgs& a, double* part, int num_cu, hip
         const int64_t most = (int64_t)len * ((ns + 255) / 256);
         const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>(most, 8 * num_cu));
         const int g2 = std::min((len + 3) / 4, 8 * num_cu);
-        if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_tiled<OP_ACC>, dim3(g1), dim3(256), 0, st, a, part, base, g1);
-        else hipLaunchKernelGGL(k_fixup_tiled<OP_GRAD>, dim3(g1), dim3(256), 0, st, a, part, base, g1);
-        hipLaunchKernelGGL(k_fixup_reduce, dim3(g2), dim3(256), 0, st, a, (const double*)part, base, g1);
+        if (op == OP_ACC) hipLaunchKernelGGL(k_fixup_tiled<OP_ACC>, dim3(g1), dim3(256), 0, st, a, part, base, g1, cap);
+        else hipLaunchKernelGGL(k_fixup_tiled<OP_GRAD>, dim3(g1), dim3(256), 0, st, a, part, base, g1, cap);
+        hipLaunchKernelGGL(k_fixup_reduce, dim3(g2), dim3(256), 0, st, a, (const double*)part, base, g1, cap);
     }
     return hipGetLastError();
 }
