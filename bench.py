@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 FLOPS_ACC = 20     # flops per pair, acceleration (FMA = 2, rsqrt = 1)
 FLOPS_GRAD = 35    # flops per pair, force gradient
+FLOPS_DT = 25      # flops per pair, free-fall / fly-by time-step
 # MI355X vector peaks: FP32 157.3 TFLOP/s (256 CUs x 128 FP32 lanes x 2 flops x 2.4 GHz, which
 # needs packed FP32 issue) and FP64 78.6 TFLOP/s (256 x 64 x 2 x 2.4 GHz).  The library is built
 # with packed FP32 instruction selection off, so the FP32 figure is an upper bound it cannot reach.
@@ -98,95 +99,261 @@ def _pass_rate(ctx, bf, op, call, reps=3):
     return float(np.mean(t)) if t else float("nan")
 
 
+def _roofline(kernel, flops, kernel_ms, n_launches, peak, prec_note):
+    """ALU roofline of a kernel class: credited flops per launch over its average HIP-event
+    duration (launches of different sizes: their total flops over their total time)."""
+    achieved = flops / (kernel_ms * 1e-3) / 1e12 if kernel_ms > 0 else float("nan")
+    return {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None, "launches": n_launches,
+            "flops_per_launch": flops / max(n_launches, 1), "avg_kernel_ms": kernel_ms / max(n_launches, 1),
+            "peak_note": prec_note}
+
+
+def _timed_ops(ctx, bf, fn, reps):
+    """Run fn reps times with kernel timing on: (wall s per rep, {op: (kernel ms per rep,
+    launches per rep)}, {op: credited pairs per rep})."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    for op in (bf.BF_OP_FORCES, bf.BF_OP_GRADIENT, bf.BF_OP_DTMIN):
+        ctx.pair_credit(op, reset=True)
+    ctx.enable_timing(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / reps
+    kt = {op: ctx.kernel_times(op) for op in (bf.BF_OP_FORCES, bf.BF_OP_GRADIENT, bf.BF_OP_DTMIN)}
+    ctx.enable_timing(False)
+    credit = {op: ctx.pair_credit(op, reset=True) / reps for op in kt}
+    return wall, {op: (float(np.sum(v)) / reps, len(v) / reps) for op, v in kt.items()}, credit
+
+
+def _dominant(bf, times, credit, names, peak, prec_note, flops_of=None):
+    """Roofline of the op whose kernels took the most time; times and credit per step."""
+    flops_of = flops_of or {bf.BF_OP_FORCES: FLOPS_ACC, bf.BF_OP_GRADIENT: FLOPS_GRAD, bf.BF_OP_DTMIN: FLOPS_DT}
+    op = max(times, key=lambda o: times[o][0])
+    ms, nl = times[op]
+    return _roofline(names[op], flops_of[op] * credit[op], ms, nl, peak, prec_note)
+
+
+def _cpu_rate(oracle, fn, pairs_of_call, seconds):
+    """Oracle pairs/s: repeat fn until `seconds` of CPU work (at least once)."""
+    k, tc, pairs = 0, 0.0, 0.0
+    while tc < seconds or k == 0:
+        t1 = time.perf_counter()
+        fn(k)
+        tc += time.perf_counter() - t1
+        pairs += pairs_of_call(k)
+        k += 1
+    return pairs / tc, tc, k
+
+
 def run_workload(name, args):
-    """The remaining workloads: each prints one JSON line with its own rates."""
+    """The other configurations: each prints one JSON line in the same form as the headline, its
+    own metric, the roofline of its dominant kernel class and the oracle's rate beside it."""
     import torch
 
     import oracle
     import paper_2210_02472_amd as bf
     from paper_2210_02472_amd import ics
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     ctx = bf.Context(0)
-    rec = {"workload": name, "n_gpus": 1, "data": "synthetic"}
+    steps, warmup = args.steps, args.warmup
+    nthreads = oracle.num_threads()
+    names_mixed = {bf.BF_OP_FORCES: "k_pairs<AccMixed> (acceleration)", bf.BF_OP_GRADIENT: "k_pairs<GradMixed> (gradient)",
+                   bf.BF_OP_DTMIN: "k_pairs<DtMixed> (free-fall / fly-by time-step)"}
+    rec = {"n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic"}
     if name == "plummer1k-fsi":
-        # N = 1024 equal-mass Plummer, eps = 0: one acceleration + gradient evaluation, then 10 FSI
-        # steps with dt = 1e-3 (FP64), energy logged every step
+        # N = 1024 equal-mass Plummer, eps = 0, FP64: one acceleration + gradient evaluation, then
+        # FSI steps with dt = 1e-3 (the first acceleration reused), energy logged every step.  A
+        # step is one FSI cycle: two acceleration passes and one gradient pass (the third
+        # acceleration pass is the next step's first).
         d = ics.config1_plummer1k()
+        n = len(d["m"])
+        dt = 1e-3
         P = bf.Particles.from_numpy(d)
         a = ctx.forces(P, prec="fp64")
         ctx.force_gradient(P, a, prec="fp64")
-        k0, u0 = ctx.energy(P)
-        energies = []
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for s in range(10):
-            a = ctx.fsi_step(P, 1e-3, prec="fp64", acc=a, acc_valid=s > 0)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t
-        k1, u1 = ctx.energy(P)
-        energies = [k0 + u0, k1 + u1]
-        rec.update({"ms_per_fsi_step": wall / 10 * 1e3, "E0": energies[0], "E10": energies[1],
-                    "rel_energy_drift_10_steps": abs(energies[1] / energies[0] - 1)})
+        e0 = sum(ctx.energy(P))
+        energies = [e0]
+        for s in range(10):  # the configured run: 10 steps, energy after each (untimed)
+            a = ctx.fsi_step(P, dt, prec="fp64", acc=a, acc_valid=s > 0)
+            energies.append(sum(ctx.energy(P)))
+        Pt = bf.Particles.from_numpy(d)
+        at = ctx.forces(Pt, prec="fp64")
+        state = {"s": 0}
+
+        def one():
+            nonlocal at
+            at = ctx.fsi_step(Pt, dt, prec="fp64", acc=at, acc_valid=state["s"] > 0)
+            state["s"] += 1
+        for _ in range(warmup):
+            one()
+        wall, times, credit = _timed_ops(ctx, bf, one, steps)
+        pairs = sum(credit.values())
+        names = {bf.BF_OP_FORCES: "k_pairs<Acc64> (acceleration)", bf.BF_OP_GRADIENT: "k_pairs<Grad64> (gradient)",
+                 bf.BF_OP_DTMIN: "-"}
+        roof = _dominant(bf, times, credit, names, PEAK_FP64_TFLOPS, "FP64 vector peak")
+        # oracle: the same FSI steps (acceleration of the first step included)
+        Po = oracle.Particles.from_dict(d)
+        rate, tc, k = _cpu_rate(oracle, lambda k: oracle.fsi_step(Po, dt), lambda k: 3.0 * n * (n - 1), 5.0)
+        rec.update({"metric": "pair interactions/s (FSI steps, N=1024 Plummer, FP64)", "value": pairs / wall,
+                    "unit": "pair interactions/s", "ms_per_step": wall * 1e3, "dtype": "f64",
+                    "config": {"workload": "Plummer N=1024 equal mass, Henon units, eps=0, all active; one "
+                                           "acceleration + gradient evaluation, then FSI steps dt=1e-3 in FP64 "
+                                           "(a step: 2 acceleration passes + 1 gradient pass, FSAL)", "n": n,
+                               "dt": dt},
+                    "pairs_per_step": pairs, "energy_log": energies,
+                    "rel_energy_drift_10_steps": abs(energies[-1] / energies[0] - 1),
+                    "roofline": roof,
+                    "cpu_baseline": {"value": rate, "unit": "pair interactions/s", "cores": nthreads,
+                                     "kind": "oracle", "sample": f"{k} full FSI steps of the same cluster, "
+                                                                 f"3 N(N-1) pairs each (the oracle recomputes "
+                                                                 f"every acceleration), {tc:.1f} s"}})
     elif name == "plummer64k-level":
         # N = 65,536 Kroupa Plummer, a random 10% level, eps = 1e-4: acc + grad + dt_min of the level
-        # against all particles, mixed vs FP64
+        # against all particles, mixed (and FP64 for the speedup)
         d, act = ics.config2_plummer64k()
         P = bf.Particles.from_numpy(d)
         T = torch.as_tensor(act, device="cuda")
         n, nt = len(d["m"]), len(act)
-        pairs = float(nt) * n
-        out = {}
+        eps2 = 1e-8
+        a = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        res = {}
         for prec in ("mixed", "fp64"):
-            a = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
-            ta = _pass_rate(ctx, bf, bf.BF_OP_FORCES, lambda: ctx.forces(P, T, None, eps2=1e-8, prec=prec, r_fb=0.0,
-                                                                         out=a))
-            tg = _pass_rate(ctx, bf, bf.BF_OP_GRADIENT, lambda: ctx.force_gradient(P, a, T, None, eps2=1e-8, prec=prec,
-                                                                                   r_fb=0.0))
-            td = _pass_rate(ctx, bf, bf.BF_OP_DTMIN, lambda: ctx.dt_min(P, T, None, prec=prec, r_fb=1e-3))
-            out[prec] = {"acc_ms": ta, "grad_ms": tg, "dtmin_ms": td, "acc_grad_pairs_per_s": pairs / ((ta + tg) * 1e-3),
-                         "dtmin_pairs_per_s": pairs / (td * 1e-3)}
+            def step():
+                ctx.forces(P, T, None, eps2=eps2, prec=prec, r_fb=0.0, out=a)
+                ctx.force_gradient(P, a, T, None, eps2=eps2, prec=prec, r_fb=0.0)
+                ctx.dt_min(P, T, None, prec=prec, r_fb=0.0)
+            for _ in range(warmup):
+                step()
+            res[prec] = _timed_ops(ctx, bf, step, steps)
+        wall, times, credit = res["mixed"]
+        pairs = sum(credit.values())
+        roof = _dominant(bf, times, credit, names_mixed, PEAK_FP32_TFLOPS, "FP32 vector peak (packed)")
         Po = oracle.Particles.from_dict(d)
-        sample = np.sort(np.random.default_rng(1).choice(act, 128, replace=False))
-        a = ctx.forces(P, T, None, eps2=1e-8, prec="mixed", r_fb=0.0)
-        ref = oracle.forces(Po, sample, None, eps2=1e-8)
-        got = np.stack([t.cpu().numpy()[sample] for t in a], axis=1)
-        e = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
-        rec.update({"n": n, "n_active": nt, "pairs_per_pass": pairs, "passes": out,
-                    "acc_rel_err_rms": float(np.sqrt(np.mean(e * e))), "acc_rel_err_max": float(e.max())})
+        # mixed vs oracle on 256 sampled level particles (acceleration, gradient, time-steps)
+        ctx.forces(P, T, None, eps2=eps2, prec="mixed", out=a)
+        g = ctx.force_gradient(P, a, T, None, eps2=eps2, prec="mixed")
+        dff, dfb = ctx.dt_min(P, T, None, prec="mixed")
+        sample = np.sort(np.random.default_rng(1).choice(act, 256, replace=False))
+        afull = np.stack([t.cpu().numpy() for t in a], axis=1)
+        ref_a = oracle.forces(Po, sample, None, eps2=eps2)
+        ref_g = oracle.gradient(Po, afull, sample, None, eps2=eps2)
+        ref_dt = oracle.dt_min(Po, sample, None)
+        def err(got, ref):
+            e = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            return float(np.sqrt(np.mean(e * e))), float(e.max())
+        e_a = err(afull[sample], ref_a)
+        e_g = err(np.stack([t.cpu().numpy()[sample] for t in g], axis=1), ref_g)
+        got_dt = np.stack([dff.cpu().numpy()[sample], dfb.cpu().numpy()[sample]], axis=1)
+        ref_dt = np.stack(ref_dt, axis=1) if isinstance(ref_dt, tuple) else np.asarray(ref_dt)
+        e_dt = float(np.max(np.abs(got_dt - ref_dt) / np.abs(ref_dt)))
+        # oracle: the whole level, acc + grad + dt_min
+        def cpu_step(k):
+            oracle.forces(Po, act, None, eps2=eps2)
+            oracle.gradient(Po, afull, act, None, eps2=eps2)
+            oracle.dt_min(Po, act, None)
+        rate, tc, k = _cpu_rate(oracle, cpu_step, lambda k: 3.0 * nt * n, 1.0)
+        w64, t64, c64 = res["fp64"]
+        rec.update({"metric": "pair interactions/s (acc+grad+dt_min of a 10% level, N=65536, mixed)",
+                    "value": pairs / wall, "unit": "pair interactions/s", "ms_per_step": wall * 1e3,
+                    "dtype": "f32 pair arithmetic, f64 accumulate",
+                    "config": {"workload": "Plummer N=65536, Kroupa IMF, Henon units, eps=1e-4; a random 10% "
+                                           "level (6554 targets) against all particles: acceleration + "
+                                           "force-gradient + free-fall/fly-by time-step passes, mixed", "n": n,
+                               "n_active": nt, "eps2": eps2},
+                    "pairs_per_step": pairs,
+                    "kernel_ms": {k2: times[v][0] / max(times[v][1], 1e-9) for k2, v in
+                                  (("acc", bf.BF_OP_FORCES), ("grad", bf.BF_OP_GRADIENT), ("dt_min", bf.BF_OP_DTMIN))},
+                    "fp64": {"ms_per_step": w64 * 1e3, "value": sum(c64.values()) / w64,
+                             "kernel_ms": {k2: t64[v][0] / max(t64[v][1], 1e-9) for k2, v in
+                                           (("acc", bf.BF_OP_FORCES), ("grad", bf.BF_OP_GRADIENT),
+                                            ("dt_min", bf.BF_OP_DTMIN))}},
+                    "speedup_vs_fp64": w64 / wall,
+                    "rel_err_vs_oracle": {"acc_rms": e_a[0], "acc_max": e_a[1], "grad_rms": e_g[0],
+                                          "grad_max": e_g[1], "dt_max": e_dt, "sample_targets": 256},
+                    "roofline": roof,
+                    "cpu_baseline": {"value": rate, "unit": "pair interactions/s", "cores": nthreads,
+                                     "kind": "oracle", "sample": f"{k} x the whole level: acceleration + gradient "
+                                                                 f"+ time-step passes, 6554 x 65536 pairs each, "
+                                                                 f"FP64, {tc:.1f} s"}})
     elif name == "ensemble256":
         # 256 equal-mass Plummer clusters, N log-uniform in [1024, 65536], active fractions 2^-k:
-        # one persistent batched launch per pass, and the HIP-graph captured batched FSI cycle
+        # one persistent batched launch per pass; a step is the HIP-graph captured batched FSI cycle
+        # (2 acceleration passes + 1 gradient pass over every cluster's active particles)
         d, off, act, aoff = ics.config4_ensemble()
         P = bf.Particles.from_numpy(d)
         co, ai, ao = (torch.as_tensor(x, device="cuda") for x in (off, act, aoff))
         sizes = np.diff(off)
         nact = np.diff(aoff)
-        pairs = float(np.sum(sizes.astype(np.float64) * nact))
-        maxn = int(sizes.max())
-        ntot = int(off[-1])
+        pairs_pass = float(np.sum(sizes.astype(np.float64) * nact))
+        maxn, ntot, na = int(sizes.max()), int(off[-1]), int(aoff[-1])
+        eps2 = 1e-8
+        dt = 1e-4
         res = {}
         for prec in ("mixed", "fp64"):
-            a = ctx.forces_batched(P, co, ai, ao, int(aoff[-1]), maxn, prec=prec)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(3):
-                ctx.forces_batched(P, co, ai, ao, int(aoff[-1]), maxn, prec=prec, out=a)
-            torch.cuda.synchronize()
-            tf = (time.perf_counter() - t) / 3
-            g = ctx.capture_batched_fsi(P, co, ai, ao, int(aoff[-1]), maxn, 1e-4, a, prec=prec)
-            g.launch()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(3):
+            a = ctx.forces_batched(P, co, ai, ao, na, maxn, eps2=eps2, prec=prec)
+            g = ctx.capture_batched_fsi(P, co, ai, ao, na, maxn, dt, a, eps2=eps2, prec=prec)
+            for _ in range(warmup):
                 g.launch()
             torch.cuda.synchronize()
-            tg = (time.perf_counter() - t) / 3
+            t = time.perf_counter()
+            for _ in range(steps):
+                g.launch()
+            torch.cuda.synchronize()
+            tg = (time.perf_counter() - t) / steps
             g.close()
-            res[prec] = {"forces_ms": tf * 1e3, "forces_pairs_per_s": pairs / tf,
-                         "fsi_cycle_graph_ms": tg * 1e3,
-                         "fsi_cycle_pairs_per_s": 3 * pairs / tg}  # 2 force passes + 1 gradient pass
-        rec.update({"clusters": len(sizes), "particles": ntot, "active": int(aoff[-1]), "active_pairs": pairs,
-                    "passes": res})
+            # per-kernel durations from the eager cycle (events are not recorded inside graphs)
+            wall_e, times, _ = _timed_ops(ctx, bf, lambda: ctx.fsi_step_batched(P, co, ai, ao, na, maxn, dt, a,
+                                                                                eps2=eps2, prec=prec), 2)
+            res[prec] = (tg, wall_e, times)
+        tg, wall_e, times = res["mixed"]
+        credit = {bf.BF_OP_FORCES: 2 * pairs_pass, bf.BF_OP_GRADIENT: pairs_pass, bf.BF_OP_DTMIN: 0.0}
+        names = {bf.BF_OP_FORCES: "k_batch_pairs<AccMixed> (acceleration)",
+                 bf.BF_OP_GRADIENT: "k_batch_pairs<GradMixed> (gradient)", bf.BF_OP_DTMIN: "-"}
+        roof = _dominant(bf, times, credit, names, PEAK_FP32_TFLOPS, "FP32 vector peak (packed)")
+        # oracle on 16 sampled clusters: acceleration + gradient of the active particles
+        Po = oracle.Particles.from_dict(d)
+        pick = np.sort(np.random.default_rng(7).choice(len(sizes), 16, replace=False))
+        sub = []
+        for c in pick:
+            rng_c = np.arange(off[c], off[c + 1])
+            sub.append((rng_c, act[aoff[c]:aoff[c + 1]]))
+
+        def cpu_clusters(k):
+            for src, tg_ in sub:
+                a_ = oracle.forces(Po, tg_, src, eps2=eps2)
+                full = np.zeros((ntot, 3))
+                full[tg_] = a_
+                oracle.gradient(Po, full, tg_, src, eps2=eps2)
+        cpu_pairs = 2.0 * sum(float(len(t_)) * len(s_) for s_, t_ in sub)
+        rate, tc, k = _cpu_rate(oracle, cpu_clusters, lambda k: cpu_pairs, 2.0)
+        t64 = res["fp64"][0]
+        rec.update({"metric": "active pair interactions/s (batched FSI cycle, 256-cluster ensemble, mixed)",
+                    "value": 3 * pairs_pass / tg, "unit": "pair interactions/s", "ms_per_step": tg * 1e3,
+                    "dtype": "f32 pair arithmetic, f64 accumulate",
+                    "config": {"workload": "256 equal-mass Plummer clusters, N log-uniform in [1024, 65536], "
+                                           "active fractions 2^-k (k uniform in 0..6), eps=1e-4; one HIP-graph "
+                                           "replay of the batched FSI cycle (persistent kernel per pass), mixed",
+                               "clusters": len(sizes), "particles": ntot, "active": na,
+                               "active_pairs_per_pass": pairs_pass, "dt": dt},
+                    "eager_cycle_ms": wall_e * 1e3,
+                    "kernel_ms": {"acc": times[bf.BF_OP_FORCES][0] / max(times[bf.BF_OP_FORCES][1], 1e-9),
+                                  "grad": times[bf.BF_OP_GRADIENT][0] / max(times[bf.BF_OP_GRADIENT][1], 1e-9)},
+                    "fp64": {"ms_per_step": t64 * 1e3, "value": 3 * pairs_pass / t64},
+                    "speedup_vs_fp64": t64 / tg,
+                    "roofline": roof,
+                    "cpu_baseline": {"value": rate, "unit": "pair interactions/s", "cores": nthreads,
+                                     "kind": "oracle", "sample": f"{k} x (acceleration + gradient of the active "
+                                                                 f"particles of 16 sampled clusters), FP64, "
+                                                                 f"{tc:.1f} s"}})
     elif name == "bh-levels":
         # N = 262,144 Kroupa Plummer with 16 BHs + 1000 Msun IMBH, levels 0..7 (2^-k at >= k):
         # per level, acceleration + gradient of the level's particles from all particles (mixed)
@@ -209,19 +376,22 @@ def run_workload(name, args):
             tp = time.perf_counter() - t
             levels.append({"level": k, "n_active": int(idx.size), "acc_ms": ta, "grad_ms": tg, "pn1_ms": tp * 1e3,
                            "acc_grad_pairs_per_s": idx.size * float(n) / ((ta + tg) * 1e-3)})
-        rec.update({"n": n, "n_bh": int(len(bh)), "levels": levels})
+        rec.update({"workload": name, "n": n, "n_bh": int(len(bh)), "levels": levels})
     elif name == "bh-hhs":
-        # One HHS-FSI interval over the same cluster and levels (Newtonian part, mixed precision):
-        # eager device driver, the same interval replayed from a HIP graph, the eager interval with
-        # every pass unsorted, and the interval with time-steps reassigned on every level (the
-        # initial time-steps put each particle on its level; the free-fall, fly-by, gradient and
-        # jerk time-steps over each level's particles may move it deeper)
+        # One HHS-FSI interval over the same cluster and levels: Newtonian part mixed, PN1.0 for
+        # every pair with a black hole (FP64, c = 1e4).  A step is one interval (fixed levels,
+        # eager device driver); also: the same interval replayed from a HIP graph, the eager
+        # interval with every pass unsorted, and the interval with time-steps reassigned on every
+        # level (Newtonian only: the initial time-steps put each particle on its level; the
+        # free-fall, fly-by, gradient and jerk time-steps over each level's particles may move it
+        # deeper)
         d, bh, lv = ics.config5_bh_cluster()
         n = len(d["m"])
         kmax = int(lv.max())
         tau = 1.0 / 4096
         level = torch.as_tensor(lv.astype(np.int32), device="cuda")
         P = bf.Particles.from_numpy(d)
+        clight = 1e4
 
         def wall(fn, reps):
             fn()
@@ -237,31 +407,66 @@ def run_workload(name, args):
             seen = []
             adaptive = wall(lambda: seen.append(ctx.hhs_interval_adaptive(P, dt0, kmax, tau, 0.05, 0.05, 0.05, 0.05,
                                                                             prec="mixed")), 2)
-            rec.update({"n": n, "kmax": kmax, "tau": tau, "interval_ms": {"adaptive": adaptive},
+            rec.update({"workload": name, "n": n, "kmax": kmax, "tau": tau, "interval_ms": {"adaptive": adaptive},
                         "adaptive_levels_visited": seen[-1][1]})
             ctx.close()
             print(json.dumps(rec), flush=True)
             return
-        eager = wall(lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed"), 3)
+        interval = lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed", bh=bh, c=clight)  # noqa: E731
         if args.hhs_eager_only:  # for a kernel trace of the eager interval alone
-            rec.update({"n": n, "kmax": kmax, "tau": tau, "interval_ms": {"eager": eager}})
+            rec.update({"workload": name, "n": n, "kmax": kmax, "tau": tau,
+                        "interval_ms": {"eager": wall(interval, steps)}})
             ctx.close()
             print(json.dumps(rec), flush=True)
             return
-        g = ctx.capture_hhs_interval(P, level, kmax, tau, prec="mixed")  # the same passes, replayed
-        graph = wall(g.launch, 3)
+        for _ in range(warmup):
+            interval()
+        w, times, credit = _timed_ops(ctx, bf, interval, steps)
+        pairs = sum(credit.values())
+        names = {bf.BF_OP_FORCES: "k_pairs_sym<SymAcc> / two-set and directed acceleration kernels",
+                 bf.BF_OP_GRADIENT: "k_pairs_sym<SymGrad> / two-set and directed gradient kernels",
+                 bf.BF_OP_DTMIN: "-"}
+        roof = _dominant(bf, times, credit, names, PEAK_FP32_TFLOPS, "FP32 vector peak (packed)")
+        g = ctx.capture_hhs_interval(P, level, kmax, tau, prec="mixed", bh=bh, c=clight)
+        graph = wall(g.launch, steps)
         g.close()
         ctx.set_spatial_sort(False, False)  # reference: every pass unsorted
-        eager_unsorted = wall(lambda: ctx.hhs_interval(P, level, kmax, tau, prec="mixed"), 3)
+        eager_unsorted = wall(interval, 2)
         ctx.set_spatial_sort(True, True)
         levels_seen = []
         adaptive = wall(lambda: levels_seen.append(ctx.hhs_interval_adaptive(P, dt0, kmax, tau, 0.05, 0.05, 0.05,
                                                                                 0.05, prec="mixed")), 2)
         counts = np.bincount(lv, minlength=kmax + 1)
-        rec.update({"n": n, "kmax": kmax, "tau": tau, "particles_per_level": counts.tolist(),
-                    "interval_ms": {"eager": eager, "eager_unsorted": eager_unsorted, "graph": graph,
-                                    "adaptive": adaptive},
-                    "adaptive_deepest_level": levels_seen[-1][0], "adaptive_levels_visited": levels_seen[-1][1]})
+        # oracle: a bounded sample of the interval's largest passes, level 0 against all particles
+        Po = oracle.Particles.from_dict(d)
+        rng = np.random.default_rng(5)
+        afield = synthetic_acc_field(d)
+
+        def cpu_sample(k):
+            Ts = np.sort(rng.choice(n, 512, replace=False))
+            oracle.forces(Po, Ts, None)
+            oracle.gradient(Po, afield, Ts, None)
+        rate, tc, k = _cpu_rate(oracle, cpu_sample, lambda k: 2.0 * 512 * (n - 1), 10.0)
+        rec.update({"metric": "pair interactions/s (one HHS-FSI interval, N=262144 with 17 BHs, PN1.0)",
+                    "value": pairs / (w), "unit": "pair interactions/s", "ms_per_step": w * 1e3,
+                    "dtype": "f32 pair arithmetic, f64 accumulate; PN1.0 f64",
+                    "config": {"workload": "Plummer N=262144, Kroupa IMF, 16 BHs (10-100 Msun) + 1000 Msun IMBH "
+                                           "at the centre, M=1, eps=0; fixed levels 0..7 (fraction 2^-k at "
+                                           "level >= k, BHs deepest); one HHS-FSI interval tau=1/4096, "
+                                           "Newtonian passes mixed, PN1.0 FP64 c=1e4", "n": n, "n_bh": int(len(bh)),
+                               "kmax": kmax, "tau": tau, "particles_per_level": counts.tolist()},
+                    "pairs_per_step": pairs,
+                    "kernel_ms_per_step": {"acc": times[bf.BF_OP_FORCES][0], "grad": times[bf.BF_OP_GRADIENT][0],
+                                           "acc_launches": times[bf.BF_OP_FORCES][1],
+                                           "grad_launches": times[bf.BF_OP_GRADIENT][1]},
+                    "interval_ms": {"eager": w * 1e3, "graph": graph, "eager_unsorted": eager_unsorted,
+                                    "adaptive_newtonian": adaptive},
+                    "adaptive_deepest_level": levels_seen[-1][0], "adaptive_levels_visited": levels_seen[-1][1],
+                    "roofline": roof,
+                    "cpu_baseline": {"value": rate, "unit": "pair interactions/s", "cores": nthreads,
+                                     "kind": "oracle", "sample": f"{k} x 512 random targets x all {n} sources, "
+                                                                 f"acceleration + gradient (the level-0 passes), "
+                                                                 f"FP64, {tc:.1f} s"}})
     elif name == "bh-aux":
         # The same 262,144-body cluster, every particle a target and a source: the passes around
         # the force sweeps, each timed on its own (wall clock, synchronised, mean of 3 after one
@@ -302,7 +507,7 @@ def run_workload(name, args):
         out["forces_excluded_ms"] = wall(lambda: ctx.forces(P, prec="mixed"))
         ctx.set_subsystems(None)
         out["energy_ms"] = wall(lambda: ctx.energy(P))
-        rec.update({"n": n, "pairs_per_pass": float(n) * n, "level_counts": [int(c) for c in counts],
+        rec.update({"workload": name, "n": n, "pairs_per_pass": float(n) * n, "level_counts": [int(c) for c in counts],
                     "neighbour_pairs": int(edges.shape[0]), "subsystems": int(nsub), "ms": out})
     ctx.close()
     print(json.dumps(rec), flush=True)
@@ -421,7 +626,7 @@ def main():
         rfb_var = {"r_fb": args.rfb_variant, "value": pairs / (wall_v / 2), "ms_per_step": wall_v / 2 * 1e3,
                    "acc_kernel_ms": float(np.mean(ka_v)), "grad_kernel_ms": float(np.mean(kg_v))}
     log("fp64 sweep ...")
-    wall_d, ka_d, kg_d = timed("fp64", args.fp64_steps, 0)
+    wall_d, ka_d, kg_d = timed("fp64", args.fp64_steps, 1)  # one untimed sweep sizes its scratch first
     ms_fp64 = wall_d / args.fp64_steps * 1e3
     log(f"fp64: {ms_fp64:.1f} ms/step")
 
@@ -515,11 +720,15 @@ def main():
         "dtype": "f32 pair arithmetic, f64 accumulate",
         "data": "synthetic",
         "config": {"workload": f"King W0=6 cluster N={n}, Kroupa IMF + 1% binaries as COM particles, Henon units, "
-                               f"eps=0, all active; acceleration + force-gradient sweep, mixed precision (every "
-                               f"pair separation formed in FP64 and rounded once, FP32 pair arithmetic, FP64 "
-                               f"merge and cancellation fix-up)",
+                               f"eps=0, all active; acceleration + force-gradient sweep, mixed precision (pair "
+                               f"separations of near tiles formed in FP64 and rounded once, of far tiles from FP32 "
+                               f"offsets to the tile centre; FP32 pair arithmetic, FP64 merge and cancellation "
+                               f"fix-up)",
                    "n": n, "eps": 0.0, "r_fb": args.r_fb,
-                   "fp64_differences": "all pairs (covers pairs at r < 1e-3)",
+                   "fp64_differences": "near tiles (gap to the wavefront's rows below kappa x tile half-extent, "
+                                       "kappa = 1, and the diagonal tiles); far-tile separations come from FP32 "
+                                       "offsets to the tile centre, relative error <= u (1 + 2 sqrt(3) / kappa) "
+                                       "= 4.5 u at every separation, pairs at r < 1e-3 included",
                    "autotuned": bool(args.autotune),
                    "acc_pass": pass_desc(cfg_a), "grad_pass": pass_desc(cfg_g)},
         "roofline": {"bound": "alu",

@@ -287,8 +287,10 @@ BF_API int bf_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, co
  * graph are the eager ones, the spatially sorted mode included; there its Morton order comes
  * from a merge sort, which launches kernels only (the eager radix sort clears its counters with
  * memset operations, which a graph must not hold): both sorts are stable, so a replay equals an
- * eager bf_hhs_interval bit for bit.  Kernel timing is off while capturing.  Errors as
- * bf_hhs_interval; an empty set is BF_ERR_ARG; prm->n_bh must be 0 (BF_ERR_UNSUPPORTED). */
+ * eager bf_hhs_interval bit for bit.  With prm->n_bh > 0 the graph holds the PN1.0 half-kicks
+ * at the same places as the eager interval (their kernels take the black-hole list captured
+ * here).  Kernel timing is off while capturing.  Errors as bf_hhs_interval; an empty set is
+ * BF_ERR_ARG. */
 BF_API int bf_graph_capture_hhs_interval(bf_ctx *ctx, const bf_state *S, const bf_set *set, const int32_t *level,
                                          int kmax, double tau, const bf_fsi_params *prm, void **graph_exec);
 
@@ -463,6 +465,14 @@ BF_API int bf_set_spatial_sort(bf_ctx *ctx, int ops_mask, double kappa);
  * took the near (FP64-difference) and far (FP32 tile-offset) paths. */
 BF_API int bf_last_pass_stats(bf_ctx *ctx, int64_t *fixups, int64_t *near_tiles, int64_t *far_tiles);
 
+/* Not synchronising.  Pair interactions credited by the passes of op (bf_op) since the context
+ * was created or last reset (reset != 0 clears the count after reading it): an acceleration,
+ * gradient or time-step pass credits n_targets x n_sources directed pairs, less the self-pairs
+ * (n_targets x (n_sources - 1)) when its targets and sources are one set (the same index array or
+ * range); the two-set sums of bf_forces_between / bf_force_gradient_between credit 2 |a| |b|;
+ * passes inside the HHS drivers credit alike.  Batched ensembles are not counted. */
+BF_API int bf_pair_credit(bf_ctx *ctx, int op, int64_t *pairs, int reset);
+
 /* Not synchronising.  How the most recent acceleration / gradient / time-step pass ran:
  * kind BF_PASS_UNSORTED, BF_PASS_SORTED (spatially sorted, directed sweep), BF_PASS_SYMMETRIC
  * (spatially sorted, each unordered pair once) or BF_PASS_BETWEEN (the two-set symmetric sweep
@@ -492,8 +502,9 @@ BF_API int bf_set_config(bf_ctx *ctx, int op, int prec, int k_per_lane, int wave
 /* ---- kernel timing ------------------------------------------------------------------ */
 
 /* When on != 0 the context records a pair of HIP events on its stream around every launch
- * of the main pair kernel of bf_forces / bf_force_gradient / bf_dt_min (pack and reduction
- * kernels excluded).  Turning timing on or off discards earlier records. */
+ * of the main pair kernel of bf_forces / bf_force_gradient / bf_dt_min, of the two-set sums and
+ * of the persistent kernel of the batched passes (pack and reduction kernels excluded; nothing
+ * inside a graph capture).  Turning timing on or off discards earlier records. */
 BF_API int bf_enable_timing(bf_ctx *ctx, int on);
 /* Synchronising.  Copy the durations (milliseconds) of the recorded launches of op
  * (bf_op) into ms[0 .. min(count, cap)), set *count to the number recorded, and discard

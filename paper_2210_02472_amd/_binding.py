@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH):
         "bf_set_config": [_vp, _int, _int, _int, _int, _int],
         "bf_enable_timing": [_vp, _int],
         "bf_set_spatial_sort": [_vp, _int, ctypes.c_double],
+        "bf_pair_credit": [_vp, _int, ctypes.POINTER(_i64), _int],
         "bf_set_hhs_reuse": [_vp, _int],
         "bf_neighbours": [_vp, P, S, S, _d, _d, _d, _d, _d, _vp, _i64, ctypes.POINTER(_i64)],
         "bf_subsystems": [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i64)],
@@ -399,8 +400,8 @@ class Context:
 
     def capture_hhs_interval(self, P: Particles, level: torch.Tensor, kmax: int, tau: float, subset=None, G=1.0,
                              eps2=0.0, prec="mixed", r_fb=0.0, bh=None, c=1e4) -> "Graph":
-        """Capture one fixed-level HHS-FSI interval into a HIP graph (launch to advance P).
-        PN1.0 is not captured: a non-empty bh is refused by the library."""
+        """Capture one fixed-level HHS-FSI interval into a HIP graph (launch to advance P), with
+        the PN1.0 half-kicks of the black holes in bh if given."""
         s = ParticleSet.of(subset, P.n)
         _need(level, torch.int32, P.n, "level")
         b = ParticleSet.of(bh, P.n) if bh is not None else ParticleSet(None, 0, 0)
@@ -409,7 +410,7 @@ class Context:
         _check("bf_graph_capture_hhs_interval",
                _lib.bf_graph_capture_hhs_interval(self._h, ctypes.byref(P._state()), ctypes.byref(s._c()), _ptr(level),
                                                   int(kmax), float(tau), ctypes.byref(prm), ctypes.byref(h)))
-        return Graph(self, h, keep=(P, level, s))
+        return Graph(self, h, keep=(P, level, s, b))
 
     def hhs_interval_adaptive(self, P: Particles, dt0: torch.Tensor, kmax: int, tau: float, eta_ff=0.2, eta_fb=0.2,
                               eta_grad=0.1, eta_jerk=0.1, subset=None, G=1.0, eps2=0.0, prec="fp64", r_fb=0.0):
@@ -513,6 +514,12 @@ class Context:
         freed = ctypes.c_size_t(0)
         _check("bf_release_scratch", _lib.bf_release_scratch(self._h, ctypes.byref(freed)))
         return freed.value
+
+    def pair_credit(self, op: int, reset: bool = False) -> int:
+        """Pair interactions credited by the passes of op since creation or the last reset."""
+        v = _i64(0)
+        _check("bf_pair_credit", _lib.bf_pair_credit(self._h, int(op), ctypes.byref(v), int(bool(reset))))
+        return v.value
 
     def last_pass_config(self):
         """(kind, k_per_lane, waves, split) of the most recent pass; kind is "unsorted", "sorted"

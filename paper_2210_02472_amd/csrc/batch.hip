@@ -256,6 +256,8 @@ int bf_internal_ensure(bf_ctx* ctx, int which, size_t need);
 void* bf_internal_scratch(bf_ctx* ctx, int which);
 int bf_internal_fail(int code, const char* msg);
 void bf_internal_swap_scratch(bf_ctx* ctx, void* bufs[3], size_t bytes[3]);
+std::pair<hipEvent_t, hipEvent_t> bf_internal_timer_begin(bf_ctx* c);
+void bf_internal_timer_end(bf_ctx* c, int op, std::pair<hipEvent_t, hipEvent_t> ev);
 
 static int batch_setup(bf_ctx* c, const bf_particles* P, int32_t nclusters, const int64_t* coff, const int32_t* aidx,
                        const int64_t* aoff, int64_t max_active, int64_t max_cluster_n, double G, double eps2, int prec,
@@ -317,9 +319,11 @@ static int batch_enqueue(bf_ctx* c, Batch& b, int op, int prec) {
     if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
     hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, st, b);
     const bool mixed = prec == BF_PREC_MIXED;
+    const auto ev = bf_internal_timer_begin(c);  // the persistent pair kernel, when timing is on
     if (op == OP_ACC) e = mixed ? launch_batch_op<AccMixed>(b, c->num_cu, st) : launch_batch_op<Acc64>(b, c->num_cu, st);
     else e = mixed ? launch_batch_op<GradMixed>(b, c->num_cu, st) : launch_batch_op<Grad64>(b, c->num_cu, st);
     if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
+    bf_internal_timer_end(c, op, ev);
     if (b.max_active > 0) {
         const dim3 g((unsigned)((b.max_active + 255) / 256));
         if (mixed) hipLaunchKernelGGL(k_batch_reduce<4>, g, dim3(256), 0, st, b);
@@ -465,7 +469,9 @@ BF_API int bf_graph_capture_batched_fsi(bf_ctx* c, const bf_state* S, int32_t nc
         return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
     }
     c->stream = cap;
+    c->capturing = true;  // no timing events inside the graph
     rc = batched_fsi_enqueue(c, S, ba, bg, prec, dt);
+    c->capturing = false;
     c->stream = user;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap, &g);

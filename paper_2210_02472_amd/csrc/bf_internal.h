@@ -310,7 +310,8 @@ struct bf_ctx {
     size_t scratch11_bytes = 0;
     bool capturing = false;           // a graph capture is recording this context's work
     bool dry = false;                 // size scratch only, launch nothing (before a capture)
-    unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass
+    unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass, [4]: HHS
+                                            // black-hole level mask
     int last_kind = 0, last_k = 0, last_waves = 0, last_split = 0;  // how the last pass ran
     // spatially sorted mixed passes: bit op set = use them for that operation when large enough
     int sort_ops = (1 << 0) | (1 << 1);  // acceleration and force-gradient passes
@@ -318,6 +319,7 @@ struct bf_ctx {
     int64_t sub_n = 0;
     float kappa = 1.0f;               // a tile is near a workgroup when their gap < kappa * tile half-extent
     bool hhs_reuse = true;            // HHS drivers keep accelerations between visits of a level
+    int64_t pair_credit[bf::OP_COUNT] = {};  // pair interactions credited by the passes of each op
     // kernel timing: event pairs around pair-kernel launches, per op
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[bf::OP_COUNT];

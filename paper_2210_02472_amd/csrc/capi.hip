@@ -494,6 +494,8 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     else if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
     else if (small) BF_HIP(launch_pairs_small(op, a, ctx->stream));
     else BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
+    // credit: every (target, source) pair, less the self-pairs when targets and sources are one set
+    ctx->pair_credit[op] += (int64_t)tg->count * (same_set(tg, sr) ? sr->count - 1 : sr->count);
     ctx->last_kind = sym || sym64 ? BF_PASS_SYMMETRIC : sorted ? BF_PASS_SORTED : BF_PASS_UNSORTED;
     ctx->last_k = sym ? sym_rows_per_wave(op) : sym64 ? 4 : small ? 1 : p.cfg.k;
     ctx->last_waves = sym ? sym_waves(op) : sym64 ? 4 : small ? 16 : p.cfg.waves;
@@ -642,6 +644,7 @@ int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
     }
+    ctx->pair_credit[op] += 2 * (int64_t)A->count * B->count;  // a <- b and b <- a
     ctx->last_kind = BF_PASS_BETWEEN;
     ctx->last_k = sym_rows_per_wave(op);
     ctx->last_waves = sym_waves(op);
@@ -666,6 +669,26 @@ int check_prec(int prec) {
 
 // shared with batch.hip
 int bf_internal_fail(int code, const char* msg) { return fail(code, msg); }
+
+// HIP events around a kernel launch of op on the context stream (when timing is on and nothing
+// is being captured): begin returns the pair (or two null events), end records it
+std::pair<hipEvent_t, hipEvent_t> bf_internal_timer_begin(bf_ctx* c) {
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (!c->timing || c->capturing) return ev;
+    if (!c->tpool.empty()) {
+        ev = c->tpool.back();
+        c->tpool.pop_back();
+    } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+        return {nullptr, nullptr};
+    }
+    if (hipEventRecord(ev.first, c->stream) != hipSuccess) return {nullptr, nullptr};
+    return ev;
+}
+void bf_internal_timer_end(bf_ctx* c, int op, std::pair<hipEvent_t, hipEvent_t> ev) {
+    if (!ev.first || !ev.second) return;
+    if (hipEventRecord(ev.second, c->stream) == hipSuccess) c->tev[op].push_back(ev);
+}
+void bf_internal_credit(bf_ctx* c, int op, int64_t pairs) { c->pair_credit[op] += pairs; }
 
 int bf_internal_ensure(bf_ctx* c, int which, size_t need) {
     switch (which) {
@@ -728,7 +751,7 @@ BF_API int bf_create(bf_ctx** out, int device, void* stream) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
     c->num_cu = prop.multiProcessorCount;
-    if (hipMalloc(&c->d_stats, 4 * sizeof(unsigned long long)) != hipSuccess ||
+    if (hipMalloc(&c->d_stats, 8 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_flags, sizeof(uint32_t)) != hipSuccess ||
         hipHostMalloc(&c->h_flags, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -993,6 +1016,7 @@ static int pn1_impl(bf_ctx* c, const Masters& M, const bf_set* t, const bf_set* 
         a.part = static_cast<double*>(c->scratch);
         a.bh_in_src = reinterpret_cast<int32_t*>(static_cast<char*>(c->scratch) + ((part_bytes + 255) & ~size_t(255)));
     }
+    if (c->dry) return BF_OK;  // sizing before a capture: the scratch now exists
     BF_HIP(launch_pn1(a, c->stream));
     return BF_OK;
 }
@@ -1097,9 +1121,9 @@ static int fsi_impl(bf_ctx* c, const bf_state* S, const bf_set* set, double dt, 
 
     auto pn_half_kick = [&]() -> int {
         if (prm->n_bh == 0) return BF_OK;
-        if (c->dry) return fail(BF_ERR_UNSUPPORTED, "PN1.0 kicks are not captured");
         if (int r = pn1_impl(c, M, set, set, prm->bh_idx, prm->n_bh, G, prm->c, gx, gy, gz)) return r;
-        BF_HIP(launch_kick(*S, ds, 0.5 * dt, gx, gy, gz, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
+        if (!c->dry)
+            BF_HIP(launch_kick(*S, ds, 0.5 * dt, gx, gy, gz, 0.0, nullptr, nullptr, nullptr, c->d_flags, c->stream));
         return BF_OK;
     };
     auto acc = [&]() { return run_pairs(c, OP_ACC, prec, M, set, set, G, e2, rfb, 0, 0, ax, ay, az); };
@@ -1234,6 +1258,23 @@ BF_API int bf_level_partition(bf_ctx* c, const bf_set* set, int64_t n, const int
 
 namespace {
 
+// bit l of *mask set when a listed black hole sits on level l (an entry outside the particle
+// range or the levels sets every bit); one workgroup
+__global__ __launch_bounds__(256) void k_bh_level_mask(const int32_t* bh, int32_t nbh, const int32_t* level, int64_t n,
+                                                      unsigned long long* mask) {
+    if (threadIdx.x == 0) *mask = 0ull;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbh; i += blockDim.x) {
+        const int32_t p = bh[i];
+        unsigned long long b = ~0ull;
+        if (p >= 0 && p < n) {
+            const int32_t l = level[p];
+            if (l >= 0 && l < 64) b = 1ull << l;
+        }
+        atomicOr(mask, b);
+    }
+}
+
 struct HhsCtx {
     bf_ctx* c;
     const bf_state* S;
@@ -1255,6 +1296,10 @@ struct HhsCtx {
     double* asf_lv[64];
     mutable bool a_ok[64], il_ok[64];
     bool reuse = false;
+    // fixed levels with PN1.0: bit l set when a black hole sits on level l.  A PN kick over sets
+    // with no black hole adds exactly zero, so it is not launched (unknown: every kick runs).
+    bool bh_known = false;
+    unsigned long long bh_levels = ~0ull;
 };
 
 bf_set segment(const HhsCtx& h, int64_t b, int64_t e) { return bf_set{h.order + b, (int32_t)(e - b), 0}; }
@@ -1278,9 +1323,15 @@ int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_
     const bf_fsi_params* p = h.prm;
     const bool keep = h.reuse && k >= 0;
     double* const as = keep && h.asf_lv[k] ? h.asf_lv[k] : h.asf;
+    // which of S (level k) and F (deeper) hold a black hole
+    const bool known = h.bh_known && k >= 0 && k < 64;
+    const unsigned long long deeper = known && k < 63 ? ~((2ull << k) - 1ull) : 0ull;
+    const bool s_bh = !known || (h.bh_levels >> k & 1ull), f_bh = !known || (h.bh_levels & deeper);
+    bf_fsi_params pf = *p;
+    if (!s_bh) pf.n_bh = 0;  // no PN pair inside S
     auto fsi = [&](double dt) {
         const int fl = keep && h.a_ok[k] ? BF_A_VALID : 0;
-        const int r = fsi_impl(c, h.S, &Sset, dt, p, h.afsi, h.afsi + n, h.afsi + 2 * n, fl, h.gfsi, h.gfsi + n,
+        const int r = fsi_impl(c, h.S, &Sset, dt, &pf, h.afsi, h.afsi + n, h.afsi + 2 * n, fl, h.gfsi, h.gfsi + n,
                                h.gfsi + 2 * n);
         if (keep) h.a_ok[k] = r == BF_OK;
         return r;
@@ -1303,14 +1354,14 @@ int hhs_cycle(const HhsCtx& h, const bf_set& Sset, const bf_set& Fset, const bf_
     // over its own pairs (fsi_impl), and each level's cycle is wrapped in half-kicks over its
     // inter-level pairs with a flagged particle
     auto pn_interlevel_half_kick = [&]() -> int {
-        if (p->n_bh == 0) return BF_OK;
-        if (c->dry) return fail(BF_ERR_UNSUPPORTED, "PN1.0 kicks are not captured");
+        if (p->n_bh == 0 || !(s_bh || f_bh)) return BF_OK;
         if (int r = pn1_impl(c, h.M, &Sset, &Fset, p->bh_idx, p->n_bh, p->G, p->c, h.gsf, h.gsf + n, h.gsf + 2 * n))
             return r;
         if (int r = pn1_impl(c, h.M, &Fset, &Sset, p->bh_idx, p->n_bh, p->G, p->c, h.gsf, h.gsf + n, h.gsf + 2 * n))
             return r;
-        BF_HIP(launch_kick(*h.S, dB, 0.5 * tau, h.gsf, h.gsf + n, h.gsf + 2 * n, 0.0, nul, nul, nul, c->d_flags,
-                           c->stream));
+        if (go)
+            BF_HIP(launch_kick(*h.S, dB, 0.5 * tau, h.gsf, h.gsf + n, h.gsf + 2 * n, 0.0, nul, nul, nul, c->d_flags,
+                               c->stream));
         return BF_OK;
     };
     if ((rc = pn_interlevel_half_kick())) return rc;
@@ -1499,6 +1550,17 @@ static int hhs_setup(bf_ctx* c, const bf_state* S, const bf_set* set, const int3
         h.asf_lv[k] = split ? static_cast<double*>(c->scratch11) + (size_t)(i++) * 3 * n : nullptr;
     }
     h.reuse = c->hhs_reuse;
+    if (prm->n_bh > 0 && set->count > 0) {
+        // the levels of the black holes, once per interval (the partition has synchronised)
+        unsigned long long mask = ~0ull;
+        hipLaunchKernelGGL(k_bh_level_mask, dim3(1), dim3(256), 0, c->stream, prm->bh_idx, prm->n_bh, level, n,
+                           c->d_stats + 4);
+        BF_HIP(hipGetLastError());
+        BF_HIP(hipMemcpyAsync(&mask, c->d_stats + 4, sizeof(mask), hipMemcpyDeviceToHost, c->stream));
+        BF_HIP(hipStreamSynchronize(c->stream));
+        h.bh_known = true;
+        h.bh_levels = mask;
+    }
     return BF_OK;
 }
 
@@ -1517,7 +1579,6 @@ BF_API int bf_graph_capture_hhs_interval(bf_ctx* c, const bf_state* S, const bf_
     if (int rc = check_ctx(c)) return rc;
     if (!graph_exec) return fail(BF_ERR_ARG, "graph pointer NULL");
     *graph_exec = nullptr;
-    if (prm && prm->n_bh != 0) return fail(BF_ERR_UNSUPPORTED, "a captured interval runs without PN1.0 (n_bh must be 0)");
     // The graph gets buffers of its own: park the context's while the interval is sized and
     // captured, then hand the new ones to the graph and give the context its own back.
     constexpr int kSlots = 9;
@@ -1672,6 +1733,15 @@ BF_API int bf_last_pass_stats(bf_ctx* c, int64_t* fixups, int64_t* near_tiles, i
     if (fixups) *fixups = (int64_t)(h[0] & 0xffffffffull);
     if (near_tiles) *near_tiles = (int64_t)h[1];
     if (far_tiles) *far_tiles = (int64_t)h[2];
+    return BF_OK;
+}
+
+BF_API int bf_pair_credit(bf_ctx* c, int op, int64_t* pairs, int reset) {
+    if (int rc = check_ctx(c)) return rc;
+    if (op < 0 || op >= OP_COUNT) return fail(BF_ERR_ARG, "bad op");
+    if (!pairs) return fail(BF_ERR_ARG, "pairs NULL");
+    *pairs = c->pair_credit[op];
+    if (reset) c->pair_credit[op] = 0;
     return BF_OK;
 }
 

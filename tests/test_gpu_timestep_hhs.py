@@ -352,5 +352,38 @@ def test_hhs_interval_with_pn_parity(ctx):
         ref = getattr(P, k)
         got = getattr(Pd, k).cpu().numpy()
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
-    with pytest.raises(bf.BifrostError):  # PN kicks are not captured into graphs
-        ctx.capture_hhs_interval(Pd, torch.as_tensor(level, device="cuda"), 2, tau, prec="fp64", bh=bh)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_hhs_interval_with_pn_graph_replays_match_eager(ctx, prec):
+    """A fixed-level interval with black holes and PN1.0 kicks captured into a HIP graph and
+    replayed three times (eager work and synchronisation in between) against three eager
+    intervals on a copy of the state: equal bit for bit after every replay; the first replay also
+    against the oracle recursion (FP64)."""
+    n = 900
+    d = _cluster(n, 13)
+    bh = np.array([3, 100, 450], dtype=np.int32)
+    d["m"][bh] *= 50.0
+    rng = np.random.default_rng(15)
+    level = rng.choice([0, 1, 2], size=n, p=[0.6, 0.3, 0.1]).astype(np.int32)
+    level[bh] = 2
+    lv = torch.as_tensor(level, device="cuda")
+    tau = 2e-3
+    A, B = bf.Particles.from_numpy(d), bf.Particles.from_numpy(d)
+    g = ctx.capture_hhs_interval(A, lv, 2, tau, prec=prec, bh=bh, c=30.0)
+    for r in range(3):
+        g.launch()
+        ctx.hhs_interval(B, lv, 2, tau, prec=prec, bh=bh, c=30.0)
+        ctx.forces(bf.Particles.from_numpy(d), prec=prec)  # unrelated eager work in between
+        torch.cuda.synchronize()
+        for k in ("x", "y", "z", "vx", "vy", "vz"):
+            assert torch.equal(getattr(A, k), getattr(B, k)), (r, k)
+        if r == 0 and prec == "fp64":
+            P = oracle.Particles.from_dict(d)
+            oracle.hhs_interval(P, level, tau, bh=bh, c=30.0)
+            for k in ("x", "y", "z", "vx", "vy", "vz"):
+                ref = getattr(P, k)
+                got = getattr(A, k).cpu().numpy()
+                assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
+    g.close()
+    assert ctx.read_flags() & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
