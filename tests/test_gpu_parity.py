@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_2210_02472_amd import ics
-from tests._parity import gather, rel_errors, stats
+from tests._parity import assert_state_close, gather, rel_errors, stats
 
 bf = pytest.importorskip("paper_2210_02472_amd")
 
@@ -344,8 +344,9 @@ def test_energy_parity(ctx):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_fsi_step_parity(ctx, prec):
     """Three FSI cycles of the N = 1024 Plummer sphere.  FP64: state within 1e-12 of its scale.
-    Mixed: the change of the state over the steps is within the mixed tolerance (1e-5) of the
-    oracle's change (the kicks carry the relative error of the accelerations)."""
+    Mixed: per particle, the position and velocity within the mixed tolerance (1e-5) of the
+    particle's own change over the steps (the kicks carry the relative error of the
+    accelerations), with a floor of 1e-3 of the largest change."""
     d = ics.config1_plummer1k()
     P, Pd = oracle.Particles.from_dict(d), _dev(d)
     P0 = P.copy()
@@ -353,14 +354,13 @@ def test_fsi_step_parity(ctx, prec):
     for s in range(3):
         oracle.fsi_step(P, 1e-3)
         acc = ctx.fsi_step(Pd, 1e-3, prec=prec, acc=acc, acc_valid=s > 0)
+    if prec == "mixed":
+        assert_state_close(Pd, P, P0, MAX_TOL)
+        return
     for k in ("x", "y", "z", "vx", "vy", "vz"):
         ref = getattr(P, k)
         got = getattr(Pd, k).cpu().numpy()
-        if prec == "fp64":
-            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
-        else:
-            change = np.abs(ref - getattr(P0, k)).max()
-            assert np.abs(got - ref).max() <= MAX_TOL * change, k
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
 
 
 def test_fsi_step_with_pn_parity(ctx):
