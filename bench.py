@@ -298,7 +298,19 @@ def run_workload(name, args):
         eps2 = 1e-8
         dt = 1e-4
         res = {}
+        shapes = {}
+        if args.autotune:
+            t1 = time.time()
+            af = synthetic_acc_field(d)
+            acc_t = [torch.as_tensor(np.ascontiguousarray(af[:, k]), device="cuda") for k in range(3)]
+            for prec in ("mixed", "fp64"):
+                ctx.autotune_batched(bf.BF_OP_FORCES, prec, P, co, ai, ao, na, maxn)
+                ctx.autotune_batched(bf.BF_OP_GRADIENT, prec, P, co, ai, ao, na, maxn, acc=acc_t)
+            log(f"autotuned the batched passes in {time.time() - t1:.1f}s")
         for prec in ("mixed", "fp64"):
+            shapes[prec] = {op_name: dict(zip(("k_per_lane", "waves", "sources_per_item"),
+                                              ctx.query_batched_config(op, prec, na, maxn)))
+                            for op_name, op in (("acc", bf.BF_OP_FORCES), ("grad", bf.BF_OP_GRADIENT))}
             a = ctx.forces_batched(P, co, ai, ao, na, maxn, eps2=eps2, prec=prec)
             g = ctx.capture_batched_fsi(P, co, ai, ao, na, maxn, dt, a, eps2=eps2, prec=prec)
             for _ in range(warmup):
@@ -343,7 +355,8 @@ def run_workload(name, args):
                                            "active fractions 2^-k (k uniform in 0..6), eps=1e-4; one HIP-graph "
                                            "replay of the batched FSI cycle (persistent kernel per pass), mixed",
                                "clusters": len(sizes), "particles": ntot, "active": na,
-                               "active_pairs_per_pass": pairs_pass, "dt": dt},
+                               "active_pairs_per_pass": pairs_pass, "dt": dt, "autotuned": bool(args.autotune),
+                               "batched_shapes": shapes},
                     "eager_cycle_ms": wall_e * 1e3,
                     "kernel_ms": {"acc": times[bf.BF_OP_FORCES][0] / max(times[bf.BF_OP_FORCES][1], 1e-9),
                                   "grad": times[bf.BF_OP_GRADIENT][0] / max(times[bf.BF_OP_GRADIENT][1], 1e-9)},
@@ -538,7 +551,7 @@ def main():
                     help="passes that use the spatially sorted mixed kernels (default: the library's; directed: sorted without the pair-symmetric sweep)")
     ap.add_argument("--kappa", type=float, default=0.0, help="near-tile threshold (0: the library's)")
     ap.add_argument("--autotune", action="store_true",
-                    help="run the library autotuner for both passes before timing")
+                    help="run the library autotuner on the workload's own particles before timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 2 GiB device-to-device copy kernel first (HBM counter calibration)")
     ap.add_argument("--workload", default="king1m",
@@ -582,12 +595,13 @@ def main():
                 "both": (True, True), "directed": (True, True)}[args.spatial_sort]
         ctx.set_spatial_sort(forces=mode[0], gradient=mode[1], kappa=args.kappa,
                              symmetric=args.spatial_sort != "directed")
-    if args.autotune:
-        t1 = time.time()
-        for op in (bf.BF_OP_FORCES, bf.BF_OP_GRADIENT):
-            ctx.autotune(op, "mixed", n, n)
-        log(f"autotuned in {time.time() - t1:.1f}s")
     out_a = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    if args.autotune:  # on this cluster: the pair-symmetric sweep's shapes
+        t1 = time.time()
+        ctx.autotune_pass(bf.BF_OP_FORCES, "mixed", P)
+        ctx.forces(P, None, None, prec="mixed", out=out_a)
+        ctx.autotune_pass(bf.BF_OP_GRADIENT, "mixed", P, acc=out_a)
+        log(f"autotuned in {time.time() - t1:.1f}s")
     out_g = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
 
     def sweep(prec, r_fb):

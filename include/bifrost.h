@@ -430,14 +430,60 @@ typedef enum { BF_OP_FORCES = 0, BF_OP_GRADIENT = 1, BF_OP_DTMIN = 2 } bf_op;
 #define BF_SORT_ANY_SIZE 0x100  /* bf_set_spatial_sort: sort passes of any size */
 #define BF_SORT_DIRECTED 0x200  /* bf_set_spatial_sort: no pair-symmetric sweep */
 
-/* Synchronising.  Time every kernel variant (targets per lane, waves per workgroup,
- * source split) for operation `op` at precision `prec` on n_targets x n_sources synthetic
- * pairs and store the fastest in the context for that size bucket.  If cache_path is not
+/* The tuning table maps (op, prec, sweep kind, log2 bucket of the two sizes) to a launch shape;
+ * passes look it up for their own sizes (a forced shape, bf_set_config and the two setters
+ * below, wins).  Sweep kinds: directed passes (targets per lane, waves per workgroup, source
+ * split), pair-symmetric sweeps (row tiles per wavefront, waves, rounds of resident workgroups
+ * that the distance shares aim at) and batched ensembles (targets per lane, waves, sources per
+ * work item; buckets of max_active_total and max_cluster_n).  The shapes are the launch
+ * parameters of the O(N_active x N) pass (Sec. 2.2's uneven level sizes decide which is
+ * fastest); results do not depend on them beyond the FP32 summation order.
+ *
+ * Synchronising; allocates its own temporaries.  Directed passes on n_targets x n_sources
+ * synthetic pairs (uniform cube): every targets-per-lane x waves variant, each with the
+ * automatic source split and 1/4, 1/2 and 2 times it; large target sets are timed on a leading
+ * sample of 131,072 targets.  The fastest is stored for that size bucket.  If cache_path is not
  * NULL the table is merged into that JSON file (read first if it exists). */
 BF_API int bf_autotune(bf_ctx *ctx, int op, int prec, int64_t n_targets, int64_t n_sources,
                        const char *cache_path);
-/* Load a tuning table written by bf_autotune. */
+/* Synchronising; allocates its own temporaries.  Tune the pass `op` that the caller is about to
+ * run, on the caller's own particles and sets (the near / far tile mix of a clustered set is
+ * what decides the spatially sorted kernels' speed).  If the pass takes the pair-symmetric
+ * sweep (mixed, spatially sorted, targets and sources one set), the shapes (16 waves of 1 row
+ * tile, 8 of 2, 4 of 4) x rounds (4, 8, 16, 32, 64) are timed on the whole set; otherwise the directed
+ * variants as in bf_autotune, on a leading sample of at most 131,072 of the targets.  ax/ay/az:
+ * the accelerations the gradient pass contracts (required for BF_OP_GRADIENT, else ignored);
+ * velocities are required for BF_OP_DTMIN.  Outputs of the timed passes are discarded.  Errors:
+ * BF_ERR_ARG (bad arguments, empty sets), BF_ERR_NOMEM. */
+BF_API int bf_autotune_pass(bf_ctx *ctx, int op, int prec, const bf_particles *P, const bf_set *targets,
+                            const bf_set *sources, const double *ax, const double *ay, const double *az,
+                            const char *cache_path);
+/* Synchronising; allocates its own temporaries.  Tune the batched pass `op` (BF_OP_FORCES or
+ * BF_OP_GRADIENT) on the caller's ensemble (arguments as bf_forces_batched /
+ * bf_force_gradient_batched, ax/ay/az required for the gradient): targets per lane {1, 2, 4} x
+ * waves {4, 8} x sources per work item {2048, 4096, 8192}; the fastest is stored for the buckets
+ * of (max_active_total, max_cluster_n) and used by every batched call and capture of that
+ * shape. */
+BF_API int bf_autotune_batched(bf_ctx *ctx, int op, int prec, const bf_particles *P, int32_t n_clusters,
+                               const int64_t *cluster_off, const int32_t *active_idx,
+                               const int64_t *active_off, int64_t max_active_total, int64_t max_cluster_n,
+                               const double *ax, const double *ay, const double *az, const char *cache_path);
+/* Not synchronising.  The shape a batched pass of op / prec with these bounds would run:
+ * targets per lane, waves per workgroup, sources per work item (forced, tuned or default).  Any
+ * output pointer may be NULL. */
+BF_API int bf_query_batched_config(bf_ctx *ctx, int op, int prec, int64_t max_active_total,
+                                   int64_t max_cluster_n, int *k_per_lane, int *waves, int *chunk);
+/* Load a tuning table written by the autotuners (tables without the sweep field hold directed
+ * entries). */
 BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
+/* Force the shape of the pair-symmetric sweep of op (BF_OP_FORCES / BF_OP_GRADIENT):
+ * rows x waves in {1 x 16, 2 x 8, 4 x 4} (BF_ERR_UNSUPPORTED otherwise), rounds of resident
+ * workgroups in [0, 64] (0: 32).  rows = 0 restores the tuned or default choice. */
+BF_API int bf_set_symmetric_config(bf_ctx *ctx, int op, int rows, int waves, int rounds);
+/* Force the shape of the batched pass op at precision prec: targets per lane {1, 2, 4}, waves
+ * {4, 8}, sources per work item a positive multiple of 64 * waves up to 2^20.  k = 0 restores the
+ * tuned or default choice (2, 4, 4096). */
+BF_API int bf_set_batched_config(bf_ctx *ctx, int op, int prec, int k_per_lane, int waves, int chunk);
 
 /* Spatially sorted mode of the mixed acceleration and gradient passes.  ops_mask selects the
  * passes that use it: bit (1 << BF_OP_FORCES) and/or bit (1 << BF_OP_GRADIENT); the default is

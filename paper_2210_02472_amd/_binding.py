@@ -110,6 +110,12 @@ def load_library(path: str = LIB_PATH):
         "bf_enable_timing": [_vp, _int],
         "bf_set_spatial_sort": [_vp, _int, ctypes.c_double],
         "bf_pair_credit": [_vp, _int, ctypes.POINTER(_i64), _int],
+        "bf_autotune_pass": [_vp, _int, _int, P, S, S, _vp, _vp, _vp, ctypes.c_char_p],
+        "bf_autotune_batched": [_vp, _int, _int, P, _i32, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_char_p],
+        "bf_set_symmetric_config": [_vp, _int, _int, _int, _int],
+        "bf_query_batched_config": [_vp, _int, _int, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                                    ctypes.POINTER(_int)],
+        "bf_set_batched_config": [_vp, _int, _int, _int, _int, _int],
         "bf_set_hhs_reuse": [_vp, _int],
         "bf_neighbours": [_vp, P, S, S, _d, _d, _d, _d, _d, _vp, _i64, ctypes.POINTER(_i64)],
         "bf_subsystems": [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i64)],
@@ -492,6 +498,48 @@ class Context:
     def autotune(self, op: int, prec: str, n_targets: int, n_sources: int, cache_path: Optional[str] = None):
         _check("bf_autotune", _lib.bf_autotune(self._h, op, PRECISIONS[prec], int(n_targets), int(n_sources),
                                                cache_path.encode() if cache_path else None))
+
+    def autotune_pass(self, op: int, prec: str, P: Particles, targets=None, sources=None, acc=None,
+                      cache_path: Optional[str] = None):
+        """Tune the launch shape of pass op on the caller's own particles and sets (the
+        pair-symmetric sweep's shapes when the pass takes it, the directed variants otherwise)."""
+        t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
+        a = list(acc) if acc is not None else [None, None, None]
+        for x in a:
+            if x is not None:
+                _need(x, torch.float64, P.n, "acc")
+        _check("bf_autotune_pass", _lib.bf_autotune_pass(self._h, int(op), PRECISIONS[prec], ctypes.byref(P._c()),
+                                                         ctypes.byref(t._c()), ctypes.byref(s._c()), *map(_ptr, a),
+                                                         cache_path.encode() if cache_path else None))
+
+    def autotune_batched(self, op: int, prec: str, P: Particles, cluster_off, active_idx, active_off,
+                         max_active_total: int, max_cluster_n: int, acc=None, cache_path: Optional[str] = None):
+        """Tune the batched pass op (targets per lane, waves, sources per work item) on the caller's
+        ensemble."""
+        a = list(acc) if acc is not None else [None, None, None]
+        nc = int(cluster_off.numel()) - 1
+        _check("bf_autotune_batched", _lib.bf_autotune_batched(
+            self._h, int(op), PRECISIONS[prec], ctypes.byref(P._c()), nc, _ptr(cluster_off), _ptr(active_idx),
+            _ptr(active_off), int(max_active_total), int(max_cluster_n), *map(_ptr, a),
+            cache_path.encode() if cache_path else None))
+
+    def set_symmetric_config(self, op: int, rows: int = 0, waves: int = 0, rounds: int = 0):
+        """Force the pair-symmetric sweep's shape (rows = 0: the tuned or default choice)."""
+        _check("bf_set_symmetric_config", _lib.bf_set_symmetric_config(self._h, int(op), int(rows), int(waves),
+                                                                       int(rounds)))
+
+    def query_batched_config(self, op: int, prec: str, max_active_total: int, max_cluster_n: int):
+        """(targets per lane, waves, sources per work item) a batched pass of these bounds runs."""
+        k, w, ch = _int(0), _int(0), _int(0)
+        _check("bf_query_batched_config", _lib.bf_query_batched_config(
+            self._h, int(op), PRECISIONS[prec], int(max_active_total), int(max_cluster_n), ctypes.byref(k),
+            ctypes.byref(w), ctypes.byref(ch)))
+        return k.value, w.value, ch.value
+
+    def set_batched_config(self, op: int, prec: str, k: int = 0, waves: int = 0, chunk: int = 0):
+        """Force the batched pass's shape (k = 0: the tuned or default choice)."""
+        _check("bf_set_batched_config", _lib.bf_set_batched_config(self._h, int(op), PRECISIONS[prec], int(k),
+                                                                   int(waves), int(chunk)))
 
     def autotune_load(self, cache_path: str):
         _check("bf_autotune_load", _lib.bf_autotune_load(self._h, cache_path.encode()))

@@ -1,8 +1,8 @@
 // Batched ensembles of independent clusters in one persistent launch.
 //
 // Cluster c owns particles [coff[c], coff[c+1]) and active particles aidx[aoff[c] .. aoff[c+1]).
-// A work item is (cluster, slab of 64*K*W active targets, chunk of kBatchChunk sources of that
-// cluster).  k_batch_plan counts items per cluster and scans them (one workgroup); the persistent
+// A work item is (cluster, slab of 64*K*W active targets, chunk of `chunk` sources of that
+// cluster); K, W and chunk are the launch shape (default 2, 4, 4096; tuned per size bucket).  k_batch_plan counts items per cluster and scans them (one workgroup); the persistent
 // workgroups of k_batch_pairs pull items from an atomic counter until the queue is empty and
 // write per-chunk partials; k_batch_reduce adds each target's chunks in chunk order.  Every
 // item's result and output location are fixed, so the outcome does not depend on which
@@ -15,9 +15,10 @@
 
 namespace bf {
 
-constexpr int kBatchChunk = 4096;  // sources per work item (16 tiles of 256)
-constexpr int kBK = 2, kBW = 4;    // targets per lane, waves per workgroup
-constexpr int kSlab = 64 * kBK * kBW;
+// default shape: 2 targets per lane, 4 waves per workgroup, 4096 sources per work item (16 tiles
+// of 256); the sources per item are a multiple of every tile (64 W)
+constexpr int kBatchChunk = 4096;
+constexpr int kBK = 2, kBW = 4;
 
 struct Batch {
     PairArgs base;        // masters, constants, flags; tgt/src/pack are set per item
@@ -29,6 +30,9 @@ struct Batch {
     int64_t max_cluster_n;
     int32_t max_chunks;
     int32_t pack_bytes;   // bytes per packed source
+    int32_t kk, ww;       // targets per lane, waves per workgroup
+    int32_t chunk;        // sources per work item
+    int32_t slab;         // active targets per work item: 64 kk ww
     int32_t* item_off;    // [nclusters + 1]
     int32_t* counter;
     int32_t* bad;         // [nclusters] 1 if the cluster's offsets are invalid
@@ -59,8 +63,8 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const Batch b) {
         if (!ok) atomicOr(b.base.flags, BF_FLAG_BADINDEX);
         b.bad[c] = ok ? 0 : 1;
         if (ok && a1 > a0 && ce > cb) {
-            const int64_t nslab = (a1 - a0 + kSlab - 1) / kSlab;
-            const int64_t nch = (ce - cb + kBatchChunk - 1) / kBatchChunk;
+            const int64_t nslab = (a1 - a0 + b.slab - 1) / b.slab;
+            const int64_t nch = (ce - cb + b.chunk - 1) / b.chunk;
             items = (int32_t)(nslab * nch);
         }
         b.item_off[c] = items;  // counts for now
@@ -111,15 +115,15 @@ __global__ __launch_bounds__(64 * W) void k_batch_pairs(const Batch b) {
         int64_t cb, ce, a0, a1;
         cluster_bounds(b, c, cb, ce, a0, a1);  // validated by k_batch_plan (bad clusters have no items)
         const int32_t na = (int32_t)(a1 - a0), ns = (int32_t)(ce - cb);
-        const int32_t nch = (ns + kBatchChunk - 1) / kBatchChunk;
+        const int32_t nch = (ns + b.chunk - 1) / b.chunk;
         const int32_t local = item - b.item_off[c];
         const int32_t slab = local / nch, q = local % nch;
         PairArgs a = b.base;
         a.tgt = DevSet{b.aidx + a0, na, 0};
         a.src = DevSet{nullptr, ns, (int32_t)cb};
         a.pack = static_cast<const char*>(b.base.pack) + cb * b.pack_bytes;
-        const int j0 = q * kBatchChunk;
-        const int j1 = min(ns, j0 + kBatchChunk);
+        const int j0 = q * b.chunk;
+        const int j1 = min(ns, j0 + b.chunk);
         typename Op::A64 acc[K];
         int slot[K], pidx[K];
         sweep<Op, K, W, false>(a, tile, slab * (64 * K * W) + wave * (64 * K), j0, j1, acc, slot, pidx);
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const Batch b) {
     int64_t cb, ce, a0, a1;
     cluster_bounds(b, c, cb, ce, a0, a1);
     if (a < a0 || a >= a1) return;
-    const int32_t nch = (int32_t)((ce - cb + kBatchChunk - 1) / kBatchChunk);
+    const int32_t nch = (int32_t)((ce - cb + b.chunk - 1) / b.chunk);
     double v[NP];
 #pragma unroll
     for (int comp = 0; comp < NP; ++comp) v[comp] = 0.0;
@@ -230,19 +234,40 @@ __global__ __launch_bounds__(256) void k_batch_drift(bf_state S, const Batch b, 
     S.z[p] = __builtin_fma(h, S.vz[p], S.z[p]);
 }
 
+using BatchKernel = void (*)(const Batch);
+
+// the shapes: K in {1, 2, 4} targets per lane, W in {4, 8} waves per workgroup
 template <class Op>
-static int batch_blocks_per_cu() {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_batch_pairs<Op, kBK, kBW>),
-                                                     64 * kBW, 0) != hipSuccess)
-        return 1;
-    return std::max(nb, 1);
+static BatchKernel batch_kernel_of(int k, int w) {
+#define BF_BK(K, W) \
+    if (k == K && w == W) return k_batch_pairs<Op, K, W>;
+    BF_BK(1, 4) BF_BK(2, 4) BF_BK(4, 4) BF_BK(1, 8) BF_BK(2, 8) BF_BK(4, 8)
+#undef BF_BK
+    return nullptr;
 }
 
-template <class Op>
-static hipError_t launch_batch_op(const Batch& b, int num_cu, hipStream_t st) {
-    const int nblocks = num_cu * batch_blocks_per_cu<Op>();
-    hipLaunchKernelGGL((k_batch_pairs<Op, kBK, kBW>), dim3(nblocks), dim3(64 * kBW), 0, st, b);
+static BatchKernel batch_kernel(int op, int prec, int k, int w) {
+    const bool mixed = prec == BF_PREC_MIXED;
+    if (op == OP_ACC) return mixed ? batch_kernel_of<AccMixed>(k, w) : batch_kernel_of<Acc64>(k, w);
+    if (op == OP_GRAD) return mixed ? batch_kernel_of<GradMixed>(k, w) : batch_kernel_of<Grad64>(k, w);
+    return nullptr;
+}
+
+}  // namespace bf
+
+bool bf_internal_batch_shape_ok(int op, int prec, int k, int waves, int chunk) {
+    return bf::batch_kernel(op, prec, k, waves) != nullptr && chunk > 0 && chunk % (64 * waves) == 0 &&
+           chunk <= (1 << 20);
+}
+
+namespace bf {
+
+static hipError_t launch_batch_op(BatchKernel f, const Batch& b, int num_cu, hipStream_t st) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(f), 64 * b.ww, 0) !=
+        hipSuccess)
+        nb = 1;
+    hipLaunchKernelGGL(f, dim3(num_cu * std::max(nb, 1)), dim3(64 * b.ww), 0, st, b);
     return hipGetLastError();
 }
 
@@ -258,6 +283,20 @@ int bf_internal_fail(int code, const char* msg);
 void bf_internal_swap_scratch(bf_ctx* ctx, void* bufs[3], size_t bytes[3]);
 std::pair<hipEvent_t, hipEvent_t> bf_internal_timer_begin(bf_ctx* c);
 void bf_internal_timer_end(bf_ctx* c, int op, std::pair<hipEvent_t, hipEvent_t> ev);
+int bf_internal_bucket(int64_t v);
+
+// launch shape of a batched pass: forced, tuned for (active total, largest cluster), or the
+// default
+static KernelConfig batch_shape(bf_ctx* c, int op, int prec, int64_t max_active, int64_t max_cluster_n) {
+    KernelConfig bc = c->batch_forced[op];
+    if (bc.k == 0) {
+        auto it = c->tuned.find(std::make_tuple(op, prec, (int)kTuneBatched, bf_internal_bucket(max_active),
+                                                bf_internal_bucket(max_cluster_n)));
+        if (it != c->tuned.end()) bc = it->second;
+    }
+    if (!bf_internal_batch_shape_ok(op, prec, bc.k, bc.waves, bc.split)) bc = KernelConfig{kBK, kBW, kBatchChunk};
+    return bc;
+}
 
 static int batch_setup(bf_ctx* c, const bf_particles* P, int32_t nclusters, const int64_t* coff, const int32_t* aidx,
                        const int64_t* aoff, int64_t max_active, int64_t max_cluster_n, double G, double eps2, int prec,
@@ -288,7 +327,12 @@ static int batch_setup(bf_ctx* c, const bf_particles* P, int32_t nclusters, cons
     b.coff = coff; b.aidx = aidx; b.aoff = aoff;
     b.max_active = max_active;
     b.max_cluster_n = max_cluster_n;
-    b.max_chunks = (int32_t)((max_cluster_n + kBatchChunk - 1) / kBatchChunk);
+    const KernelConfig bc = batch_shape(c, op, prec, max_active, max_cluster_n);
+    b.kk = bc.k;
+    b.ww = bc.waves;
+    b.chunk = bc.split;
+    b.slab = 64 * bc.k * bc.waves;
+    b.max_chunks = (int32_t)((max_cluster_n + b.chunk - 1) / b.chunk);
     b.pack_bytes = pack_bytes(op, prec);
     const size_t pack_total = (size_t)P->n * b.pack_bytes;
     const size_t part_bytes = (size_t)b.max_chunks * stored_components(op, prec) *
@@ -319,9 +363,10 @@ static int batch_enqueue(bf_ctx* c, Batch& b, int op, int prec) {
     if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
     hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, st, b);
     const bool mixed = prec == BF_PREC_MIXED;
+    const BatchKernel f = batch_kernel(op, prec, b.kk, b.ww);
+    if (!f) return bf_internal_fail(BF_ERR_UNSUPPORTED, "no batched kernel of this shape");
     const auto ev = bf_internal_timer_begin(c);  // the persistent pair kernel, when timing is on
-    if (op == OP_ACC) e = mixed ? launch_batch_op<AccMixed>(b, c->num_cu, st) : launch_batch_op<Acc64>(b, c->num_cu, st);
-    else e = mixed ? launch_batch_op<GradMixed>(b, c->num_cu, st) : launch_batch_op<Grad64>(b, c->num_cu, st);
+    e = launch_batch_op(f, b, c->num_cu, st);
     if (e != hipSuccess) return bf_internal_fail(BF_ERR_HIP, hipGetErrorString(e));
     bf_internal_timer_end(c, op, ev);
     if (b.max_active > 0) {
@@ -340,6 +385,18 @@ static int batch_enqueue(bf_ctx* c, Batch& b, int op, int prec) {
 }
 
 extern "C" {
+
+BF_API int bf_query_batched_config(bf_ctx* c, int op, int prec, int64_t max_active, int64_t max_cluster_n, int* k,
+                                   int* waves, int* chunk) {
+    if (!c) return bf_internal_fail(BF_ERR_ARG, "NULL context");
+    if (op != OP_ACC && op != OP_GRAD) return bf_internal_fail(BF_ERR_ARG, "BF_OP_FORCES or BF_OP_GRADIENT");
+    if (prec != BF_PREC_FP64 && prec != BF_PREC_MIXED) return bf_internal_fail(BF_ERR_ARG, "bad prec");
+    const KernelConfig bc = batch_shape(c, op, prec, max_active, max_cluster_n);
+    if (k) *k = bc.k;
+    if (waves) *waves = bc.waves;
+    if (chunk) *chunk = bc.split;
+    return BF_OK;
+}
 
 BF_API int bf_forces_batched(bf_ctx* c, const bf_particles* P, int32_t nclusters, const int64_t* coff,
                              const int32_t* aidx, const int64_t* aoff, int64_t max_active, int64_t max_cluster_n,
@@ -381,10 +438,13 @@ static int batched_fsi_setup(bf_ctx* c, const bf_state* S, int32_t nclusters, co
     if (!ax || !ay || !az) return bf_internal_fail(BF_ERR_ARG, "acceleration pointer NULL");
     if (!(dt > -INFINITY && dt < INFINITY)) return bf_internal_fail(BF_ERR_ARG, "dt not finite");
     bf_particles P{S->x, S->y, S->z, S->vx, S->vy, S->vz, S->m, S->n};
-    // the gradient pass needs the larger pack: size it first
+    // both passes share the pack and partial buffers: size them for both, then take the
+    // gradient pass's pointers again (the acceleration sizing may have grown the buffers)
     if (int rc = batch_setup(c, &P, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, OP_GRAD, bg))
         return rc;
     if (int rc = batch_setup(c, &P, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, OP_ACC, ba))
+        return rc;
+    if (int rc = batch_setup(c, &P, nclusters, coff, aidx, aoff, max_active, max_cluster_n, G, eps2, prec, r_fb, OP_GRAD, bg))
         return rc;
     if (int rc = bf_internal_ensure(c, 3, (size_t)3 * S->n * sizeof(double))) return rc;
     double* gx = static_cast<double*>(bf_internal_scratch(c, 3));

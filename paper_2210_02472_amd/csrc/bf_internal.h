@@ -60,10 +60,12 @@ struct PairArgs {
 enum Op { OP_ACC = 0, OP_GRAD = 1, OP_DT = 2, OP_COUNT = 3 };
 
 struct KernelConfig {
-    int k = 0;      // targets per lane
+    int k = 0;      // targets per lane (symmetric sweep: row tiles per wavefront)
     int waves = 0;  // waves per workgroup
-    int split = 0;  // source chunks (0 = automatic)
+    int split = 0;  // source chunks (0 = automatic); symmetric: rounds of resident workgroups the
+                    // distance shares aim at (0 = 2); batched: sources per work item (0 = 4096)
 };
+enum { kTuneDirected = 0, kTuneSymmetric = 1, kTuneBatched = 2 };
 
 // Launch one pair kernel (returns the hip error of the launch).
 hipError_t launch_pairs(int op, int prec, const KernelConfig& cfg, const PairArgs& a, int nblocks,
@@ -171,12 +173,14 @@ size_t sym64_own_bytes(int64_t n, int chunks);
 int sym64_blocks_per_cu(int op);
 hipError_t launch_pairs_sym64(int op, const SymArgs& g, double eps2t, hipStream_t st);
 hipError_t launch_sym_reduce64(int op, const PairArgs& a, const SymArgs& g, hipStream_t st);
-// resident workgroups per CU, wavefronts per workgroup and row tiles per wavefront of the
-// symmetric kernel of op
-int sym_blocks_per_cu(int op);
-int sym_waves(int op);
-int sym_rows_per_wave(int op);
-hipError_t launch_pairs_sym(int op, const SymArgs& g, hipStream_t st);
+// resident workgroups per CU of the symmetric kernel of op with a given shape, the default
+// shape, and the launch
+// shapes: W wavefronts of R row tiles each (W R = kSymBlockTiles): (16, 1), (8, 2), (4, 4)
+int sym_default_waves(int op);
+int sym_default_rows(int op);
+bool sym_variant_exists(int op, int waves, int rows);
+int sym_blocks_per_cu(int op, int waves, int rows);
+hipError_t launch_pairs_sym(int op, int waves, int rows, const SymArgs& g, hipStream_t st);
 // adds the row-side sums and the partials in a fixed order and writes the particle-indexed
 // outputs of a.tgt (the sorted list), queueing ill-conditioned targets for the fix-up
 hipError_t launch_sym_reduce(int op, const PairArgs& a, const SymArgs& g, hipStream_t st);
@@ -327,5 +331,11 @@ struct bf_ctx {
     // (op, prec) -> forced configuration
     bf::KernelConfig forced[bf::OP_COUNT][2];
     // (op, prec, log2 bucket nt, log2 bucket ns) -> tuned configuration
-    std::map<std::tuple<int, int, int, int>, bf::KernelConfig> tuned;
+    // (op, prec, sweep kind, log2 bucket nt, log2 bucket ns) -> tuned configuration; sweep kinds:
+    // kTuneDirected (k per lane, waves, split), kTuneSymmetric (row tiles per wavefront, waves,
+    // rounds of resident workgroups), kTuneBatched (k per lane, waves, sources per work item;
+    // buckets of the active total and the largest cluster)
+    std::map<std::tuple<int, int, int, int, int>, bf::KernelConfig> tuned;
+    bf::KernelConfig sym_forced[bf::OP_COUNT];    // forced symmetric shape (k = 0: none)
+    bf::KernelConfig batch_forced[bf::OP_COUNT];  // forced batched shape (k = 0: none)
 };

@@ -167,11 +167,34 @@ bool same_set(const bf_set* t, const bf_set* s) {
     return t->idx == s->idx && t->count == s->count && (t->idx != nullptr || t->begin == s->begin);
 }
 
-// Shares of the block distances per row block: at least two rounds of resident workgroups.
-int sym_chunks(bf_ctx* ctx, int op, int64_t n) {
+// Shape of the pair-symmetric sweep of op over na rows and nb columns: forced, tuned for the
+// size bucket, or the default (k = row tiles per wavefront, split = rounds of resident
+// workgroups, 0 meaning kSymRounds).
+KernelConfig sym_config(bf_ctx* ctx, int op, int64_t na, int64_t nb) {
+    if (ctx->sym_forced[op].k) return ctx->sym_forced[op];
+    auto it = ctx->tuned.find(std::make_tuple(op, (int)BF_PREC_MIXED, (int)kTuneSymmetric, ilog2_bucket(na),
+                                              ilog2_bucket(nb)));
+    if (it != ctx->tuned.end() && sym_variant_exists(op, it->second.waves, it->second.k)) return it->second;
+    return KernelConfig{sym_default_rows(op), sym_default_waves(op), 0};
+}
+
+// Default rounds of resident workgroups: 32.  At N = 2^20 the gradient sweep takes 414 ms with
+// 2 rounds (1 share of the distances per row block), 396 ms with 4 (2 shares), 389 ms with 8,
+// 381-383 ms with 16 and 375 ms with 32 (16 shares); the acceleration 254, 246, 244, 240 and
+// 240 ms: the shares even out the workgroups' lengths and the last round is shorter.
+constexpr int kSymRounds = 32;
+
+// resident workgroups the shares of a sweep aim at
+int64_t sym_want(bf_ctx* ctx, int op, const KernelConfig& sc) {
+    return (int64_t)(sc.split > 0 ? sc.split : kSymRounds) * ctx->num_cu * sym_blocks_per_cu(op, sc.waves, sc.k);
+}
+
+// Shares of the block distances per row block: at least the configured rounds of resident
+// workgroups.
+int sym_chunks(bf_ctx* ctx, int op, int64_t n, const KernelConfig& sc) {
     const int64_t n_tiles = (n + 63) / 64;
     const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
-    const int64_t want = 2 * (int64_t)ctx->num_cu * sym_blocks_per_cu(op);
+    const int64_t want = sym_want(ctx, op, sc);
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb / 2 + 1, (want + nb - 1) / nb));
 }
 
@@ -192,7 +215,9 @@ int sym64_chunks(bf_ctx* ctx, int op, int64_t n) {
 
 bool use_symmetric(bf_ctx* ctx, int op, bool sorted, const bf_set* tg, const bf_set* sr) {
     return sorted && !(ctx->sort_ops & BF_SORT_DIRECTED) && same_set(tg, sr) &&
-           sym_scratch_bytes(tg->count, sym_chunks(ctx, op, tg->count)) <= kSymMaxScratch;
+           sym_scratch_bytes(tg->count,
+                             sym_chunks(ctx, op, tg->count, sym_config(ctx, op, tg->count, tg->count))) <=
+               kSymMaxScratch;
 }
 
 bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb,
@@ -208,7 +233,7 @@ bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_
 int plan(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, Plan& p, bool sorted = false) {
     KernelConfig c = ctx->forced[op][prec];
     if (c.k == 0) {
-        auto it = ctx->tuned.find(std::make_tuple(op, prec, ilog2_bucket(nt), ilog2_bucket(ns)));
+        auto it = ctx->tuned.find(std::make_tuple(op, prec, (int)kTuneDirected, ilog2_bucket(nt), ilog2_bucket(ns)));
         if (it != ctx->tuned.end()) c = it->second;
         else c = default_config(op, prec, nt);
         if (it == ctx->tuned.end() && sorted) c.k = 1;  // measured best for the sorted kernels
@@ -295,10 +320,11 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         return fail(BF_ERR_UNSUPPORTED, "no sorted kernel variant for this configuration");
     bool sym = !arena && use_symmetric(ctx, op, sorted, tg, sr);
     int sym_shares = 0;
+    const KernelConfig sc = sym ? sym_config(ctx, op, sr->count, sr->count) : KernelConfig{};
     if (sym) {
         // the column partials are large (8.6 GB at n = 2^20): without the memory, the directed
         // sweep runs instead
-        sym_shares = sym_chunks(ctx, op, sr->count);
+        sym_shares = sym_chunks(ctx, op, sr->count, sc);
         if (ensure(&ctx->scratch9, &ctx->scratch9_bytes, sym_scratch_bytes(sr->count, sym_shares), ctx->stream)) {
             g_err.clear();
             sym = false;
@@ -319,8 +345,8 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     const bool small = !sorted && !sym && !sym64 && prec == BF_PREC_MIXED && (op == OP_ACC || op == OP_GRAD) &&
                        ctx->sub == nullptr && r_fb == 0.0 && tg->count <= kSmallMaxTargets &&
                        sr->count <= kSmallMaxSources && ctx->forced[op][prec].k == 0 &&
-                       ctx->tuned.find(std::make_tuple(op, prec, ilog2_bucket(tg->count), ilog2_bucket(sr->count))) ==
-                           ctx->tuned.end();
+                       ctx->tuned.find(std::make_tuple(op, prec, (int)kTuneDirected, ilog2_bucket(tg->count),
+                                                       ilog2_bucket(sr->count))) == ctx->tuned.end();
     if (sym || sym64 || small) p.split = 1;  // no source split in memory
     // scratch: [fix counter | fix list (one slot per target)], the split partials, the packed
     // sources (unsorted) and the fix-up partials: from the context's buffers, or the arena
@@ -489,7 +515,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         }
         BF_HIP(hipEventRecord(ev.first, ctx->stream));
     }
-    if (sym) BF_HIP(launch_pairs_sym(op, g, ctx->stream));
+    if (sym) BF_HIP(launch_pairs_sym(op, sc.waves, sc.k, g, ctx->stream));
     else if (sym64) BF_HIP(launch_pairs_sym64(op, g, eps2 + 1e-150 /* the FP64 kernels' tiny */, ctx->stream));
     else if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
     else if (small) BF_HIP(launch_pairs_small(op, a, ctx->stream));
@@ -497,8 +523,8 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     // credit: every (target, source) pair, less the self-pairs when targets and sources are one set
     ctx->pair_credit[op] += (int64_t)tg->count * (same_set(tg, sr) ? sr->count - 1 : sr->count);
     ctx->last_kind = sym || sym64 ? BF_PASS_SYMMETRIC : sorted ? BF_PASS_SORTED : BF_PASS_UNSORTED;
-    ctx->last_k = sym ? sym_rows_per_wave(op) : sym64 ? 4 : small ? 1 : p.cfg.k;
-    ctx->last_waves = sym ? sym_waves(op) : sym64 ? 4 : small ? 16 : p.cfg.waves;
+    ctx->last_k = sym ? sc.k : sym64 ? 4 : small ? 1 : p.cfg.k;
+    ctx->last_waves = sym ? sc.waves : sym64 ? 4 : small ? 16 : p.cfg.waves;
     ctx->last_split = sym || sym64 ? g.n_chunks : p.split;
     if (timed) {
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
@@ -529,7 +555,8 @@ int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_
     // shares of each row block's column tiles: at least two rounds of resident workgroups
     const int64_t a_tiles = (na + 63) / 64, b_tiles = (nb + 63) / 64;
     const int64_t rblocks = (a_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
-    const int64_t want = 2 * (int64_t)ctx->num_cu * sym_blocks_per_cu(op);
+    const KernelConfig sc = sym_config(ctx, op, na, nb);
+    const int64_t want = sym_want(ctx, op, sc);
     const int shares = (int)std::max<int64_t>(1, std::min<int64_t>(b_tiles, (want + rblocks - 1) / rblocks));
     if (between_scratch_bytes(na, nb, shares) > kSymMaxScratch ||
         ensure(&ctx->scratch9, &ctx->scratch9_bytes, between_scratch_bytes(na, nb, shares), ctx->stream)) {
@@ -639,15 +666,15 @@ int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_
         }
         BF_HIP(hipEventRecord(ev.first, ctx->stream));
     }
-    BF_HIP(launch_pairs_sym(op, g, ctx->stream));
+    BF_HIP(launch_pairs_sym(op, sc.waves, sc.k, g, ctx->stream));
     if (timed) {
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
     }
     ctx->pair_credit[op] += 2 * (int64_t)A->count * B->count;  // a <- b and b <- a
     ctx->last_kind = BF_PASS_BETWEEN;
-    ctx->last_k = sym_rows_per_wave(op);
-    ctx->last_waves = sym_waves(op);
+    ctx->last_k = sc.k;
+    ctx->last_waves = sc.waves;
     ctx->last_split = shares;
     BF_HIP(launch_between_reduce(op, ab, ba, g, ctx->stream));
     BF_HIP(launch_fixup(op, ab, static_cast<double*>(ctx->scratch8), kFixChunks * kFixTiled, ctx->num_cu, ctx->stream));
@@ -689,6 +716,8 @@ void bf_internal_timer_end(bf_ctx* c, int op, std::pair<hipEvent_t, hipEvent_t> 
     if (hipEventRecord(ev.second, c->stream) == hipSuccess) c->tev[op].push_back(ev);
 }
 void bf_internal_credit(bf_ctx* c, int op, int64_t pairs) { c->pair_credit[op] += pairs; }
+int bf_internal_bucket(int64_t v) { return ilog2_bucket(v); }
+bool bf_internal_batch_shape_ok(int op, int prec, int k, int waves, int chunk);  // batch.hip
 
 int bf_internal_ensure(bf_ctx* c, int which, size_t need) {
     switch (which) {
@@ -1894,12 +1923,22 @@ static int write_cache(bf_ctx* c, const char* path) {
     size_t i = 0;
     for (const auto& kv : c->tuned) {
         f << "  {\"op\": " << std::get<0>(kv.first) << ", \"prec\": " << std::get<1>(kv.first)
-          << ", \"nt_log2\": " << std::get<2>(kv.first) << ", \"ns_log2\": " << std::get<3>(kv.first)
-          << ", \"k\": " << kv.second.k << ", \"waves\": " << kv.second.waves << ", \"split\": " << kv.second.split << "}"
+          << ", \"sweep\": " << std::get<2>(kv.first) << ", \"nt_log2\": " << std::get<3>(kv.first)
+          << ", \"ns_log2\": " << std::get<4>(kv.first) << ", \"k\": " << kv.second.k
+          << ", \"waves\": " << kv.second.waves << ", \"split\": " << kv.second.split << "}"
           << (++i < c->tuned.size() ? ",\n" : "\n");
     }
     f << "]\n";
     return BF_OK;
+}
+
+// a table entry names an instantiated shape
+static bool tuned_entry_ok(int op, int prec, int sweep, int k, int w, int sp) {
+    if (op < 0 || op >= OP_COUNT || (prec != 0 && prec != 1) || sp < 0) return false;
+    if (sweep == kTuneDirected) return variant_exists(op, prec, k, w);
+    if (sweep == kTuneSymmetric) return prec == BF_PREC_MIXED && sym_variant_exists(op, w, k);
+    if (sweep == kTuneBatched) return bf_internal_batch_shape_ok(op, prec, k, w, sp);
+    return false;
 }
 
 BF_API int bf_autotune_load(bf_ctx* c, const char* path) {
@@ -1909,12 +1948,17 @@ BF_API int bf_autotune_load(bf_ctx* c, const char* path) {
     if (!f) return fail(BF_ERR_ARG, std::string("cannot read ") + path);
     std::string line;
     while (std::getline(f, line)) {
-        int op, prec, bt, bs, k, w, sp;
-        if (sscanf(line.c_str(), " {\"op\": %d, \"prec\": %d, \"nt_log2\": %d, \"ns_log2\": %d, \"k\": %d, \"waves\": %d, \"split\": %d",
-                   &op, &prec, &bt, &bs, &k, &w, &sp) == 7) {
-            if (op >= 0 && op < OP_COUNT && (prec == 0 || prec == 1) && variant_exists(op, prec, k, w) && sp >= 0)
-                c->tuned[std::make_tuple(op, prec, bt, bs)] = KernelConfig{k, w, sp};
-        }
+        int op, prec, sw = kTuneDirected, bt, bs, k, w, sp;
+        const bool v2 = sscanf(line.c_str(), " {\"op\": %d, \"prec\": %d, \"sweep\": %d, \"nt_log2\": %d, \"ns_log2\": "
+                                             "%d, \"k\": %d, \"waves\": %d, \"split\": %d",
+                               &op, &prec, &sw, &bt, &bs, &k, &w, &sp) == 8;
+        // tables written before the sweep kind existed hold directed entries only
+        const bool v1 = !v2 && sscanf(line.c_str(), " {\"op\": %d, \"prec\": %d, \"nt_log2\": %d, \"ns_log2\": %d, "
+                                                    "\"k\": %d, \"waves\": %d, \"split\": %d",
+                                      &op, &prec, &bt, &bs, &k, &w, &sp) == 7;
+        if (v1) sw = kTuneDirected;
+        if ((v1 || v2) && tuned_entry_ok(op, prec, sw, k, w, sp))
+            c->tuned[std::make_tuple(op, prec, sw, bt, bs)] = KernelConfig{k, w, sp};
     }
     return BF_OK;
 }
@@ -1932,6 +1976,123 @@ __global__ void k_tune_fill(double* x, double* y, double* z, double* v, double* 
     v[i] = nxt() - 0.5; v[n + i] = nxt() - 0.5; v[2 * n + i] = nxt() - 0.5;
     m[i] = 1.0 / (double)n;
 }
+
+extern "C++" {
+namespace {
+
+// Time `run` once after one warm-up call (HIP events on the context stream), in ms; < 0 on error
+// (the error is left in rc).
+template <class Run>
+float time_candidate(bf_ctx* c, Run&& run, int& rc) {
+    rc = run();
+    if (rc) return -1.f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return -1.f;
+    }
+    hipEventRecord(e0, c->stream);
+    rc = run();
+    hipEventRecord(e1, c->stream);
+    float ms = -1.f;
+    if (!rc && hipEventSynchronize(e1) == hipSuccess) hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc ? -1.f : ms;
+}
+
+// Directed passes: targets per lane x waves per workgroup x source split (the automatic split
+// and 1/4, 1/2 and 2 times it).  The pass is timed on tg (the caller's sample) against sr; the
+// winner is stored for the bucket of (nt_bucket, ns_bucket).
+int tune_directed(bf_ctx* c, int op, int prec, const Masters& M, const bf_set& tg, const bf_set& sr, int64_t nt_bucket,
+                  int64_t ns_bucket, double* o) {
+    const int64_t n = M.n;
+    const KernelConfig saved = c->forced[op][prec];
+    KernelConfig best{};
+    float best_ms = 1e30f;
+    int rc = BF_OK;
+    const bool sorted = use_sorted(c, op, prec, tg.count, sr.count, 0.0);
+    const int ks[] = {1, 2, 4};
+    const int ws[] = {2, 4, 8};
+    for (int k : ks) {
+        for (int w : ws) {
+            if (!variant_exists(op, prec, k, w) || (sorted && !sorted_variant_exists(op, k, w))) continue;
+            c->forced[op][prec] = KernelConfig{k, w, 0};
+            Plan p;
+            if ((rc = plan(c, op, prec, tg.count, sr.count, p, sorted))) break;
+            const int s0 = p.split;
+            const int cand[] = {0, std::max(1, s0 / 4), std::max(1, s0 / 2), 2 * s0};
+            int tried[4];
+            int nt_ = 0;
+            for (int ci = 0; ci < 4; ++ci) {
+                // the split a forced value turns into (whole groups, at most one chunk per group)
+                c->forced[op][prec] = KernelConfig{k, w, cand[ci]};
+                Plan q;
+                if ((rc = plan(c, op, prec, tg.count, sr.count, q, sorted))) break;
+                const int es = q.split;
+                bool dup = false;
+                for (int t = 0; t < nt_; ++t) dup = dup || tried[t] == es;
+                if (dup) continue;
+                tried[nt_++] = es;
+                const float ms = time_candidate(c, [&]() {
+                    return run_pairs(c, op, prec, M, &tg, &sr, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);
+                }, rc);
+                if (rc) break;
+                if (ms >= 0.f && ms < best_ms) {
+                    best_ms = ms;
+                    best = KernelConfig{k, w, ci == 0 ? 0 : es};  // 0: automatic for each size
+                }
+            }
+            if (rc) break;
+        }
+        if (rc) break;
+    }
+    c->forced[op][prec] = saved;
+    if (rc) return rc;
+    if (best.k == 0) return fail(BF_ERR_UNSUPPORTED, "no variant ran");
+    c->tuned[std::make_tuple(op, prec, (int)kTuneDirected, (int)nt_bucket, (int)ns_bucket)] = best;
+    return BF_OK;
+}
+
+// Pair-symmetric sweeps over one set: (row tiles, waves) shapes x rounds of resident workgroups
+// (1, 2, 4), timed on the caller's whole set.
+int tune_symmetric(bf_ctx* c, int op, const Masters& M, const bf_set& set, double* o) {
+    const int64_t n = M.n;
+    const KernelConfig saved = c->sym_forced[op];
+    KernelConfig best{};
+    float best_ms = 1e30f;
+    int rc = BF_OK;
+    const int shapes[][2] = {{16, 1}, {8, 2}, {4, 4}};  // (waves, rows)
+    for (const auto& sh : shapes) {
+        if (!sym_variant_exists(op, sh[0], sh[1])) continue;
+        for (int rounds : {4, 8, 16, 32, 64}) {
+            c->sym_forced[op] = KernelConfig{sh[1], sh[0], rounds};
+            const float ms = time_candidate(c, [&]() {
+                return run_pairs(c, op, BF_PREC_MIXED, M, &set, &set, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);
+            }, rc);
+            if (rc) break;
+            if (c->last_kind != BF_PASS_SYMMETRIC) {  // the sweep did not apply (size, memory)
+                c->sym_forced[op] = saved;
+                return fail(BF_ERR_UNSUPPORTED, "this pass does not take the pair-symmetric sweep");
+            }
+            if (ms >= 0.f && ms < best_ms) {
+                best_ms = ms;
+                best = KernelConfig{sh[1], sh[0], rounds};
+            }
+        }
+        if (rc) break;
+    }
+    c->sym_forced[op] = saved;
+    if (rc) return rc;
+    if (best.k == 0) return fail(BF_ERR_UNSUPPORTED, "no variant ran");
+    c->tuned[std::make_tuple(op, (int)BF_PREC_MIXED, (int)kTuneSymmetric, ilog2_bucket(set.count),
+                             ilog2_bucket(set.count))] = best;
+    return BF_OK;
+}
+
+}  // namespace
+}  // extern "C++"
 
 BF_API int bf_autotune(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, const char* cache_path) {
     g_err.clear();
@@ -1953,53 +2114,135 @@ BF_API int bf_autotune(bf_ctx* c, int op, int prec, int64_t nt, int64_t ns, cons
     Masters M{};
     M.x = x; M.y = y; M.z = z; M.vx = v; M.vy = v + n; M.vz = v + 2 * n; M.m = m;
     M.ax = a; M.ay = a + n; M.az = a + 2 * n; M.n = n;
-    // Candidates: targets per lane x waves per workgroup, each with the automatic source split.
     // Large target sets are timed on a leading sample of targets (the rate per pair is what is
-    // compared); the split is recomputed for the real size when the configuration is used.
+    // compared); an automatic split is recomputed for the real size when the entry is used.
     const int64_t nt_time = std::min<int64_t>(nt, (int64_t)1 << 17);
-    bf_set tg{nullptr, (int32_t)nt_time, 0}, sr{nullptr, (int32_t)ns, 0};
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
-    const KernelConfig saved = c->forced[op][prec];
+    const bf_set tg{nullptr, (int32_t)nt_time, 0}, sr{nullptr, (int32_t)ns, 0};
     const int32_t* saved_sub = c->sub;
     c->sub = nullptr;  // tuning runs on its own synthetic particles
-    KernelConfig best{};
-    float best_ms = 1e30f;
-    int rc = BF_OK;
-    const int ks[] = {1, 2, 4};
-    const int ws[] = {2, 4, 8};
-    const bool sorted = use_sorted(c, op, prec, nt_time, ns, 0.0);
-    for (int k : ks) {
-        for (int w : ws) {
-            if (!variant_exists(op, prec, k, w) || (sorted && !sorted_variant_exists(op, k, w))) continue;
-            c->forced[op][prec] = KernelConfig{k, w, 0};
-            rc = run_pairs(c, op, prec, M, &tg, &sr, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);  // warm-up
-            if (rc) break;
-            hipEventRecord(e0, c->stream);
-            rc = run_pairs(c, op, prec, M, &tg, &sr, 1.0, 0.0, 0.0, 0.2, 0.2, o, o + n, o + 2 * n);
-            hipEventRecord(e1, c->stream);
-            if (rc) break;
-            hipEventSynchronize(e1);
-            float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = KernelConfig{k, w, 0};
-            }
-        }
-        if (rc) break;
-    }
-    c->forced[op][prec] = saved;
+    int rc = tune_directed(c, op, prec, M, tg, sr, ilog2_bucket(nt), ilog2_bucket(ns), o);
     c->sub = saved_sub;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     hipStreamSynchronize(c->stream);
     hipFree(buf);
     if (rc) return rc;
-    if (best.k == 0) return fail(BF_ERR_UNSUPPORTED, "no variant ran");
-    c->tuned[std::make_tuple(op, prec, ilog2_bucket(nt), ilog2_bucket(ns))] = best;
     if (cache_path) return write_cache(c, cache_path);
+    return BF_OK;
+}
+
+BF_API int bf_autotune_pass(bf_ctx* c, int op, int prec, const bf_particles* P, const bf_set* targets,
+                            const bf_set* sources, const double* ax, const double* ay, const double* az,
+                            const char* cache_path) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (op < 0 || op >= OP_COUNT) return fail(BF_ERR_ARG, "bad op");
+    if (int rc = check_prec(prec)) return rc;
+    if (int rc = check_particles(P, op == OP_DT)) return rc;
+    if (int rc = check_set(targets, P->n, "target")) return rc;
+    if (int rc = check_set(sources, P->n, "source")) return rc;
+    if (targets->count == 0 || sources->count == 0) return fail(BF_ERR_ARG, "empty set");
+    if (op == OP_GRAD && (!ax || !ay || !az)) return fail(BF_ERR_ARG, "the gradient needs the accelerations");
+    if (cache_path) {
+        std::ifstream probe(cache_path);
+        if (probe) bf_autotune_load(c, cache_path);
+    }
+    const int64_t n = P->n;
+    double* o = nullptr;
+    if (hipMalloc(&o, (size_t)3 * n * sizeof(double)) != hipSuccess) return fail(BF_ERR_NOMEM, "tuning buffers");
+    Masters M = masters_of(P);
+    M.ax = ax; M.ay = ay; M.az = az;
+    int rc = BF_OK;
+    // the pass takes the pair-symmetric sweep: tune its shapes on the whole set
+    const bool sorted = use_sorted(c, op, prec, targets->count, sources->count, 0.0);
+    if (sorted && use_symmetric(c, op, sorted, targets, sources)) {
+        rc = tune_symmetric(c, op, M, *targets, o);
+    } else {
+        // directed: a leading sample of the targets (a sub-range or the head of the list)
+        const int64_t nt_time = std::min<int64_t>(targets->count, (int64_t)1 << 17);
+        bf_set tg = *targets;
+        tg.count = (int32_t)nt_time;
+        rc = tune_directed(c, op, prec, M, tg, *sources, ilog2_bucket(targets->count), ilog2_bucket(sources->count), o);
+    }
+    hipStreamSynchronize(c->stream);
+    hipFree(o);
+    if (rc) return rc;
+    if (cache_path) return write_cache(c, cache_path);
+    return BF_OK;
+}
+
+BF_API int bf_autotune_batched(bf_ctx* c, int op, int prec, const bf_particles* P, int32_t n_clusters,
+                               const int64_t* cluster_off, const int32_t* active_idx, const int64_t* active_off,
+                               int64_t max_active, int64_t max_cluster_n, const double* ax, const double* ay,
+                               const double* az, const char* cache_path) {
+    g_err.clear();
+    if (int rc = check_ctx(c)) return rc;
+    if (op != OP_ACC && op != OP_GRAD) return fail(BF_ERR_ARG, "batched passes: BF_OP_FORCES or BF_OP_GRADIENT");
+    if (int rc = check_prec(prec)) return rc;
+    if (int rc = check_particles(P, false)) return rc;
+    if (op == OP_GRAD && (!ax || !ay || !az)) return fail(BF_ERR_ARG, "the gradient needs the accelerations");
+    if (max_active <= 0 || max_cluster_n <= 0) return fail(BF_ERR_ARG, "bad bounds");
+    if (cache_path) {
+        std::ifstream probe(cache_path);
+        if (probe) bf_autotune_load(c, cache_path);
+    }
+    const int64_t n = P->n;
+    double* o = nullptr;
+    if (hipMalloc(&o, (size_t)3 * n * sizeof(double)) != hipSuccess) return fail(BF_ERR_NOMEM, "tuning buffers");
+    const KernelConfig saved = c->batch_forced[op];
+    KernelConfig best{};
+    float best_ms = 1e30f;
+    int rc = BF_OK;
+    for (int k : {1, 2, 4}) {
+        for (int w : {4, 8}) {
+            for (int chunk : {2048, 4096, 8192}) {
+                if (!bf_internal_batch_shape_ok(op, prec, k, w, chunk)) continue;
+                c->batch_forced[op] = KernelConfig{k, w, chunk};
+                const float ms = time_candidate(c, [&]() {
+                    return op == OP_ACC ? bf_forces_batched(c, P, n_clusters, cluster_off, active_idx, active_off,
+                                                            max_active, max_cluster_n, 1.0, 0.0, prec, 0.0, o, o + n,
+                                                            o + 2 * n)
+                                        : bf_force_gradient_batched(c, P, n_clusters, cluster_off, active_idx,
+                                                                    active_off, max_active, max_cluster_n, ax, ay, az,
+                                                                    1.0, 0.0, prec, 0.0, o, o + n, o + 2 * n);
+                }, rc);
+                if (rc) break;
+                if (ms >= 0.f && ms < best_ms) {
+                    best_ms = ms;
+                    best = KernelConfig{k, w, chunk};
+                }
+            }
+            if (rc) break;
+        }
+        if (rc) break;
+    }
+    c->batch_forced[op] = saved;
+    hipStreamSynchronize(c->stream);
+    hipFree(o);
+    if (rc) return rc;
+    if (best.k == 0) return fail(BF_ERR_UNSUPPORTED, "no variant ran");
+    c->tuned[std::make_tuple(op, prec, (int)kTuneBatched, ilog2_bucket(max_active), ilog2_bucket(max_cluster_n))] =
+        best;
+    if (cache_path) return write_cache(c, cache_path);
+    return BF_OK;
+}
+
+BF_API int bf_set_symmetric_config(bf_ctx* c, int op, int rows, int waves, int rounds) {
+    if (int rc = check_ctx(c)) return rc;
+    if (op != OP_ACC && op != OP_GRAD) return fail(BF_ERR_ARG, "symmetric sweeps: BF_OP_FORCES or BF_OP_GRADIENT");
+    if (rows == 0) { c->sym_forced[op] = KernelConfig{}; return BF_OK; }
+    if (!sym_variant_exists(op, waves, rows)) return fail(BF_ERR_UNSUPPORTED, "no such symmetric shape");
+    if (rounds < 0 || rounds > 64) return fail(BF_ERR_ARG, "rounds must be in [0, 64]");
+    c->sym_forced[op] = KernelConfig{rows, waves, rounds};
+    return BF_OK;
+}
+
+BF_API int bf_set_batched_config(bf_ctx* c, int op, int prec, int k, int waves, int chunk) {
+    if (int rc = check_ctx(c)) return rc;
+    if (op != OP_ACC && op != OP_GRAD) return fail(BF_ERR_ARG, "batched passes: BF_OP_FORCES or BF_OP_GRADIENT");
+    if (int rc = check_prec(prec)) return rc;
+    if (k == 0) { c->batch_forced[op] = KernelConfig{}; return BF_OK; }
+    if (!bf_internal_batch_shape_ok(op, prec, k, waves, chunk))
+        return fail(BF_ERR_UNSUPPORTED, "no such batched shape (chunk: a positive multiple of 64 * waves)");
+    c->batch_forced[op] = KernelConfig{k, waves, chunk};
     return BF_OK;
 }
 

@@ -798,29 +798,43 @@ size_t sym_scratch_bytes(int64_t n, int chunks) {
     return sym_own_bytes(n, chunks) + (size_t)(nb / 2 + 1) * 4 * 64 * n_tiles * sizeof(float);
 }
 
-// Launch shapes, measured at N = 2^20: 8 wavefronts of 2 row tiles for the acceleration, 4 of 4
-// for the gradient (more row tiles per lane share each column read and rotation; fewer fit the
-// VGPRs).
+// Launch shapes.  Defaults, measured at N = 2^20: 8 wavefronts of 2 row tiles for the
+// acceleration, 4 of 4 for the gradient (more row tiles per lane share each column read and
+// rotation; fewer fit the VGPRs).  The other shapes (W wavefronts of R row tiles, W R =
+// kSymBlockTiles) are there for the autotuner and for forced configurations.
 constexpr int kAccWaves = 8, kAccRows = 2, kGradWaves = 4, kGradRows = 4;
-int sym_waves(int op) { return op == OP_ACC ? kAccWaves : kGradWaves; }
-int sym_rows_per_wave(int op) { return op == OP_ACC ? kAccRows : kGradRows; }
+int sym_default_waves(int op) { return op == OP_ACC ? kAccWaves : kGradWaves; }
+int sym_default_rows(int op) { return op == OP_ACC ? kAccRows : kGradRows; }
 
-int sym_blocks_per_cu(int op) {
-    const void* f = op == OP_ACC ? reinterpret_cast<const void*>(k_pairs_sym<SymAcc, kAccWaves, kAccRows>)
-                                 : reinterpret_cast<const void*>(k_pairs_sym<SymGrad, kGradWaves, kGradRows>);
+using SymKernel = void (*)(const SymArgs);
+
+static SymKernel sym_kernel(int op, int waves, int rows) {
+#define BF_SYM(S, W, R) \
+    if (waves == W && rows == R) return k_pairs_sym<S, W, R>;
+    if (op == OP_ACC) { BF_SYM(SymAcc, 16, 1) BF_SYM(SymAcc, 8, 2) BF_SYM(SymAcc, 4, 4) }
+    if (op == OP_GRAD) { BF_SYM(SymGrad, 16, 1) BF_SYM(SymGrad, 8, 2) BF_SYM(SymGrad, 4, 4) }
+#undef BF_SYM
+    return nullptr;
+}
+
+bool sym_variant_exists(int op, int waves, int rows) { return sym_kernel(op, waves, rows) != nullptr; }
+
+int sym_blocks_per_cu(int op, int waves, int rows) {
+    const SymKernel f = sym_kernel(op, waves, rows);
+    if (!f) return 1;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * sym_waves(op), 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(f), 64 * waves, 0) !=
+        hipSuccess)
+        return 1;
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_pairs_sym(int op, const SymArgs& g, hipStream_t st) {
+hipError_t launch_pairs_sym(int op, int waves, int rows, const SymArgs& g, hipStream_t st) {
     if (g.n <= 0) return hipSuccess;
+    const SymKernel f = sym_kernel(op, waves, rows);
+    if (!f) return hipErrorInvalidValue;
     const dim3 grid((unsigned)g.n_blocks * (unsigned)g.n_chunks);
-    if (op == OP_ACC)
-        hipLaunchKernelGGL((k_pairs_sym<SymAcc, kAccWaves, kAccRows>), grid, dim3(64 * kAccWaves), 0, st, g);
-    else if (op == OP_GRAD)
-        hipLaunchKernelGGL((k_pairs_sym<SymGrad, kGradWaves, kGradRows>), grid, dim3(64 * kGradWaves), 0, st, g);
-    else return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, grid, dim3(64 * waves), 0, st, g);
     return hipGetLastError();
 }
 
