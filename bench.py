@@ -36,10 +36,11 @@ PEAK_FP64_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.64
 
 # HBM traffic of the dominant kernel, measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE)
 # and scaled by the same counters' reading for a copy kernel of known size.  The figure is used
-# only while the kernel sources hash to the value recorded with it.
+# only while the sources that define the kernel and its tile packs hash to the value recorded
+# with it and the pass runs the recorded launch shape (row tiles, waves, distance shares).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_sym_SymGrad_king1m_hbm_traffic.txt")
 TRAFFIC_KIND = "symmetric"  # the pass kind whose kernel the counters were taken on
-KERNEL_SOURCES = ["pair_ops.h", "pairs.hip", "spatial.hip", "symmetric.hip", "bf_internal.h", "capi.hip"]
+KERNEL_SOURCES = ["pair_ops.h", "spatial.hip", "symmetric.hip", "bf_internal.h"]
 
 # gradient kernel of each pass kind (the library's launch of that kind at this size)
 KERNEL_NAMES = {"unsorted": "k_pairs<GradMixed>", "sorted": "k_pairs_sorted<GradMixed>",
@@ -65,8 +66,9 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(n):
-    """Bytes per launch from the committed counter summary, or None if absent or stale."""
+def measured_traffic(n, cfg):
+    """Bytes per launch from the committed counter summary, or None if absent or stale (other
+    kernel sources, size or launch shape)."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as fh:
@@ -74,7 +76,9 @@ def measured_traffic(n):
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("source_sha256") != kernel_source_hash() or int(kv.get("n", -1)) != n:
+        shape = [int(x) for x in kv["shape"].split(",")]
+        if (kv.get("source_sha256") != kernel_source_hash() or int(kv.get("n", -1)) != n or cfg[0] != TRAFFIC_KIND
+                or list(cfg[1:4]) != shape):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -749,7 +753,7 @@ def main():
                      "kernel": KERNEL_NAMES[cfg_g[0]] + " (force-gradient pass)",
                      "achieved": grad_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": grad_tflops / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(n) if cfg_g[0] == TRAFFIC_KIND else None,
+                     "traffic": measured_traffic(n, cfg_g),
                      "flops_per_pair": FLOPS_GRAD, "pairs_per_launch": pairs,
                      "pair_evaluations_per_launch": pairs // 2 if cfg_g[0] == "symmetric" else pairs,
                      "avg_kernel_ms": kg},
