@@ -557,7 +557,12 @@ int run_pairs_between(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_
     const int64_t rblocks = (a_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
     const KernelConfig sc = sym_config(ctx, op, na, nb);
     const int64_t want = sym_want(ctx, op, sc);
-    const int shares = (int)std::max<int64_t>(1, std::min<int64_t>(b_tiles, (want + rblocks - 1) / rblocks));
+    // at least a block of column tiles per share, the granularity of the one-set sweep's
+    // distances: each share writes row sums of its own (32 B per row particle), and with one
+    // tile per share those writes and their reduction outweigh the sweep (a 32,768 x 32,768
+    // level of the 262,144-body interval took 512 shares of one tile at 32 rounds)
+    const int64_t most = std::max<int64_t>(1, b_tiles / kSymBlockTiles);
+    const int shares = (int)std::max<int64_t>(1, std::min<int64_t>(most, (want + rblocks - 1) / rblocks));
     if (between_scratch_bytes(na, nb, shares) > kSymMaxScratch ||
         ensure(&ctx->scratch9, &ctx->scratch9_bytes, between_scratch_bytes(na, nb, shares), ctx->stream)) {
         g_err.clear();
