@@ -202,7 +202,11 @@ BF_API int bf_pn1_bh(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, 
 
 /* Synchronising.  Kinetic and potential energy of a set (Sec. 2.1, the N-body
  * Hamiltonian) in FP64: T = sum 1/2 m v^2, U = -sum_{i<j} G m_i m_j / s_ij, written to the
- * host scalars *kinetic and *potential.  Deterministic for a given set and device. */
+ * host scalars *kinetic and *potential.  Each unordered pair is evaluated once (1/s from the
+ * hardware reciprocal square root refined to about 2^-69); sums of 64 terms are folded into
+ * compensated (Neumaier) sums in a fixed order, so the result is deterministic for a given set
+ * and device.  A coincident pair at eps2 = 0 adds nothing.  At most 2^24 particles
+ * (BF_ERR_UNSUPPORTED beyond). */
 BF_API int bf_energy(bf_ctx *ctx, const bf_particles *P, const bf_set *set, double G, double eps2,
                      double *kinetic, double *potential);
 

@@ -263,10 +263,13 @@ struct EnergyArgs {
     Masters P;
     DevSet set;
     double G, eps2;
-    double* rows;   // [count] per-row potential sums (pairs with b > a)
+    double* rows;   // [energy_partials(count)] potential partials of the pair workgroups
     double* kin;    // [count] per-particle kinetic terms
     double* out;    // [2] final kinetic, potential
+    double4* pack;  // [count] (x, y, z, m) of the set, in set order
 };
+// number of pair workgroups (and potential partials) of the energy of a set of n
+int energy_partials(int n);
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t st);
 
 // elementwise updates

@@ -1078,6 +1078,8 @@ BF_API int bf_energy(bf_ctx* c, const bf_particles* P, const bf_set* s, double G
     if (!finite_nonneg(eps2)) return fail(BF_ERR_ARG, "eps2 must be finite and >= 0");
     if (!kinetic || !potential) return fail(BF_ERR_ARG, "output pointer NULL");
     if (s->count == 0) { *kinetic = 0; *potential = 0; return BF_OK; }
+    // one partial per upper-triangular pair of 512-particle blocks: at most 2^24 particles
+    if (s->count > (1 << 24)) return fail(BF_ERR_UNSUPPORTED, "bf_energy takes at most 2^24 particles");
     if (s->idx) {
         if (int rc = bf_validate_set(c, s, P->n)) return rc;
     }
@@ -1086,10 +1088,13 @@ BF_API int bf_energy(bf_ctx* c, const bf_particles* P, const bf_set* s, double G
     e.set = devset(s);
     e.G = G;
     e.eps2 = eps2;
-    const size_t need = (size_t)2 * s->count * sizeof(double) + 2 * sizeof(double);
+    const size_t np = (size_t)energy_partials(s->count);
+    const size_t packb = ((size_t)s->count * sizeof(double4) + 255) & ~size_t(255);
+    const size_t need = packb + (np + (size_t)s->count + 2) * sizeof(double);
     if (int rc = ensure(&c->scratch, &c->scratch_bytes, need, c->stream)) return rc;
-    e.rows = static_cast<double*>(c->scratch);
-    e.kin = e.rows + s->count;
+    e.pack = static_cast<double4*>(c->scratch);
+    e.rows = reinterpret_cast<double*>(static_cast<char*>(c->scratch) + packb);
+    e.kin = e.rows + np;
     e.out = e.kin + s->count;
     BF_HIP(launch_energy(e, c->stream));
     double h[2];

@@ -25,52 +25,147 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double v) {
     s = t;
 }
 
-// Row sums: rows[a] = m_a * sum_{b != a} G m_b / s_ab (every pair appears in two rows), and the
-// kinetic terms.  One thread per row, sources staged through LDS in tiles of 256.
-__global__ __launch_bounds__(256) void k_energy_rows(const EnergyArgs e) {
-    __shared__ double4 tile[256];
-    const int n = e.set.count;
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ac = a < n ? a : n - 1;
-    const int32_t p = clamp_particle(e.set, ac, e.P.n);
-    const double xi = e.P.x[p], yi = e.P.y[p], zi = e.P.z[p];
-    double s = 0.0, c = 0.0;
-    for (int t0 = 0; t0 < n; t0 += 256) {
-        const int len = min(256, n - t0);
-        __syncthreads();
-        if ((int)threadIdx.x < len) {
-            const int q = t0 + threadIdx.x;
-            const int32_t pj = clamp_particle(e.set, q, e.P.n);
-            tile[threadIdx.x] = make_double4(e.P.x[pj], e.P.y[pj], e.P.z[pj], e.P.m[pj]);
-        }
-        __syncthreads();
-        for (int j = 0; j < len; ++j) {
-            if (t0 + j == a) continue;
-            const double4 q = tile[j];
-            const double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
-            const double r2 = dx * dx + dy * dy + dz * dz + e.eps2;
-            if (r2 == 0.0) continue;
-            neumaier(s, c, q.w / sqrt(r2));
-        }
-    }
-    if (a < n) {
-        e.rows[a] = e.G * e.P.m[p] * (s + c);
-        const double v2 = e.P.vx[p] * e.P.vx[p] + e.P.vy[p] * e.P.vy[p] + e.P.vz[p] * e.P.vz[p];
-        e.kin[a] = 0.5 * e.P.m[p] * v2;
-    }
+// 1/sqrt(r2) in FP64: the hardware estimate (about 24 correct bits) refined by one third-order
+// step of y (1 - e)^(-1/2) = y (1 + e/2 + 3e^2/8 + ...), e = 1 - r2 y^2 (about 69 bits before
+// rounding); r2 = 0 (a coincident pair at eps = 0) gives 0: the pair is left out
+__device__ __forceinline__ double energy_rsqrt(double r2) {
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double h = r2 * y;
+    const double e = __builtin_fma(-h, y, 1.0);
+    const double t = __builtin_fma(e, 0.375, 0.5);
+    const double r = __builtin_fma(y * e, t, y);
+    return r2 > 0.0 ? r : 0.0;
 }
 
-// Single workgroup: compensated sums over fixed contiguous ranges, then thread 0 combines them in
-// order.  out[0] = kinetic, out[1] = potential = -1/2 sum rows.
-__global__ __launch_bounds__(1024) void k_energy_final(const EnergyArgs e) {
+// (x, y, z, m) of set position k, packed for the pair kernel
+__global__ __launch_bounds__(256) void k_energy_pack(const EnergyArgs e) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= e.set.count) return;
+    const int32_t p = clamp_particle(e.set, k, e.P.n);
+    e.pack[k] = make_double4(e.P.x[p], e.P.y[p], e.P.z[p], e.P.m[p]);
+}
+
+// Column data the same for every lane of a wavefront, read through the constant address space:
+// the compiler issues scalar loads and the operands arrive in SGPRs (no LDS staging, no
+// barrier).  The pack is not written while the pair kernel runs.
+typedef const double __attribute__((address_space(4))) cdouble_e;
+__device__ __forceinline__ double4 column(const double4* pack, int q) {
+    const cdouble_e* f = (const cdouble_e*)(pack) + 4 * (size_t)q;
+    return make_double4(f[0], f[1], f[2], f[3]);
+}
+
+// The potential U = -sum_{a<b} G m_a m_b / s_ab (Sec. 2.1) with every unordered pair evaluated
+// once.  Set positions are cut into blocks of kEB = 512; workgroup w takes the w-th pair (rb, q)
+// with q >= rb in row-major order: rows a of block rb (two per thread, a0 + t and a0 + t + 256)
+// against the columns b > a of block q.  Only those pairs are launched, and short workgroups
+// keep the chip filled to the end (chunks of 8,192 columns took 36 ms at N = 262,144, of 512
+// 19 ms).  Every column, read through scalar loads, serves the thread's two rows.  Each row sums
+// 64-column slices in plain FP64 and folds every slice into a compensated (Neumaier) row sum;
+// the rows are added in a fixed tree and the workgroup writes part[w].  Workgroups with q == rb
+// also write their rows' kinetic terms.
+constexpr int kEB = 512, kER = 2;
+static_assert(kEB == 256 * kER, "a workgroup's 256 threads cover its row block");
+
+// (rb, q) of the w-th upper-triangular block pair of nb blocks: rows rb before hold
+// nb + (nb - 1) + ... pairs
+__device__ __forceinline__ void block_pair(int w, int nb, int& rb, int& q) {
+    int lo = 0, hi = nb - 1;  // largest rb with first(rb) <= w, first(rb) = rb nb - rb (rb - 1) / 2
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const long long first = (long long)mid * nb - (long long)mid * (mid - 1) / 2;
+        if (first <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    rb = lo;
+    q = rb + (int)(w - ((long long)rb * nb - (long long)rb * (rb - 1) / 2));
+}
+
+__global__ __launch_bounds__(256) void k_energy_pairs(const EnergyArgs e, int nb) {
+    __shared__ double red[256];
+    const int n = e.set.count;
+    int rb, q;
+    block_pair(blockIdx.x, nb, rb, q);
+    const int a0 = rb * kEB, b0 = q * kEB, b1 = min(n, b0 + kEB);
+    int a[kER];
+#pragma unroll
+    for (int r = 0; r < kER; ++r) a[r] = a0 + threadIdx.x + 256 * r;
+    if (q == rb) {
+#pragma unroll
+        for (int r = 0; r < kER; ++r) {
+            if (a[r] < n) {
+                const int32_t p = clamp_particle(e.set, a[r], e.P.n);
+                const double v2 = e.P.vx[p] * e.P.vx[p] + e.P.vy[p] * e.P.vy[p] + e.P.vz[p] * e.P.vz[p];
+                e.kin[a[r]] = 0.5 * e.P.m[p] * v2;
+            }
+        }
+    }
+    double4 me[kER];
+    double s[kER], c[kER];
+#pragma unroll
+    for (int r = 0; r < kER; ++r) {
+        me[r] = e.pack[a[r] < n ? a[r] : n - 1];
+        s[r] = c[r] = 0.0;
+    }
+    for (int j0 = b0; j0 < b1; j0 += 64) {
+        double slice[kER];
+#pragma unroll
+        for (int r = 0; r < kER; ++r) slice[r] = 0.0;
+        if (q > rb && b1 - j0 >= 64) {  // past every row of the block: every pair counts, unrolled
+#pragma unroll 4
+            for (int j = 0; j < 64; ++j) {
+                const double4 o = column(e.pack, j0 + j);
+#pragma unroll
+                for (int r = 0; r < kER; ++r) {
+                    const double dx = o.x - me[r].x, dy = o.y - me[r].y, dz = o.z - me[r].z;
+                    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, e.eps2)));
+                    slice[r] = __builtin_fma(o.w, energy_rsqrt(r2), slice[r]);
+                }
+            }
+        } else {  // the block's own rows or a ragged end: columns b > a only
+            const int j1 = min(b1, j0 + 64);
+            for (int j = j0; j < j1; ++j) {
+                const double4 o = column(e.pack, j);
+#pragma unroll
+                for (int r = 0; r < kER; ++r) {
+                    const double dx = o.x - me[r].x, dy = o.y - me[r].y, dz = o.z - me[r].z;
+                    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, e.eps2)));
+                    const double w = j > a[r] ? o.w : 0.0;
+                    slice[r] = __builtin_fma(w, energy_rsqrt(r2), slice[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kER; ++r) neumaier(s[r], c[r], slice[r]);
+    }
+    double row = 0.0;
+#pragma unroll
+    for (int r = 0; r < kER; ++r)
+        if (a[r] < n) row += e.G * me[r].w * (s[r] + c[r]);
+    red[threadIdx.x] = row;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) e.rows[blockIdx.x] = red[0];
+}
+
+// Single workgroup: compensated sums over fixed contiguous ranges of the workgroup partials and
+// of the kinetic terms, then thread 0 combines them in order.  out[0] = kinetic, out[1] =
+// potential = -(sum of the partials).
+__global__ __launch_bounds__(1024) void k_energy_final(const EnergyArgs e, int nparts) {
     __shared__ double ps[1024], pc[1024], ks[1024], kc[1024];
     const int n = e.set.count;
-    const int per = (n + 1023) / 1024;
-    const int lo = threadIdx.x * per, hi = min(n, lo + per);
     double s = 0.0, c = 0.0, s2 = 0.0, c2 = 0.0;
-    for (int a = lo; a < hi; ++a) {
-        neumaier(s, c, e.rows[a]);
-        neumaier(s2, c2, e.kin[a]);
+    {
+        const int per = (nparts + 1023) / 1024;
+        const int lo = threadIdx.x * per, hi = min(nparts, lo + per);
+        for (int a = lo; a < hi; ++a) neumaier(s, c, e.rows[a]);
+    }
+    {
+        const int per = (n + 1023) / 1024;
+        const int lo = threadIdx.x * per, hi = min(n, lo + per);
+        for (int a = lo; a < hi; ++a) neumaier(s2, c2, e.kin[a]);
     }
     ps[threadIdx.x] = s; pc[threadIdx.x] = c; ks[threadIdx.x] = s2; kc[threadIdx.x] = c2;
     __syncthreads();
@@ -83,15 +178,23 @@ __global__ __launch_bounds__(1024) void k_energy_final(const EnergyArgs e) {
             neumaier(K, KC, kc[t]);
         }
         e.out[0] = K + KC;
-        e.out[1] = -0.5 * (S + C);
+        e.out[1] = -(S + C);
     }
+}
+
+int energy_partials(int n) {
+    const long long nb = (n + kEB - 1) / kEB;
+    return (int)(nb * (nb + 1) / 2);
 }
 
 hipError_t launch_energy(const EnergyArgs& e, hipStream_t st) {
     const int n = e.set.count;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_energy_rows, dim3((n + 255) / 256), dim3(256), 0, st, e);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, st, e);
+    const int nb = (n + kEB - 1) / kEB;
+    const int parts = energy_partials(n);
+    hipLaunchKernelGGL(k_energy_pack, dim3((n + 255) / 256), dim3(256), 0, st, e);
+    hipLaunchKernelGGL(k_energy_pairs, dim3(parts), dim3(256), 0, st, e, nb);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, st, e, parts);
     return hipGetLastError();
 }
 

@@ -337,6 +337,23 @@ def test_energy_parity(ctx):
     assert abs(k1 / k0 - 1) < 1e-13 and abs(u1 / u0 - 1) < 1e-13
 
 
+@pytest.mark.parametrize("eps2", [0.0, 1e-6])
+def test_energy_chunks_ragged_and_coincident(ctx, eps2):
+    """The energy's pair workgroups span several 8,192-column chunks with ragged last tiles
+    (20,037 particles; a sampled list of 9,001 of them), every unordered pair once; at eps = 0 a
+    coincident pair of distinct particles adds nothing, as in the oracle."""
+    d = _cluster(20037, 42)
+    d["x"][7], d["y"][7], d["z"][7] = d["x"][19000], d["y"][19000], d["z"][19000]
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    k0, u0 = oracle.energy(P, eps2=eps2)
+    k1, u1 = ctx.energy(Pd, eps2=eps2)
+    assert abs(k1 / k0 - 1) < 1e-13 and abs(u1 / u0 - 1) < 1e-13, (k1 / k0 - 1, u1 / u0 - 1)
+    sub = np.sort(np.random.default_rng(4).choice(20037, 9001, replace=False))
+    k0, u0 = oracle.energy(P, sub, eps2=eps2)
+    k1, u1 = ctx.energy(Pd, sub, eps2=eps2)
+    assert abs(k1 / k0 - 1) < 1e-13 and abs(u1 / u0 - 1) < 1e-13, (k1 / k0 - 1, u1 / u0 - 1)
+
+
 # --------------------------------------------------------------------------------------------
 # FSI cycle
 # --------------------------------------------------------------------------------------------
