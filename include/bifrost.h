@@ -182,7 +182,7 @@ BF_API int bf_force_gradient_between(bf_ctx *ctx, const bf_particles *P, const b
  * over sources j != i.  A pair with v_ij = 0 gives no fly-by bound; a target without a
  * valid source gets +inf.  Needs velocities.  prec as in bf_forces (the mixed path takes
  * the maxima of G(m_i+m_j)/r^3 and |v_ij|^2/r^2 in FP32 and finishes in FP64; tiles with a
- * pair closer than max(r_fb, tiny) are re-evaluated in FP64).
+ * pair closer than max(r_fb, tiny) or a rate beyond the FP32 range are re-evaluated in FP64).
  * Writes dt_ff[i], dt_fb[i] for every target i. */
 BF_API int bf_dt_min(bf_ctx *ctx, const bf_particles *P, const bf_set *targets, const bf_set *sources,
                      double G, double eta_ff, double eta_fb, int prec, double r_fb,
@@ -480,7 +480,7 @@ BF_API int bf_query_batched_config(bf_ctx *ctx, int op, int prec, int64_t max_ac
 /* Load a tuning table written by the autotuners (tables without the sweep field hold directed
  * entries). */
 BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
-/* Force the shape of the pair-symmetric sweep of op (BF_OP_FORCES / BF_OP_GRADIENT):
+/* Force the shape of the pair-symmetric sweep of op (BF_OP_FORCES / BF_OP_GRADIENT / BF_OP_DTMIN):
  * rows x waves in {1 x 16, 2 x 8, 4 x 4} (BF_ERR_UNSUPPORTED otherwise), rounds of resident
  * workgroups in [0, 64] (0: 32).  rows = 0 restores the tuned or default choice. */
 BF_API int bf_set_symmetric_config(bf_ctx *ctx, int op, int rows, int waves, int rounds);
@@ -507,7 +507,13 @@ BF_API int bf_set_batched_config(bf_ctx *ctx, int op, int prec, int k_per_lane, 
  * force-gradient term): about 0.6 of the arithmetic.  It needs (n / 2048 + 1) * 16 bytes of
  * scratch per particle (8.6 GB at n = 2^20; up to 32 GiB, beyond that the directed sweep
  * runs).  The column sums go through fixed-order partials, so results stay bitwise repeatable.
- * Bit BF_SORT_DIRECTED in ops_mask keeps the directed sweep for such passes. */
+ * Bit BF_SORT_DIRECTED in ops_mask keeps the directed sweep for such passes.
+ *
+ * Bit (1 << BF_OP_DTMIN) (on by default) does the same for the mixed time-step pass over one set
+ * with r_fb = 0, in the set's own order (no sort): a pair's free-fall and fly-by rates are the
+ * same number for both particles, so each unordered pair is evaluated once for the two maxima.
+ * Same size limits; (n / 2048 + 1) * 8 + 16 bytes of scratch per particle.  Results as the
+ * directed pass (a maximum is exact in any order), bitwise repeatable. */
 BF_API int bf_set_spatial_sort(bf_ctx *ctx, int ops_mask, double kappa);
 
 /* Synchronising.  Counters of the most recent acceleration / gradient / time-step pass: targets

@@ -324,9 +324,10 @@ class Context:
             float(eps2), PRECISIONS[prec], float(r_fb), *map(_ptr, o)))
         return o
 
-    def dt_min(self, P: Particles, targets=None, sources=None, G=1.0, eta_ff=0.2, eta_fb=0.2, prec="mixed", r_fb=1e-3,
+    def dt_min(self, P: Particles, targets=None, sources=None, G=1.0, eta_ff=0.2, eta_fb=0.2, prec="mixed", r_fb=0.0,
                out: Optional[Sequence[torch.Tensor]] = None):
-        """Free-fall and fly-by time-steps (particle-indexed dt_ff, dt_fb)."""
+        """Free-fall and fly-by time-steps (particle-indexed dt_ff, dt_fb); r_fb > 0 re-evaluates
+        the tiles with a pair closer than r_fb in FP64 (mixed)."""
         t, s = ParticleSet.of(targets, P.n), ParticleSet.of(sources, P.n)
         o = self._outs(P, out, 2)
         _check("bf_dt_min", _lib.bf_dt_min(self._h, ctypes.byref(P._c()), ctypes.byref(t._c()), ctypes.byref(s._c()),
@@ -577,11 +578,13 @@ class Context:
         return ("unsorted", "sorted", "symmetric", "between")[v[0].value], v[1].value, v[2].value, v[3].value
 
     def set_spatial_sort(self, forces: bool = True, gradient: bool = True, kappa: float = 0.0,
-                         any_size: bool = False, symmetric: bool = True):
+                         any_size: bool = False, symmetric: bool = True, timestep: bool = True):
         """Select the passes that use the spatially sorted mixed kernels (default: both); kappa = 0
         keeps the near-tile threshold (default 1); any_size lifts the minimum pass size;
-        symmetric = False keeps the directed sweep where targets and sources are one set."""
+        symmetric = False keeps the directed sweep where targets and sources are one set;
+        timestep selects the pair-symmetric mixed time-step pass over one set (set order)."""
         mask = (int(bool(forces)) << BF_OP_FORCES) | (int(bool(gradient)) << BF_OP_GRADIENT)
+        mask |= int(bool(timestep)) << BF_OP_DTMIN
         mask |= BF_SORT_ANY_SIZE if any_size else 0
         mask |= 0 if symmetric else BF_SORT_DIRECTED
         _check("bf_set_spatial_sort", _lib.bf_set_spatial_sort(self._h, mask, float(kappa)))

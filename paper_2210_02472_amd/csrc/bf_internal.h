@@ -155,6 +155,12 @@ struct SymArgs {
                                // two sets: [n_blocks][4][n_pad] column partials per row block
     double* own;               // [n_chunks][4][n_row_pad] row sums, one row per share
     unsigned long long* tile_stats;  // [near, far] wavefront-tile visits (NULL: not counted)
+    // time-step sweep only: the masses and G of the FP64 re-evaluation, the device flags
+    // (coincident pairs), the FP64 maxima of re-evaluated tiles [2][n_pad]
+    const double* m;
+    double G;
+    uint32_t* flags;
+    double* hi;
 };
 // bytes of own (256-byte aligned) and of own + part for n particles and `chunks` shares (one set)
 size_t sym_own_bytes(int64_t n, int chunks);
@@ -173,9 +179,18 @@ size_t sym64_own_bytes(int64_t n, int chunks);
 int sym64_blocks_per_cu(int op);
 hipError_t launch_pairs_sym64(int op, const SymArgs& g, double eps2t, hipStream_t st);
 hipError_t launch_sym_reduce64(int op, const PairArgs& a, const SymArgs& g, hipStream_t st);
+// mixed time-step one-set sweep: the time-step pack (launch_pack, mixed) in the set's own order as
+// columns and rows, FP32 row maxima [chunks][2][n_pad] (own holds floats), FP64 maxima of the
+// tiles evaluated again in FP64 and FP32 partials [n_blocks/2 + 1][2][n_pad]; launched by
+// launch_pairs_sym / launch_sym_reduce with op OP_DT
+// [own | hi | part]
+size_t symdt_scratch_bytes(int64_t n, int chunks);
+size_t symdt_own_bytes(int64_t n, int chunks);
+size_t symdt_hi_bytes(int64_t n);
 // resident workgroups per CU of the symmetric kernel of op with a given shape, the default
 // shape, and the launch
-// shapes: W wavefronts of R row tiles each (W R = kSymBlockTiles): (16, 1), (8, 2), (4, 4)
+// shapes: W wavefronts of R row tiles each (W R = kSymBlockTiles): (16, 1), (8, 2), (4, 4);
+// op OP_ACC, OP_GRAD (sorted, mixed) or OP_DT (set order, mixed)
 int sym_default_waves(int op);
 int sym_default_rows(int op);
 bool sym_variant_exists(int op, int waves, int rows);
@@ -321,7 +336,7 @@ struct bf_ctx {
                                             // black-hole level mask
     int last_kind = 0, last_k = 0, last_waves = 0, last_split = 0;  // how the last pass ran
     // spatially sorted mixed passes: bit op set = use them for that operation when large enough
-    int sort_ops = (1 << 0) | (1 << 1);  // acceleration and force-gradient passes
+    int sort_ops = (1 << 0) | (1 << 1) | (1 << 2);  // acceleration, force-gradient and time-step passes
     const int32_t* sub = nullptr;     // subsystem labels applied to acc / grad / dt passes (NULL: none)
     int64_t sub_n = 0;
     float kappa = 1.0f;               // a tile is near a workgroup when their gap < kappa * tile half-extent

@@ -213,6 +213,15 @@ int sym64_chunks(bf_ctx* ctx, int op, int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb / 2 + 1, (want + nb - 1) / nb));
 }
 
+// Mixed time-step passes over one set, r_fb = 0: each unordered pair once, in the set's own order
+bool use_symmetric_dt(bf_ctx* ctx, int op, int prec, const bf_set* tg, const bf_set* sr, double r_fb) {
+    const int64_t n = sr->count;
+    return op == OP_DT && prec == BF_PREC_MIXED && r_fb == 0.0 && (ctx->sort_ops >> OP_DT & 1) &&
+           !(ctx->sort_ops & BF_SORT_DIRECTED) &&
+           same_set(tg, sr) && ctx->sub == nullptr && n >= 64 &&
+           ((ctx->sort_ops & BF_SORT_ANY_SIZE) || (n >= kSortMinSources && n * n >= kSortMinPairs));
+}
+
 bool use_symmetric(bf_ctx* ctx, int op, bool sorted, const bf_set* tg, const bf_set* sr) {
     return sorted && !(ctx->sort_ops & BF_SORT_DIRECTED) && same_set(tg, sr) &&
            sym_scratch_bytes(tg->count,
@@ -319,8 +328,17 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     if (sorted && !sorted_variant_exists(op, p.cfg.k, p.cfg.waves))
         return fail(BF_ERR_UNSUPPORTED, "no sorted kernel variant for this configuration");
     bool sym = !arena && use_symmetric(ctx, op, sorted, tg, sr);
+    bool symdt = !arena && use_symmetric_dt(ctx, op, prec, tg, sr, r_fb);
     int sym_shares = 0;
-    const KernelConfig sc = sym ? sym_config(ctx, op, sr->count, sr->count) : KernelConfig{};
+    const KernelConfig sc = sym || symdt ? sym_config(ctx, op, sr->count, sr->count) : KernelConfig{};
+    if (symdt) {
+        sym_shares = sym_chunks(ctx, op, sr->count, sc);
+        const size_t need = symdt_scratch_bytes(sr->count, sym_shares);
+        if (need > kSymMaxScratch || ensure(&ctx->scratch9, &ctx->scratch9_bytes, need, ctx->stream)) {
+            g_err.clear();
+            symdt = false;
+        }
+    }
     if (sym) {
         // the column partials are large (8.6 GB at n = 2^20): without the memory, the directed
         // sweep runs instead
@@ -347,7 +365,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
                        sr->count <= kSmallMaxSources && ctx->forced[op][prec].k == 0 &&
                        ctx->tuned.find(std::make_tuple(op, prec, (int)kTuneDirected, ilog2_bucket(tg->count),
                                                        ilog2_bucket(sr->count))) == ctx->tuned.end();
-    if (sym || sym64 || small) p.split = 1;  // no source split in memory
+    if (sym || sym64 || symdt || small) p.split = 1;  // no source split in memory
     // scratch: [fix counter | fix list (one slot per target)], the split partials, the packed
     // sources (unsorted) and the fix-up partials: from the context's buffers, or the arena
     const bool fix = prec == BF_PREC_MIXED && op != OP_DT;
@@ -502,6 +520,24 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
             g.own = static_cast<double*>(ctx->scratch9);
             g.part = reinterpret_cast<float*>(static_cast<char*>(ctx->scratch9) + sym64_own_bytes(ns, sym64_shares));
         }
+        if (symdt) {  // rows and columns: the time-step pack in the set's order
+            const int64_t ns = sr->count, ntiles = (ns + 63) / 64;
+            g.near_pack = g.row_pack = a.pack;
+            g.n = g.n_rows = (int32_t)ns;
+            g.n_tiles = g.n_row_tiles = (int32_t)ntiles;
+            g.n_blocks = (int32_t)((ntiles + kSymBlockTiles - 1) / kSymBlockTiles);
+            g.n_pad = g.n_row_pad = (int32_t)(64 * ntiles);
+            g.between = 0;
+            g.n_chunks = sym_shares;
+            g.chunk_len = (g.n_blocks / 2 + 1 + sym_shares - 1) / sym_shares;
+            char* base = static_cast<char*>(ctx->scratch9);
+            g.own = reinterpret_cast<double*>(base);  // holds floats
+            g.hi = reinterpret_cast<double*>(base + symdt_own_bytes(ns, sym_shares));
+            g.part = reinterpret_cast<float*>(base + symdt_own_bytes(ns, sym_shares) + symdt_hi_bytes(ns));
+            g.m = M.m;
+            g.G = G;
+            g.flags = ctx->d_flags;
+        }
     }
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     const bool timed = ctx->timing && !ctx->capturing && !arena;
@@ -515,22 +551,22 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         }
         BF_HIP(hipEventRecord(ev.first, ctx->stream));
     }
-    if (sym) BF_HIP(launch_pairs_sym(op, sc.waves, sc.k, g, ctx->stream));
+    if (sym || symdt) BF_HIP(launch_pairs_sym(op, sc.waves, sc.k, g, ctx->stream));
     else if (sym64) BF_HIP(launch_pairs_sym64(op, g, eps2 + 1e-150 /* the FP64 kernels' tiny */, ctx->stream));
     else if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
     else if (small) BF_HIP(launch_pairs_small(op, a, ctx->stream));
     else BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
     // credit: every (target, source) pair, less the self-pairs when targets and sources are one set
     ctx->pair_credit[op] += (int64_t)tg->count * (same_set(tg, sr) ? sr->count - 1 : sr->count);
-    ctx->last_kind = sym || sym64 ? BF_PASS_SYMMETRIC : sorted ? BF_PASS_SORTED : BF_PASS_UNSORTED;
-    ctx->last_k = sym ? sc.k : sym64 ? 4 : small ? 1 : p.cfg.k;
-    ctx->last_waves = sym ? sc.waves : sym64 ? 4 : small ? 16 : p.cfg.waves;
-    ctx->last_split = sym || sym64 ? g.n_chunks : p.split;
+    ctx->last_kind = sym || sym64 || symdt ? BF_PASS_SYMMETRIC : sorted ? BF_PASS_SORTED : BF_PASS_UNSORTED;
+    ctx->last_k = sym || symdt ? sc.k : sym64 ? 4 : small ? 1 : p.cfg.k;
+    ctx->last_waves = sym || symdt ? sc.waves : sym64 ? 4 : small ? 16 : p.cfg.waves;
+    ctx->last_split = sym || sym64 || symdt ? g.n_chunks : p.split;
     if (timed) {
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
     }
-    if (sym) BF_HIP(launch_sym_reduce(op, a, g, ctx->stream));
+    if (sym || symdt) BF_HIP(launch_sym_reduce(op, a, g, ctx->stream));
     else if (sym64) BF_HIP(launch_sym_reduce64(op, a, g, ctx->stream));
     else if (p.split > 1) BF_HIP(launch_reduce(op, prec, a, ctx->stream));
     if (fix) BF_HIP(launch_fixup(op, a, fix_buf, fix_cap, ctx->num_cu, ctx->stream));
@@ -1795,8 +1831,9 @@ BF_API int bf_last_pass_config(bf_ctx* c, int* kind, int* k, int* waves, int* sp
 
 BF_API int bf_set_spatial_sort(bf_ctx* c, int ops_mask, double kappa) {
     if (int rc = check_ctx(c)) return rc;
-    if (ops_mask & ~((1 << OP_ACC) | (1 << OP_GRAD) | BF_SORT_ANY_SIZE | BF_SORT_DIRECTED))
-        return fail(BF_ERR_ARG, "ops_mask: only the force and gradient passes, BF_SORT_ANY_SIZE and BF_SORT_DIRECTED");
+    if (ops_mask & ~((1 << OP_ACC) | (1 << OP_GRAD) | (1 << OP_DT) | BF_SORT_ANY_SIZE | BF_SORT_DIRECTED))
+        return fail(BF_ERR_ARG, "ops_mask: only the force, gradient and time-step passes, BF_SORT_ANY_SIZE and "
+                                "BF_SORT_DIRECTED");
     if (kappa != 0.0 && !(kappa >= kKappaMin && kappa <= kKappaMax))
         return fail(BF_ERR_ARG, "kappa must be 0 (keep) or in [0.5, 64]");
     c->sort_ops = ops_mask;
@@ -2163,7 +2200,7 @@ BF_API int bf_autotune_pass(bf_ctx* c, int op, int prec, const bf_particles* P, 
     int rc = BF_OK;
     // the pass takes the pair-symmetric sweep: tune its shapes on the whole set
     const bool sorted = use_sorted(c, op, prec, targets->count, sources->count, 0.0);
-    if (sorted && use_symmetric(c, op, sorted, targets, sources)) {
+    if ((sorted && use_symmetric(c, op, sorted, targets, sources)) || use_symmetric_dt(c, op, prec, targets, sources, 0.0)) {
         rc = tune_symmetric(c, op, M, *targets, o);
     } else {
         // directed: a leading sample of the targets (a sub-range or the head of the list)
@@ -2237,7 +2274,7 @@ BF_API int bf_autotune_batched(bf_ctx* c, int op, int prec, const bf_particles* 
 
 BF_API int bf_set_symmetric_config(bf_ctx* c, int op, int rows, int waves, int rounds) {
     if (int rc = check_ctx(c)) return rc;
-    if (op != OP_ACC && op != OP_GRAD) return fail(BF_ERR_ARG, "symmetric sweeps: BF_OP_FORCES or BF_OP_GRADIENT");
+    if (op < 0 || op >= OP_COUNT) return fail(BF_ERR_ARG, "bad op");
     if (rows == 0) { c->sym_forced[op] = KernelConfig{}; return BF_OK; }
     if (!sym_variant_exists(op, waves, rows)) return fail(BF_ERR_UNSUPPORTED, "no such symmetric shape");
     if (rounds < 0 || rounds > 64) return fail(BF_ERR_ARG, "rounds must be in [0, 64]");

@@ -255,6 +255,7 @@ struct DtMixed {
         return self ? __builtin_huge_valf() : r2;
     }
     __device__ static void fold(A64& o, const A32& i) { o.ff = fmax(o.ff, (double)i.ff); o.fb = fmax(o.fb, (double)i.fb); }
+    __device__ static bool beyond(const A32& r) { return !(fmaxf(r.ff, r.fb) < __builtin_huge_valf()); }
     __device__ static void redo(A64& o, const PairArgs& a, int pi, int q0, int len) {
         const double xi = a.P.x[pi], yi = a.P.y[pi], zi = a.P.z[pi];
         const double vxi = a.P.vx[pi], vyi = a.P.vy[pi], vzi = a.P.vz[pi], mi = a.P.m[pi];
@@ -651,7 +652,14 @@ __device__ __forceinline__ void sweep(const PairArgs& a, typename Op::Src* tile,
                     }
                 }
                 bool redo = false;
-                if constexpr (DETECT) redo = __any(dmin < a.rfb2f);
+                if constexpr (DETECT) {
+                    bool close = dmin < a.rfb2f;
+                    if constexpr (Op::kMax) {  // a rate beyond the FP32 range (overflow or r = 0)
+#pragma unroll
+                        for (int k = 0; k < K; ++k) close = close || Op::beyond(part[k]);
+                    }
+                    redo = __any(close);
+                }
                 if (redo) {
 #pragma unroll
                     for (int k = 0; k < K; ++k) Op::redo(acc[k], a, pidx[k], jt + js, je - js);

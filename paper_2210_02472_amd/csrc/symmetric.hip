@@ -770,6 +770,300 @@ __global__ __launch_bounds__(256) void k_between_reduce(const PairArgs ar, const
     }
 }
 
+
+// ---- the time-step rates ---------------------------------------------------------------------
+// The pairwise free-fall and fly-by rates (Sec. 3.5.3, Eqs. dt-freefall and dt-flyby):
+//   W_ff = G (m_i + m_j) / r^3,   W_fb = |v_ij|^2 / r^2,
+// are the same number for i and for j, so one evaluation of an unordered pair serves the row
+// maximum and the column maximum.  The walk is the one above, the set in its own order (no
+// sort), the columns staged from the time-step pack (double4 (x, y, z, [G m]), double4 (vx, vy,
+// vz, particle index)).  FP64 differences rounded once to FP32 and FP32 rates, with the same
+// operations as the directed mixed pass, so a pair gives the same FP32 rates in either
+// orientation.  A maximum is exact in any order, so the row maxima, the column accumulators
+// (moved by DPP, as above) and the partials all stay FP32.
+// A rate has no cancellation: its FP32 value is good to a few units of rounding unless it
+// overflows (pairs closer than about (G m)^(1/3) 1e-13) or r = 0.  A wavefront whose tile
+// produced a non-finite maximum evaluates that tile again in FP64, drops its FP32 values and
+// puts the FP64 maxima of its rows and columns into hi (64-bit atomic maximum on the bit
+// patterns: the rates are >= 0, so their order is that of the integers); a pair at r = 0 in
+// FP64 is left out and flagged.  (A NaN rate, from 0 * inf, is dropped by the maximum: a
+// coincident pair of massless particles with equal velocities adds nothing and may go
+// unflagged.)  Self-pairs (diagonal tiles) and the fillers past the last particle are masked out.
+
+struct DtRow { double x, y, z, vx, vy, vz; float gm; int pi; };
+
+__device__ __forceinline__ void dt_load_row(const SymArgs& g, int s, bool live, DtRow& t) {
+    if (live) {
+        const double4* pk = static_cast<const double4*>(g.row_pack);
+        const double4 p = pk[2 * s], v = pk[2 * s + 1];
+        t.x = p.x; t.y = p.y; t.z = p.z; t.gm = unpack_gm(p.w);
+        t.vx = v.x; t.vy = v.y; t.vz = v.z; t.pi = (int)v.w;
+    } else {
+        t.x = t.y = t.z = 0.0; t.gm = 0.f;
+        t.vx = t.vy = t.vz = 0.0; t.pi = -1;
+    }
+}
+
+// planes: (x, y), (z, [G m]), (vx, vy), (vz, index) of the pack; zeros past the last particle
+__device__ __forceinline__ uint4 dt_stage_elem(const SymArgs& g, int plane, int s, bool ok) {
+    return ok ? static_cast<const uint4*>(g.near_pack)[4 * s + plane] : make_uint4(0u, 0u, 0u, 0u);
+}
+
+// One pair in FP32: maxima of the row (r) and the column terms (c).  MASK: a pair that does not
+// count (ok false) gives zero rates.
+template <bool MASK>
+__device__ __forceinline__ void dt_pair(float (&r)[2], float (&c)[2], const DtRow& t, const uint4* pl, int j,
+                                        bool ok) {
+    const double2 xy = __builtin_bit_cast(double2, pl[j]);
+    const double2 zw = __builtin_bit_cast(double2, pl[kPlaneLen + j]);
+    const double2 vxy = __builtin_bit_cast(double2, pl[2 * kPlaneLen + j]);
+    const double2 vz = __builtin_bit_cast(double2, pl[3 * kPlaneLen + j]);
+    const float dx = dif32(xy.x, t.x), dy = dif32(xy.y, t.y), dz = dif32(zw.x, t.z);
+    const float ux = dif32(vxy.x, t.vx), uy = dif32(vxy.y, t.vy), uz = dif32(vz.x, t.vz);
+    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const float u2 = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+    float ri = rsqrt32(r2);
+    if (MASK) ri = ok ? ri : 0.f;
+    const float ri2 = ri * ri;
+    const float fb = u2 * ri2;
+    const float ff = ((unpack_gm(zw.y) + t.gm) * ri2) * ri;
+    r[0] = fmaxf(r[0], ff);
+    r[1] = fmaxf(r[1], fb);
+    c[0] = ff;
+    c[1] = fb;
+}
+
+__device__ __forceinline__ void max_bits(double* p, double v) {
+    atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+// The wavefront's tile again in FP64 (rare): row and column maxima into hi, one row tile at a
+// time (few registers).  Masses from g.m (the particle indices ride in the pack).
+template <int R>
+__device__ __forceinline__ void dt_redo(const SymArgs& g, int ct, const int (&mode)[R], const bool (&rok)[R],
+                                        const int (&rs)[R], const DtRow (&row)[R], const uint4* pl) {
+    const int lane = threadIdx.x & 63;
+    double cmax[2] = {0.0, 0.0};  // column (lane + 63) mod 64, over the row tiles
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (mode[r] == kSkip) continue;  // uniform over the wavefront
+        const double mi = rok[r] ? g.m[row[r].pi] : 0.0;
+        double rmax[2] = {0.0, 0.0}, acc[2] = {0.0, 0.0};
+        for (int k = 0; k < 64; ++k) {
+            const int j = lane + k;
+            double ff = 0.0, fb = 0.0;
+            if (rok[r] && ct * 64 + (j & 63) < g.n && counts(mode[r], lane, k)) {
+                const double2 xy = __builtin_bit_cast(double2, pl[j]);
+                const double2 zw = __builtin_bit_cast(double2, pl[kPlaneLen + j]);
+                const double dx = xy.x - row[r].x, dy = xy.y - row[r].y, dz = zw.x - row[r].z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 == 0.0) {
+                    atomicOr(g.flags, BF_FLAG_COINCIDENT);
+                } else {
+                    const double2 vxy = __builtin_bit_cast(double2, pl[2 * kPlaneLen + j]);
+                    const double2 vz = __builtin_bit_cast(double2, pl[3 * kPlaneLen + j]);
+                    const double ux = vxy.x - row[r].vx, uy = vxy.y - row[r].vy, uz = vz.x - row[r].vz;
+                    const double ri = rsqrt64(r2);
+                    fb = (ux * ux + uy * uy + uz * uz) * ri * ri;
+                    ff = g.G * (mi + g.m[(int)vz.y]) * ri * ri * ri;
+                }
+            }
+            rmax[0] = fmax(rmax[0], ff);
+            rmax[1] = fmax(rmax[1], fb);
+            acc[0] = fmax(rol1d(acc[0]), ff);
+            acc[1] = fmax(rol1d(acc[1]), fb);
+        }
+        if (rok[r]) {
+            max_bits(g.hi + rs[r], rmax[0]);
+            max_bits(g.hi + g.n_pad + rs[r], rmax[1]);
+        }
+        cmax[0] = fmax(cmax[0], acc[0]);
+        cmax[1] = fmax(cmax[1], acc[1]);
+    }
+    const int col = ct * 64 + ((lane + 63) & 63);
+    if (col < g.n) {
+        max_bits(g.hi + col, cmax[0]);
+        max_bits(g.hi + g.n_pad + col, cmax[1]);
+    }
+}
+
+template <int W, int R>
+__global__ __launch_bounds__(64 * W) void k_pairs_symdt(const SymArgs g) {
+    static_assert(W * R == kSymBlockTiles, "a workgroup covers one block");
+    constexpr int NPL = 4;
+    __shared__ uint4 colbuf[2][NPL * kPlaneLen];
+    __shared__ float xch[2][W][2][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wg = blockIdx.x % g.n_blocks, chunk = blockIdx.x / g.n_blocks;
+    const int d0 = chunk * g.chunk_len, d1 = d0 + g.chunk_len;
+    const int rbase = wg * (W * R) + wave * R;
+    DtRow row[R];
+    bool tile_live[R], rok[R], ragged_rows = false;
+    int rs[R];
+    float own[R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        tile_live[r] = rbase + r < g.n_row_tiles;
+        rs[r] = (rbase + r) * 64 + lane;
+        rok[r] = tile_live[r] && rs[r] < g.n_rows;
+        ragged_rows = ragged_rows || (tile_live[r] && (rbase + r + 1) * 64 > g.n_rows);
+        dt_load_row(g, rs[r], rok[r], row[r]);
+        own[r][0] = own[r][1] = 0.f;
+    }
+    constexpr int SPT = (NPL + W - 1) / W;
+    const int st_k = threadIdx.x & 63;
+    TileWalk cur, pre;
+    cur.d = d0;
+    cur.d_end = d1;
+    cur.next(g, wg);
+    pre = cur;
+    pre.next(g, wg);
+    uint4 held[SPT];
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+        const int pl = wave + W * u;
+        if (pl < NPL && cur.ct >= 0) {
+            const int s = cur.ct * 64 + st_k;
+            const uint4 e = dt_stage_elem(g, pl, s, s < g.n);
+            colbuf[0][pl * kPlaneLen + st_k] = e;
+            colbuf[0][pl * kPlaneLen + st_k + 64] = e;
+        }
+        held[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (pl < NPL && pre.ct >= 0) {
+            const int s = pre.ct * 64 + st_k;
+            held[u] = dt_stage_elem(g, pl, s, s < g.n);
+        }
+    }
+    __syncthreads();
+    for (int i = 0; cur.ct >= 0; ++i) {
+        const int buf = i & 1;
+        const int ct = cur.ct;
+        const uint4* pls = colbuf[buf];
+        int mode[R];
+        bool any = false;
+        bool masked = ragged_rows || (ct + 1) * 64 > g.n;  // fillers among the rows or the columns
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int rt = rbase + r;
+            mode[r] = !tile_live[r] ? kSkip : (cur.d > 0 || ct > rt) ? kFull : ct == rt ? kDiag : kSkip;
+            any = any || mode[r] != kSkip;
+            masked = masked || mode[r] != kFull;
+        }
+        float ja[2] = {0.f, 0.f};  // accumulator of column (lane + k) mod 64 after step k
+        if (any) {
+            float part[R][2];
+#pragma unroll
+            for (int r = 0; r < R; ++r) part[r][0] = part[r][1] = 0.f;
+            if (masked) {
+                for (int k = 0; k < 64; ++k) {
+                    float cs[2] = {0.f, 0.f};
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        float cv[2];
+                        const bool ok = rok[r] && ct * 64 + ((lane + k) & 63) < g.n && counts(mode[r], lane, k);
+                        dt_pair<true>(part[r], cv, row[r], pls, lane + k, ok);
+                        cs[0] = fmaxf(cs[0], cv[0]);
+                        cs[1] = fmaxf(cs[1], cv[1]);
+                    }
+                    ja[0] = fmaxf(rol1(ja[0]), cs[0]);
+                    ja[1] = fmaxf(rol1(ja[1]), cs[1]);
+                }
+            } else {
+#pragma unroll 2
+                for (int k = 0; k < 64; ++k) {
+                    float cs[2];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        float cv[2];
+                        dt_pair<false>(part[r], cv, row[r], pls, lane + k, true);
+                        cs[0] = r == 0 ? cv[0] : fmaxf(cs[0], cv[0]);
+                        cs[1] = r == 0 ? cv[1] : fmaxf(cs[1], cv[1]);
+                    }
+                    ja[0] = fmaxf(rol1(ja[0]), cs[0]);
+                    ja[1] = fmaxf(rol1(ja[1]), cs[1]);
+                }
+            }
+            // non-finite maxima (overflow, r = 0): the tile again in FP64
+            float top = fmaxf(ja[0], ja[1]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) top = fmaxf(top, fmaxf(part[r][0], part[r][1]));
+            if (__any(!(top < __builtin_huge_valf()))) {
+                dt_redo<R>(g, ct, mode, rok, rs, row, pls);
+                ja[0] = ja[1] = 0.f;
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    own[r][0] = fmaxf(own[r][0], part[r][0]);
+                    own[r][1] = fmaxf(own[r][1], part[r][1]);
+                }
+            }
+        }
+        const int slot = any ? (lane + 63) & 63 : lane;
+        xch[buf][wave][0][slot] = ja[0];
+        xch[buf][wave][1][slot] = ja[1];
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int pl = wave + W * u;
+            if (pl < NPL && pre.ct >= 0) {
+                colbuf[buf ^ 1][pl * kPlaneLen + st_k] = held[u];
+                colbuf[buf ^ 1][pl * kPlaneLen + st_k + 64] = held[u];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * 64) {
+            const int q = threadIdx.x >> 6, k = threadIdx.x & 63;
+            float s = 0.f;
+#pragma unroll
+            for (int v = 0; v < W; ++v) s = fmaxf(s, xch[buf][v][q][k]);
+            const int col = ct * 64 + k;
+            if (col < g.n) g.part[((size_t)cur.d * 2 + q) * g.n_pad + col] = s;
+        }
+        cur = pre;
+        pre.next(g, wg);
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int pl = wave + W * u;
+            if (pl < NPL && pre.ct >= 0) {
+                const int s = pre.ct * 64 + st_k;
+                held[u] = dt_stage_elem(g, pl, s, s < g.n);
+            }
+        }
+    }
+    float* o = reinterpret_cast<float*>(g.own) + (size_t)chunk * 2 * g.n_row_pad;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (rok[r]) {
+            o[rs[r]] = own[r][0];
+            o[(size_t)g.n_row_pad + rs[r]] = own[r][1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_symdt_clear(double* hi, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) hi[i] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_symdt_reduce(const PairArgs a, const SymArgs g) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= g.n) return;
+    const int b = (s >> 6) / kSymBlockTiles;
+    const int nb = g.n_blocks, D = nb / 2;
+    const float* own = reinterpret_cast<const float*>(g.own);
+    float v[2] = {0.f, 0.f};
+    for (int c = 0; c < g.n_chunks; ++c) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) v[q] = fmaxf(v[q], own[((size_t)c * 2 + q) * g.n_row_pad + s]);
+    }
+    for (int d = 0; d <= D; ++d) {
+        if (d > 0 && 2 * d == nb && b < d) continue;  // no partial: this block pair was swept from here
+#pragma unroll
+        for (int q = 0; q < 2; ++q) v[q] = fmaxf(v[q], g.part[((size_t)d * 2 + q) * g.n_pad + s]);
+    }
+    const double w[2] = {fmax((double)v[0], g.hi[s]), fmax((double)v[1], g.hi[g.n_pad + s])};
+    write_result<DtMixed>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), w);
+}
+
 }  // namespace
 
 size_t between_scratch_bytes(int64_t n_rows, int64_t n_cols, int chunks) {
@@ -800,11 +1094,12 @@ size_t sym_scratch_bytes(int64_t n, int chunks) {
 
 // Launch shapes.  Defaults, measured at N = 2^20: 8 wavefronts of 2 row tiles for the
 // acceleration, 4 of 4 for the gradient (more row tiles per lane share each column read and
-// rotation; fewer fit the VGPRs).  The other shapes (W wavefronts of R row tiles, W R =
+// rotation; fewer fit the VGPRs); 8 of 2 for the time-step rates (341 ms against 349 ms with 4
+// of 4 and 472 ms with 16 of 1).  The other shapes (W wavefronts of R row tiles, W R =
 // kSymBlockTiles) are there for the autotuner and for forced configurations.
-constexpr int kAccWaves = 8, kAccRows = 2, kGradWaves = 4, kGradRows = 4;
-int sym_default_waves(int op) { return op == OP_ACC ? kAccWaves : kGradWaves; }
-int sym_default_rows(int op) { return op == OP_ACC ? kAccRows : kGradRows; }
+constexpr int kAccWaves = 8, kAccRows = 2, kGradWaves = 4, kGradRows = 4, kDtWaves = 8, kDtRows = 2;
+int sym_default_waves(int op) { return op == OP_ACC ? kAccWaves : op == OP_GRAD ? kGradWaves : kDtWaves; }
+int sym_default_rows(int op) { return op == OP_ACC ? kAccRows : op == OP_GRAD ? kGradRows : kDtRows; }
 
 using SymKernel = void (*)(const SymArgs);
 
@@ -814,6 +1109,11 @@ static SymKernel sym_kernel(int op, int waves, int rows) {
     if (op == OP_ACC) { BF_SYM(SymAcc, 16, 1) BF_SYM(SymAcc, 8, 2) BF_SYM(SymAcc, 4, 4) }
     if (op == OP_GRAD) { BF_SYM(SymGrad, 16, 1) BF_SYM(SymGrad, 8, 2) BF_SYM(SymGrad, 4, 4) }
 #undef BF_SYM
+    if (op == OP_DT) {
+        if (waves == 16 && rows == 1) return k_pairs_symdt<16, 1>;
+        if (waves == 8 && rows == 2) return k_pairs_symdt<8, 2>;
+        if (waves == 4 && rows == 4) return k_pairs_symdt<4, 4>;
+    }
     return nullptr;
 }
 
@@ -833,9 +1133,25 @@ hipError_t launch_pairs_sym(int op, int waves, int rows, const SymArgs& g, hipSt
     if (g.n <= 0) return hipSuccess;
     const SymKernel f = sym_kernel(op, waves, rows);
     if (!f) return hipErrorInvalidValue;
+    if (op == OP_DT) {  // the FP64 maxima of re-evaluated tiles start at zero (a fill kernel: capturable)
+        const int nh = 2 * g.n_pad;
+        hipLaunchKernelGGL(k_symdt_clear, dim3((nh + 255) / 256), dim3(256), 0, st, g.hi, nh);
+    }
     const dim3 grid((unsigned)g.n_blocks * (unsigned)g.n_chunks);
     hipLaunchKernelGGL(f, grid, dim3(64 * waves), 0, st, g);
     return hipGetLastError();
+}
+
+// time-step rates: FP32 row maxima and partials, two components
+size_t symdt_own_bytes(int64_t n, int chunks) {
+    return ((size_t)chunks * 2 * 64 * ((n + 63) / 64) * sizeof(float) + 255) & ~size_t(255);
+}
+// [own | hi (2 n_pad doubles) | part]
+size_t symdt_hi_bytes(int64_t n) { return (size_t)2 * 64 * ((n + 63) / 64) * sizeof(double); }
+size_t symdt_scratch_bytes(int64_t n, int chunks) {
+    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
+    return symdt_own_bytes(n, chunks) + symdt_hi_bytes(n) + (size_t)(nb / 2 + 1) * 2 * 64 * n_tiles * sizeof(float);
 }
 
 // FP64: 4 wavefronts of 4 row tiles for both passes
@@ -883,6 +1199,7 @@ hipError_t launch_sym_reduce(int op, const PairArgs& a, const SymArgs& g, hipStr
     const dim3 grid((g.n + 255) / 256);
     if (op == OP_ACC) hipLaunchKernelGGL(k_sym_reduce<AccMixed>, grid, dim3(256), 0, st, a, g);
     else if (op == OP_GRAD) hipLaunchKernelGGL(k_sym_reduce<GradMixed>, grid, dim3(256), 0, st, a, g);
+    else if (op == OP_DT) hipLaunchKernelGGL(k_symdt_reduce, grid, dim3(256), 0, st, a, g);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

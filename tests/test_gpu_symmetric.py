@@ -271,3 +271,98 @@ def test_symmetric_fp64_parity(ctx, n, op, eps2):
     got = gather(out, np.arange(n))
     assert np.all(np.linalg.norm(got - ref, axis=1) <= 1e-12 * mag)
     assert ctx.read_flags(clear=True) & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
+
+
+# --------------------------------------------------------------------------------------------
+# the time-step pass over one set (each unordered pair once, the set's own order)
+# --------------------------------------------------------------------------------------------
+
+def _dt_both(ctx, Pd, **kw):
+    """The mixed time-step pass twice with the symmetric sweep, then with the directed one."""
+    s1 = ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.15, prec="mixed", **kw)
+    cfg = ctx.last_pass_config()
+    s2 = ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.15, prec="mixed", **kw)
+    try:
+        ctx.set_spatial_sort(forces=True, gradient=True, any_size=True, timestep=False)
+        dr = ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.15, prec="mixed", **kw)
+        assert ctx.last_pass_config()[0] == "unsorted"
+    finally:
+        ctx.set_spatial_sort(forces=True, gradient=True, any_size=True)
+    return s1, s2, dr, cfg
+
+
+@pytest.mark.parametrize("n", [64, 65, 1000, 1100, 17000, 20000])
+def test_symmetric_dt_parity(ctx, n):
+    """Both time-steps of every particle within relative 1e-6 of the oracle; bitwise repeatable
+    and bitwise equal to the directed pass (a pair's FP32 rates do not depend on its orientation
+    and a maximum is exact in any order).  Sizes: one tile (the diagonal only), a ragged second
+    tile, one and two blocks, odd and even block counts with ragged last tiles."""
+    print(f"dt n={n}", flush=True)
+    d = _king(n, 60 + n % 11)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    ff, fb = oracle.dt_min(P, eta_ff=0.2, eta_fb=0.15)
+    s1, s2, dr, cfg = _dt_both(ctx, Pd)
+    assert cfg[:3] == ("symmetric", 2, 8), cfg
+    for x, y, z in zip(s1, s2, dr):
+        assert torch.equal(x, y) and torch.equal(x, z)
+    np.testing.assert_allclose(s1[0].cpu().numpy(), ff, rtol=1e-6)
+    np.testing.assert_allclose(s1[1].cpu().numpy(), fb, rtol=1e-6)
+    assert ctx.read_flags(clear=True) == 0
+
+
+def test_symmetric_dt_close_and_coincident(ctx):
+    """A coincident pair is left out and flagged; a pair 3e-15 apart, whose FP32 free-fall rate
+    overflows, and a pair one FP64 ulp apart send their tiles through the FP64 evaluation: every
+    time-step within relative 1e-6 of the oracle (the close pairs' own time-steps included), in
+    the symmetric and the directed pass; equal velocities give no fly-by bound."""
+    n = 3000
+    d = _king(n, 71)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        d[k][2500] = d[k][10]            # coincident, equal velocities
+        d[k][1700] = d[k][40]
+        d[k][2999] = d[k][900]
+    d["x"][1700] = d["x"][40] + 3e-15    # r^2 = 9e-30: the FP32 free-fall rate overflows
+    d["vx"][1700] += 1e-3
+    d["y"][2999] = np.nextafter(d["y"][900], np.inf)  # one ulp: r^2 below the FP32 range
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    ff, fb = oracle.dt_min(P, eta_ff=0.2, eta_fb=0.15)
+    ctx.read_flags(clear=True)
+    s1, s2, dr, cfg = _dt_both(ctx, Pd)
+    assert cfg[0] == "symmetric"
+    assert ctx.read_flags(clear=True) & bf.BF_FLAG_COINCIDENT
+    for x, y in zip(s1, s2):
+        assert torch.equal(x, y)
+    for out in (s1, dr):
+        np.testing.assert_allclose(out[0].cpu().numpy(), ff, rtol=1e-6)
+        np.testing.assert_allclose(out[1].cpu().numpy(), fb, rtol=1e-6)
+    assert np.all(np.isfinite(ff[[40, 1700, 900, 2999]])) and ff[1700] < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(1, 16), (2, 8), (4, 4)])
+@pytest.mark.parametrize("rounds", [1, 4, 32])
+def test_symmetric_dt_shapes_bitwise(ctx, shape, rounds):
+    """Every shape and share count of the time-step sweep gives bitwise the same maxima."""
+    n = 9000
+    d = _king(n, 73)
+    Pd = _dev(d)
+    ref = ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.15, prec="mixed")
+    rows, waves = shape
+    try:
+        ctx.set_symmetric_config(bf.BF_OP_DTMIN, rows, waves, rounds)
+        got = ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.15, prec="mixed")
+        assert ctx.last_pass_config()[:3] == ("symmetric", rows, waves)
+    finally:
+        ctx.set_symmetric_config(bf.BF_OP_DTMIN, 0, 0, 0)
+    assert all(torch.equal(x, y) for x, y in zip(ref, got))
+
+
+def test_symmetric_dt_fly_by_radius_runs_directed(ctx):
+    """A fly-by radius (r_fb > 0) keeps the directed pass, with its close-pair re-evaluation."""
+    n = 2000
+    d = _king(n, 75)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    ff, fb = oracle.dt_min(P, eta_ff=0.2, eta_fb=0.15)
+    out = ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.15, prec="mixed", r_fb=0.05)
+    assert ctx.last_pass_config()[0] == "unsorted"
+    np.testing.assert_allclose(out[0].cpu().numpy(), ff, rtol=1e-6)
+    np.testing.assert_allclose(out[1].cpu().numpy(), fb, rtol=1e-6)
