@@ -27,15 +27,16 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double v) {
 
 // 1/sqrt(r2) in FP64: the hardware estimate (about 24 correct bits) refined by one third-order
 // step of y (1 - e)^(-1/2) = y (1 + e/2 + 3e^2/8 + ...), e = 1 - r2 y^2 (about 69 bits before
-// rounding); r2 = 0 (a coincident pair at eps = 0) gives 0: the pair is left out
-__device__ __forceinline__ double energy_rsqrt(double r2) {
+// rounding).  r2 = 0 (a coincident pair at eps = 0) gives NaN here ...
+__device__ __forceinline__ double energy_rsqrt_raw(double r2) {
     const double y = __builtin_amdgcn_rsq(r2);
     const double h = r2 * y;
     const double e = __builtin_fma(-h, y, 1.0);
     const double t = __builtin_fma(e, 0.375, 0.5);
-    const double r = __builtin_fma(y * e, t, y);
-    return r2 > 0.0 ? r : 0.0;
+    return __builtin_fma(y * e, t, y);
 }
+// ... and 0 here: the pair is left out
+__device__ __forceinline__ double energy_rsqrt(double r2) { return r2 > 0.0 ? energy_rsqrt_raw(r2) : 0.0; }
 
 // (x, y, z, m) of set position k, packed for the pair kernel
 __global__ __launch_bounds__(256) void k_energy_pack(const EnergyArgs e) {
@@ -116,6 +117,18 @@ __global__ __launch_bounds__(256) void k_energy_pairs(const EnergyArgs e, int nb
                 const double4 o = column(e.pack, j0 + j);
 #pragma unroll
                 for (int r = 0; r < kER; ++r) {
+                    const double dx = o.x - me[r].x, dy = o.y - me[r].y, dz = o.z - me[r].z;
+                    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, e.eps2)));
+                    slice[r] = __builtin_fma(o.w, energy_rsqrt_raw(r2), slice[r]);
+                }
+            }
+            // a coincident pair made the slice NaN: that row's slice again, leaving the pair out
+#pragma unroll
+            for (int r = 0; r < kER; ++r) {
+                if (__builtin_isfinite(slice[r])) continue;
+                slice[r] = 0.0;
+                for (int j = 0; j < 64; ++j) {
+                    const double4 o = column(e.pack, j0 + j);
                     const double dx = o.x - me[r].x, dy = o.y - me[r].y, dz = o.z - me[r].z;
                     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, e.eps2)));
                     slice[r] = __builtin_fma(o.w, energy_rsqrt(r2), slice[r]);
