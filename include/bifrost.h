@@ -484,6 +484,16 @@ BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
  * rows x waves in {1 x 16, 2 x 8, 4 x 4} (BF_ERR_UNSUPPORTED otherwise), rounds of resident
  * workgroups in [0, 64] (0: 32).  rows = 0 restores the tuned or default choice. */
 BF_API int bf_set_symmetric_config(bf_ctx *ctx, int op, int rows, int waves, int rounds);
+/* Scratch limit of a pass that takes a pair-symmetric sweep over one set (its row sums, column
+ * partials and running sums; bytes, 0: the default 32 GiB).  A sweep whose partials exceed it
+ * runs its distance shares in several passes, each adding its partials onto FP64 running sums
+ * per particle (FP32 for the time-step maxima) in the order a single pass uses: the results are
+ * bitwise the same.  The share count grows until one share fits; the smallest pass is one
+ * block distance (16 bytes per particle for the mixed passes). */
+BF_API int bf_set_symmetric_scratch_limit(bf_ctx *ctx, size_t bytes);
+/* Sweeps (passes over the distance shares) of the most recent
+ * pass; 1 when it did not take a pair-symmetric sweep or ran in one. */
+BF_API int bf_last_symmetric_passes(bf_ctx *ctx, int *passes);
 /* Force the shape of the batched pass op at precision prec: targets per lane {1, 2, 4}, waves
  * {4, 8}, sources per work item a positive multiple of 64 * waves up to 2^20.  k = 0 restores the
  * tuned or default choice (2, 4, 4096). */
@@ -505,8 +515,9 @@ BF_API int bf_set_batched_config(bf_ctx *ctx, int op, int prec, int k_per_lane, 
  * sorted pass evaluates every unordered pair once and applies its two equal and opposite terms
  * (Sec. 2.1: the acceleration term of j on i is -m_j/m_i times that of i on j, and so is the
  * force-gradient term): about 0.6 of the arithmetic.  It needs (n / 2048 + 1) * 16 bytes of
- * scratch per particle (8.6 GB at n = 2^20; up to 32 GiB, beyond that the directed sweep
- * runs).  The column sums go through fixed-order partials, so results stay bitwise repeatable.
+ * scratch per particle (8.6 GB at n = 2^20); above the limit of bf_set_symmetric_scratch_limit
+ * (32 GiB) it runs in several passes over its distance shares.  The column sums go through
+ * fixed-order partials, so results stay bitwise repeatable.
  * Bit BF_SORT_DIRECTED in ops_mask keeps the directed sweep for such passes.
  *
  * Bit (1 << BF_OP_DTMIN) (on by default) does the same for the mixed time-step pass over one set

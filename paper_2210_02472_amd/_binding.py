@@ -113,6 +113,8 @@ def load_library(path: str = LIB_PATH):
         "bf_autotune_pass": [_vp, _int, _int, P, S, S, _vp, _vp, _vp, ctypes.c_char_p],
         "bf_autotune_batched": [_vp, _int, _int, P, _i32, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_char_p],
         "bf_set_symmetric_config": [_vp, _int, _int, _int, _int],
+        "bf_set_symmetric_scratch_limit": [_vp, ctypes.c_size_t],
+        "bf_last_symmetric_passes": [_vp, ctypes.POINTER(_int)],
         "bf_query_batched_config": [_vp, _int, _int, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int),
                                     ctypes.POINTER(_int)],
         "bf_set_batched_config": [_vp, _int, _int, _int, _int, _int],
@@ -528,6 +530,17 @@ class Context:
         """Force the pair-symmetric sweep's shape (rows = 0: the tuned or default choice)."""
         _check("bf_set_symmetric_config", _lib.bf_set_symmetric_config(self._h, int(op), int(rows), int(waves),
                                                                        int(rounds)))
+
+    def set_symmetric_scratch_limit(self, nbytes: int = 0):
+        """Scratch limit of a pair-symmetric pass (0: the default); above it the sweep runs its
+        distance shares in several passes, with bitwise the same results."""
+        _check("bf_set_symmetric_scratch_limit", _lib.bf_set_symmetric_scratch_limit(self._h, int(nbytes)))
+
+    def last_symmetric_passes(self) -> int:
+        """Sweeps over the distance shares of the most recent pass (1: one, or not symmetric)."""
+        v = _int(0)
+        _check("bf_last_symmetric_passes", _lib.bf_last_symmetric_passes(self._h, ctypes.byref(v)))
+        return v.value
 
     def query_batched_config(self, op: int, prec: str, max_active_total: int, max_cluster_n: int):
         """(targets per lane, waves, sources per work item) a batched pass of these bounds runs."""

@@ -151,9 +151,16 @@ struct SymArgs {
     float eps2f, kappa;
     int32_t n_chunks;          // the column range of a row block is split into n_chunks shares of
     int32_t chunk_len;         // chunk_len block distances (one set) or column tiles (two sets)
-    float* part;               // one set: [n_blocks / 2 + 1][4][n_pad] column partials per block distance;
-                               // two sets: [n_blocks][4][n_pad] column partials per row block
-    double* own;               // [n_chunks][4][n_row_pad] row sums, one row per share
+    float* part;               // one set: [distances of the pass][4][n_pad] column partials per block
+                               // distance (slot d - d_base); two sets: [n_blocks][4][n_pad] per row block
+    double* own;               // [shares of the pass][4][n_row_pad] row sums, one row per share
+    // One set: the shares run in passes whose partials fit the scratch limit.  This pass covers
+    // shares [chunk0, chunk0 + pass_chunks), distances from d_base = chunk0 chunk_len; acc holds
+    // the running per-particle sums between passes (NULL for a single pass); first / last: this
+    // is the first / last pass.  Two sets: chunk0 = d_base = 0, one pass.
+    int32_t chunk0, pass_chunks, d_base;
+    int32_t first, last;
+    double* acc;
     unsigned long long* tile_stats;  // [near, far] wavefront-tile visits (NULL: not counted)
     // time-step sweep only: the masses and G of the FP64 re-evaluation, the device flags
     // (coincident pairs), the FP64 maxima of re-evaluated tiles [2][n_pad]
@@ -162,9 +169,8 @@ struct SymArgs {
     uint32_t* flags;
     double* hi;
 };
-// bytes of own (256-byte aligned) and of own + part for n particles and `chunks` shares (one set)
+// bytes of own (256-byte aligned) for n rows and `chunks` shares (two sets)
 size_t sym_own_bytes(int64_t n, int chunks);
-size_t sym_scratch_bytes(int64_t n, int chunks);
 // the same for rows of n_rows particles against columns of n_cols (two sets)
 size_t between_scratch_bytes(int64_t n_rows, int64_t n_cols, int chunks);
 // adds the row sums (rows: a_rows.tgt, sorted) and the column partials (columns: a_cols.tgt) in a
@@ -172,21 +178,15 @@ size_t between_scratch_bytes(int64_t n_rows, int64_t n_cols, int chunks);
 hipError_t launch_between_reduce(int op, const PairArgs& a_rows, const PairArgs& a_cols, const SymArgs& g,
                                  hipStream_t st);
 // FP64 one-set sweep: the set in its own order, FP64 pack (launch_pack, FP64) as columns and
-// rows, FP64 row sums [chunks][3][n_pad] and partials [n_blocks/2 + 1][3][n_pad] (part holds
+// rows, FP64 row sums [shares][3][n_pad] and partials [distances][3][n_pad] (part holds
 // doubles), no fix-up
-size_t sym64_scratch_bytes(int64_t n, int chunks);
-size_t sym64_own_bytes(int64_t n, int chunks);
 int sym64_blocks_per_cu(int op);
 hipError_t launch_pairs_sym64(int op, const SymArgs& g, double eps2t, hipStream_t st);
 hipError_t launch_sym_reduce64(int op, const PairArgs& a, const SymArgs& g, hipStream_t st);
 // mixed time-step one-set sweep: the time-step pack (launch_pack, mixed) in the set's own order as
-// columns and rows, FP32 row maxima [chunks][2][n_pad] (own holds floats), FP64 maxima of the
-// tiles evaluated again in FP64 and FP32 partials [n_blocks/2 + 1][2][n_pad]; launched by
+// columns and rows, FP32 row maxima [shares][2][n_pad] (own and acc hold floats), FP64 maxima
+// of the tiles evaluated again in FP64 (hi) and FP32 partials [distances][2][n_pad]; launched by
 // launch_pairs_sym / launch_sym_reduce with op OP_DT
-// [own | hi | part]
-size_t symdt_scratch_bytes(int64_t n, int chunks);
-size_t symdt_own_bytes(int64_t n, int chunks);
-size_t symdt_hi_bytes(int64_t n);
 // resident workgroups per CU of the symmetric kernel of op with a given shape, the default
 // shape, and the launch
 // shapes: W wavefronts of R row tiles each (W R = kSymBlockTiles): (16, 1), (8, 2), (4, 4);
@@ -335,6 +335,8 @@ struct bf_ctx {
     unsigned long long* d_stats = nullptr;  // [fix-ups, near tiles, far tiles] of the last pass, [4]: HHS
                                             // black-hole level mask
     int last_kind = 0, last_k = 0, last_waves = 0, last_split = 0;  // how the last pass ran
+    int last_passes = 1;     // sweeps of the last pair-symmetric pass (its shares in passes)
+    size_t sym_limit = 0;    // scratch limit of a pair-symmetric pass (0: the default)
     // spatially sorted mixed passes: bit op set = use them for that operation when large enough
     int sort_ops = (1 << 0) | (1 << 1) | (1 << 2);  // acceleration, force-gradient and time-step passes
     const int32_t* sub = nullptr;     // subsystem labels applied to acc / grad / dt passes (NULL: none)

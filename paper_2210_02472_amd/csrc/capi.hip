@@ -178,6 +178,60 @@ KernelConfig sym_config(bf_ctx* ctx, int op, int64_t na, int64_t nb) {
     return KernelConfig{sym_default_rows(op), sym_default_waves(op), 0};
 }
 
+// One-set pair-symmetric sweeps run their distance shares in passes whose scratch fits the
+// limit (kSymMaxScratch, or the context's): the share count grows until one share's column
+// partials fit, and a pass takes as many shares as fit beside the running sums.  Scratch of a
+// pass: [row sums of its shares | partials of its distances | running sums (several passes) |
+// FP64 maxima (time-step)].
+struct SymKind {
+    int comps;         // components per particle
+    size_t own_elem;   // bytes of a row sum and of a running sum
+    size_t part_elem;  // bytes of a partial
+    bool hi;           // time-step rates: the FP64 maxima of re-evaluated tiles
+};
+constexpr SymKind kSymMixed{4, sizeof(double), sizeof(float), false};
+constexpr SymKind kSym64{3, sizeof(double), sizeof(double), false};
+constexpr SymKind kSymDt{2, sizeof(float), sizeof(float), true};
+
+struct SymPasses {
+    int chunks = 1, chunk_len = 1, per_pass = 1, passes = 1;
+    size_t own = 0, part = 0, acc = 0, hi = 0;  // region bytes, each a multiple of 256
+    size_t total() const { return own + part + acc + hi; }
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+SymPasses sym_passes(bf_ctx* ctx, int64_t n, int chunks, const SymKind& k) {
+    const int64_t n_tiles = (n + 63) / 64, n_pad = 64 * n_tiles;
+    const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles, D = nb / 2 + 1;
+    const size_t limit = ctx->sym_limit ? ctx->sym_limit : kSymMaxScratch;
+    const size_t per_d = (size_t)k.comps * n_pad * k.part_elem;   // one distance's partials
+    const size_t per_c = (size_t)k.comps * n_pad * k.own_elem;    // one share's row sums
+    const size_t acc = align256((size_t)k.comps * n_pad * k.own_elem);
+    const size_t hi = k.hi ? align256((size_t)2 * n_pad * sizeof(double)) : 0;
+    const size_t fixed = acc + hi + per_c + 512;
+    const int64_t len_max = limit > fixed ? std::max<int64_t>(1, (int64_t)((limit - fixed) / per_d)) : 1;
+    SymPasses sp;
+    int64_t c = std::max<int64_t>(std::max(1, chunks), (D + len_max - 1) / len_max);
+    c = std::min(c, D);
+    sp.chunk_len = (int)((D + c - 1) / c);
+    sp.chunks = (int)((D + sp.chunk_len - 1) / sp.chunk_len);
+    const size_t one = align256(sp.chunks * per_c) + align256(D * per_d) + hi;
+    if (one <= limit) {
+        sp.per_pass = sp.chunks;
+    } else {
+        const size_t per_share = per_c + sp.chunk_len * per_d;
+        sp.per_pass = (int)std::max<int64_t>(1, limit > acc + hi + 512 ? (int64_t)((limit - acc - hi - 512) / per_share) : 1);
+        sp.per_pass = std::min(sp.per_pass, sp.chunks);
+    }
+    sp.passes = (sp.chunks + sp.per_pass - 1) / sp.per_pass;
+    sp.own = align256(sp.per_pass * per_c);
+    sp.part = align256(std::min<int64_t>(D, (int64_t)sp.per_pass * sp.chunk_len) * per_d);
+    sp.acc = sp.passes > 1 ? acc : 0;
+    sp.hi = hi;
+    return sp;
+}
+
 // Default rounds of resident workgroups: 32.  At N = 2^20 the gradient sweep takes 414 ms with
 // 2 rounds (1 share of the distances per row block), 396 ms with 4 (2 shares), 389 ms with 8,
 // 381-383 ms with 16 and 375 ms with 32 (16 shares); the acceleration 254, 246, 244, 240 and
@@ -223,10 +277,8 @@ bool use_symmetric_dt(bf_ctx* ctx, int op, int prec, const bf_set* tg, const bf_
 }
 
 bool use_symmetric(bf_ctx* ctx, int op, bool sorted, const bf_set* tg, const bf_set* sr) {
-    return sorted && !(ctx->sort_ops & BF_SORT_DIRECTED) && same_set(tg, sr) &&
-           sym_scratch_bytes(tg->count,
-                             sym_chunks(ctx, op, tg->count, sym_config(ctx, op, tg->count, tg->count))) <=
-               kSymMaxScratch;
+    (void)ctx; (void)op;
+    return sorted && !(ctx->sort_ops & BF_SORT_DIRECTED) && same_set(tg, sr);
 }
 
 bool use_sorted(bf_ctx* ctx, int op, int prec, int64_t nt, int64_t ns, double r_fb,
@@ -329,33 +381,17 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         return fail(BF_ERR_UNSUPPORTED, "no sorted kernel variant for this configuration");
     bool sym = !arena && use_symmetric(ctx, op, sorted, tg, sr);
     bool symdt = !arena && use_symmetric_dt(ctx, op, prec, tg, sr, r_fb);
-    int sym_shares = 0;
-    const KernelConfig sc = sym || symdt ? sym_config(ctx, op, sr->count, sr->count) : KernelConfig{};
-    if (symdt) {
-        sym_shares = sym_chunks(ctx, op, sr->count, sc);
-        const size_t need = symdt_scratch_bytes(sr->count, sym_shares);
-        if (need > kSymMaxScratch || ensure(&ctx->scratch9, &ctx->scratch9_bytes, need, ctx->stream)) {
-            g_err.clear();
-            symdt = false;
-        }
-    }
-    if (sym) {
-        // the column partials are large (8.6 GB at n = 2^20): without the memory, the directed
-        // sweep runs instead
-        sym_shares = sym_chunks(ctx, op, sr->count, sc);
-        if (ensure(&ctx->scratch9, &ctx->scratch9_bytes, sym_scratch_bytes(sr->count, sym_shares), ctx->stream)) {
-            g_err.clear();
-            sym = false;
-        }
-    }
     bool sym64 = !arena && use_symmetric64(ctx, op, prec, tg, sr);
-    int sym64_shares = 0;
-    if (sym64) {
-        sym64_shares = sym64_chunks(ctx, op, sr->count);
-        const size_t need = sym64_scratch_bytes(sr->count, sym64_shares);
-        if (need > kSymMaxScratch || ensure(&ctx->scratch9, &ctx->scratch9_bytes, need, ctx->stream)) {
+    const KernelConfig sc = sym || symdt ? sym_config(ctx, op, sr->count, sr->count) : KernelConfig{};
+    SymPasses sp;
+    if (sym || symdt || sym64) {
+        // the column partials are large (8.6 GB in one pass at n = 2^20): without the memory,
+        // the directed sweep runs instead
+        const int shares = sym64 ? sym64_chunks(ctx, op, sr->count) : sym_chunks(ctx, op, sr->count, sc);
+        sp = sym_passes(ctx, sr->count, shares, sym64 ? kSym64 : symdt ? kSymDt : kSymMixed);
+        if (ensure(&ctx->scratch9, &ctx->scratch9_bytes, sp.total(), ctx->stream)) {
             g_err.clear();
-            sym64 = false;
+            sym = symdt = sym64 = false;
         }
     }
     // few targets and sources, mixed, unsorted, no exclusion or close-pair re-evaluation, no
@@ -486,7 +522,6 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         BF_HIP(launch_pack_tiles(op, tile_waves, a, ctx->scratch2, ctx->scratch6,
                                  reinterpret_cast<double4*>(static_cast<char*>(ctx->scratch6) + far_bytes), ctx->stream));
         if (sym) {
-            const int chunks = sym_shares;
             g.near_pack = a.pack;
             g.far_pack = a.pack_far;
             g.tile_meta = a.tile_meta;
@@ -498,10 +533,6 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
             g.between = 0;
             g.eps2f = a.eps2f;
             g.kappa = a.kappa;
-            g.n_chunks = chunks;
-            g.chunk_len = (g.n_blocks / 2 + 1 + chunks - 1) / chunks;
-            g.own = static_cast<double*>(ctx->scratch9);
-            g.part = reinterpret_cast<float*>(static_cast<char*>(ctx->scratch9) + sym_own_bytes(ns, chunks));
             g.tile_stats = a.tile_stats;
         }
     } else if (sr->count > 0) {
@@ -515,10 +546,6 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
             g.n_blocks = (int32_t)((ntiles + kSymBlockTiles - 1) / kSymBlockTiles);
             g.n_pad = g.n_row_pad = (int32_t)(64 * ntiles);
             g.between = 0;
-            g.n_chunks = sym64_shares;
-            g.chunk_len = (g.n_blocks / 2 + 1 + sym64_shares - 1) / sym64_shares;
-            g.own = static_cast<double*>(ctx->scratch9);
-            g.part = reinterpret_cast<float*>(static_cast<char*>(ctx->scratch9) + sym64_own_bytes(ns, sym64_shares));
         }
         if (symdt) {  // rows and columns: the time-step pack in the set's order
             const int64_t ns = sr->count, ntiles = (ns + 63) / 64;
@@ -528,17 +555,28 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
             g.n_blocks = (int32_t)((ntiles + kSymBlockTiles - 1) / kSymBlockTiles);
             g.n_pad = g.n_row_pad = (int32_t)(64 * ntiles);
             g.between = 0;
-            g.n_chunks = sym_shares;
-            g.chunk_len = (g.n_blocks / 2 + 1 + sym_shares - 1) / sym_shares;
-            char* base = static_cast<char*>(ctx->scratch9);
-            g.own = reinterpret_cast<double*>(base);  // holds floats
-            g.hi = reinterpret_cast<double*>(base + symdt_own_bytes(ns, sym_shares));
-            g.part = reinterpret_cast<float*>(base + symdt_own_bytes(ns, sym_shares) + symdt_hi_bytes(ns));
             g.m = M.m;
             g.G = G;
             g.flags = ctx->d_flags;
         }
     }
+    if (sym || sym64 || symdt) {  // the shares and the scratch regions of the passes
+        char* base = static_cast<char*>(ctx->scratch9);
+        g.n_chunks = sp.chunks;
+        g.chunk_len = sp.chunk_len;
+        g.own = reinterpret_cast<double*>(base);  // the time-step sweep keeps floats
+        g.part = reinterpret_cast<float*>(base + sp.own);
+        g.acc = sp.acc ? reinterpret_cast<double*>(base + sp.own + sp.part) : nullptr;
+        g.hi = sp.hi ? reinterpret_cast<double*>(base + sp.own + sp.part + sp.acc) : nullptr;
+    }
+    // pass q of the shares
+    auto sym_pass = [&](int q) {
+        g.chunk0 = q * sp.per_pass;
+        g.pass_chunks = std::min(sp.per_pass, sp.chunks - g.chunk0);
+        g.d_base = g.chunk0 * sp.chunk_len;
+        g.first = q == 0;
+        g.last = q == sp.passes - 1;
+    };
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     const bool timed = ctx->timing && !ctx->capturing && !arena;
     if (timed) {
@@ -551,9 +589,18 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         }
         BF_HIP(hipEventRecord(ev.first, ctx->stream));
     }
-    if (sym || symdt) BF_HIP(launch_pairs_sym(op, sc.waves, sc.k, g, ctx->stream));
-    else if (sym64) BF_HIP(launch_pairs_sym64(op, g, eps2 + 1e-150 /* the FP64 kernels' tiny */, ctx->stream));
-    else if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
+    if (sym || symdt || sym64) {
+        // every pass but the last adds its partials onto the running sums between the sweeps
+        for (int q = 0; q < sp.passes; ++q) {
+            sym_pass(q);
+            if (sym64) BF_HIP(launch_pairs_sym64(op, g, eps2 + 1e-150 /* the FP64 kernels' tiny */, ctx->stream));
+            else BF_HIP(launch_pairs_sym(op, sc.waves, sc.k, g, ctx->stream));
+            if (q + 1 < sp.passes) {
+                if (sym64) BF_HIP(launch_sym_reduce64(op, a, g, ctx->stream));
+                else BF_HIP(launch_sym_reduce(op, a, g, ctx->stream));
+            }
+        }
+    } else if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
     else if (small) BF_HIP(launch_pairs_small(op, a, ctx->stream));
     else BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
     // credit: every (target, source) pair, less the self-pairs when targets and sources are one set
@@ -562,6 +609,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     ctx->last_k = sym || symdt ? sc.k : sym64 ? 4 : small ? 1 : p.cfg.k;
     ctx->last_waves = sym || symdt ? sc.waves : sym64 ? 4 : small ? 16 : p.cfg.waves;
     ctx->last_split = sym || sym64 || symdt ? g.n_chunks : p.split;
+    ctx->last_passes = sym || sym64 || symdt ? sp.passes : 1;
     if (timed) {
         BF_HIP(hipEventRecord(ev.second, ctx->stream));
         ctx->tev[op].push_back(ev);
@@ -2279,6 +2327,19 @@ BF_API int bf_set_symmetric_config(bf_ctx* c, int op, int rows, int waves, int r
     if (!sym_variant_exists(op, waves, rows)) return fail(BF_ERR_UNSUPPORTED, "no such symmetric shape");
     if (rounds < 0 || rounds > 64) return fail(BF_ERR_ARG, "rounds must be in [0, 64]");
     c->sym_forced[op] = KernelConfig{rows, waves, rounds};
+    return BF_OK;
+}
+
+BF_API int bf_set_symmetric_scratch_limit(bf_ctx* c, size_t bytes) {
+    if (int rc = check_ctx(c)) return rc;
+    c->sym_limit = bytes;
+    return BF_OK;
+}
+
+BF_API int bf_last_symmetric_passes(bf_ctx* c, int* passes) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!passes) return fail(BF_ERR_ARG, "passes NULL");
+    *passes = c->last_passes;
     return BF_OK;
 }
 

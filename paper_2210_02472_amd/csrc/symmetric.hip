@@ -360,7 +360,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // workgroup (chunk, block): block wg's rows against its share [d0, d1) of the distances (one
     // set) or of the column tiles (two sets)
-    const int wg = blockIdx.x % g.n_blocks, chunk = blockIdx.x / g.n_blocks;
+    const int wg = blockIdx.x % g.n_blocks, chunk = g.chunk0 + (int)(blockIdx.x / g.n_blocks);
     const int d0 = chunk * g.chunk_len, d1 = d0 + g.chunk_len;
     const int rbase = wg * (W * R) + wave * R;
     typename S::Row row[R];
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
             for (int v = 0; v < W; ++v) s += (double)xch[buf][v][q][k];
             const int col = ct * 64 + k;
             // the column term carries the opposite sign (the estimate M does not)
-            if (col < g.n) g.part[((size_t)cur.d * 4 + q) * g.n_pad + col] = (float)(q < 3 ? -s : s);
+            if (col < g.n) g.part[((size_t)(cur.d - g.d_base) * 4 + q) * g.n_pad + col] = (float)(q < 3 ? -s : s);
         }
         cur = pre;
         pre.next(g, wg);
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (tile_live[r] && rs[r] < g.n_rows) {
-            double* o = g.own + (size_t)chunk * 4 * g.n_row_pad;  // every chunk writes its row sums
+            double* o = g.own + (size_t)(chunk - g.chunk0) * 4 * g.n_row_pad;  // every chunk writes its row sums
             o[rs[r]] = own[r].x;
             o[(size_t)g.n_row_pad + rs[r]] = own[r].y;
             o[(size_t)2 * g.n_row_pad + rs[r]] = own[r].z;
@@ -486,25 +486,55 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
     }
 }
 
+// Adds, per particle, the shares of this pass in order, each share's row sum and then its
+// distances' column partials, onto the running sum of the earlier passes (g.acc); the last pass
+// writes the result.  One pass or several: the same additions in the same order.
+// (row sums of type TO, partials of type TP)
+template <int NC, class TO, class TP, class V>
+__device__ __forceinline__ void sym_gather(const SymArgs& g, int s, V (&v)[NC], bool mx) {
+    const int b = (s >> 6) / kSymBlockTiles;
+    const int nb = g.n_blocks, D = nb / 2;
+    const TO* own = reinterpret_cast<const TO*>(g.own);
+    const TP* part = reinterpret_cast<const TP*>(g.part);
+    for (int c = g.chunk0; c < g.chunk0 + g.pass_chunks; ++c) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const V x = (V)own[((size_t)(c - g.chunk0) * NC + q) * g.n_row_pad + s];
+            v[q] = mx ? fmax(v[q], x) : v[q] + x;
+        }
+        const int e = min(D + 1, (c + 1) * g.chunk_len);
+        for (int d = c * g.chunk_len; d < e; ++d) {
+            if (d > 0 && 2 * d == nb && b < d) continue;  // no partial: this block pair was swept from here
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+                const V x = (V)part[((size_t)(d - g.d_base) * NC + q) * g.n_pad + s];
+                v[q] = mx ? fmax(v[q], x) : v[q] + x;
+            }
+        }
+    }
+}
+
+// the running sums of the passes before (zero for the first) and after (stored unless last)
+template <int NC, class V>
+__device__ __forceinline__ void sym_acc_load(const SymArgs& g, int s, V (&v)[NC]) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) v[q] = g.first ? (V)0 : reinterpret_cast<const V*>(g.acc)[(size_t)q * g.n_pad + s];
+}
+template <int NC, class V>
+__device__ __forceinline__ void sym_acc_store(const SymArgs& g, int s, const V (&v)[NC]) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) reinterpret_cast<V*>(g.acc)[(size_t)q * g.n_pad + s] = v[q];
+}
+
 template <class Op>
 __global__ __launch_bounds__(256) void k_sym_reduce(const PairArgs a, const SymArgs g) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= g.n) return;
-    const int b = (s >> 6) / kSymBlockTiles;
-    const int nb = g.n_blocks, D = nb / 2;
     double v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = 0.0;
-    for (int c = 0; c < g.n_chunks; ++c) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += g.own[((size_t)c * 4 + q) * g.n_row_pad + s];
-    }
-    for (int d = 0; d <= D; ++d) {
-        if (d > 0 && 2 * d == nb && b < d) continue;  // no partial: this block pair was swept from here
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += (double)g.part[((size_t)d * 4 + q) * g.n_pad + s];
-    }
-    write_result<Op>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), v);
+    sym_acc_load<4>(g, s, v);
+    sym_gather<4, double, float>(g, s, v, false);
+    if (g.last) write_result<Op>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), v);
+    else sym_acc_store<4>(g, s, v);
 }
 
 // ---- FP64 -----------------------------------------------------------------------------------
@@ -604,7 +634,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym64(const SymArgs g, double 
     __shared__ uint4 colbuf[2][NPL * kPlaneLen];
     __shared__ double xch[2][W][3][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wg = blockIdx.x % g.n_blocks, chunk = blockIdx.x / g.n_blocks;
+    const int wg = blockIdx.x % g.n_blocks, chunk = g.chunk0 + (int)(blockIdx.x / g.n_blocks);
     const int d0 = chunk * g.chunk_len, d1 = d0 + g.chunk_len;
     const int rbase = wg * (W * R) + wave * R;
     typename S::Row row[R];
@@ -705,7 +735,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym64(const SymArgs g, double 
 #pragma unroll
             for (int v = 0; v < W; ++v) s += xch[buf][v][q][k];
             const int col = ct * 64 + k;
-            if (col < g.n) reinterpret_cast<double*>(g.part)[((size_t)cur.d * 3 + q) * g.n_pad + col] = -s;
+            if (col < g.n) reinterpret_cast<double*>(g.part)[((size_t)(cur.d - g.d_base) * 3 + q) * g.n_pad + col] = -s;
         }
         cur = pre;
         pre.next(g, wg);
@@ -721,7 +751,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym64(const SymArgs g, double 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (tile_live[r] && rs[r] < g.n_rows) {
-            double* o = g.own + (size_t)chunk * 3 * g.n_row_pad;
+            double* o = g.own + (size_t)(chunk - g.chunk0) * 3 * g.n_row_pad;
 #pragma unroll
             for (int q = 0; q < 3; ++q) o[(size_t)q * g.n_row_pad + rs[r]] = own[r][q];
         }
@@ -732,20 +762,11 @@ template <class Op>
 __global__ __launch_bounds__(256) void k_sym_reduce64(const PairArgs a, const SymArgs g) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= g.n) return;
-    const int b = (s >> 6) / kSymBlockTiles;
-    const int nb = g.n_blocks, D = nb / 2;
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int c = 0; c < g.n_chunks; ++c) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) v[q] += g.own[((size_t)c * 3 + q) * g.n_row_pad + s];
-    }
-    const double* part = reinterpret_cast<const double*>(g.part);
-    for (int d = 0; d <= D; ++d) {
-        if (d > 0 && 2 * d == nb && b < d) continue;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) v[q] += part[((size_t)d * 3 + q) * g.n_pad + s];
-    }
-    write_result<Op>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), v);
+    double v[3];
+    sym_acc_load<3>(g, s, v);
+    sym_gather<3, double, double>(g, s, v, false);
+    if (g.last) write_result<Op>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), v);
+    else sym_acc_store<3>(g, s, v);
 }
 
 // Two sets: threads [0, n_rows) finish the rows (sums over the shares), threads [n_rows,
@@ -894,7 +915,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_symdt(const SymArgs g) {
     __shared__ uint4 colbuf[2][NPL * kPlaneLen];
     __shared__ float xch[2][W][2][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wg = blockIdx.x % g.n_blocks, chunk = blockIdx.x / g.n_blocks;
+    const int wg = blockIdx.x % g.n_blocks, chunk = g.chunk0 + (int)(blockIdx.x / g.n_blocks);
     const int d0 = chunk * g.chunk_len, d1 = d0 + g.chunk_len;
     const int rbase = wg * (W * R) + wave * R;
     DtRow row[R];
@@ -1016,7 +1037,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_symdt(const SymArgs g) {
 #pragma unroll
             for (int v = 0; v < W; ++v) s = fmaxf(s, xch[buf][v][q][k]);
             const int col = ct * 64 + k;
-            if (col < g.n) g.part[((size_t)cur.d * 2 + q) * g.n_pad + col] = s;
+            if (col < g.n) g.part[((size_t)(cur.d - g.d_base) * 2 + q) * g.n_pad + col] = s;
         }
         cur = pre;
         pre.next(g, wg);
@@ -1029,7 +1050,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_symdt(const SymArgs g) {
             }
         }
     }
-    float* o = reinterpret_cast<float*>(g.own) + (size_t)chunk * 2 * g.n_row_pad;
+    float* o = reinterpret_cast<float*>(g.own) + (size_t)(chunk - g.chunk0) * 2 * g.n_row_pad;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (rok[r]) {
@@ -1047,23 +1068,16 @@ __global__ __launch_bounds__(256) void k_symdt_clear(double* hi, int n) {
 __global__ __launch_bounds__(256) void k_symdt_reduce(const PairArgs a, const SymArgs g) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= g.n) return;
-    const int b = (s >> 6) / kSymBlockTiles;
-    const int nb = g.n_blocks, D = nb / 2;
-    const float* own = reinterpret_cast<const float*>(g.own);
-    float v[2] = {0.f, 0.f};
-    for (int c = 0; c < g.n_chunks; ++c) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) v[q] = fmaxf(v[q], own[((size_t)c * 2 + q) * g.n_row_pad + s]);
-    }
-    for (int d = 0; d <= D; ++d) {
-        if (d > 0 && 2 * d == nb && b < d) continue;  // no partial: this block pair was swept from here
-#pragma unroll
-        for (int q = 0; q < 2; ++q) v[q] = fmaxf(v[q], g.part[((size_t)d * 2 + q) * g.n_pad + s]);
+    float v[2];
+    sym_acc_load<2>(g, s, v);
+    sym_gather<2, float, float>(g, s, v, true);
+    if (!g.last) {
+        sym_acc_store<2>(g, s, v);
+        return;
     }
     const double w[2] = {fmax((double)v[0], g.hi[s]), fmax((double)v[1], g.hi[g.n_pad + s])};
     write_result<DtMixed>(a, s, particle_of(a.tgt, s, a.P.n, a.flags), w);
 }
-
 }  // namespace
 
 size_t between_scratch_bytes(int64_t n_rows, int64_t n_cols, int chunks) {
@@ -1086,11 +1100,6 @@ size_t sym_own_bytes(int64_t n, int chunks) {
     return ((size_t)chunks * 4 * 64 * ((n + 63) / 64) * sizeof(double) + 255) & ~size_t(255);
 }
 
-size_t sym_scratch_bytes(int64_t n, int chunks) {
-    const int64_t n_tiles = (n + 63) / 64;
-    const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
-    return sym_own_bytes(n, chunks) + (size_t)(nb / 2 + 1) * 4 * 64 * n_tiles * sizeof(float);
-}
 
 // Launch shapes.  Defaults, measured at N = 2^20: 8 wavefronts of 2 row tiles for the
 // acceleration, 4 of 4 for the gradient (more row tiles per lane share each column read and
@@ -1133,39 +1142,18 @@ hipError_t launch_pairs_sym(int op, int waves, int rows, const SymArgs& g, hipSt
     if (g.n <= 0) return hipSuccess;
     const SymKernel f = sym_kernel(op, waves, rows);
     if (!f) return hipErrorInvalidValue;
-    if (op == OP_DT) {  // the FP64 maxima of re-evaluated tiles start at zero (a fill kernel: capturable)
+    if (op == OP_DT && g.first) {  // the FP64 maxima of re-evaluated tiles start at zero (a fill kernel: capturable)
         const int nh = 2 * g.n_pad;
         hipLaunchKernelGGL(k_symdt_clear, dim3((nh + 255) / 256), dim3(256), 0, st, g.hi, nh);
     }
-    const dim3 grid((unsigned)g.n_blocks * (unsigned)g.n_chunks);
+    const dim3 grid((unsigned)g.n_blocks * (unsigned)(g.between ? g.n_chunks : g.pass_chunks));
     hipLaunchKernelGGL(f, grid, dim3(64 * waves), 0, st, g);
     return hipGetLastError();
-}
-
-// time-step rates: FP32 row maxima and partials, two components
-size_t symdt_own_bytes(int64_t n, int chunks) {
-    return ((size_t)chunks * 2 * 64 * ((n + 63) / 64) * sizeof(float) + 255) & ~size_t(255);
-}
-// [own | hi (2 n_pad doubles) | part]
-size_t symdt_hi_bytes(int64_t n) { return (size_t)2 * 64 * ((n + 63) / 64) * sizeof(double); }
-size_t symdt_scratch_bytes(int64_t n, int chunks) {
-    const int64_t n_tiles = (n + 63) / 64;
-    const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
-    return symdt_own_bytes(n, chunks) + symdt_hi_bytes(n) + (size_t)(nb / 2 + 1) * 2 * 64 * n_tiles * sizeof(float);
 }
 
 // FP64: 4 wavefronts of 4 row tiles for both passes
 constexpr int kSym64Waves = 4, kSym64Rows = 4;
 
-size_t sym64_scratch_bytes(int64_t n, int chunks) {
-    const int64_t n_tiles = (n + 63) / 64;
-    const int64_t nb = (n_tiles + kSymBlockTiles - 1) / kSymBlockTiles;
-    const size_t own = ((size_t)chunks * 3 * 64 * n_tiles * sizeof(double) + 255) & ~size_t(255);
-    return own + (size_t)(nb / 2 + 1) * 3 * 64 * n_tiles * sizeof(double);
-}
-size_t sym64_own_bytes(int64_t n, int chunks) {
-    return ((size_t)chunks * 3 * 64 * ((n + 63) / 64) * sizeof(double) + 255) & ~size_t(255);
-}
 int sym64_blocks_per_cu(int op) {
     const void* f = op == OP_ACC ? reinterpret_cast<const void*>(k_pairs_sym64<Sym64Acc, kSym64Waves, kSym64Rows>)
                                  : reinterpret_cast<const void*>(k_pairs_sym64<Sym64Grad, kSym64Waves, kSym64Rows>);
@@ -1176,7 +1164,7 @@ int sym64_blocks_per_cu(int op) {
 
 hipError_t launch_pairs_sym64(int op, const SymArgs& g, double eps2t, hipStream_t st) {
     if (g.n <= 0) return hipSuccess;
-    const dim3 grid((unsigned)g.n_blocks * (unsigned)g.n_chunks);
+    const dim3 grid((unsigned)g.n_blocks * (unsigned)g.pass_chunks);
     if (op == OP_ACC)
         hipLaunchKernelGGL((k_pairs_sym64<Sym64Acc, kSym64Waves, kSym64Rows>), grid, dim3(64 * kSym64Waves), 0, st, g, eps2t);
     else if (op == OP_GRAD)

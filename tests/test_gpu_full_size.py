@@ -52,6 +52,21 @@ def test_king_2e20_sweep_sampled(ctx):
     g = ctx.force_gradient(Pd, [torch.as_tensor(np.ascontiguousarray(af[:, k]), device="cuda") for k in range(3)],
                            prec="mixed", r_fb=0.0)
     _check_mixed(gather(g, T), oracle.gradient(P, af, T, None))
+    # the time-step pass over the whole set (pair-symmetric), sampled
+    ff, fb = ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.2, prec="mixed")
+    assert ctx.last_pass_config()[0] == "symmetric"
+    rff, rfb = oracle.dt_min(P, T, None, eta_ff=0.2, eta_fb=0.2)
+    np.testing.assert_allclose(ff.cpu().numpy()[T], rff, rtol=1e-6)
+    np.testing.assert_allclose(fb.cpu().numpy()[T], rfb, rtol=1e-6)
+    # a 4 GiB scratch limit: the acceleration sweep's 16 shares of 33 block distances in passes
+    try:
+        ctx.set_symmetric_scratch_limit(4 << 30)
+        a2 = ctx.forces(Pd, prec="mixed", r_fb=0.0)
+        passes = ctx.last_symmetric_passes()
+    finally:
+        ctx.set_symmetric_scratch_limit(0)
+    assert passes >= 2, passes
+    assert all(torch.equal(x, y) for x, y in zip(a, a2))
     assert ctx.read_flags() == 0
 
 

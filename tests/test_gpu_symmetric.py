@@ -366,3 +366,37 @@ def test_symmetric_dt_fly_by_radius_runs_directed(ctx):
     assert ctx.last_pass_config()[0] == "unsorted"
     np.testing.assert_allclose(out[0].cpu().numpy(), ff, rtol=1e-6)
     np.testing.assert_allclose(out[1].cpu().numpy(), fb, rtol=1e-6)
+
+
+# --------------------------------------------------------------------------------------------
+# sweeps in several passes over the distance shares (a scratch limit below one pass)
+# --------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("op", ["forces", "gradient", "fp64", "dt"])
+def test_symmetric_passes_bitwise(ctx, op):
+    """A scratch limit below one sweep's partials splits its distance shares over several
+    passes, each adding onto running sums in the order of a single pass: bitwise the same
+    results (20,000 bodies: 20 blocks, 11 block distances, one share each)."""
+    n = 20000
+    d = _king(n, 80)
+    Pd = _dev(d)
+    a = oracle.forces(oracle.Particles.from_dict(d))
+    acc = [torch.as_tensor(np.ascontiguousarray(a[:, k]), device="cuda") for k in range(3)]
+    run = {
+        "forces": lambda: ctx.forces(Pd, prec="mixed"),
+        "gradient": lambda: ctx.force_gradient(Pd, acc, prec="mixed"),
+        "fp64": lambda: ctx.forces(Pd, prec="fp64"),
+        "dt": lambda: ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.15, prec="mixed"),
+    }[op]
+    ref = run()
+    assert ctx.last_pass_config()[0] == "symmetric" and ctx.last_symmetric_passes() == 1
+    try:
+        ctx.set_symmetric_scratch_limit(3 << 20)
+        got = run()
+        kind, passes = ctx.last_pass_config()[0], ctx.last_symmetric_passes()
+    finally:
+        ctx.set_symmetric_scratch_limit(0)
+    print(f"{op}: {passes} passes", flush=True)
+    assert kind == "symmetric" and passes >= 2, (kind, passes)
+    assert all(torch.equal(x, y) for x, y in zip(ref, got))
+    assert ctx.read_flags(clear=True) & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
