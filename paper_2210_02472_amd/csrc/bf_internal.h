@@ -265,9 +265,9 @@ struct PnArgs {
     const int32_t* bh;
     int32_t nbh;
     double G, c2inv;
-    double* part;        // [nbh][nchunk][3] partial sums of BH targets over all sources
+    double* part;        // [nbh][nchunk][4] partial sums of BH targets over all sources, BH-is-source record
     int32_t nchunk, chunk;
-    int32_t* bh_in_src;  // [nbh] 1 if bh[k] is a source
+    int32_t* bh_in_src;  // [nbh] 1 if bh[k] is a source (lists of more than 4096 BHs)
     double *o0, *o1, *o2;
     uint32_t* flags;
 };

@@ -1128,7 +1128,7 @@ static int pn1_impl(bf_ctx* c, const Masters& M, const bf_set* t, const bf_set* 
     a.o0 = o0; a.o1 = o1; a.o2 = o2;
     a.flags = c->d_flags;
     if (nbh > 0) {
-        const size_t part_bytes = (size_t)nbh * a.nchunk * 3 * sizeof(double);
+        const size_t part_bytes = (size_t)nbh * a.nchunk * 4 * sizeof(double);
         const size_t need = part_bytes + (size_t)nbh * sizeof(int32_t) + 256;
         if (int rc = ensure(&c->scratch, &c->scratch_bytes, need, c->stream)) return rc;
         a.part = static_cast<double*>(c->scratch);

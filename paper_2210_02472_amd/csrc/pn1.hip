@@ -1,13 +1,18 @@
 // Global PN1.0 acceleration for pairs that involve a flagged massive particle (black hole),
 // in FP64.  The pair set is {(i, j): i target, j source, j != i, i or j in the BH list}.
-//  * k_pn_flags:    which BHs are sources (range test, or a scan of the source list);
 //  * k_pn_bh_sums:  for every BH b and source chunk, a workgroup sums the PN1.0 acceleration
-//                   of b from all sources of the chunk (fixed-order LDS tree) -> partials;
-//  * k_pn_targets:  per target: a BH target adds its partials in chunk order, any other
-//                   target sums over the BH sources directly.
-#include "bf_internal.h"
+//                   of b from all sources of the chunk (fixed-order LDS tree) -> partials, and
+//                   records whether b is one of the chunk's sources;
+//  * k_pn_targets:  which BHs are sources (a range test, or those records), then per target: a
+//                   BH target adds its partials in chunk order, any other target sums over the
+//                   BH sources directly.
+// Two launches per pass.  Lists of more than kPnInLds BHs take two more (k_pn_clear and
+// k_pn_flags mark the BH sources in memory).
+#include "pair_ops.h"
 
 namespace bf {
+
+constexpr int kPnInLds = 4096;
 
 __device__ __forceinline__ int32_t pn_particle(const DevSet& s, int32_t k, int64_t n, uint32_t* flags) {
     if (s.idx == nullptr) return s.begin + k;
@@ -30,8 +35,7 @@ __device__ __forceinline__ void pn_pair(const Masters& P, int i, int j, double G
         atomicOr(flags, BF_FLAG_COINCIDENT);
         return;
     }
-    const double r = sqrt(r2);
-    const double ir = 1.0 / r;
+    const double ir = rsqrt64(r2);
     const double nx = rx * ir, ny = ry * ir, nz = rz * ir;
     const double vix = P.vx[i], viy = P.vy[i], viz = P.vz[i];
     const double vjx = P.vx[j], vjy = P.vy[j], vjz = P.vz[j];
@@ -68,7 +72,8 @@ __global__ __launch_bounds__(256) void k_pn_clear(int32_t* v, int n) {
     if (q < n) v[q] = 0;
 }
 
-// grid (nchunk, nbh); 256 threads
+// grid (nchunk, nbh); 256 threads.  part: [nbh][nchunk][4], the fourth value 1 when b is one of
+// the chunk's sources
 __global__ __launch_bounds__(256) void k_pn_bh_sums(const PnArgs a) {
     __shared__ double red[3][256];
     const int kb = blockIdx.y;
@@ -78,13 +83,17 @@ __global__ __launch_bounds__(256) void k_pn_bh_sums(const PnArgs a) {
     const int q0 = c * a.chunk;
     const int q1 = min(a.src.count, q0 + a.chunk);
     double sx = 0.0, sy = 0.0, sz = 0.0;
+    int found = 0;
     for (int q = q0 + threadIdx.x; q < q1; q += 256) {
         const int j = pn_particle(a.src, q, a.P.n, a.flags);
-        if (j == b) continue;
+        if (j == b) {
+            found = 1;
+            continue;
+        }
         pn_pair(a.P, b, j, a.G, a.c2inv, sx, sy, sz, a.flags);
     }
     red[0][threadIdx.x] = sx; red[1][threadIdx.x] = sy; red[2][threadIdx.x] = sz;
-    __syncthreads();
+    found = __syncthreads_or(found);
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             red[0][threadIdx.x] += red[0][threadIdx.x + s];
@@ -94,12 +103,27 @@ __global__ __launch_bounds__(256) void k_pn_bh_sums(const PnArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double* o = a.part + ((size_t)kb * a.nchunk + c) * 3;
-        o[0] = red[0][0]; o[1] = red[1][0]; o[2] = red[2][0];
+        double* o = a.part + ((size_t)kb * a.nchunk + c) * 4;
+        o[0] = red[0][0]; o[1] = red[1][0]; o[2] = red[2][0]; o[3] = found ? 1.0 : 0.0;
     }
 }
 
 __global__ __launch_bounds__(256) void k_pn_targets(const PnArgs a) {
+    __shared__ int in_src[kPnInLds];  // which BHs are sources (lists of up to kPnInLds BHs)
+    const bool lds = a.nbh <= kPnInLds;
+    if (lds) {
+        for (int kb = threadIdx.x; kb < a.nbh; kb += 256) {
+            int v = 0;
+            if (a.src.idx == nullptr) {
+                const int b = a.bh[kb];
+                v = b >= a.src.begin && b < a.src.begin + a.src.count;
+            } else {
+                for (int c = 0; c < a.nchunk; ++c) v |= a.part[((size_t)kb * a.nchunk + c) * 4 + 3] != 0.0;
+            }
+            in_src[kb] = v;
+        }
+        __syncthreads();
+    }
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.tgt.count) return;
     const int i = pn_particle(a.tgt, k, a.P.n, a.flags);
@@ -109,12 +133,12 @@ __global__ __launch_bounds__(256) void k_pn_targets(const PnArgs a) {
     double sx = 0.0, sy = 0.0, sz = 0.0;
     if (self >= 0) {
         for (int c = 0; c < a.nchunk; ++c) {
-            const double* o = a.part + ((size_t)self * a.nchunk + c) * 3;
+            const double* o = a.part + ((size_t)self * a.nchunk + c) * 4;
             sx += o[0]; sy += o[1]; sz += o[2];
         }
     } else {
         for (int kb = 0; kb < a.nbh; ++kb) {
-            if (!a.bh_in_src[kb]) continue;
+            if (!(lds ? in_src[kb] : a.bh_in_src[kb])) continue;
             int j = a.bh[kb];
             if (j < 0 || j >= a.P.n) continue;  // flagged by k_pn_bh_sums
             pn_pair(a.P, i, j, a.G, a.c2inv, sx, sy, sz, a.flags);
@@ -128,12 +152,14 @@ __global__ __launch_bounds__(256) void k_pn_targets(const PnArgs a) {
 hipError_t launch_pn1(const PnArgs& a, hipStream_t st) {
     if (a.tgt.count <= 0) return hipSuccess;
     if (a.nbh > 0) {
-        if (a.src.idx != nullptr) {
-            hipLaunchKernelGGL(k_pn_clear, dim3((a.nbh + 255) / 256), dim3(256), 0, st, a.bh_in_src, a.nbh);
-            if (a.src.count > 0)
-                hipLaunchKernelGGL(k_pn_flags, dim3((a.src.count + 255) / 256), dim3(256), 0, st, a);
-        } else {
-            hipLaunchKernelGGL(k_pn_flags, dim3((a.nbh + 255) / 256), dim3(256), 0, st, a);
+        if (a.nbh > kPnInLds) {
+            if (a.src.idx != nullptr) {
+                hipLaunchKernelGGL(k_pn_clear, dim3((a.nbh + 255) / 256), dim3(256), 0, st, a.bh_in_src, a.nbh);
+                if (a.src.count > 0)
+                    hipLaunchKernelGGL(k_pn_flags, dim3((a.src.count + 255) / 256), dim3(256), 0, st, a);
+            } else {
+                hipLaunchKernelGGL(k_pn_flags, dim3((a.nbh + 255) / 256), dim3(256), 0, st, a);
+            }
         }
         hipLaunchKernelGGL(k_pn_bh_sums, dim3(a.nchunk, a.nbh), dim3(256), 0, st, a);
     }
