@@ -82,7 +82,7 @@ constexpr int kPlaneLen = 128;
 // ---- the acceleration ----------------------------------------------------------------------
 // planes: 0 far (x - cx, y - cy, z - cz, G m) FP32; 1 near (x, y) FP64; 2 near (z, [G m]) FP64
 struct SymAcc {
-    static constexpr int kS = 1, kMeta = 1, kPlanes = 3, kRedNear = 4, kRedFar = 3;
+    static constexpr int kS = 1, kMeta = 1, kPlanes = 3, kFarPlanes = 1, kRedNear = 4, kRedFar = 3;
     static constexpr bool kAcc = true;
     struct Row { double x, y, z; float gm; };
     struct Rel { float x, y, z; };
@@ -142,7 +142,7 @@ struct SymAcc {
 // planes: 0 far position offsets + G m, 1 far acceleration offsets (FP32); 2 near (x, y),
 // 3 near (z, [G m]), 4 near (ax, ay), 5 near (az, 0) (FP64)
 struct SymGrad {
-    static constexpr int kS = 2, kMeta = 2, kPlanes = 6, kRedNear = 4, kRedFar = 4;
+    static constexpr int kS = 2, kMeta = 2, kPlanes = 6, kFarPlanes = 2, kRedNear = 4, kRedFar = 4;
     static constexpr bool kAcc = false;
     struct Row { double x, y, z, ax, ay, az; float gm; };
     struct Rel { float x, y, z, ax, ay, az; };
@@ -251,6 +251,21 @@ enum { kSkip = 0, kDiag = 1, kFull = 2 };
 // pair (lane, column (lane + k) mod 64) counts for a row in `mode`
 __device__ __forceinline__ bool counts(int mode, int lane, int k) {
     return mode == kFull || (mode == kDiag && k > 0 && lane + k < 64);
+}
+
+// Is column tile ct near the box [lo, hi] (gap below kappa times the tile's half-extent)?
+template <class S>
+__device__ __forceinline__ bool tile_near(const SymArgs& g, int ct, const float (&lo)[3], const float (&hi)[3]) {
+    const double4 c = load_uniform4d(g.tile_meta, S::kMeta * ct);
+    const float h = __builtin_bit_cast(float2, c.w).x;
+    const float cc[3] = {(float)c.x, (float)c.y, (float)c.z};
+    float gap2 = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float gg = fmaxf(0.f, fmaxf(cc[d] - h - hi[d], lo[d] - (cc[d] + h)));
+        gap2 = __builtin_fmaf(gg, gg, gap2);
+    }
+    return gap2 < (g.kappa * h) * (g.kappa * h);
 }
 
 // One column tile for the R row particles of each lane: row terms into own[r]; the column sums
@@ -389,6 +404,31 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
 #pragma unroll
     for (int r = 0; r < R; ++r) own[r] = P64{0.0, 0.0, 0.0, 0.0};
     unsigned n_near = 0, n_far = 0;
+    // The workgroup's box (the union of its wavefronts' boxes): a column tile far from it is far
+    // from every wavefront, which then read only its FP32 planes; the FP64 planes are staged only
+    // when some wavefront may take the near path.  A workgroup with dead row tiles (the ragged last
+    // block) masks, and so reads the FP64 planes, on every tile.
+    __shared__ float wbox[W][6];
+    __shared__ float ubox[6];
+    if (lane == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { wbox[wave][d] = lo[d]; wbox[wave][3 + d] = hi[d]; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int q = threadIdx.x;
+        float u = wbox[0][q];
+        for (int v = 1; v < W; ++v) u = q < 3 ? fminf(u, wbox[v][q]) : fmaxf(u, wbox[v][q]);
+        ubox[q] = u;
+    }
+    __syncthreads();
+    const bool all_near = (wg + 1) * (W * R) > g.n_row_tiles;
+    // FP64 planes needed for the visit of column tile ct at distance d (one set: the own block masks)
+    auto wants_near = [&](const TileWalk& t) {
+        if (all_near || (!g.between && t.d == 0)) return true;
+        const float ulo[3] = {ubox[0], ubox[1], ubox[2]}, uhi[3] = {ubox[3], ubox[4], ubox[5]};
+        return tile_near<S>(g, t.ct, ulo, uhi);
+    };
 
     // staging: element k of plane p is copied (twice) by thread 64 p' + k, p = p' + W u
     constexpr int SPT = (NPL + W - 1) / W;  // planes per staging thread
@@ -405,18 +445,20 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
     cur.next(g, wg);
     pre = cur;
     pre.next(g, wg);
+    const bool cur_near = cur.ct >= 0 && wants_near(cur);
+    bool pre_near = pre.ct >= 0 && wants_near(pre);
     uint4 held[SPT];
 #pragma unroll
     for (int u = 0; u < SPT; ++u) {
         const int pl = wave + W * u;
-        if (pl < NPL && cur.ct >= 0) {
+        if (pl < NPL && cur.ct >= 0 && (pl < S::kFarPlanes || cur_near)) {
             const int s = cur.ct * 64 + st_k;
             const uint4 e = S::stage_elem(g, pl, s, s < g.n);
             colbuf[0][pl * kPlaneLen + st_k] = e;
             colbuf[0][pl * kPlaneLen + st_k + 64] = e;
         }
         held[u] = make_uint4(0u, 0u, 0u, 0u);
-        if (pl < NPL && pre.ct >= 0) {
+        if (pl < NPL && pre.ct >= 0 && (pl < S::kFarPlanes || pre_near)) {
             const int s = pre.ct * 64 + st_k;
             held[u] = S::stage_elem(g, pl, s, s < g.n);
         }
@@ -444,7 +486,7 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
 #pragma unroll
         for (int u = 0; u < SPT; ++u) {
             const int pl = wave + W * u;
-            if (pl < NPL && pre.ct >= 0) {
+            if (pl < NPL && pre.ct >= 0 && (pl < S::kFarPlanes || pre_near)) {
                 colbuf[buf ^ 1][pl * kPlaneLen + st_k] = held[u];
                 colbuf[buf ^ 1][pl * kPlaneLen + st_k + 64] = held[u];
             }
@@ -461,10 +503,11 @@ __global__ __launch_bounds__(64 * W) void k_pairs_sym(const SymArgs g) {
         }
         cur = pre;
         pre.next(g, wg);
+        pre_near = pre.ct >= 0 && wants_near(pre);
 #pragma unroll
         for (int u = 0; u < SPT; ++u) {
             const int pl = wave + W * u;
-            if (pl < NPL && pre.ct >= 0) {
+            if (pl < NPL && pre.ct >= 0 && (pl < S::kFarPlanes || pre_near)) {
                 const int s = pre.ct * 64 + st_k;
                 held[u] = S::stage_elem(g, pl, s, s < g.n);
             }
