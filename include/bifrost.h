@@ -523,8 +523,10 @@ BF_API int bf_set_batched_config(bf_ctx *ctx, int op, int prec, int k_per_lane, 
  * Bit (1 << BF_OP_DTMIN) (on by default) does the same for the mixed time-step pass over one set
  * with r_fb = 0, in the set's own order (no sort): a pair's free-fall and fly-by rates are the
  * same number for both particles, so each unordered pair is evaluated once for the two maxima.
- * Same size limits; (n / 2048 + 1) * 8 + 16 bytes of scratch per particle.  Results as the
- * directed pass (a maximum is exact in any order), bitwise repeatable. */
+ * From 24,576 particles (BF_SORT_ANY_SIZE: any size; the FP64 acceleration and gradient passes
+ * over one set, swept the same way in their own order, from 32,768); (n / 2048 + 1) * 8 + 16
+ * bytes of scratch per particle.
+ * Results as the directed pass (a maximum is exact in any order), bitwise repeatable. */
 BF_API int bf_set_spatial_sort(bf_ctx *ctx, int ops_mask, double kappa);
 
 /* Synchronising.  Counters of the most recent acceleration / gradient / time-step pass: targets
