@@ -226,6 +226,8 @@ struct NgbArgs {
     unsigned long long* count;    // pairs found (may exceed cap)
     uint32_t* flags;
 };
+// targets per thread of the neighbour kernel (a workgroup of 64 waves threads takes 64 waves kNgbK)
+constexpr int kNgbK = 2;
 hipError_t launch_ngb(const NgbArgs& a, int waves, int nblocks, hipStream_t st);
 size_t ngb_sort_tmp_bytes(int64_t m);
 hipError_t launch_ngb_finish(unsigned long long* keys_in, unsigned long long* keys_out, int64_t m, void* tmp,

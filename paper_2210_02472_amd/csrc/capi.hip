@@ -1937,7 +1937,7 @@ BF_API int bf_neighbours(bf_ctx* c, const bf_particles* P, const bf_set* t, cons
     a.cap = cap;
     a.flags = c->d_flags;
     constexpr int T = 256;
-    const int64_t nslabs = (t->count + T - 1) / T, ntiles = (s->count + T - 1) / T;
+    const int64_t nslabs = (t->count + T * kNgbK - 1) / (T * kNgbK), ntiles = (s->count + T - 1) / T;
     int64_t split = std::max<int64_t>(1, (8 * (int64_t)c->num_cu + nslabs - 1) / nslabs);
     split = std::min(split, ntiles);
     const int64_t tiles_per_chunk = (ntiles + split - 1) / split;

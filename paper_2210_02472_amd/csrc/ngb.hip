@@ -1,6 +1,7 @@
 // Subsystem neighbour search and subsystem labels (Sec. 3.3).
 //
-//  * k_ngb: tiled pass over target x source pairs.  Only pairs closer than r_max are examined
+//  * k_ngb: tiled pass over target x source pairs, kNgbK targets per thread.  Only pairs closer
+//    than r_max are examined
 //    further; for those the two-body elements of the relative orbit decide (Eqs. ngb-bound,
 //    ngb-unbound): with mu = G (m_i + m_j), specific energy E = v^2/2 - mu/r and specific
 //    angular momentum h, a bound pair (E < 0, a = -mu / 2E) is a neighbour when a < r_ngb or
@@ -36,18 +37,25 @@ __device__ __forceinline__ bool ngb_criterion(double rx, double ry, double rz, d
     return rp < a.r_ngb && a.C * r < a.tau * sqrt(v2);
 }
 
-template <int W>
+// A workgroup of W wavefronts stages T = 64 W sources at a time in LDS; each thread takes K
+// targets (slots slab T K + t + T k), so every source read from LDS serves K pairs.
+template <int W, int K>
 __global__ __launch_bounds__(64 * W) void k_ngb(const NgbArgs a) {
     constexpr int T = 64 * W;
     __shared__ double4 tp[T];  // (x, y, z, m)
     __shared__ double4 tv[T];  // (vx, vy, vz, particle index)
     const int c = blockIdx.x % a.split;
     const int slab = blockIdx.x / a.split;
-    const int k = slab * T + threadIdx.x;
-    const bool active = k < a.tgt.count;
-    const int pi = particle_of(a.tgt, active ? k : 0, a.P.n, a.flags);
-    const double xi = a.P.x[pi], yi = a.P.y[pi], zi = a.P.z[pi];
-    const double vxi = a.P.vx[pi], vyi = a.P.vy[pi], vzi = a.P.vz[pi], mi = a.P.m[pi];
+    int pi[K];
+    bool active[K];
+    double xi[K], yi[K], zi[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int slot = slab * (T * K) + (int)threadIdx.x + T * k;
+        active[k] = slot < a.tgt.count;
+        pi[k] = particle_of(a.tgt, active[k] ? slot : 0, a.P.n, a.flags);
+        xi[k] = a.P.x[pi[k]]; yi[k] = a.P.y[pi[k]]; zi[k] = a.P.z[pi[k]];
+    }
     const int j0 = c * a.chunk, j1 = min(a.src.count, j0 + a.chunk);
     for (int jt = j0; jt < j1; jt += T) {
         const int len = min(T, j1 - jt);
@@ -58,29 +66,34 @@ __global__ __launch_bounds__(64 * W) void k_ngb(const NgbArgs a) {
             tv[threadIdx.x] = make_double4(a.P.vx[p], a.P.vy[p], a.P.vz[p], (double)p);
         }
         __syncthreads();
-        if (!active) continue;
+        if (!(active[0])) continue;  // slots past the end come last
         for (int j = 0; j < len; ++j) {
             const double4 s = tp[j];
-            const double rx = s.x - xi, ry = s.y - yi, rz = s.z - zi;
-            const double r2 = __builtin_fma(rx, rx, __builtin_fma(ry, ry, rz * rz));
-            if (r2 >= a.r_max2) continue;
-            const double4 u = tv[j];
-            const int pj = (int)u.w;
-            if (pj == pi) continue;
-            if (r2 == 0.0) {  // coincident: no orbit; reported, not linked
-                atomicOr(a.flags, BF_FLAG_COINCIDENT);
-                continue;
-            }
-            if (ngb_criterion(rx, ry, rz, u.x - vxi, u.y - vyi, u.z - vzi, a.G * (mi + s.w), a)) {
-                const unsigned long long e = atomicAdd(a.count, 1ull);
-                if ((int64_t)e < a.cap) a.keys[e] = (unsigned long long)(uint32_t)pi << 32 | (uint32_t)pj;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double rx = s.x - xi[k], ry = s.y - yi[k], rz = s.z - zi[k];
+                const double r2 = __builtin_fma(rx, rx, __builtin_fma(ry, ry, rz * rz));
+                if (r2 >= a.r_max2 || !active[k]) continue;
+                const double4 u = tv[j];
+                const int pj = (int)u.w;
+                const int i = pi[k];
+                if (pj == i) continue;
+                if (r2 == 0.0) {  // coincident: no orbit; reported, not linked
+                    atomicOr(a.flags, BF_FLAG_COINCIDENT);
+                    continue;
+                }
+                if (ngb_criterion(rx, ry, rz, u.x - a.P.vx[i], u.y - a.P.vy[i], u.z - a.P.vz[i],
+                                  a.G * (a.P.m[i] + s.w), a)) {
+                    const unsigned long long e = atomicAdd(a.count, 1ull);
+                    if ((int64_t)e < a.cap) a.keys[e] = (unsigned long long)(uint32_t)i << 32 | (uint32_t)pj;
+                }
             }
         }
     }
 }
 
 hipError_t launch_ngb(const NgbArgs& a, int waves, int nblocks, hipStream_t st) {
-    if (waves == 4) hipLaunchKernelGGL(k_ngb<4>, dim3(nblocks), dim3(256), 0, st, a);
+    if (waves == 4) hipLaunchKernelGGL((k_ngb<4, kNgbK>), dim3(nblocks), dim3(256), 0, st, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
