@@ -204,6 +204,27 @@ def run_workload(name, args):
         names = {bf.BF_OP_FORCES: "k_pairs<Acc64> (acceleration)", bf.BF_OP_GRADIENT: "k_pairs<Grad64> (gradient)",
                  bf.BF_OP_DTMIN: "-"}
         roof = _dominant(bf, times, credit, names, PEAK_FP64_TFLOPS, "FP64 vector peak")
+        # the same step replayed from a HIP graph: a one-level HHS interval of length dt (every
+        # particle on level 0) is one FSI cycle whose first acceleration is computed afresh
+        Pg = bf.Particles.from_numpy(d)
+        lv0 = torch.zeros(n, dtype=torch.int32, device="cuda")
+        ctx.hhs_interval(Pg, lv0, 0, dt, prec="fp64")
+        torch.cuda.synchronize()
+        for op in (bf.BF_OP_FORCES, bf.BF_OP_GRADIENT, bf.BF_OP_DTMIN):
+            ctx.pair_credit(op, reset=True)
+        ctx.hhs_interval(Pg, lv0, 0, dt, prec="fp64")
+        torch.cuda.synchronize()
+        g_pairs = sum(ctx.pair_credit(op, reset=True) for op in (bf.BF_OP_FORCES, bf.BF_OP_GRADIENT, bf.BF_OP_DTMIN))
+        gr = ctx.capture_hhs_interval(Pg, lv0, 0, dt, prec="fp64")
+        for _ in range(max(1, warmup)):
+            gr.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            gr.launch()
+        torch.cuda.synchronize()
+        g_wall = (time.perf_counter() - t0) / steps
+        gr.close()
         # oracle: the same FSI steps (acceleration of the first step included)
         Po = oracle.Particles.from_dict(d)
         rate, tc, k = _cpu_rate(oracle, lambda k: oracle.fsi_step(Po, dt), lambda k: 3.0 * n * (n - 1), 5.0)
@@ -215,6 +236,9 @@ def run_workload(name, args):
                                "dt": dt},
                     "pairs_per_step": pairs, "energy_log": energies,
                     "rel_energy_drift_10_steps": abs(energies[-1] / energies[0] - 1),
+                    "graph": {"ms_per_step": g_wall * 1e3, "pairs_per_step": g_pairs, "value": g_pairs / g_wall,
+                              "note": "one-level HHS interval of length dt captured once and replayed; "
+                                      "pairs as the library credits them for that interval"},
                     "roofline": roof,
                     "cpu_baseline": {"value": rate, "unit": "pair interactions/s", "cores": nthreads,
                                      "kind": "oracle", "sample": f"{k} full FSI steps of the same cluster, "
