@@ -86,6 +86,9 @@ hipError_t launch_reduce(int op, int prec, const PairArgs& a, hipStream_t st);
 // Mixed acceleration / gradient pass over few targets and sources in one launch (no source
 // split in memory): results and the fix-up queue written directly.
 hipError_t launch_pairs_small(int op, const PairArgs& a, hipStream_t st);
+// FP64 acceleration / gradient, the same limits: sources read from the masters, no pack, the pass
+// statistics cleared by the kernel (one launch)
+hipError_t launch_pairs_small64(int op, const PairArgs& a, hipStream_t st);
 hipError_t launch_zero_count(int32_t* c, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* c, int n, hipStream_t st);
 // one kernel: zero the fix-up counter (if not NULL) and the three pass statistics

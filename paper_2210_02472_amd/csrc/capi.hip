@@ -409,7 +409,13 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
                        sr->count <= kSmallMaxSources && ctx->forced[op][prec].k == 0 &&
                        ctx->tuned.find(std::make_tuple(op, prec, (int)kTuneDirected, ilog2_bucket(tg->count),
                                                        ilog2_bucket(sr->count))) == ctx->tuned.end();
-    if (sym || sym64 || symdt || small) p.split = 1;  // no source split in memory
+    // the same for FP64 passes: one launch, sources straight from the masters, no pack
+    const bool small64 = !sorted && !sym && !sym64 && prec == BF_PREC_FP64 && (op == OP_ACC || op == OP_GRAD) &&
+                         ctx->sub == nullptr && tg->count <= kSmallMaxTargets && sr->count <= kSmallMaxSources &&
+                         ctx->forced[op][prec].k == 0 &&
+                         ctx->tuned.find(std::make_tuple(op, prec, (int)kTuneDirected, ilog2_bucket(tg->count),
+                                                         ilog2_bucket(sr->count))) == ctx->tuned.end();
+    if (sym || sym64 || symdt || small || small64) p.split = 1;  // no source split in memory
     // scratch: [fix counter | fix list (one slot per target)], the split partials, the packed
     // sources (unsorted) and the fix-up partials: from the context's buffers, or the arena
     const bool fix = prec == BF_PREC_MIXED && op != OP_DT;
@@ -443,7 +449,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
                         ctx->stream);
             if (rc) return rc;
         }
-        if (!sorted && sr->count > 0) {
+        if (!sorted && !small64 && sr->count > 0) {
             rc = ensure(&ctx->scratch2, &ctx->scratch2_bytes, (size_t)sr->count * pack_bytes(op, prec), ctx->stream);
             if (rc) return rc;
         }
@@ -496,8 +502,9 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
     if (p.split > 1) a.part = part_buf;
     a.tile_stats = ctx->d_stats + 1;
     a.pass_stats = ctx->d_stats;
-    const bool pack_begins = !sorted && sr->count > 0;  // the pack kernel starts the pass
-    if (!pack_begins) BF_HIP(launch_pass_begin(fix ? a.fix_count : nullptr, ctx->d_stats, ctx->stream));
+    const bool pack_begins = !sorted && !small64 && sr->count > 0;  // the pack kernel starts the pass
+    // (the FP64 one-launch kernel clears the pass statistics itself)
+    if (!pack_begins && !small64) BF_HIP(launch_pass_begin(fix ? a.fix_count : nullptr, ctx->d_stats, ctx->stream));
     SymArgs g{};
     if (sorted) {
         // order targets and sources along a Morton curve, then pack the sorted sources into tiles
@@ -543,7 +550,7 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
             g.kappa = a.kappa;
             g.tile_stats = a.tile_stats;
         }
-    } else if (sr->count > 0) {
+    } else if (sr->count > 0 && !small64) {
         a.pack = pack_buf;
         BF_HIP(launch_pack(op, prec, a, ctx->stream, fix ? 2 : 1));
         if (sym64) {  // rows and columns: the FP64 pack in the set's order
@@ -610,12 +617,13 @@ int run_pairs(bf_ctx* ctx, int op, int prec, const Masters& M, const bf_set* tg,
         }
     } else if (sorted) BF_HIP(launch_pairs_sorted(op, p.cfg, a, p.nblocks, ctx->stream));
     else if (small) BF_HIP(launch_pairs_small(op, a, ctx->stream));
+    else if (small64) BF_HIP(launch_pairs_small64(op, a, ctx->stream));
     else BF_HIP(launch_pairs(op, prec, p.cfg, a, p.nblocks, ctx->stream));
     // credit: every (target, source) pair, less the self-pairs when targets and sources are one set
     ctx->pair_credit[op] += (int64_t)tg->count * (same_set(tg, sr) ? sr->count - 1 : sr->count);
     ctx->last_kind = sym || sym64 || symdt ? BF_PASS_SYMMETRIC : sorted ? BF_PASS_SORTED : BF_PASS_UNSORTED;
-    ctx->last_k = sym || symdt ? sc.k : sym64 ? 4 : small ? 1 : p.cfg.k;
-    ctx->last_waves = sym || symdt ? sc.waves : sym64 ? 4 : small ? 16 : p.cfg.waves;
+    ctx->last_k = sym || symdt ? sc.k : sym64 ? 4 : small || small64 ? 1 : p.cfg.k;
+    ctx->last_waves = sym || symdt ? sc.waves : sym64 ? 4 : small || small64 ? 16 : p.cfg.waves;
     ctx->last_split = sym || sym64 || symdt ? g.n_chunks : p.split;
     ctx->last_passes = sym || sym64 || symdt ? sp.passes : 1;
     if (timed) {

@@ -285,6 +285,11 @@ struct Acc64 {
     using A32 = int;  // unused
     struct A64 { double x, y, z; };
     __device__ static Src load(const PairArgs& a, int q) { return {static_cast<const double4*>(a.pack)[q]}; }
+    // source q straight from the masters (the one-launch small pass has no pack)
+    __device__ static Src load_master(const PairArgs& a, int q) {
+        const int p = particle_of(a.src, q, a.P.n, a.flags);
+        return {make_double4(a.P.x[p], a.P.y[p], a.P.z[p], a.G * a.P.m[p])};
+    }
     __device__ static void target(const PairArgs& a, int p, Tgt& t) { t.x = a.P.x[p]; t.y = a.P.y[p]; t.z = a.P.z[p]; }
     __device__ static void zero(A64& r) { r.x = r.y = r.z = 0.0; }
     __device__ static void pair64(A64& r, const Tgt& t, const Src& s, double eps2t, int /*pi*/) {
@@ -310,6 +315,11 @@ struct Grad64 {
     __device__ static Src load(const PairArgs& a, int q) {
         const double4* pk = static_cast<const double4*>(a.pack);
         return {pk[2 * q], pk[2 * q + 1]};
+    }
+    __device__ static Src load_master(const PairArgs& a, int q) {
+        const int p = particle_of(a.src, q, a.P.n, a.flags);
+        return {make_double4(a.P.x[p], a.P.y[p], a.P.z[p], a.G * a.P.m[p]),
+                make_double4(a.P.ax[p], a.P.ay[p], a.P.az[p], 0.0)};
     }
     __device__ static void target(const PairArgs& a, int p, Tgt& t) {
         t.x = a.P.x[p]; t.y = a.P.y[p]; t.z = a.P.z[p];

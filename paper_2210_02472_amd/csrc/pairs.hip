@@ -116,6 +116,69 @@ __global__ __launch_bounds__(64 * kSmallWaves) void k_pairs_small(const PairArgs
     }
 }
 
+// The same in FP64 for the FP64 passes: sources straight from the masters (no pack kernel),
+// FP64 pairs with the FP64 kernels' tiny added to s^2, and the pass statistics cleared here (an
+// FP64 pass queues no fix-up): one launch per pass.
+template <class Op>
+__global__ __launch_bounds__(64 * kSmallWaves) void k_pairs_small64(const PairArgs a) {
+    constexpr int NP = Op::NC;
+    constexpr int kTileBytes = kSmallWaves * 64 * (int)sizeof(typename Op::Src);
+    constexpr int kRedBytes = kSmallWaves * kSmallG * NP * kSmallT * (int)sizeof(double);
+    __shared__ __align__(16) unsigned char lds[kTileBytes > kRedBytes ? kTileBytes : kRedBytes];
+    if (blockIdx.x == 0 && threadIdx.x < 3 && a.pass_stats) a.pass_stats[threadIdx.x] = 0;
+    typename Op::Src* tile = reinterpret_cast<typename Op::Src*>(lds) + (threadIdx.x >> 6) * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = lane % kSmallT, grp = lane / kSmallT;
+    const int nt = a.tgt.count, ns = a.src.count;
+    const int slot = blockIdx.x * kSmallT + t;
+    const int pi = particle_of(a.tgt, slot < nt ? slot : nt - 1, a.P.n, a.flags);
+    typename Op::Tgt tg;
+    Op::target(a, pi, tg);
+    typename Op::A64 acc;
+    Op::zero(acc);
+    const double eps2t = a.eps2 + kTiny64;
+    const int per = (ns + kSmallWaves - 1) / kSmallWaves;  // sources per wavefront
+    const int j0 = wave * per, j1 = min(ns, j0 + per);
+    const int steps = (per + 63) / 64;  // the same for every wavefront
+    for (int st = 0; st < steps; ++st) {
+        const int jt = j0 + st * 64;
+        const int len = min(64, j1 - jt);  // <= 0 past this wavefront's slice
+        __syncthreads();
+        if (lane < len) tile[lane] = Op::load_master(a, jt + lane);
+        __syncthreads();
+        const int e0 = grp * (64 / kSmallG), e1 = min(len, e0 + 64 / kSmallG);
+#pragma unroll 2
+        for (int e = e0; e < e1; ++e) Op::pair64(acc, tg, tile[e], eps2t, pi);
+    }
+    double v[NP];
+    Op::comps(acc, v);
+    __syncthreads();  // the tiles are done with: the LDS now holds the sums
+    double* red = reinterpret_cast<double*>(lds);  // [wave][group][comp][target]
+#pragma unroll
+    for (int c = 0; c < NP; ++c) red[((wave * kSmallG + grp) * NP + c) * kSmallT + t] = v[c];
+    __syncthreads();
+    if ((int)threadIdx.x < kSmallT && slot < nt) {
+        double r[NP];
+#pragma unroll
+        for (int c = 0; c < NP; ++c) r[c] = 0.0;
+#pragma unroll 4
+        for (int q = 0; q < kSmallWaves * kSmallG; ++q)
+#pragma unroll
+            for (int c = 0; c < NP; ++c) r[c] += red[(q * NP + c) * kSmallT + t];
+        write_result<Op>(a, slot, pi, r);
+    }
+}
+
+hipError_t launch_pairs_small64(int op, const PairArgs& a, hipStream_t st) {
+    const int nt = a.tgt.count;
+    if (nt <= 0) return hipSuccess;
+    const dim3 grid((nt + kSmallT - 1) / kSmallT), block(64 * kSmallWaves);
+    if (op == OP_ACC) hipLaunchKernelGGL(k_pairs_small64<Acc64>, grid, block, 0, st, a);
+    else if (op == OP_GRAD) hipLaunchKernelGGL(k_pairs_small64<Grad64>, grid, block, 0, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_pairs_small(int op, const PairArgs& a, hipStream_t st) {
     const int nt = a.tgt.count;
     if (nt <= 0) return hipSuccess;
