@@ -492,6 +492,44 @@ def test_small_pass_kernel_parity(ctx, op):
         assert rms <= RMS_TOL and mx <= MAX_TOL, (nt, ns, rms, mx)
 
 
+@pytest.mark.parametrize("op", ["forces", "gradient"])
+def test_small_pass_kernel_fp64_parity(ctx, op):
+    """FP64 passes of up to 6,144 targets and sources run as one launch that reads the sources
+    straight from the masters (no pack, no reduction kernel): ragged and tiny shapes within the
+    FP64 tolerance of the oracle (1e-12 of the magnitude sum), bitwise repeatable, and within
+    that tolerance of the split kernels a forced configuration selects, softened and not."""
+    d = _cluster(20000, 73)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    rng = np.random.default_rng(74)
+    af = oracle.forces(P)
+    ad = [torch.as_tensor(af[:, k].copy(), device="cuda") for k in range(3)]
+    opc = bf.BF_OP_FORCES if op == "forces" else bf.BF_OP_GRADIENT
+    for (nt, ns), eps2 in zip(((1, 5), (17, 1000), (333, 4097), (6144, 6144), (6145, 100)),
+                              (0.0, 1e-6, 0.0, 1e-6, 0.0)):
+        tg = np.sort(rng.choice(20000, nt, replace=False))
+        sr = np.sort(rng.choice(20000, ns, replace=False))
+        run = (lambda: ctx.forces(Pd, tg, sr, eps2=eps2, prec="fp64")) if op == "forces" else \
+            (lambda: ctx.force_gradient(Pd, ad, tg, sr, eps2=eps2, prec="fp64"))
+        a, b = run(), run()
+        assert all(torch.equal(x, y) for x, y in zip(a, b))
+        kind, k, waves, split = ctx.last_pass_config()
+        assert kind == "unsorted" and (waves == 16) == (nt <= 6144 and ns <= 6144), (nt, ns, waves)
+        if op == "forces":
+            ref, mag, _ = oracle.forces(P, tg, sr, eps2=eps2, return_mag=True)
+        else:
+            ref, mag, _ = oracle.gradient(P, af, tg, sr, eps2=eps2, return_mag=True)
+        got = gather(a, tg)
+        assert np.all(np.linalg.norm(got - ref, axis=1) <= 1e-12 * mag), (nt, ns)
+        try:
+            ctx.set_config(opc, "fp64", 1, 4, 0)
+            c = run()
+            assert ctx.last_pass_config()[2] == 4
+        finally:
+            ctx.set_config(opc, "fp64", 0)
+        assert np.all(np.linalg.norm(gather(c, tg) - got, axis=1) <= 1e-12 * mag), (nt, ns)
+    assert ctx.read_flags(clear=True) & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
+
+
 def test_autotune_table_round_trip(ctx, tmp_path):
     """The autotuner times the kernel variants for one size bucket, stores the fastest in the
     context and in a JSON cache; a fresh context loading the cache plans the same variant, and
