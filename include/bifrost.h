@@ -482,7 +482,7 @@ BF_API int bf_query_batched_config(bf_ctx *ctx, int op, int prec, int64_t max_ac
 BF_API int bf_autotune_load(bf_ctx *ctx, const char *cache_path);
 /* Force the shape of the pair-symmetric sweep of op (BF_OP_FORCES / BF_OP_GRADIENT / BF_OP_DTMIN):
  * rows x waves in {1 x 16, 2 x 8, 4 x 4} (BF_ERR_UNSUPPORTED otherwise), rounds of resident
- * workgroups in [0, 64] (0: 32).  rows = 0 restores the tuned or default choice. */
+ * workgroups in [0, 64] (0: 64).  rows = 0 restores the tuned or default choice. */
 BF_API int bf_set_symmetric_config(bf_ctx *ctx, int op, int rows, int waves, int rounds);
 /* Scratch limit of a pass that takes a pair-symmetric sweep over one set (its row sums, column
  * partials and running sums; bytes, 0: the default 32 GiB).  A sweep whose partials exceed it

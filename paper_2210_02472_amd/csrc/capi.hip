@@ -232,11 +232,13 @@ SymPasses sym_passes(bf_ctx* ctx, int64_t n, int chunks, const SymKind& k) {
     return sp;
 }
 
-// Default rounds of resident workgroups: 32.  At N = 2^20 the gradient sweep takes 414 ms with
+// Default rounds of resident workgroups: 64.  At N = 2^20 the gradient sweep takes 414 ms with
 // 2 rounds (1 share of the distances per row block), 396 ms with 4 (2 shares), 389 ms with 8,
-// 381-383 ms with 16 and 375 ms with 32 (16 shares); the acceleration 254, 246, 244, 240 and
-// 240 ms: the shares even out the workgroups' lengths and the last round is shorter.
-constexpr int kSymRounds = 32;
+// 381-383 ms with 16, 375 ms with 32 (16 shares) and 373 ms with 64 (32 shares); the
+// acceleration 254, 246, 244, 240, 241 and 239 ms: the shares even out the workgroups' lengths
+// and the last round is shorter.  The 262,144-body HHS interval takes the same time with 32 and
+// 64 (258 ms without PN).
+constexpr int kSymRounds = 64;
 
 // resident workgroups the shares of a sweep aim at
 int64_t sym_want(bf_ctx* ctx, int op, const KernelConfig& sc) {
