@@ -488,8 +488,11 @@ BF_API int bf_set_symmetric_config(bf_ctx *ctx, int op, int rows, int waves, int
  * partials and running sums; bytes, 0: the default 32 GiB).  A sweep whose partials exceed it
  * runs its distance shares in several passes, each adding its partials onto FP64 running sums
  * per particle (FP32 for the time-step maxima) in the order a single pass uses: the results are
- * bitwise the same.  The share count grows until one share fits; the smallest pass is one
- * block distance (16 bytes per particle for the mixed passes). */
+ * bitwise those of one pass with the same shares.  If one share does not fit, the share count
+ * grows until it does (the smallest pass is one block distance, 16 bytes per particle for the
+ * mixed passes); the row sums are then grouped differently, and the sums may differ from the
+ * unlimited pass's in the last bits (the time-step maxima do not).  Results stay bitwise
+ * repeatable for a given limit. */
 BF_API int bf_set_symmetric_scratch_limit(bf_ctx *ctx, size_t bytes);
 /* Sweeps (passes over the distance shares) of the most recent
  * pass; 1 when it did not take a pair-symmetric sweep or ran in one. */

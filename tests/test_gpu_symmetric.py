@@ -400,3 +400,47 @@ def test_symmetric_passes_bitwise(ctx, op):
     assert kind == "symmetric" and passes >= 2, (kind, passes)
     assert all(torch.equal(x, y) for x, y in zip(ref, got))
     assert ctx.read_flags(clear=True) & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
+
+
+@pytest.mark.parametrize("n", [5000, 70000])
+def test_symmetric_passes_limits(ctx, n):
+    """Scratch limits from below one distance's partials up to one pass less than needed, on a
+    small and a larger set (whose default shares hold several distances): results are bitwise
+    repeatable at every limit; bitwise those of a single pass while the limit leaves the shares
+    as they are (it only groups them into passes), and within 1e-13 of them when it has to cut
+    the shares finer (the row sums are then grouped differently); the time-step maxima are
+    bitwise the same at every limit."""
+    d = _king(n, 90 + n % 13)
+    Pd = _dev(d)
+    a = ctx.forces(Pd, prec="mixed")
+    runs = {
+        "forces": lambda: ctx.forces(Pd, prec="mixed"),
+        "gradient": lambda: ctx.force_gradient(Pd, a, prec="mixed"),
+        "fp64": lambda: ctx.force_gradient(Pd, a, prec="fp64"),
+        "dt": lambda: ctx.dt_min(Pd, eta_ff=0.2, eta_fb=0.15, prec="mixed"),
+    }
+    for name, run in runs.items():
+        ref = run()
+        ref_shares = ctx.last_pass_config()[3]
+        assert ctx.last_symmetric_passes() == 1
+        seen = set()
+        for limit in (1, 1 << 20, 5 << 20, 40 << 20):
+            try:
+                ctx.set_symmetric_scratch_limit(limit)
+                got = run()
+                kind, shares = ctx.last_pass_config()[0], ctx.last_pass_config()[3]
+                passes = ctx.last_symmetric_passes()
+                again = run()
+            finally:
+                ctx.set_symmetric_scratch_limit(0)
+            assert kind == "symmetric", (name, limit)
+            seen.add((passes, shares))
+            assert all(torch.equal(x, y) for x, y in zip(got, again)), (name, limit)
+            if shares == ref_shares or name == "dt":
+                assert all(torch.equal(x, y) for x, y in zip(ref, got)), (name, limit, passes, shares)
+            else:
+                for x, y in zip(ref, got):
+                    assert torch.allclose(x, y, rtol=1e-13, atol=1e-13 * float(y.abs().max())), (name, limit)
+        print(f"n={n} {name}: (passes, shares) {sorted(seen)}, one pass {ref_shares} shares", flush=True)
+        assert max(p for p, _ in seen) > 1, (name, seen)
+    assert ctx.read_flags(clear=True) & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
