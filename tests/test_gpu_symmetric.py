@@ -444,3 +444,30 @@ def test_symmetric_passes_limits(ctx, n):
         print(f"n={n} {name}: (passes, shares) {sorted(seen)}, one pass {ref_shares} shares", flush=True)
         assert max(p for p, _ in seen) > 1, (name, seen)
     assert ctx.read_flags(clear=True) & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
+
+
+def test_set_order_sweeps_on_an_index_list(ctx):
+    """The set-order sweeps (time-step rates, FP64 acceleration) take a permuted index list that
+    is both targets and sources (the same list): each unordered pair of the listed particles
+    once; results at the listed particles against the oracle over the same list, the rest of
+    the output untouched."""
+    n, m = 40000, 33001
+    d = _king(n, 97)
+    P, Pd = oracle.Particles.from_dict(d), _dev(d)
+    rng = np.random.default_rng(98)
+    lst = rng.permutation(n)[:m]
+    S = bf.ParticleSet.of(torch.as_tensor(lst.astype(np.int32), device="cuda"), n)
+    ff, fb = oracle.dt_min(P, lst, lst, eta_ff=0.2, eta_fb=0.15)
+    out = [torch.full((n,), -1.0, dtype=torch.float64, device="cuda") for _ in range(2)]
+    ctx.dt_min(Pd, S, S, eta_ff=0.2, eta_fb=0.15, prec="mixed", out=out)
+    assert ctx.last_pass_config()[0] == "symmetric"
+    np.testing.assert_allclose(out[0].cpu().numpy()[lst], ff, rtol=1e-6)
+    np.testing.assert_allclose(out[1].cpu().numpy()[lst], fb, rtol=1e-6)
+    rest = np.setdiff1d(np.arange(n), lst)
+    assert np.all(out[0].cpu().numpy()[rest] == -1.0) and np.all(out[1].cpu().numpy()[rest] == -1.0)
+    ref, mag, _ = oracle.forces(P, lst, lst, return_mag=True)
+    acc = ctx.forces(Pd, S, S, prec="fp64")
+    assert ctx.last_pass_config()[0] == "symmetric"
+    got = gather(acc, lst)
+    assert np.all(np.linalg.norm(got - ref, axis=1) <= 1e-12 * mag)
+    assert ctx.read_flags(clear=True) & (bf.BF_FLAG_NONFINITE | bf.BF_FLAG_BADINDEX) == 0
