@@ -325,6 +325,33 @@ def test_pn1_parity(ctx, kind):
     _flags_clean(ctx)
 
 
+@pytest.mark.parametrize("kind", ["range", "list"])
+def test_pn1_many_bhs(ctx, kind):
+    """A list of 5,000 BHs (more than the target kernel keeps in LDS: the BH-source flags come
+    from their own kernels) and of 300 (the flags from the BH sums' records), sources a range or
+    an index list that holds some of the BHs: against the oracle."""
+    n = 9000
+    d = _cluster(n, 33)
+    rng = np.random.default_rng(11)
+    for nbh in (5000, 300):
+        bh = np.sort(rng.choice(n, nbh, replace=False))
+        P, Pd = oracle.Particles.from_dict(d), _dev(d)
+        if kind == "range":
+            T, S = None, bf.ParticleSet.range(1000, 6000)
+            So = np.arange(1000, 7000)
+        else:
+            T = np.sort(rng.choice(n, 2500, replace=False))
+            So = np.sort(rng.choice(n, 5000, replace=False))
+            S = So
+        ref = oracle.pn1(P, bh, T, So, c=50.0)
+        out = ctx.pn1_bh(Pd, bh, T, S, c=50.0)
+        ti = np.arange(n) if T is None else T
+        got = gather(out, ti)
+        scale = np.abs(ref).max()
+        assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-14 * np.abs(ref)), (nbh, kind)
+    _flags_clean(ctx)
+
+
 def test_energy_parity(ctx):
     d = _cluster(4097, 41)
     P, Pd = oracle.Particles.from_dict(d), _dev(d)
